@@ -1,0 +1,241 @@
+/*
+ * slrf.h - C ABI of the MI355X shifted-Laplace rational-filter eigensolver.
+ *
+ * The library computes eigenpairs of a sparse symmetric-definite pencil
+ * A x = lambda B x in an interval (0, gamma] (Eq. (1) of the ParaSLRF paper)
+ * by rational-filter subspace iteration (Algorithms 1 and 2).  Its hot path is
+ * the filter application of Eq. (2)-(3) with conjugate-pole halving
+ * (Section 2):
+ *
+ *     U = sum_{j=1}^{N} 2 Re( w_j (A - sigma_j B)^{-1} B X ),
+ *
+ * one complex shifted system per upper-half-plane pole sigma_j and per column
+ * of X, each solved by restarted right-preconditioned GCR (Section 3.2) to the
+ * relative residual ||f - M y||_2 / ||f||_2 <= tol_lin, or truncated at
+ * It_max-linear (Section 4).  All (pole, column) systems of a call run as one
+ * batch on one GPU.
+ *
+ * Conventions shared by every entry point:
+ *  - Device pointers are HIP device addresses on the device that was current
+ *    when slrf_setup ran; host pointers are ordinary host memory.
+ *  - Dense real blocks (X, U, V, ...) are column-major n x ncols FP64 with
+ *    leading dimension n, unless stated otherwise.
+ *  - Every call is ordered on the stream given to slrf_setup.  Calls that
+ *    return host results (statistics, counts, eigenvalues in host memory)
+ *    synchronise that stream before returning.
+ *  - Status codes are returned; no exception crosses the ABI.  After an error
+ *    slrf_last_error(h) returns a message (thread-unsafe per handle).
+ *  - A handle must not be used from two host threads at once.
+ */
+#ifndef SLRF_H
+#define SLRF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct slrf_ctx* slrf_handle;
+
+/* ABI-stable complex double (real part first, as in C99 double complex). */
+typedef struct {
+  double re, im;
+} slrf_zd;
+
+typedef enum {
+  SLRF_OK = 0,
+  SLRF_E_ARG = 1,       /* invalid argument (null pointer, bad size, malformed CSR, ...) */
+  SLRF_E_NOMEM = 2,     /* device or host allocation failed / over the memory budget   */
+  SLRF_E_HIP = 3,       /* a HIP runtime call failed                                   */
+  SLRF_E_BREAKDOWN = 4, /* projected B-Gram not positive definite even after fallback  */
+  SLRF_E_NOCONV = 5,    /* iteration cap reached; partial results are written          */
+  SLRF_E_NUMERIC = 6,   /* NaN or Inf detected in a residual norm                       */
+  SLRF_E_NOGPU = 7      /* no usable gfx950 device                                      */
+} slrf_status;
+
+enum { SLRF_PREC_FP64 = 0, SLRF_PREC_MIXED = 1 };
+enum { SLRF_PC_NONE = 0, SLRF_PC_JACOBI = 1 };
+
+/*
+ * Sparse matrix in CSR form, device memory, owned by the caller.
+ * rowptr: int32[n+1], rowptr[0] = 0, nondecreasing, rowptr[n] = nnz.
+ * col:    int32[nnz], strictly increasing within each row, 0 <= col < n.
+ * val:    double[nnz].
+ * A and B passed to slrf_setup must have identical rowptr/col contents (one
+ * shared pattern; store explicit zeros where only one matrix has an entry) and
+ * every row must hold its diagonal entry.
+ */
+typedef struct {
+  int32_t n;
+  int32_t nnz;
+  const int32_t* rowptr;
+  const int32_t* col;
+  const double* val;
+} slrf_csr;
+
+/*
+ * Solver options.  slrf_default_options fills the paper's settings:
+ * tol_lin 1e-10 and maxit_lin 10000 (Section 3.2), tol_eig 1e-8 (Section 3.2
+ * residual test), max_outer 100 (Section 4), restart 30, FP64, Jacobi.
+ */
+typedef struct {
+  int32_t precision;   /* SLRF_PREC_FP64: complex FP64 Krylov sweeps.
+                          SLRF_PREC_MIXED: complex FP32 Krylov sweeps inside an
+                          FP64 residual / iterative-refinement loop.           */
+  int32_t precond;     /* SLRF_PC_JACOBI (point Jacobi on A - sigma_j B) or NONE */
+  int32_t restart;     /* GCR restart length m, 1..32                           */
+  int32_t maxit_lin;   /* cap on inner iterations per system (10000)            */
+  int32_t it_max_lin;  /* Algorithm 2 It_max-linear; 0 = off                    */
+  int32_t max_outer;   /* outer iteration cap for slrf_solve                    */
+  int32_t warm_start;  /* slrf_solve: Y_init = v/(theta - sigma) (Algorithm 2)   */
+  int32_t lock;        /* slrf_solve: locking + B-orthogonalisation (Alg. 2)    */
+  int32_t timing;      /* record per-kernel HIP event timings into the stats    */
+  int32_t max_slots;   /* systems resident at once (multiple of 16); 0 = auto   */
+  double tol_lin;      /* relative residual target of each shifted solve        */
+  double inner_rtol;   /* MIXED: a Krylov cycle stops once its residual fell by
+                          this factor (then the FP64 residual is recomputed)    */
+  double tol_eig;      /* Ritz pair converged when ||r||_2 < tol_eig             */
+  double mem_budget;   /* bytes of device workspace the planner may use; 0 = 60%
+                          of the free device memory at setup                   */
+} slrf_options;
+
+/* Per-kernel-class counters (algorithmic bytes, launches, event time). */
+enum {
+  SLRF_K_APPLY = 0, /* shifted SpMM q = (A - sigma B) z fused with the CGS dots */
+  SLRF_K_ORTH = 1,  /* CGS update of q, p                                        */
+  SLRF_K_STEP = 2,  /* r -= alpha q, z = P^-1 r, ||r||                            */
+  SLRF_K_RESID = 3, /* FP64 residual f - (A - sigma B) y and solution update      */
+  SLRF_K_REDUCE = 4,/* second-stage reductions and per-system scalars             */
+  SLRF_K_OTHER = 5, /* admission, compaction, filter sum, RHS SpMM, transposes    */
+  SLRF_K_COUNT = 6
+};
+
+typedef struct {
+  int64_t nsystems;      /* N * ncols                                             */
+  int64_t total_iters;   /* inner GCR iterations summed over systems              */
+  int32_t min_iters, max_iters;
+  int32_t cycles;        /* Krylov cycles (restart / refinement boundaries)       */
+  int32_t converged;     /* systems that met tol_lin                              */
+  int32_t capped;        /* systems stopped by it_max_lin or maxit_lin            */
+  int32_t max_pole_iters_ratio_x1000; /* 1000 * max/min over poles of the summed
+                                         iterations (the single-GPU analogue of
+                                         the paper's Ratio, Table 1)           */
+  double max_rel_resid;  /* max final FP64 relative residual over systems         */
+  double seconds;        /* wall time of the call                                 */
+  int64_t launches[SLRF_K_COUNT];
+  double bytes[SLRF_K_COUNT]; /* algorithmic HBM bytes                             */
+  double ms[SLRF_K_COUNT];    /* summed kernel time (only with options.timing)     */
+  int32_t* sys_iters;    /* optional, caller-owned host int32[N*ncols]: iterations
+                            of system (column c, pole j) at index c*N + j          */
+} slrf_filter_stats;
+
+typedef struct {
+  int32_t outer_iters;
+  int32_t nconv;
+  int64_t inner_iters;   /* summed over all filter calls                          */
+  double seconds;
+  double filter_seconds;
+  double rr_seconds;
+} slrf_solve_stats;
+
+const char* slrf_status_string(slrf_status s);
+const char* slrf_last_error(slrf_handle h);
+void slrf_default_options(slrf_options* opt);
+
+/*
+ * slrf_setup - bind a pencil, an interval and a pole/weight table.
+ * A, B: CSR descriptors (device arrays, caller-owned; must stay valid and
+ *   unchanged until slrf_destroy).  Validated on the host (a copy is read).
+ * gamma: upper end of the interval (0, gamma], > 0.
+ * npoles, poles, weights: the N upper-half-plane poles (Im > 0) and weights,
+ *   host arrays; conjugates are implied (Section 2).  1 <= N <= 64.
+ * opt: options (NULL = defaults).  stream: hipStream_t (NULL = null stream).
+ * Errors: SLRF_E_ARG for malformed input, SLRF_E_NOGPU, SLRF_E_HIP.
+ */
+slrf_status slrf_setup(slrf_handle* h, const slrf_csr* A, const slrf_csr* B, double gamma,
+                       int32_t npoles, const slrf_zd* poles, const slrf_zd* weights,
+                       const slrf_options* opt, void* stream);
+
+/* Frees the handle and all library-owned device memory.  NULL is a no-op. */
+void slrf_destroy(slrf_handle h);
+
+/* Replace options after setup (same validation as setup). */
+slrf_status slrf_set_options(slrf_handle h, const slrf_options* opt);
+
+/*
+ * slrf_filter - U = sum_j 2 Re(w_j Y_j), (A - sigma_j B) Y_j = B X
+ * (Eq. (2)-(3); Algorithm 1 solve and sum-reduce steps).
+ * X: device, n x ncols column-major.  U: device, n x ncols column-major
+ * (may not alias X).  theta_warm: device double[ncols] or NULL; when given,
+ * the solve of column c for pole j starts from y0 = x_c / (theta_c - sigma_j)
+ * and its initial residual is taken from Proposition 4.1 as
+ * (A - theta_c B) x_c / (sigma_j - theta_c) (no complex SpMM).
+ * stats: host, may be NULL.
+ * Returns SLRF_E_NOCONV when some system stopped at maxit_lin without meeting
+ * tol_lin (U is still written); it_max_lin truncation is not an error.
+ */
+slrf_status slrf_filter(slrf_handle h, int32_t ncols, const double* X, const double* theta_warm,
+                        double* U, slrf_filter_stats* stats);
+
+/*
+ * slrf_rayleigh_ritz - projected problem (U^T A U) s = theta (U^T B U) s
+ * (Algorithm 1, Rayleigh-Ritz step), theta ascending, v = U s with
+ * ||v||_B = 1, and the residual norms ||(A - theta B) v||_2 / (theta ||v||_B)
+ * (Section 3.2).  When nlocked > 0, U is first B-orthogonalised twice against
+ * the B-orthonormal locked block Xlocked (Algorithm 2).
+ * U: device n x ncols column-major, overwritten by the Ritz vectors V.
+ * Xlocked: device n x nlocked column-major or NULL when nlocked == 0.
+ * theta, resid: device double[ncols].
+ * Returns SLRF_E_BREAKDOWN if U^T B U is numerically singular beyond repair.
+ */
+slrf_status slrf_rayleigh_ritz(slrf_handle h, int32_t ncols, double* U, int32_t nlocked,
+                               const double* Xlocked, double* theta, double* resid);
+
+/*
+ * slrf_solve - Algorithm 1 (opt.lock = opt.warm_start = 0, it_max_lin = 0) or
+ * Algorithm 2 (locking, warm start, It_max-linear).
+ * nev: wanted eigenpairs in (0, gamma]; L >= nev: subspace width.
+ * V1: device n x L column-major start block (not modified).
+ * theta_out: device double[nev]; X_out: device n x nev column-major
+ * (B-orthonormal eigenvectors, ascending eigenvalues); nconv_out: host.
+ * Returns SLRF_E_NOCONV with partial results when max_outer is reached.
+ */
+slrf_status slrf_solve(slrf_handle h, int32_t nev, int32_t L, const double* V1, double* theta_out,
+                       double* X_out, int32_t* nconv_out, slrf_solve_stats* stats);
+
+/*
+ * slrf_shifted_spmm - one sweep of the shifted operator over a batch of
+ * complex block vectors, Q_s = (A - sigma_{pole[s]} B) Z_s (Eq. (2) operator).
+ * Z, Q: device, "panel layout": systems in panels of 16; element (row i,
+ * system s) at complex index ((s / 16) * n + i) * 16 + s % 16, interleaved
+ * (re, im); nsys is rounded up to a multiple of 16 and padding systems must
+ * be allocated.  precision SLRF_PREC_FP64: complex double; SLRF_PREC_MIXED:
+ * complex float (with FP32 copies of A and B).  pole: host int32[nsys],
+ * indices into the setup pole table.  Exposed for kernel parity tests and
+ * bandwidth measurement.
+ */
+slrf_status slrf_shifted_spmm(slrf_handle h, int32_t nsys, const int32_t* pole, int32_t precision,
+                              const void* Z, void* Q, double* ms_out);
+
+/* Problem size of a handle (-1 for NULL). */
+int32_t slrf_get_n(slrf_handle h);
+
+/*
+ * slrf_host_projected_eig - host-only solve of the small projected problem
+ * Ah s = theta Bh s (Algorithm 1, Rayleigh-Ritz step) as used inside
+ * slrf_rayleigh_ritz: Ah, Bh symmetric n x n row-major host arrays (Bh
+ * positive definite; if Cholesky fails, directions of Bh with eigenvalue below
+ * 1e-14 of the largest are dropped), theta host double[n] ascending, S host
+ * n x n row-major with S^T Bh S = I.  Returns the number of pairs (n, or fewer
+ * after truncation, trailing theta = +inf) or -1.  Makes no GPU call.
+ */
+int32_t slrf_host_projected_eig(int32_t n, const double* Ah, const double* Bh, double* theta,
+                                double* S);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLRF_H */

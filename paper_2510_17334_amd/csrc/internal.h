@@ -1,0 +1,145 @@
+// Internal declarations shared by the host orchestrator and the HIP kernels.
+//
+// Block-vector layout ("panel layout"): the complex vectors of a batch of
+// systems are grouped in panels of 16 systems; element (row i, slot t) lives at
+// complex index ((t / 16) * n + i) * 16 + t % 16.  A 16-lane group of a wave
+// reads one row of a panel as one contiguous segment (128 B for complex float,
+// 256 B for complex double), so every gather of the shifted SpMM is a
+// coalesced row read.
+//
+// Dense real blocks used by Rayleigh-Ritz are row-major n x ld internally (the
+// ABI is column-major; entry points transpose once on the way in and out).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace slrf {
+
+constexpr int kPanel = 16;      // systems per panel
+constexpr int kMaxRestart = 32; // GCR(m) with m <= 32
+constexpr int kThreads = 256;   // workgroup size of the block-vector kernels
+
+// Device view of the pencil (shared CSR pattern).
+struct DevPencil {
+  int n = 0, nnz = 0;
+  const int* rowptr = nullptr;
+  const int* col = nullptr;
+  const double* a = nullptr;  // FP64 values (caller-owned)
+  const double* b = nullptr;
+  const float* a32 = nullptr; // FP32 copies (library-owned)
+  const float* b32 = nullptr;
+  const double* da = nullptr; // diag(A), diag(B) (library-owned)
+  const double* db = nullptr;
+};
+
+// Launch geometry of the panel kernels: a grid of (row block, panel) tiles.
+struct PanelGrid {
+  int rpb = 512;   // rows per workgroup
+  int nrb = 0;     // row blocks
+  int npan = 0;    // panels covered by the launch
+  int group = 8;   // panels that share a row block before moving on (CSR reuse)
+  int C = 0;       // slot capacity (stride of per-slot arrays)
+  int ND = 0;      // stride of the partial-sum buffer (values per row block)
+  unsigned blocks() const {
+    long total = (long)nrb * npan;
+    long per = (total + 7) / 8;
+    return (unsigned)(per * 8);
+  }
+};
+
+// Per-slot tables of the resident systems.
+struct SlotTables {
+  const int* sys = nullptr;        // system id (c * N + j) or -1
+  const double2* sigma = nullptr;  // pole of the slot
+  const int* col = nullptr;        // column of X / F
+  const double* theta = nullptr;   // warm-start Ritz value of the column
+  const int* src = nullptr;        // compaction source slot (-1 = newly admitted)
+  int* active = nullptr;           // 1 while the slot iterates in the current cycle
+};
+
+// ----- shifted block kernels (inner precision T = float or double) -----
+template <typename T>
+hipError_t launch_apply_dots(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
+                             const void* Z, void* Qk, const void* Qbase, size_t vstride, int k,
+                             double2* part, bool precond, hipStream_t s);
+template <typename T>
+hipError_t launch_orth(const DevPencil& P, const PanelGrid& g, const SlotTables& st, void* Qk,
+                       void* Pk, const void* Z, const void* R, const void* Qbase,
+                       const void* Pbase, size_t vstride, int k, const double2* beta,
+                       double2* part, hipStream_t s);
+template <typename T>
+hipError_t launch_step(const DevPencil& P, const PanelGrid& g, const SlotTables& st, void* R,
+                       void* Z, const void* Qk, const double2* alpha_k, double2* part,
+                       bool precond, hipStream_t s);
+template <typename T>
+hipError_t launch_yupdate(int n, const PanelGrid& g, const SlotTables& st, double2* Y,
+                          const void* Pbase, size_t vstride, int kk, const double2* alpha,
+                          hipStream_t s);
+template <typename T>
+hipError_t launch_true_resid(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
+                             const double2* Y, const double* F, int ldf, void* R, void* Z,
+                             double2* part, bool precond, hipStream_t s);
+template <typename T>
+hipError_t launch_admit(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
+                        const double2* Yold, const void* Rold, const void* Zold, double2* Ynew,
+                        void* Rnew, void* Znew, const double* F, const double* E,
+                        const double* X, int ld, bool warm, double2* part, bool precond,
+                        hipStream_t s);
+template <typename T>
+hipError_t launch_spmm_panel(const DevPencil& P, const PanelGrid& g, const double2* sigma_slot,
+                             const void* Z, void* Q, hipStream_t s);
+
+hipError_t launch_retire(int n, const PanelGrid& g, const int* retire_sys, const double2* Y,
+                         double2* Ystore, hipStream_t s);
+hipError_t launch_filter_sum(int n, int ncols, int npoles, const double2* Ystore,
+                             const double2* w, double* Ur, hipStream_t s);
+
+// ----- second-stage reductions and per-slot scalar updates -----
+hipError_t launch_reduce(const double2* part, int nrb, int ND, int C, int nd, int nslots,
+                         double2* out, hipStream_t s);
+struct SlotScalars {
+  double2* beta = nullptr;   // [kMaxRestart][C]
+  double2* alpha = nullptr;  // [kMaxRestart][C]
+  double* qq = nullptr;      // [kMaxRestart][C]
+  double* target2 = nullptr; // [C] squared residual target of the current cycle
+  double* fnorm2 = nullptr;  // [ncols] squared column norms of F
+  int* sys_its = nullptr;    // [S]
+  double* sys_rn2 = nullptr; // [S] last FP64 squared residual norm
+  int* status = nullptr;     // [C] 0 continue, 1 converged, 2 capped, 3 numeric, -1 empty
+};
+hipError_t launch_fin_beta(const double2* red, int k, int C, int nslots, const SlotTables& st,
+                           const SlotScalars& sc, hipStream_t s);
+hipError_t launch_fin_alpha(const double2* red, int k, int C, int nslots, const SlotTables& st,
+                            const SlotScalars& sc, hipStream_t s);
+hipError_t launch_fin_rnorm(const double2* red, int nslots, const SlotTables& st,
+                            const SlotScalars& sc, int itcap, hipStream_t s);
+hipError_t launch_fin_true(const double2* red, int nslots, const SlotTables& st,
+                           const SlotScalars& sc, double tol, double inner_rtol, double safety,
+                           int itcap, hipStream_t s);
+
+// ----- real dense / sparse kernels for Rayleigh-Ritz (row-major blocks) -----
+hipError_t launch_spmm_real(const DevPencil& P, const double* X, int ld, int nc, double* AX,
+                            double* BX, const double* theta, double* E, hipStream_t s);
+hipError_t launch_transpose(const double* in, int rows, int cols, int ldin, double* out,
+                            int ldout, hipStream_t s);
+// G (p x q, row-major, ldg) = X^T Y; X: n x p (ldx), Y: n x q (ldy); part: scratch
+hipError_t launch_gram(int n, int p, int q, const double* X, int ldx, const double* Y, int ldy,
+                       double* part, int nchunk, double* G, int ldg, hipStream_t s);
+int gram_chunks(int n);
+// Z (n x q, ldz) = alpha * X (n x p, ldx) * S (p x q, lds) + beta * Z
+hipError_t launch_gemm_tall(int n, int p, int q, double alpha, const double* X, int ldx,
+                            const double* S, int lds, double beta, double* Z, int ldz,
+                            hipStream_t s);
+// per column c: out[c] = sum_r (X - theta_c Y)[r,c]^2 (theta NULL => X only) and
+// out2[c] = sum_r W[r,c] * Y[r,c] (W NULL => skipped)
+hipError_t launch_colstats(int n, int nc, const double* X, const double* Y, int ld,
+                           const double* theta, const double* W, double* part, int nchunk,
+                           double* out, double* out2, hipStream_t s);
+int colstat_chunks(int n);
+hipError_t launch_cast_f32(const double* in, float* out, size_t cnt, hipStream_t s);
+hipError_t launch_diag(const DevPencil& P, double* da, double* db, int* missing, hipStream_t s);
+
+}  // namespace slrf

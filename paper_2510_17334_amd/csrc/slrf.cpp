@@ -1,0 +1,1085 @@
+// C ABI and host orchestration of the MI355X rational-filter eigensolver.
+//
+// slrf_filter runs every (pole, column) shifted system of Eq. (2) through a
+// resident pool of "slots" on the GPU.  Systems enter the pool in order
+// s = c * N + j, iterate in Krylov cycles (restarted GCR, Section 3.2), and at
+// each cycle boundary the host (a) folds the cycle's directions into the FP64
+// solution, (b) recomputes the FP64 true residual, (c) retires converged or
+// capped systems to the per-system solution store, (d) compacts the survivors
+// to the front of the pool and admits waiting systems into the freed slots.
+// The mixed-precision form runs the cycles in complex FP32 and is otherwise the
+// same loop: the boundary steps are the FP64 iterative-refinement steps.
+// Host <-> device traffic inside a filter call is limited to per-slot flags.
+#include "slrf.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dense_host.h"
+#include "internal.h"
+
+using namespace slrf;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+struct Timer {
+  std::vector<hipEvent_t> pool;
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  size_t used = 0;
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  void reset() {
+    pending.clear();
+    used = 0;
+  }
+  ~Timer() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+}  // namespace
+
+struct slrf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  DevPencil P;
+  double gamma = 0.0;
+  int N = 0;
+  std::vector<double2> poles, weights;
+  slrf_options opt{};
+  std::string err;
+  size_t budget = 0;
+  // library-owned copies
+  float* a32 = nullptr;
+  float* b32 = nullptr;
+  double* da = nullptr;
+  double* db = nullptr;
+  double2* d_w = nullptr;
+  // workspace
+  std::vector<DevBuf> bufs;
+  int* h_flags = nullptr;  // pinned host mirror of per-slot flags
+  size_t h_flags_cap = 0;
+  Timer timer;
+  slrf_filter_stats* cur_stats = nullptr;
+
+  ~slrf_ctx() {
+    for (auto& b : bufs)
+      if (b.p) (void)hipFree(b.p);
+    if (a32) (void)hipFree(a32);
+    if (b32) (void)hipFree(b32);
+    if (da) (void)hipFree(da);
+    if (db) (void)hipFree(db);
+    if (d_w) (void)hipFree(d_w);
+    if (h_flags) (void)hipHostFree(h_flags);
+  }
+};
+
+namespace {
+
+enum BufId {
+  B_XR, B_F, B_E, B_UR, B_FN2, B_YS, B_Y0, B_Y1, B_R0, B_R1, B_Z0, B_Z1, B_Q, B_P, B_PART, B_RED,
+  B_TAB_I, B_TAB_D, B_SCAL, B_SYS, B_AU, B_BU, B_V, B_AV, B_BV, B_GPART, B_SMALL, B_XL, B_BXL,
+  B_CST, B_TMP, B_SSP, B_NBUF
+};
+
+#define HIPCHK(x)                                                     \
+  do {                                                                \
+    hipError_t e_ = (x);                                              \
+    if (e_ != hipSuccess) return fail_hip(h, e_, #x, __LINE__);       \
+  } while (0)
+
+slrf_status fail(slrf_ctx* h, slrf_status s, const std::string& msg) {
+  if (h) h->err = msg;
+  return s;
+}
+
+slrf_status fail_hip(slrf_ctx* h, hipError_t e, const char* what, int line) {
+  char buf[512];
+  std::snprintf(buf, sizeof(buf), "HIP error %d (%s) in %s at slrf.cpp:%d", (int)e,
+                hipGetErrorString(e), what, line);
+  if (h) h->err = buf;
+  return e == hipErrorOutOfMemory ? SLRF_E_NOMEM : SLRF_E_HIP;
+}
+
+hipError_t ensure(slrf_ctx* h, int id, size_t bytes, void** out) {
+  if ((int)h->bufs.size() < B_NBUF) h->bufs.resize(B_NBUF);
+  DevBuf& b = h->bufs[id];
+  if (bytes == 0) bytes = 256;
+  if (b.cap < bytes) {
+    if (b.p) {
+      hipError_t e = hipStreamSynchronize(h->stream);
+      if (e != hipSuccess) return e;
+      (void)hipFree(b.p);
+      b.p = nullptr;
+      b.cap = 0;
+    }
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) return e;
+    b.cap = bytes;
+  }
+  *out = b.p;
+  return hipSuccess;
+}
+
+template <typename P>
+hipError_t ensure_t(slrf_ctx* h, int id, size_t count, P** out) {
+  void* p = nullptr;
+  hipError_t e = ensure(h, id, count * sizeof(P), &p);
+  *out = static_cast<P*>(p);
+  return e;
+}
+
+hipError_t flags_host(slrf_ctx* h, size_t count) {
+  if (h->h_flags_cap >= count) return hipSuccess;
+  if (h->h_flags) (void)hipHostFree(h->h_flags);
+  h->h_flags = nullptr;
+  h->h_flags_cap = 0;
+  hipError_t e = hipHostMalloc((void**)&h->h_flags, count * sizeof(int), hipHostMallocDefault);
+  if (e == hipSuccess) h->h_flags_cap = count;
+  return e;
+}
+
+// Kernel-class timing and byte accounting.
+struct Scope {
+  slrf_ctx* h;
+  int cls;
+  hipEvent_t b = nullptr;
+  Scope(slrf_ctx* hh, int c, double bytes) : h(hh), cls(c) {
+    if (h->cur_stats) {
+      h->cur_stats->launches[cls] += 1;
+      h->cur_stats->bytes[cls] += bytes;
+    }
+    if (h->opt.timing && h->cur_stats) {
+      hipEvent_t a = h->timer.get();
+      b = h->timer.get();
+      if (a && b) {
+        (void)hipEventRecord(a, h->stream);
+        h->timer.pending.push_back({cls, a, b});
+      } else {
+        b = nullptr;
+      }
+    }
+  }
+  ~Scope() {
+    if (b) (void)hipEventRecord(b, h->stream);
+  }
+};
+
+void harvest_timers(slrf_ctx* h) {
+  if (!h->cur_stats) {
+    h->timer.reset();
+    return;
+  }
+  for (auto& r : h->timer.pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) h->cur_stats->ms[r.cls] += ms;
+  }
+  h->timer.reset();
+}
+
+hipError_t sync(slrf_ctx* h) {
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess) harvest_timers(h);
+  return e;
+}
+
+slrf_status validate_options(slrf_ctx* h, const slrf_options& o) {
+  if (o.precision != SLRF_PREC_FP64 && o.precision != SLRF_PREC_MIXED)
+    return fail(h, SLRF_E_ARG, "precision must be SLRF_PREC_FP64 or SLRF_PREC_MIXED");
+  if (o.precond != SLRF_PC_NONE && o.precond != SLRF_PC_JACOBI)
+    return fail(h, SLRF_E_ARG, "unknown preconditioner");
+  if (o.restart < 1 || o.restart > kMaxRestart)
+    return fail(h, SLRF_E_ARG, "restart must be in [1, 32]");
+  if (o.maxit_lin < 1) return fail(h, SLRF_E_ARG, "maxit_lin must be >= 1");
+  if (o.it_max_lin < 0) return fail(h, SLRF_E_ARG, "it_max_lin must be >= 0");
+  if (!(o.tol_lin >= 0.0) || !(o.tol_eig > 0.0))
+    return fail(h, SLRF_E_ARG, "tolerances must be positive");
+  if (!(o.inner_rtol >= 0.0 && o.inner_rtol < 1.0))
+    return fail(h, SLRF_E_ARG, "inner_rtol must be in [0, 1)");
+  if (o.max_outer < 1) return fail(h, SLRF_E_ARG, "max_outer must be >= 1");
+  if (o.max_slots < 0 || o.max_slots % kPanel != 0)
+    return fail(h, SLRF_E_ARG, "max_slots must be a non-negative multiple of 16");
+  if (o.mem_budget < 0) return fail(h, SLRF_E_ARG, "mem_budget must be >= 0");
+  return SLRF_OK;
+}
+
+PanelGrid make_grid(int n, int C, int occ, int ND) {
+  PanelGrid g;
+  g.rpb = n >= 65536 ? 512 : (n >= 8192 ? 256 : 64);
+  g.nrb = (n + g.rpb - 1) / g.rpb;
+  g.npan = (occ + kPanel - 1) / kPanel;
+  g.group = 8;
+  g.C = C;
+  g.ND = ND;
+  return g;
+}
+
+int nrb_for(int n) {
+  const int rpb = n >= 65536 ? 512 : (n >= 8192 ? 256 : 64);
+  return (n + rpb - 1) / rpb;
+}
+
+// Workspace plan of one filter call.
+struct Plan {
+  int C;         // slots
+  size_t bytes;  // total device bytes
+};
+
+template <typename T>
+Plan plan_filter(const slrf_ctx* h, int ncols) {
+  const size_t n = h->P.n;
+  const int m = h->opt.restart;
+  const int S = h->N * ncols;
+  const int Spad = (S + kPanel - 1) / kPanel * kPanel;
+  const size_t sT = 2 * sizeof(T);
+  const int ND = std::max(m, 2);
+  const size_t nrb = nrb_for((int)n);
+  const size_t fixed = 4 * n * ncols * sizeof(double) + (size_t)Spad * n * 16 + 64 * (size_t)S;
+  const size_t per_slot = n * (2 * 16 + 4 * sT + 2 * (size_t)m * sT) + nrb * ND * 16 +
+                          (size_t)ND * 16 + 3 * (size_t)kMaxRestart * 16 + 64;
+  int C = Spad;
+  if (h->opt.max_slots > 0) C = std::min(C, h->opt.max_slots);
+  if (fixed + (size_t)C * per_slot > h->budget) {
+    const size_t avail = h->budget > fixed ? h->budget - fixed : 0;
+    C = (int)std::min<size_t>((size_t)C, avail / per_slot) / kPanel * kPanel;
+  }
+  return Plan{C, fixed + (size_t)std::max(C, 0) * per_slot};
+}
+
+// ---------------------------------------------------------------------------
+// slrf_filter
+// ---------------------------------------------------------------------------
+template <typename T>
+slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta, double* U,
+                       slrf_filter_stats* st) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const int n = h->P.n, N = h->N, S = N * nc, m = h->opt.restart;
+  const size_t sT = 2 * sizeof(T);
+  const bool pc = h->opt.precond == SLRF_PC_JACOBI;
+  const bool warm = theta != nullptr;
+  const bool mixed = std::is_same<T, float>::value;
+  const double inner_rtol = mixed ? h->opt.inner_rtol : 0.0;
+  const double safety = mixed ? 0.5 : 0.9;
+  int itcap = h->opt.maxit_lin;
+  if (h->opt.it_max_lin > 0) itcap = std::min(itcap, h->opt.it_max_lin);
+  hipStream_t s = h->stream;
+  const int ND = std::max(m, 2);
+
+  Plan plan = plan_filter<T>(h, nc);
+  if (plan.C < kPanel)
+    return fail(h, SLRF_E_NOMEM, "memory budget too small for one panel of 16 systems");
+  const int C = plan.C;
+  const int Spad = (S + kPanel - 1) / kPanel * kPanel;
+  const int nrb = nrb_for(n);
+
+  double *Xr, *F, *E = nullptr, *Ur, *fn2;
+  double2 *Ys, *Ya, *Yb, *part, *red;
+  void *Ra, *Rb, *Za, *Zb, *Q, *Pb;
+  HIPCHK(ensure_t(h, B_XR, (size_t)n * nc, &Xr));
+  HIPCHK(ensure_t(h, B_F, (size_t)n * nc, &F));
+  if (warm) HIPCHK(ensure_t(h, B_E, (size_t)n * nc, &E));
+  HIPCHK(ensure_t(h, B_UR, (size_t)n * nc, &Ur));
+  HIPCHK(ensure_t(h, B_FN2, (size_t)nc + 1, &fn2));
+  HIPCHK(ensure_t(h, B_YS, (size_t)Spad * n, &Ys));
+  HIPCHK(ensure_t(h, B_Y0, (size_t)C * n, &Ya));
+  HIPCHK(ensure_t(h, B_Y1, (size_t)C * n, &Yb));
+  HIPCHK(ensure(h, B_R0, (size_t)C * n * sT, &Ra));
+  HIPCHK(ensure(h, B_R1, (size_t)C * n * sT, &Rb));
+  HIPCHK(ensure(h, B_Z0, (size_t)C * n * sT, &Za));
+  HIPCHK(ensure(h, B_Z1, (size_t)C * n * sT, &Zb));
+  HIPCHK(ensure(h, B_Q, (size_t)m * C * n * sT, &Q));
+  HIPCHK(ensure(h, B_P, (size_t)m * C * n * sT, &Pb));
+  HIPCHK(ensure_t(h, B_PART, (size_t)nrb * ND * C, &part));
+  HIPCHK(ensure_t(h, B_RED, (size_t)ND * C, &red));
+  // slot tables: int: sys, col, src, active, status, retire (6C); double2 sigma (C);
+  // double theta (C)
+  int* itab;
+  double* dtab;
+  HIPCHK(ensure_t(h, B_TAB_I, (size_t)6 * C, &itab));
+  HIPCHK(ensure_t(h, B_TAB_D, (size_t)3 * C, &dtab));
+  int *d_sys = itab, *d_col = itab + C, *d_src = itab + 2 * C, *d_act = itab + 3 * C,
+      *d_status = itab + 4 * C, *d_retire = itab + 5 * C;
+  double2* d_sigma = reinterpret_cast<double2*>(dtab);
+  double* d_theta_slot = dtab + 2 * C;
+  // scalars: beta, alpha (kMaxRestart*C double2 each), qq (kMaxRestart*C), target2 (C)
+  double* scal;
+  HIPCHK(ensure_t(h, B_SCAL, (size_t)kMaxRestart * C * 5 + C, &scal));
+  SlotScalars sc;
+  sc.beta = reinterpret_cast<double2*>(scal);
+  sc.alpha = reinterpret_cast<double2*>(scal + (size_t)2 * kMaxRestart * C);
+  sc.qq = scal + (size_t)4 * kMaxRestart * C;
+  sc.target2 = scal + (size_t)5 * kMaxRestart * C;
+  sc.fnorm2 = fn2;
+  int* sysi;
+  HIPCHK(ensure_t(h, B_SYS, (size_t)3 * S + 8, &sysi));
+  sc.sys_its = sysi;
+  sc.sys_rn2 = reinterpret_cast<double*>(sysi + S + (S & 1));
+  sc.status = d_status;
+  HIPCHK(flags_host(h, (size_t)std::max(C, S) * 2 + 16));
+  int* hflags = h->h_flags;
+
+  // ----- right-hand sides: F = B X (and E = (A - theta B) X for the warm start)
+  {
+    Scope sp(h, SLRF_K_OTHER, 16.0 * n * nc);
+    HIPCHK(launch_transpose(X, nc, n, n, Xr, nc, s));  // col-major -> row-major
+  }
+  {
+    Scope sp(h, SLRF_K_OTHER, (warm ? 24.0 : 16.0) * n * nc + 20.0 * h->P.nnz);
+    HIPCHK(launch_spmm_real(h->P, Xr, nc, nc, nullptr, F, warm ? theta : nullptr, E, s));
+  }
+  {
+    double* cpart;
+    const int nch = colstat_chunks(n);
+    HIPCHK(ensure_t(h, B_CST, (size_t)2 * nch * nc + 2, &cpart));
+    Scope sp(h, SLRF_K_OTHER, 8.0 * n * nc);
+    HIPCHK(launch_colstats(n, nc, F, nullptr, nc, nullptr, nullptr, cpart, nch, fn2, nullptr, s));
+  }
+  HIPCHK(hipMemsetAsync(sc.sys_its, 0, sizeof(int) * S, s));
+
+  // host-side pool state
+  std::vector<int> h_sys(C, -1), h_col(C, 0), h_src(C, -1);
+  std::vector<double2> h_sig(C, make_double2(0, 0));
+  std::vector<double> h_th(C, 0.0);
+  std::vector<double> h_theta_col;
+  if (warm) {
+    h_theta_col.resize(nc);
+    HIPCHK(hipMemcpyAsync(h_theta_col.data(), theta, sizeof(double) * nc, hipMemcpyDeviceToHost,
+                          s));
+  }
+  HIPCHK(sync(h));
+  int next = 0;  // next system to admit
+  int occ = 0;   // occupied slots (a prefix of the pool after compaction)
+  int cur = 0;   // which of the double buffers holds the live state
+  double2* Ybuf[2] = {Ya, Yb};
+  void* Rbuf[2] = {Ra, Rb};
+  void* Zbuf[2] = {Za, Zb};
+  std::vector<int> status(C, -1);
+  int kk_last = 0;
+  int cycles = 0;
+  bool numeric = false;
+  const size_t vstride = (size_t)C * n;  // elements between consecutive P_i / Q_i
+  const double csr_bytes = (double)h->P.nnz * (4.0 + 2.0 * sizeof(T)) + 4.0 * (n + 1);
+
+  SlotTables tabs;
+  tabs.sys = d_sys;
+  tabs.sigma = d_sigma;
+  tabs.col = d_col;
+  tabs.theta = d_theta_slot;
+  tabs.active = d_act;
+
+  while (true) {
+    // ----- cycle boundary: fold directions into y, FP64 true residual, status
+    if (occ > 0) {
+      const PanelGrid g = make_grid(n, C, occ, ND);
+      SlotTables t0 = tabs;
+      t0.src = nullptr;
+      if (kk_last > 0) {
+        Scope sp(h, SLRF_K_RESID, (double)occ * n * (32.0 + kk_last * sT));
+        HIPCHK(launch_yupdate<T>(n, g, t0, Ybuf[cur], Pb, vstride, kk_last, sc.alpha, s));
+      }
+      {
+        Scope sp(h, SLRF_K_RESID, (double)occ * n * (16.0 + 8.0 + 2 * sT) + 20.0 * h->P.nnz);
+        HIPCHK(launch_true_resid<T>(h->P, g, t0, Ybuf[cur], F, nc, Rbuf[cur], Zbuf[cur], part,
+                                    pc, s));
+      }
+      {
+        Scope sp(h, SLRF_K_REDUCE, 16.0 * nrb * occ);
+        HIPCHK(launch_reduce(part, nrb, ND, C, 1, occ, red, s));
+        HIPCHK(launch_fin_true(red, occ, t0, sc, h->opt.tol_lin, inner_rtol, safety, itcap, s));
+      }
+      HIPCHK(hipMemcpyAsync(hflags, d_status, sizeof(int) * occ, hipMemcpyDeviceToHost, s));
+      HIPCHK(sync(h));
+      for (int i = 0; i < occ; ++i) status[i] = hflags[i];
+    }
+    // ----- retire finished systems, compact the survivors, admit new ones
+    int nret = 0;
+    std::vector<int> keep;
+    keep.reserve(occ);
+    std::vector<int> h_ret(C, -1);
+    for (int i = 0; i < occ; ++i) {
+      if (status[i] == 0) {
+        keep.push_back(i);
+      } else {
+        h_ret[i] = h_sys[i];
+        ++nret;
+        if (status[i] == 3) numeric = true;
+      }
+    }
+    const int nadmit = std::min(C - (int)keep.size(), S - next);
+    if (nret > 0) {
+      HIPCHK(hipMemcpyAsync(d_retire, h_ret.data(), sizeof(int) * C, hipMemcpyHostToDevice, s));
+      const PanelGrid g = make_grid(n, C, occ, ND);
+      Scope sp(h, SLRF_K_OTHER, 32.0 * nret * n);
+      HIPCHK(launch_retire(n, g, d_retire, Ybuf[cur], Ys, s));
+    }
+    if (numeric) break;
+    if (nret > 0 || nadmit > 0) {
+      std::vector<int> ns(C, -1), ncl(C, 0), nsrc(C, -1);
+      std::vector<double2> nsg(C, make_double2(0, 0));
+      std::vector<double> nth(C, 0.0);
+      int t = 0;
+      for (int i : keep) {
+        ns[t] = h_sys[i];
+        ncl[t] = h_col[i];
+        nsg[t] = h_sig[i];
+        nth[t] = h_th[i];
+        nsrc[t] = i;
+        ++t;
+      }
+      for (int a = 0; a < nadmit; ++a, ++t, ++next) {
+        const int sys = next, c = sys / N, j = sys % N;
+        ns[t] = sys;
+        ncl[t] = c;
+        nsg[t] = h->poles[j];
+        nth[t] = warm ? h_theta_col[c] : 0.0;
+        nsrc[t] = -1;
+      }
+      const int nocc = t;
+      h_sys = ns;
+      h_col = ncl;
+      h_src = nsrc;
+      h_sig = nsg;
+      h_th = nth;
+      HIPCHK(hipMemcpyAsync(d_sys, h_sys.data(), sizeof(int) * C, hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(d_col, h_col.data(), sizeof(int) * C, hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(d_src, h_src.data(), sizeof(int) * C, hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(d_sigma, h_sig.data(), sizeof(double2) * C, hipMemcpyHostToDevice,
+                            s));
+      HIPCHK(hipMemcpyAsync(d_theta_slot, h_th.data(), sizeof(double) * C,
+                            hipMemcpyHostToDevice, s));
+      occ = nocc;
+      if (occ > 0) {
+        const PanelGrid g = make_grid(n, C, occ, ND);
+        SlotTables ta = tabs;
+        ta.src = d_src;
+        {
+          Scope sp(h, SLRF_K_OTHER,
+                   (double)keep.size() * n * 2 * (16.0 + 2 * sT) +
+                       (double)nadmit * n * (16.0 + 2 * sT + (warm ? 16.0 : 8.0)));
+          HIPCHK(launch_admit<T>(h->P, g, ta, Ybuf[cur], Rbuf[cur], Zbuf[cur], Ybuf[1 - cur],
+                                 Rbuf[1 - cur], Zbuf[1 - cur], F, E, Xr, nc, warm, part, pc, s));
+        }
+        cur = 1 - cur;
+        {
+          Scope sp(h, SLRF_K_REDUCE, 16.0 * nrb * occ);
+          HIPCHK(launch_reduce(part, nrb, ND, C, 1, occ, red, s));
+          HIPCHK(launch_fin_true(red, occ, ta, sc, h->opt.tol_lin, inner_rtol, safety, itcap,
+                                 s));
+        }
+        HIPCHK(hipMemcpyAsync(hflags, d_status, sizeof(int) * occ, hipMemcpyDeviceToHost, s));
+        HIPCHK(sync(h));
+        for (int i = 0; i < occ; ++i) status[i] = hflags[i];
+      }
+    }
+    if (occ == 0) break;
+    // active count after the boundary
+    int nact = 0;
+    for (int i = 0; i < occ; ++i) nact += status[i] == 0 ? 1 : 0;
+    kk_last = 0;
+    if (nact == 0) continue;  // everything resident is finished: next boundary retires it
+    ++cycles;
+    // ----- one Krylov cycle (at most m GCR steps)
+    const PanelGrid g = make_grid(n, C, occ, ND);
+    SlotTables tc = tabs;
+    tc.src = nullptr;
+    void* R = Rbuf[cur];
+    void* Z = Zbuf[cur];
+    for (int k = 0; k < m; ++k) {
+      char* Qk = static_cast<char*>(Q) + (size_t)k * vstride * sT;
+      char* Pk = static_cast<char*>(Pb) + (size_t)k * vstride * sT;
+      {
+        Scope sp(h, SLRF_K_APPLY, (double)nact * n * sT * (k + 2) + csr_bytes);
+        HIPCHK(launch_apply_dots<T>(h->P, g, tc, Z, Qk, Q, vstride, k, part, pc, s));
+      }
+      if (k > 0) {
+        Scope sp(h, SLRF_K_REDUCE, 16.0 * nrb * occ * k);
+        HIPCHK(launch_reduce(part, nrb, ND, C, k, occ, red, s));
+        HIPCHK(launch_fin_beta(red, k, C, occ, tc, sc, s));
+      }
+      {
+        Scope sp(h, SLRF_K_ORTH, (double)nact * n * sT * (2.0 * k + 5));
+        HIPCHK(launch_orth<T>(h->P, g, tc, Qk, Pk, Z, R, Q, Pb, vstride, k, sc.beta, part, s));
+      }
+      {
+        Scope sp(h, SLRF_K_REDUCE, 32.0 * nrb * occ);
+        HIPCHK(launch_reduce(part, nrb, ND, C, 2, occ, red, s));
+        HIPCHK(launch_fin_alpha(red, k, C, occ, tc, sc, s));
+      }
+      {
+        Scope sp(h, SLRF_K_STEP, (double)nact * n * sT * 4.0);
+        HIPCHK(launch_step<T>(h->P, g, tc, R, Z, Qk, sc.alpha + (size_t)k * C, part, pc, s));
+      }
+      {
+        Scope sp(h, SLRF_K_REDUCE, 16.0 * nrb * occ);
+        HIPCHK(launch_reduce(part, nrb, ND, C, 1, occ, red, s));
+        HIPCHK(launch_fin_rnorm(red, occ, tc, sc, itcap, s));
+      }
+      kk_last = k + 1;
+      HIPCHK(hipMemcpyAsync(hflags, d_act, sizeof(int) * occ, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(hflags + C, d_status, sizeof(int) * occ, hipMemcpyDeviceToHost, s));
+      HIPCHK(sync(h));
+      nact = 0;
+      for (int i = 0; i < occ; ++i) {
+        nact += hflags[i];
+        if (hflags[C + i] == 3) numeric = true;
+      }
+      if (nact == 0 || numeric) break;
+    }
+    if (numeric) break;
+  }
+
+  // ----- filter sum U = sum_j 2 Re(w_j Y_j) and back to column-major
+  {
+    Scope sp(h, SLRF_K_OTHER, (double)S * n * 16.0 + 8.0 * n * nc);
+    HIPCHK(launch_filter_sum(n, nc, N, Ys, h->d_w, Ur, s));
+  }
+  {
+    Scope sp(h, SLRF_K_OTHER, 16.0 * n * nc);
+    HIPCHK(launch_transpose(Ur, n, nc, nc, U, n, s));
+  }
+  // ----- statistics
+  std::vector<int> its(S);
+  std::vector<double> rn2(S), f2(nc);
+  HIPCHK(hipMemcpyAsync(its.data(), sc.sys_its, sizeof(int) * S, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(rn2.data(), sc.sys_rn2, sizeof(double) * S, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(f2.data(), fn2, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
+  HIPCHK(sync(h));
+  int conv = 0, capped = 0;
+  double maxrel = 0.0;
+  int64_t tot = 0;
+  int mn = S > 0 ? its[0] : 0, mx = 0;
+  std::vector<int64_t> pole_sum(N, 0);
+  for (int sys = 0; sys < S; ++sys) {
+    const int c = sys / N;
+    const double rel = f2[c] > 0 ? std::sqrt(rn2[sys] / f2[c]) : std::sqrt(rn2[sys]);
+    const bool ok = rn2[sys] <= h->opt.tol_lin * h->opt.tol_lin * f2[c];
+    conv += ok ? 1 : 0;
+    capped += ok ? 0 : 1;
+    maxrel = std::max(maxrel, rel);
+    tot += its[sys];
+    mn = std::min(mn, its[sys]);
+    mx = std::max(mx, its[sys]);
+    pole_sum[sys % N] += its[sys];
+  }
+  if (st) {
+    st->nsystems = S;
+    st->total_iters = tot;
+    st->min_iters = mn;
+    st->max_iters = mx;
+    st->cycles = cycles;
+    st->converged = conv;
+    st->capped = capped;
+    int64_t pmin = INT64_MAX, pmax = 0;
+    for (int j = 0; j < N; ++j) {
+      pmin = std::min(pmin, pole_sum[j]);
+      pmax = std::max(pmax, pole_sum[j]);
+    }
+    st->max_pole_iters_ratio_x1000 = pmin > 0 ? (int32_t)(1000.0 * pmax / pmin) : 0;
+    st->max_rel_resid = maxrel;
+    if (st->sys_iters) std::memcpy(st->sys_iters, its.data(), sizeof(int) * S);
+    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (numeric) return fail(h, SLRF_E_NUMERIC, "NaN or Inf in a residual norm");
+  if (capped > 0 && h->opt.it_max_lin == 0)
+    return fail(h, SLRF_E_NOCONV, "some shifted systems reached maxit_lin before tol_lin");
+  return SLRF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Rayleigh-Ritz on a row-major block (internal)
+// ---------------------------------------------------------------------------
+// Ur: n x nc row-major (in: filtered block; out: Ritz vectors V).  Xl/BXl:
+// row-major n x nl locked vectors and B times them.  Outputs: theta_h, res_h
+// (host), and AV/BV (row-major) when the buffers are given.
+slrf_status rr_rowmajor(slrf_ctx* h, int nc, double* Ur, int nl, const double* Xl,
+                        const double* BXl, std::vector<double>& theta_h,
+                        std::vector<double>& res_h, double** BV_out) {
+  const int n = h->P.n;
+  hipStream_t s = h->stream;
+  double *AU, *BU, *V, *AV, *BV, *gpart, *small, *cpart;
+  HIPCHK(ensure_t(h, B_AU, (size_t)n * nc, &AU));
+  HIPCHK(ensure_t(h, B_BU, (size_t)n * nc, &BU));
+  HIPCHK(ensure_t(h, B_V, (size_t)n * nc, &V));
+  HIPCHK(ensure_t(h, B_AV, (size_t)n * nc, &AV));
+  HIPCHK(ensure_t(h, B_BV, (size_t)n * nc, &BV));
+  const int gch = gram_chunks(n);
+  const int pq = std::max(nc, nl);
+  HIPCHK(ensure_t(h, B_GPART, (size_t)gch * pq * pq + 16, &gpart));
+  HIPCHK(ensure_t(h, B_SMALL, (size_t)3 * pq * pq + 4 * pq + 16, &small));
+  const int cch = colstat_chunks(n);
+  HIPCHK(ensure_t(h, B_CST, (size_t)2 * cch * nc + 2, &cpart));
+  double* Gd = small;                          // nc x nc or nl x nc
+  double* Gd2 = small + (size_t)pq * pq;       // second Gram
+  double* Sd = small + (size_t)2 * pq * pq;    // S
+  double* thd = small + (size_t)3 * pq * pq;   // theta (device)
+  double* r2 = thd + pq;
+  double* vb = r2 + pq;
+
+  if (nl > 0) {
+    // U <- U - X (X^T B U), twice (Algorithm 2, B-orthogonalisation vs locked X)
+    HIPCHK(launch_spmm_real(h->P, Ur, nc, nc, nullptr, BU, nullptr, nullptr, s));
+    for (int pass = 0; pass < 2; ++pass) {
+      HIPCHK(launch_gram(n, nl, nc, Xl, nl, BU, nc, gpart, gch, Gd, nc, s));
+      HIPCHK(launch_gemm_tall(n, nl, nc, -1.0, Xl, nl, Gd, nc, 1.0, Ur, nc, s));
+      if (pass == 0) HIPCHK(launch_gemm_tall(n, nl, nc, -1.0, BXl, nl, Gd, nc, 1.0, BU, nc, s));
+    }
+  }
+  HIPCHK(launch_spmm_real(h->P, Ur, nc, nc, AU, BU, nullptr, nullptr, s));
+  HIPCHK(launch_gram(n, nc, nc, Ur, nc, AU, nc, gpart, gch, Gd, nc, s));
+  HIPCHK(launch_gram(n, nc, nc, Ur, nc, BU, nc, gpart, gch, Gd2, nc, s));
+  std::vector<double> Ah((size_t)nc * nc), Bh((size_t)nc * nc), Sh((size_t)nc * nc);
+  HIPCHK(hipMemcpyAsync(Ah.data(), Gd, sizeof(double) * nc * nc, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(Bh.data(), Gd2, sizeof(double) * nc * nc, hipMemcpyDeviceToHost, s));
+  HIPCHK(sync(h));
+  theta_h.assign(nc, 0.0);
+  int fb = 0;
+  const int kgood = sym_gen_eig(nc, Ah.data(), Bh.data(), theta_h.data(), Sh.data(), &fb);
+  if (kgood < 0) return fail(h, SLRF_E_BREAKDOWN, "projected eigenproblem failed");
+  HIPCHK(hipMemcpyAsync(Sd, Sh.data(), sizeof(double) * nc * nc, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(thd, theta_h.data(), sizeof(double) * nc, hipMemcpyHostToDevice, s));
+  HIPCHK(launch_gemm_tall(n, nc, nc, 1.0, Ur, nc, Sd, nc, 0.0, V, nc, s));
+  HIPCHK(launch_gemm_tall(n, nc, nc, 1.0, AU, nc, Sd, nc, 0.0, AV, nc, s));
+  HIPCHK(launch_gemm_tall(n, nc, nc, 1.0, BU, nc, Sd, nc, 0.0, BV, nc, s));
+  // residual norms ||AV - theta BV|| and ||v||_B^2 = v^T B v
+  std::vector<double> thr(theta_h);
+  for (auto& t : thr)
+    if (!std::isfinite(t)) t = 0.0;
+  HIPCHK(hipMemcpyAsync(thd, thr.data(), sizeof(double) * nc, hipMemcpyHostToDevice, s));
+  HIPCHK(launch_colstats(n, nc, AV, BV, nc, thd, V, cpart, cch, r2, vb, s));
+  HIPCHK(hipMemcpyAsync(Ur, V, sizeof(double) * n * nc, hipMemcpyDeviceToDevice, s));
+  std::vector<double> r2h(nc), vbh(nc);
+  HIPCHK(hipMemcpyAsync(r2h.data(), r2, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(vbh.data(), vb, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
+  HIPCHK(sync(h));
+  res_h.assign(nc, HUGE_VAL);
+  for (int c = 0; c < nc; ++c) {
+    if (c >= kgood || !std::isfinite(theta_h[c])) continue;
+    const double den = std::fabs(theta_h[c]) * std::sqrt(std::max(vbh[c], 0.0));
+    res_h[c] = den > 0 ? std::sqrt(std::max(r2h[c], 0.0)) / den : HUGE_VAL;
+  }
+  if (BV_out) *BV_out = BV;
+  return SLRF_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* slrf_status_string(slrf_status s) {
+  switch (s) {
+    case SLRF_OK: return "ok";
+    case SLRF_E_ARG: return "invalid argument";
+    case SLRF_E_NOMEM: return "out of memory";
+    case SLRF_E_HIP: return "HIP runtime error";
+    case SLRF_E_BREAKDOWN: return "breakdown in the projected problem";
+    case SLRF_E_NOCONV: return "iteration cap reached";
+    case SLRF_E_NUMERIC: return "NaN or Inf detected";
+    case SLRF_E_NOGPU: return "no usable GPU";
+  }
+  return "unknown status";
+}
+
+const char* slrf_last_error(slrf_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+void slrf_default_options(slrf_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = SLRF_PREC_FP64;
+  o->precond = SLRF_PC_JACOBI;
+  o->restart = 30;
+  o->maxit_lin = 10000;
+  o->it_max_lin = 0;
+  o->max_outer = 100;
+  o->warm_start = 0;
+  o->lock = 0;
+  o->timing = 0;
+  o->max_slots = 0;
+  o->tol_lin = 1e-10;
+  o->inner_rtol = 1e-5;
+  o->tol_eig = 1e-8;
+  o->mem_budget = 0.0;
+}
+
+int32_t slrf_get_n(slrf_handle h) { return h ? h->P.n : -1; }
+
+slrf_status slrf_setup(slrf_handle* out, const slrf_csr* A, const slrf_csr* B, double gamma,
+                       int32_t npoles, const slrf_zd* poles, const slrf_zd* weights,
+                       const slrf_options* opt, void* stream) {
+  if (!out) return SLRF_E_ARG;
+  *out = nullptr;
+  auto* h = new (std::nothrow) slrf_ctx();
+  if (!h) return SLRF_E_NOMEM;
+  auto bad = [&](slrf_status st, const std::string& m) {
+    h->err = m;
+    *out = h;  // hand the handle back so slrf_last_error works; caller destroys
+    return st;
+  };
+  if (!A || !B || !poles || !weights) return bad(SLRF_E_ARG, "null argument");
+  if (A->n <= 0 || A->nnz <= 0 || A->n != B->n || A->nnz != B->nnz)
+    return bad(SLRF_E_ARG, "A and B must be non-empty with equal n and nnz");
+  if (!A->rowptr || !A->col || !A->val || !B->rowptr || !B->col || !B->val)
+    return bad(SLRF_E_ARG, "null CSR array");
+  if (!(gamma > 0.0) || !std::isfinite(gamma)) return bad(SLRF_E_ARG, "gamma must be > 0");
+  if (npoles < 1 || npoles > 64) return bad(SLRF_E_ARG, "npoles must be in [1, 64]");
+  if (opt) h->opt = *opt; else slrf_default_options(&h->opt);
+  {
+    slrf_status vs = validate_options(h, h->opt);
+    if (vs != SLRF_OK) {
+      *out = h;
+      return vs;
+    }
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
+    return bad(SLRF_E_NOGPU, "no HIP device visible");
+  if (hipGetDevice(&h->device) != hipSuccess) return bad(SLRF_E_NOGPU, "hipGetDevice failed");
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, h->device) != hipSuccess)
+    return bad(SLRF_E_NOGPU, "hipGetDeviceProperties failed");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return bad(SLRF_E_NOGPU, std::string("library built for gfx950, device is ") + prop.gcnArchName);
+  h->stream = static_cast<hipStream_t>(stream);
+  for (int j = 0; j < npoles; ++j) {
+    if (!(poles[j].im > 0.0)) return bad(SLRF_E_ARG, "poles must lie in the upper half plane");
+    if (!std::isfinite(poles[j].re) || !std::isfinite(weights[j].re) ||
+        !std::isfinite(weights[j].im))
+      return bad(SLRF_E_ARG, "non-finite pole or weight");
+    h->poles.push_back(make_double2(poles[j].re, poles[j].im));
+    h->weights.push_back(make_double2(weights[j].re, weights[j].im));
+  }
+  h->N = npoles;
+  h->gamma = gamma;
+  const int n = A->n, nnz = A->nnz;
+  // ---- host validation of the CSR structure (one copy)
+  std::vector<int> rp(n + 1), cl(nnz), rp2(n + 1), cl2(nnz);
+  hipStream_t s = h->stream;
+  if (hipMemcpyAsync(rp.data(), A->rowptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost, s) ||
+      hipMemcpyAsync(cl.data(), A->col, sizeof(int) * nnz, hipMemcpyDeviceToHost, s) ||
+      hipMemcpyAsync(rp2.data(), B->rowptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost, s) ||
+      hipMemcpyAsync(cl2.data(), B->col, sizeof(int) * nnz, hipMemcpyDeviceToHost, s) ||
+      hipStreamSynchronize(s))
+    return bad(SLRF_E_ARG, "CSR arrays are not readable device memory");
+  if (rp[0] != 0 || rp[n] != nnz) return bad(SLRF_E_ARG, "rowptr[0] must be 0 and rowptr[n] nnz");
+  for (int i = 0; i < n; ++i) {
+    if (rp[i + 1] < rp[i]) return bad(SLRF_E_ARG, "rowptr must be nondecreasing");
+    bool diag = false;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+      if (cl[e] < 0 || cl[e] >= n) return bad(SLRF_E_ARG, "column index out of range");
+      if (e > rp[i] && cl[e] <= cl[e - 1])
+        return bad(SLRF_E_ARG, "column indices must be strictly increasing within a row");
+      diag |= cl[e] == i;
+    }
+    if (!diag) return bad(SLRF_E_ARG, "every row must store its diagonal entry");
+  }
+  if (rp != rp2 || cl != cl2) return bad(SLRF_E_ARG, "A and B must share one CSR pattern");
+  h->P.n = n;
+  h->P.nnz = nnz;
+  h->P.rowptr = A->rowptr;
+  h->P.col = A->col;
+  h->P.a = A->val;
+  h->P.b = B->val;
+  // ---- library-owned copies: FP32 values, diagonals, weights
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) return bad(SLRF_E_HIP, "hipMemGetInfo failed");
+  if (hipMalloc(&h->a32, sizeof(float) * nnz) || hipMalloc(&h->b32, sizeof(float) * nnz) ||
+      hipMalloc(&h->da, sizeof(double) * n) || hipMalloc(&h->db, sizeof(double) * n) ||
+      hipMalloc(&h->d_w, sizeof(double2) * npoles))
+    return bad(SLRF_E_NOMEM, "allocation of setup arrays failed");
+  h->P.a32 = h->a32;
+  h->P.b32 = h->b32;
+  h->P.da = h->da;
+  h->P.db = h->db;
+  int* d_missing = nullptr;
+  int missing = 0;
+  if (hipMalloc(&d_missing, sizeof(int)) || hipMemsetAsync(d_missing, 0, sizeof(int), s) ||
+      launch_cast_f32(A->val, h->a32, nnz, s) || launch_cast_f32(B->val, h->b32, nnz, s) ||
+      launch_diag(h->P, h->da, h->db, d_missing, s) ||
+      hipMemcpyAsync(h->d_w, h->weights.data(), sizeof(double2) * npoles, hipMemcpyHostToDevice,
+                     s) ||
+      hipMemcpyAsync(&missing, d_missing, sizeof(int), hipMemcpyDeviceToHost, s) ||
+      hipStreamSynchronize(s)) {
+    if (d_missing) (void)hipFree(d_missing);
+    return bad(SLRF_E_HIP, "setup kernels failed");
+  }
+  (void)hipFree(d_missing);
+  if (missing) return bad(SLRF_E_ARG, "missing diagonal entry");
+  h->budget = h->opt.mem_budget > 0 ? (size_t)h->opt.mem_budget : (size_t)(0.6 * (double)fr);
+  *out = h;
+  return SLRF_OK;
+}
+
+void slrf_destroy(slrf_handle h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  else (void)hipDeviceSynchronize();
+  delete h;
+}
+
+slrf_status slrf_set_options(slrf_handle h, const slrf_options* opt) {
+  if (!h || !opt) return SLRF_E_ARG;
+  slrf_status s = validate_options(h, *opt);
+  if (s != SLRF_OK) return s;
+  h->opt = *opt;
+  if (opt->mem_budget > 0) h->budget = (size_t)opt->mem_budget;
+  return SLRF_OK;
+}
+
+slrf_status slrf_filter(slrf_handle h, int32_t ncols, const double* X, const double* theta_warm,
+                        double* U, slrf_filter_stats* st) {
+  if (!h) return SLRF_E_ARG;
+  if (ncols < 1 || !X || !U) return fail(h, SLRF_E_ARG, "ncols >= 1 and non-null X, U required");
+  if (X == U) return fail(h, SLRF_E_ARG, "U may not alias X");
+  if (st) {
+    int32_t* keep = st->sys_iters;
+    std::memset(st, 0, sizeof(*st));
+    st->sys_iters = keep;
+  }
+  h->cur_stats = st;
+  slrf_status r = h->opt.precision == SLRF_PREC_MIXED
+                      ? run_filter<float>(h, ncols, X, theta_warm, U, st)
+                      : run_filter<double>(h, ncols, X, theta_warm, U, st);
+  h->cur_stats = nullptr;
+  h->timer.reset();
+  return r;
+}
+
+slrf_status slrf_rayleigh_ritz(slrf_handle h, int32_t ncols, double* U, int32_t nlocked,
+                               const double* Xlocked, double* theta, double* resid) {
+  if (!h) return SLRF_E_ARG;
+  if (ncols < 1 || !U || !theta || !resid || nlocked < 0 || (nlocked > 0 && !Xlocked))
+    return fail(h, SLRF_E_ARG, "bad Rayleigh-Ritz arguments");
+  const int n = h->P.n;
+  hipStream_t s = h->stream;
+  double *Ur, *Xl = nullptr, *BXl = nullptr;
+  HIPCHK(ensure_t(h, B_TMP, (size_t)n * ncols, &Ur));
+  HIPCHK(launch_transpose(U, ncols, n, n, Ur, ncols, s));
+  if (nlocked > 0) {
+    HIPCHK(ensure_t(h, B_XL, (size_t)n * nlocked, &Xl));
+    HIPCHK(ensure_t(h, B_BXL, (size_t)n * nlocked, &BXl));
+    HIPCHK(launch_transpose(Xlocked, nlocked, n, n, Xl, nlocked, s));
+    HIPCHK(launch_spmm_real(h->P, Xl, nlocked, nlocked, nullptr, BXl, nullptr, nullptr, s));
+  }
+  std::vector<double> th, res;
+  slrf_status r = rr_rowmajor(h, ncols, Ur, nlocked, Xl, BXl, th, res, nullptr);
+  if (r != SLRF_OK) return r;
+  HIPCHK(launch_transpose(Ur, n, ncols, ncols, U, n, s));
+  HIPCHK(hipMemcpyAsync(theta, th.data(), sizeof(double) * ncols, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(resid, res.data(), sizeof(double) * ncols, hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return SLRF_OK;
+}
+
+slrf_status slrf_solve(slrf_handle h, int32_t nev, int32_t L, const double* V1, double* theta_out,
+                       double* X_out, int32_t* nconv_out, slrf_solve_stats* stats) {
+  if (!h) return SLRF_E_ARG;
+  if (nev < 1 || L < nev || !V1 || !theta_out || !X_out)
+    return fail(h, SLRF_E_ARG, "need 1 <= nev <= L and non-null buffers");
+  const auto t0 = std::chrono::steady_clock::now();
+  const int n = h->P.n;
+  hipStream_t s = h->stream;
+  const bool alg2 = h->opt.lock != 0;
+  const bool warm = h->opt.warm_start != 0;
+  if (nconv_out) *nconv_out = 0;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  double *V, *U, *Xlk, *th_d;
+  HIPCHK(ensure_t(h, B_SSP, (size_t)n * (2 * L + nev) + 2 * L + 16, &V));
+  U = V + (size_t)n * L;
+  Xlk = U + (size_t)n * L;  // locked vectors, column-major n x nev
+  th_d = Xlk + (size_t)n * nev;
+  HIPCHK(hipMemcpyAsync(V, V1, sizeof(double) * n * L, hipMemcpyDeviceToDevice, s));
+  std::vector<double> Theta;  // locked values
+  std::vector<double> th_warm;
+  int nconv = 0;
+  slrf_status result = SLRF_E_NOCONV;
+  std::vector<double> lastTheta;
+  std::vector<int> lastIdx;
+  double fsec = 0, rsec = 0;
+  int k = 1;
+  for (; k <= h->opt.max_outer; ++k) {
+    const int nact = alg2 ? L - nconv : L;
+    if (nact <= 0) break;
+    slrf_filter_stats fst;
+    std::memset(&fst, 0, sizeof(fst));
+    if (warm && !th_warm.empty())
+      HIPCHK(hipMemcpyAsync(th_d, th_warm.data(), sizeof(double) * nact, hipMemcpyHostToDevice,
+                            s));
+    const auto tf = std::chrono::steady_clock::now();
+    slrf_status fs = slrf_filter(h, nact, V, (warm && !th_warm.empty()) ? th_d : nullptr, U, &fst);
+    if (fs != SLRF_OK && fs != SLRF_E_NOCONV) return fs;
+    fsec += std::chrono::duration<double>(std::chrono::steady_clock::now() - tf).count();
+    if (stats) stats->inner_iters += fst.total_iters;
+    // Rayleigh-Ritz (with B-orthogonalisation against the locked set)
+    const auto tr = std::chrono::steady_clock::now();
+    double *Ur, *Xl = nullptr, *BXl = nullptr;
+    HIPCHK(ensure_t(h, B_TMP, (size_t)n * nact, &Ur));
+    HIPCHK(launch_transpose(U, nact, n, n, Ur, nact, s));
+    const int nl = alg2 ? nconv : 0;
+    if (nl > 0) {
+      HIPCHK(ensure_t(h, B_XL, (size_t)n * nl, &Xl));
+      HIPCHK(ensure_t(h, B_BXL, (size_t)n * nl, &BXl));
+      HIPCHK(launch_transpose(Xlk, nl, n, n, Xl, nl, s));
+      HIPCHK(launch_spmm_real(h->P, Xl, nl, nl, nullptr, BXl, nullptr, nullptr, s));
+    }
+    std::vector<double> th, res;
+    slrf_status r = rr_rowmajor(h, nact, Ur, nl, Xl, BXl, th, res, nullptr);
+    if (r != SLRF_OK) return r;
+    HIPCHK(launch_transpose(Ur, n, nact, nact, U, n, s));  // Ritz vectors, column-major
+    rsec += std::chrono::duration<double>(std::chrono::steady_clock::now() - tr).count();
+    std::vector<int> conv, rest;
+    for (int c = 0; c < nact; ++c) {
+      const bool ok = th[c] > 0.0 && th[c] <= h->gamma && res[c] < h->opt.tol_eig;
+      (ok ? conv : rest).push_back(c);
+    }
+    if (!alg2) {
+      lastTheta = th;
+      lastIdx = conv;
+      if ((int)conv.size() >= nev) {
+        for (int i = 0; i < nev; ++i)
+          HIPCHK(hipMemcpyAsync(X_out + (size_t)i * n, U + (size_t)conv[i] * n,
+                                sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        std::vector<double> tout(nev);
+        for (int i = 0; i < nev; ++i) tout[i] = th[conv[i]];
+        HIPCHK(hipMemcpyAsync(theta_out, tout.data(), sizeof(double) * nev,
+                              hipMemcpyHostToDevice, s));
+        nconv = nev;
+        result = SLRF_OK;
+        break;
+      }
+      std::swap(V, U);  // V_{k+1} = all Ritz vectors
+      th_warm = th;
+    } else {
+      for (int c : conv) {
+        if (nconv >= nev) break;
+        HIPCHK(hipMemcpyAsync(Xlk + (size_t)nconv * n, U + (size_t)c * n, sizeof(double) * n,
+                              hipMemcpyDeviceToDevice, s));
+        Theta.push_back(th[c]);
+        ++nconv;
+      }
+      if (nconv >= nev) {
+        result = SLRF_OK;
+        break;
+      }
+      const int nnext = L - nconv;
+      th_warm.clear();
+      for (int i = 0; i < nnext && i < (int)rest.size(); ++i) {
+        HIPCHK(hipMemcpyAsync(V + (size_t)i * n, U + (size_t)rest[i] * n, sizeof(double) * n,
+                              hipMemcpyDeviceToDevice, s));
+        th_warm.push_back(th[rest[i]]);
+      }
+      // fewer unconverged Ritz vectors than needed cannot happen (nact - |conv| = L - nconv)
+    }
+  }
+  if (alg2) {
+    // sort the locked pairs ascending into the outputs
+    std::vector<int> ord(Theta.size());
+    for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return Theta[a] < Theta[b]; });
+    const int nout = std::min<int>(nev, (int)ord.size());
+    std::vector<double> tout(nout);
+    for (int i = 0; i < nout; ++i) {
+      tout[i] = Theta[ord[i]];
+      HIPCHK(hipMemcpyAsync(X_out + (size_t)i * n, Xlk + (size_t)ord[i] * n, sizeof(double) * n,
+                            hipMemcpyDeviceToDevice, s));
+    }
+    if (nout > 0)
+      HIPCHK(hipMemcpyAsync(theta_out, tout.data(), sizeof(double) * nout, hipMemcpyHostToDevice,
+                            s));
+  } else if (result != SLRF_OK) {
+    const int nout = std::min<int>(nev, (int)lastIdx.size());
+    std::vector<double> tout(nout);
+    for (int i = 0; i < nout; ++i) {
+      tout[i] = lastTheta[lastIdx[i]];
+      HIPCHK(hipMemcpyAsync(X_out + (size_t)i * n, V + (size_t)lastIdx[i] * n,
+                            sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    }
+    if (nout > 0)
+      HIPCHK(hipMemcpyAsync(theta_out, tout.data(), sizeof(double) * nout, hipMemcpyHostToDevice,
+                            s));
+    nconv = nout;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  if (nconv_out) *nconv_out = nconv;
+  if (stats) {
+    stats->outer_iters = std::min(k, h->opt.max_outer);
+    stats->nconv = nconv;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    stats->filter_seconds = fsec;
+    stats->rr_seconds = rsec;
+  }
+  if (result != SLRF_OK) return fail(h, SLRF_E_NOCONV, "max_outer reached before nev pairs");
+  return SLRF_OK;
+}
+
+slrf_status slrf_shifted_spmm(slrf_handle h, int32_t nsys, const int32_t* pole, int32_t precision,
+                              const void* Z, void* Q, double* ms_out) {
+  if (!h) return SLRF_E_ARG;
+  if (nsys < 1 || !pole || !Z || !Q) return fail(h, SLRF_E_ARG, "bad shifted_spmm arguments");
+  if (precision != SLRF_PREC_FP64 && precision != SLRF_PREC_MIXED)
+    return fail(h, SLRF_E_ARG, "bad precision");
+  const int C = (nsys + kPanel - 1) / kPanel * kPanel;
+  std::vector<double2> sg(C, make_double2(0.0, 0.0));
+  for (int i = 0; i < nsys; ++i) {
+    if (pole[i] < 0 || pole[i] >= h->N) return fail(h, SLRF_E_ARG, "pole index out of range");
+    sg[i] = h->poles[pole[i]];
+  }
+  double* dtab;
+  HIPCHK(ensure_t(h, B_TAB_D, (size_t)3 * C, &dtab));
+  hipStream_t s = h->stream;
+  HIPCHK(hipMemcpyAsync(dtab, sg.data(), sizeof(double2) * C, hipMemcpyHostToDevice, s));
+  const PanelGrid g = make_grid(h->P.n, C, C, 2);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ms_out) {
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, s));
+  }
+  const double2* sgd = reinterpret_cast<const double2*>(dtab);
+  if (precision == SLRF_PREC_FP64)
+    HIPCHK(launch_spmm_panel<double>(h->P, g, sgd, Z, Q, s));
+  else
+    HIPCHK(launch_spmm_panel<float>(h->P, g, sgd, Z, Q, s));
+  if (ms_out) {
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    *ms_out = ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  } else {
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  return SLRF_OK;
+}
+
+int32_t slrf_host_projected_eig(int32_t n, const double* Ah, const double* Bh, double* theta,
+                                double* S) {
+  if (n < 0 || (n > 0 && (!Ah || !Bh || !theta || !S))) return -1;
+  int fb = 0;
+  return sym_gen_eig(n, Ah, Bh, theta, S, &fb);
+}
+
+}  // extern "C"

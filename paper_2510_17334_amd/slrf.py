@@ -1,0 +1,322 @@
+"""ctypes binding of the C ABI declared in include/slrf.h.
+
+Argument marshalling only: tensors are checked for device, dtype and layout and
+their data pointers handed to the library; every step of the computation runs
+in the HIP kernels of ``libslrf.so``.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "libslrf.so")
+
+SLRF_PREC_FP64 = 0
+SLRF_PREC_MIXED = 1
+SLRF_PC_NONE = 0
+SLRF_PC_JACOBI = 1
+KERNEL_CLASSES = ("apply", "orth", "step", "resid", "reduce", "other")
+_STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP runtime error",
+           4: "breakdown", 5: "iteration cap reached", 6: "NaN/Inf detected", 7: "no usable GPU"}
+
+
+class SlrfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"slrf status {status} ({_STATUS.get(status, '?')}): {msg}")
+        self.status = status
+
+
+class Csr(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("rowptr", C.c_void_p),
+                ("col", C.c_void_p), ("val", C.c_void_p)]
+
+
+class Zd(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("precond", C.c_int32), ("restart", C.c_int32),
+                ("maxit_lin", C.c_int32), ("it_max_lin", C.c_int32), ("max_outer", C.c_int32),
+                ("warm_start", C.c_int32), ("lock", C.c_int32), ("timing", C.c_int32),
+                ("max_slots", C.c_int32), ("tol_lin", C.c_double), ("inner_rtol", C.c_double),
+                ("tol_eig", C.c_double), ("mem_budget", C.c_double)]
+
+
+class FilterStats(C.Structure):
+    _fields_ = [("nsystems", C.c_int64), ("total_iters", C.c_int64), ("min_iters", C.c_int32),
+                ("max_iters", C.c_int32), ("cycles", C.c_int32), ("converged", C.c_int32),
+                ("capped", C.c_int32), ("max_pole_iters_ratio_x1000", C.c_int32),
+                ("max_rel_resid", C.c_double), ("seconds", C.c_double),
+                ("launches", C.c_int64 * 6), ("bytes", C.c_double * 6), ("ms", C.c_double * 6),
+                ("sys_iters", C.POINTER(C.c_int32))]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("outer_iters", C.c_int32), ("nconv", C.c_int32), ("inner_iters", C.c_int64),
+                ("seconds", C.c_double), ("filter_seconds", C.c_double),
+                ("rr_seconds", C.c_double)]
+
+
+_lib = None
+
+# name -> (restype, argtypes): every entry point declared in include/slrf.h
+SIGNATURES = {
+    "slrf_status_string": (C.c_char_p, [C.c_int]),
+    "slrf_last_error": (C.c_char_p, [C.c_void_p]),
+    "slrf_default_options": (None, [C.POINTER(Options)]),
+    "slrf_setup": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(Csr), C.POINTER(Csr), C.c_double,
+                             C.c_int32, C.POINTER(Zd), C.POINTER(Zd), C.POINTER(Options),
+                             C.c_void_p]),
+    "slrf_destroy": (None, [C.c_void_p]),
+    "slrf_set_options": (C.c_int, [C.c_void_p, C.POINTER(Options)]),
+    "slrf_filter": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                              C.POINTER(FilterStats)]),
+    "slrf_rayleigh_ritz": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
+                                     C.c_void_p, C.c_void_p]),
+    "slrf_solve": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                             C.c_void_p, C.POINTER(C.c_int32), C.POINTER(SolveStats)]),
+    "slrf_shifted_spmm": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_int32,
+                                    C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "slrf_get_n": (C.c_int32, [C.c_void_p]),
+    "slrf_host_projected_eig": (C.c_int32, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                            C.c_void_p]),
+}
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load libslrf.so (raises if it has not been built: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"HIP library {_LIB_PATH} is missing; build it with "
+                               "`python -m paper_2510_17334_amd.build`")
+        L = C.CDLL(_LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    lib().slrf_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def host_projected_eig(Ah: np.ndarray, Bh: np.ndarray):
+    """The library's host solve of Ah s = theta Bh s (no GPU)."""
+    Ah = np.ascontiguousarray(Ah, dtype=np.float64)
+    Bh = np.ascontiguousarray(Bh, dtype=np.float64)
+    n = Ah.shape[0]
+    th = np.zeros(n)
+    S = np.zeros((n, n))
+    k = lib().slrf_host_projected_eig(n, Ah.ctypes.data, Bh.ctypes.data, th.ctypes.data,
+                                      S.ctypes.data)
+    return k, th, S
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _colmajor(x, n: int):
+    """(n, k) float64 CUDA tensor in column-major storage (returns a view or copy)."""
+    torch = _torch()
+    if x.dim() != 2 or x.shape[0] != n:
+        raise ValueError(f"expected an (n={n}, k) block, got {tuple(x.shape)}")
+    if x.dtype != torch.float64 or not x.is_cuda:
+        raise ValueError("blocks must be float64 CUDA tensors")
+    if x.stride(0) == 1 and (x.shape[1] <= 1 or x.stride(1) == n):
+        return x
+    return x.t().contiguous().t()
+
+
+def _empty_colmajor(n: int, k: int, device):
+    torch = _torch()
+    return torch.empty((k, n), dtype=torch.float64, device=device).t()
+
+
+class Handle:
+    """A pencil bound to the GPU library (slrf_setup ... slrf_destroy).
+
+    ``indptr``/``indices``/``a``/``b`` are host arrays (numpy) of a shared-pattern
+    CSR pencil; they are uploaded once and kept alive by the handle.
+    """
+
+    def __init__(self, indptr, indices, a, b, gamma: float, poles, weights,
+                 options: Optional[Options] = None, device: str = "cuda", stream=None):
+        torch = _torch()
+        self._L = lib()
+        self.device = torch.device(device)
+        self.n = int(len(indptr) - 1)
+        self.indptr = torch.as_tensor(np.asarray(indptr, dtype=np.int32), device=self.device)
+        self.indices = torch.as_tensor(np.asarray(indices, dtype=np.int32), device=self.device)
+        self.a = torch.as_tensor(np.asarray(a, dtype=np.float64), device=self.device)
+        self.b = torch.as_tensor(np.asarray(b, dtype=np.float64), device=self.device)
+        self.gamma = float(gamma)
+        poles = np.asarray(poles, dtype=np.complex128)
+        weights = np.asarray(weights, dtype=np.complex128)
+        self.npoles = int(poles.shape[0])
+        self.poles = poles
+        self.weights = weights
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        A = Csr(self.n, int(self.indices.numel()), self.indptr.data_ptr(), self.indices.data_ptr(),
+                self.a.data_ptr())
+        B = Csr(self.n, int(self.indices.numel()), self.indptr.data_ptr(), self.indices.data_ptr(),
+                self.b.data_ptr())
+        zp = (Zd * self.npoles)(*[Zd(p.real, p.imag) for p in poles])
+        zw = (Zd * self.npoles)(*[Zd(w.real, w.imag) for w in weights])
+        self.options = options if options is not None else default_options()
+        h = C.c_void_p()
+        torch.cuda.synchronize(self.device)
+        st = self._L.slrf_setup(C.byref(h), C.byref(A), C.byref(B), self.gamma, self.npoles, zp,
+                                zw, C.byref(self.options), C.c_void_p(self.stream.cuda_stream))
+        self._h = h
+        if st != 0:
+            msg = self._L.slrf_last_error(h).decode() if h.value else "setup failed"
+            self.close()
+            raise SlrfError(st, msg)
+
+    @classmethod
+    def from_pencil(cls, p, gamma, poles, weights, options=None, **kw):
+        return cls(p.indptr, p.indices, p.a, p.b, gamma, poles, weights, options, **kw)
+
+    def _check(self, st: int, allow=()):
+        if st != 0 and st not in allow:
+            raise SlrfError(st, self._L.slrf_last_error(self._h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._L.slrf_destroy(self._h)
+        self._h = C.c_void_p()
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_options(self, options: Options):
+        self._check(self._L.slrf_set_options(self._h, C.byref(options)))
+        self.options = options
+
+    # --- slrf_filter ---------------------------------------------------------
+    def slrf_filter(self, X, theta_warm=None, want_sys_iters: bool = False, allow_noconv=False):
+        """U = sum_j 2 Re(w_j (A - sigma_j B)^{-1} B X).  Returns (U, stats dict)."""
+        torch = _torch()
+        X = _colmajor(X, self.n)
+        k = X.shape[1]
+        U = _empty_colmajor(self.n, k, X.device)
+        st = FilterStats()
+        its = None
+        if want_sys_iters:
+            its = np.zeros(k * self.npoles, dtype=np.int32)
+            st.sys_iters = its.ctypes.data_as(C.POINTER(C.c_int32))
+        th = None
+        if theta_warm is not None:
+            th = torch.as_tensor(theta_warm, dtype=torch.float64, device=X.device).contiguous()
+            if th.numel() != k:
+                raise ValueError("theta_warm needs one value per column")
+        r = self._L.slrf_filter(self._h, k, X.data_ptr(), th.data_ptr() if th is not None else None,
+                                U.data_ptr(), C.byref(st))
+        self._check(r, allow=(5,) if allow_noconv else ())
+        return U, self._stats_dict(st, its, r)
+
+    @staticmethod
+    def _stats_dict(st: FilterStats, its, status):
+        d = {f: getattr(st, f) for f, _ in FilterStats._fields_ if f not in
+             ("launches", "bytes", "ms", "sys_iters")}
+        d["launches"] = dict(zip(KERNEL_CLASSES, list(st.launches)))
+        d["bytes"] = dict(zip(KERNEL_CLASSES, list(st.bytes)))
+        d["ms"] = dict(zip(KERNEL_CLASSES, list(st.ms)))
+        d["sys_iters"] = its
+        d["status"] = status
+        return d
+
+    # --- slrf_rayleigh_ritz --------------------------------------------------
+    def slrf_rayleigh_ritz(self, U, Xlocked=None):
+        """Ritz values/vectors of span(U) (B-orthogonalised against Xlocked).
+
+        Returns (V, theta, resid); V is a new column-major block.
+        """
+        torch = _torch()
+        V = _colmajor(U, self.n).t().clone().t()
+        k = V.shape[1]
+        theta = torch.empty(k, dtype=torch.float64, device=V.device)
+        resid = torch.empty(k, dtype=torch.float64, device=V.device)
+        nl = 0
+        xp = None
+        if Xlocked is not None and Xlocked.shape[1] > 0:
+            Xl = _colmajor(Xlocked, self.n)
+            nl = Xl.shape[1]
+            xp = Xl.data_ptr()
+        self._check(self._L.slrf_rayleigh_ritz(self._h, k, V.data_ptr(), nl, xp, theta.data_ptr(),
+                                               resid.data_ptr()))
+        return V, theta, resid
+
+    # --- slrf_solve ----------------------------------------------------------
+    def slrf_solve(self, nev: int, V1, allow_noconv=False):
+        """Algorithm 1 or 2 (per options).  Returns (theta, X, nconv, stats dict)."""
+        torch = _torch()
+        V1 = _colmajor(V1, self.n)
+        L = V1.shape[1]
+        theta = torch.full((nev,), float("nan"), dtype=torch.float64, device=V1.device)
+        X = _empty_colmajor(self.n, nev, V1.device)
+        nconv = C.c_int32(0)
+        st = SolveStats()
+        r = self._L.slrf_solve(self._h, nev, L, V1.data_ptr(), theta.data_ptr(), X.data_ptr(),
+                               C.byref(nconv), C.byref(st))
+        self._check(r, allow=(5,) if allow_noconv else ())
+        stats = {f: getattr(st, f) for f, _ in SolveStats._fields_}
+        stats["status"] = r
+        return theta[:nconv.value], X[:, :nconv.value], nconv.value, stats
+
+    # --- slrf_shifted_spmm ---------------------------------------------------
+    def slrf_shifted_spmm(self, Z, pole_idx, precision: int = SLRF_PREC_FP64, timed=False):
+        """Q = (A - sigma_{pole[s]} B) Z on a panel-layout block (see include/slrf.h)."""
+        torch = _torch()
+        pole_idx = np.ascontiguousarray(pole_idx, dtype=np.int32)
+        nsys = pole_idx.shape[0]
+        npad = (nsys + 15) // 16 * 16
+        dt = torch.complex128 if precision == SLRF_PREC_FP64 else torch.complex64
+        if Z.dtype != dt or not Z.is_cuda or Z.numel() != npad * self.n or not Z.is_contiguous():
+            raise ValueError("Z must be a contiguous panel-layout complex CUDA tensor")
+        Q = torch.empty_like(Z)
+        ms = C.c_double(0.0)
+        self._check(self._L.slrf_shifted_spmm(self._h, nsys,
+                                              pole_idx.ctypes.data_as(C.POINTER(C.c_int32)),
+                                              precision, Z.data_ptr(), Q.data_ptr(),
+                                              C.byref(ms) if timed else None))
+        return (Q, ms.value) if timed else Q
+
+
+def to_panels(Y, n: int):
+    """(n, nsys) complex tensor -> contiguous panel layout [nsys/16, n, 16] (padded)."""
+    torch = _torch()
+    nsys = Y.shape[1]
+    npad = (nsys + 15) // 16 * 16
+    Z = torch.zeros((n, npad), dtype=Y.dtype, device=Y.device)
+    Z[:, :nsys] = Y
+    return Z.reshape(n, npad // 16, 16).permute(1, 0, 2).contiguous()
+
+
+def from_panels(Z, n: int, nsys: int):
+    return Z.permute(1, 0, 2).reshape(n, -1)[:, :nsys]

@@ -1,0 +1,76 @@
+"""The C-ABI library loads on the CPU and exports every declared entry point."""
+
+import re
+import os
+
+import numpy as np
+import scipy.linalg as sla
+
+import paper_2510_17334_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "slrf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(slrf_[a-z_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    L = P.lib()
+    names = declared_functions()
+    assert "slrf_filter" in names and "slrf_solve" in names and "slrf_setup" in names
+    for nm in names:
+        assert hasattr(L, nm), nm
+    # the binding wraps exactly the declared set
+    assert set(names) == set(P.slrf.SIGNATURES)
+
+
+def test_default_options_are_the_papers():
+    o = P.default_options()
+    assert o.tol_lin == 1e-10 and o.maxit_lin == 10000  # Section 3.2
+    assert o.tol_eig == 1e-8 and o.max_outer == 100
+    assert o.precision == P.SLRF_PREC_FP64 and o.restart == 30
+
+
+def test_status_strings():
+    L = P.lib()
+    assert L.slrf_status_string(0) == b"ok"
+    assert b"argument" in L.slrf_status_string(1)
+
+
+def _rand_pencil(n, seed, cond=1e3):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n))
+    A = A + A.T
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    B = Q @ np.diag(np.logspace(0, np.log10(cond), n)) @ Q.T
+    return A, 0.5 * (B + B.T)
+
+
+def test_host_projected_eig_matches_lapack():
+    for n, seed in [(1, 0), (2, 1), (17, 2), (160, 3), (300, 4)]:
+        A, B = _rand_pencil(n, seed)
+        k, th, S = P.host_projected_eig(A, B)
+        w = sla.eigh(A, B, eigvals_only=True)
+        assert k == n
+        scale = np.abs(w).max()
+        assert np.max(np.abs(th - w)) <= 1e-11 * scale
+        assert np.max(np.abs(S.T @ B @ S - np.eye(n))) <= 1e-10
+        assert np.max(np.abs(A @ S - (B @ S) * th)) <= 1e-10 * scale * np.abs(B).max()
+
+
+def test_host_projected_eig_truncates_singular_gram():
+    rng = np.random.default_rng(5)
+    U = rng.standard_normal((40, 6))
+    U = np.concatenate([U, U[:, :2]], axis=1)  # two duplicated columns
+    Kd = np.diag(np.linspace(1, 5, 40))
+    A = U.T @ Kd @ U
+    B = U.T @ U
+    k, th, S = P.host_projected_eig(A, B)
+    assert k == 6
+    w = sla.eigh(U[:, :6].T @ Kd @ U[:, :6], U[:, :6].T @ U[:, :6], eigvals_only=True)
+    assert np.allclose(th[:6], w, rtol=1e-8)
+    assert np.all(np.isinf(th[6:]))

@@ -56,7 +56,7 @@ typedef enum {
 } slrf_status;
 
 enum { SLRF_PREC_FP64 = 0, SLRF_PREC_MIXED = 1 };
-enum { SLRF_PC_NONE = 0, SLRF_PC_JACOBI = 1 };
+enum { SLRF_PC_NONE = 0, SLRF_PC_JACOBI = 1, SLRF_PC_AMG = 2 };
 
 /*
  * Sparse matrix in CSR form, device memory, owned by the caller.
@@ -84,7 +84,11 @@ typedef struct {
   int32_t precision;   /* SLRF_PREC_FP64: complex FP64 Krylov sweeps.
                           SLRF_PREC_MIXED: complex FP32 Krylov sweeps inside an
                           FP64 residual / iterative-refinement loop.           */
-  int32_t precond;     /* SLRF_PC_JACOBI (point Jacobi on A - sigma_j B) or NONE */
+  int32_t precond;     /* SLRF_PC_JACOBI: point Jacobi on A - sigma_j B;
+                          SLRF_PC_AMG: one V-cycle of a smoothed-aggregation
+                          hierarchy built once from A and shared by all poles
+                          (levels A_l - sigma_j B_l, damped-Jacobi smoothing,
+                          dense coarsest solve); SLRF_PC_NONE                  */
   int32_t restart;     /* GCR restart length m, 1..32                           */
   int32_t maxit_lin;   /* cap on inner iterations per system (10000)            */
   int32_t it_max_lin;  /* Algorithm 2 It_max-linear; 0 = off                    */
@@ -109,7 +113,8 @@ enum {
   SLRF_K_RESID = 3, /* FP64 residual f - (A - sigma B) y and solution update      */
   SLRF_K_REDUCE = 4,/* second-stage reductions and per-system scalars             */
   SLRF_K_OTHER = 5, /* admission, compaction, filter sum, RHS SpMM, transposes    */
-  SLRF_K_COUNT = 6
+  SLRF_K_PRECOND = 6,/* AMG V-cycle (all levels)                                 */
+  SLRF_K_COUNT = 7
 };
 
 typedef struct {
@@ -218,6 +223,26 @@ slrf_status slrf_solve(slrf_handle h, int32_t nev, int32_t L, const double* V1, 
  */
 slrf_status slrf_shifted_spmm(slrf_handle h, int32_t nsys, const int32_t* pole, int32_t precision,
                               const void* Z, void* Q, double* ms_out);
+
+/*
+ * slrf_eig_grad - eigenvalue sensitivities for per-element parameters
+ * (the differentiation form).  For B-normalised eigenpairs (lam_i, x_i) and a
+ * loss gradient glam_i = dL/dlam_i:
+ *     grad[e] = sum_{i<k} glam_i * x_{i,e}^T (dA_e - lam_i dB_e) x_{i,e},
+ * the derivative of the Rayleigh quotient, with dA_e = dA/dtheta_e and
+ * dB_e = dB/dtheta_e acting on element e's dofs.
+ * X: device n x k column-major; lam, glam: device double[k];
+ * elem_dofs: device int32[nelem * ndof_e] row-major, -1 = constrained dof
+ * (contributes zero); ndof_e in {4, 8, 24} (bilinear, trilinear, trilinear
+ * elasticity); dA: device double, element e's ndof_e x ndof_e row-major matrix
+ * at dA + e * dA_stride (stride 0: one matrix shared by all elements);
+ * dB likewise or NULL (parameter does not enter B); grad: device double[nelem].
+ * Synchronises the stream.
+ */
+slrf_status slrf_eig_grad(slrf_handle h, int32_t k, const double* X, const double* lam,
+                          const double* glam, int32_t nelem, int32_t ndof_e,
+                          const int32_t* elem_dofs, const double* dA, int32_t dA_stride,
+                          const double* dB, int32_t dB_stride, double* grad);
 
 /* Problem size of a handle (-1 for NULL). */
 int32_t slrf_get_n(slrf_handle h);

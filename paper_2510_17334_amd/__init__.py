@@ -11,8 +11,10 @@ from .slrf import (  # noqa: F401
     SLRF_PREC_MIXED,
     SLRF_PC_NONE,
     SLRF_PC_JACOBI,
+    SLRF_PC_AMG,
     SlrfError,
     Handle,
+    EigFn,
     default_options,
     lib,
     library_path,

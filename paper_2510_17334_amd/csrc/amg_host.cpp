@@ -1,0 +1,326 @@
+// Host setup of the shared-hierarchy smoothed-aggregation AMG preconditioner.
+//
+// The paper preconditions GCR with PETSc's GAMG and builds it once, reusing it
+// for every pole (Section 3.2).  Here one real hierarchy is built from the
+// stiffness matrix: P_l (smoothed aggregation), A_{l+1} = P_l^T A_l P_l and
+// B_{l+1} = P_l^T B_l P_l on one shared pattern, so that for any pole
+// P^T (A - sigma B) P = A_c - sigma B_c and the level operators of every pole
+// come from the same arrays.  The coarsest level is inverted densely per pole.
+#include "amg_host.h"
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <numeric>
+#include <random>
+
+namespace slrf {
+
+namespace {
+
+// Gustavson product C = X * Y (pattern only + values for one or two value
+// arrays of X sharing its pattern).  Rows of C are sorted.
+struct SpRow {
+  std::vector<int> marker, cols;
+  std::vector<double> acc1, acc2;
+  explicit SpRow(int ncols) : marker(ncols, -1), acc1(ncols, 0.0), acc2(ncols, 0.0) {}
+};
+
+// Y is given by (rp, ci, v).  X has two value arrays xa, xb (xb may be null).
+void spgemm2(int nrows, int ncols, const std::vector<int>& xrp, const std::vector<int>& xci,
+             const std::vector<double>& xa, const std::vector<double>* xb,
+             const std::vector<int>& yrp, const std::vector<int>& yci,
+             const std::vector<double>& yv, std::vector<int>& crp, std::vector<int>& cci,
+             std::vector<double>& ca, std::vector<double>* cb) {
+  SpRow w(ncols);
+  crp.assign(nrows + 1, 0);
+  cci.clear();
+  ca.clear();
+  if (cb) cb->clear();
+  for (int i = 0; i < nrows; ++i) {
+    w.cols.clear();
+    for (int e = xrp[i]; e < xrp[i + 1]; ++e) {
+      const int k = xci[e];
+      const double va = xa[e], vb = xb ? (*xb)[e] : 0.0;
+      for (int f = yrp[k]; f < yrp[k + 1]; ++f) {
+        const int j = yci[f];
+        if (w.marker[j] != i) {
+          w.marker[j] = i;
+          w.cols.push_back(j);
+          w.acc1[j] = 0.0;
+          w.acc2[j] = 0.0;
+        }
+        w.acc1[j] += va * yv[f];
+        w.acc2[j] += vb * yv[f];
+      }
+    }
+    std::sort(w.cols.begin(), w.cols.end());
+    for (int j : w.cols) {
+      cci.push_back(j);
+      ca.push_back(w.acc1[j]);
+      if (cb) cb->push_back(w.acc2[j]);
+    }
+    crp[i + 1] = (int)cci.size();
+  }
+}
+
+void transpose(int nrows, int ncols, const std::vector<int>& rp, const std::vector<int>& ci,
+               const std::vector<double>& v, std::vector<int>& trp, std::vector<int>& tci,
+               std::vector<double>& tv) {
+  trp.assign(ncols + 1, 0);
+  for (int e = 0; e < rp[nrows]; ++e) trp[ci[e] + 1]++;
+  for (int j = 0; j < ncols; ++j) trp[j + 1] += trp[j];
+  tci.assign(rp[nrows], 0);
+  tv.assign(rp[nrows], 0.0);
+  std::vector<int> pos(trp.begin(), trp.end() - 1);
+  for (int i = 0; i < nrows; ++i)
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+      const int p = pos[ci[e]]++;
+      tci[p] = i;
+      tv[p] = v[e];
+    }
+}
+
+// Greedy aggregation on the strength graph (three passes: seed aggregates of
+// fully unaggregated neighbourhoods, attach leftovers to a neighbouring
+// aggregate, group what remains).
+int aggregate(const HostLevel& L, double theta, std::vector<int>& agg) {
+  const int n = L.n;
+  std::vector<double> d(n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int e = L.rp[i]; e < L.rp[i + 1]; ++e)
+      if (L.ci[e] == i) d[i] = L.a[e];
+  auto strong = [&](int i, int e) {
+    const int j = L.ci[e];
+    if (j == i) return false;
+    const double v = std::fabs(L.a[e]);
+    return v > theta * std::sqrt(std::fabs(d[i] * d[j])) && v > 1e-14 * std::fabs(d[i]);
+  };
+  agg.assign(n, -1);
+  int na = 0;
+  for (int i = 0; i < n; ++i) {
+    if (agg[i] >= 0) continue;
+    bool free = true;
+    for (int e = L.rp[i]; e < L.rp[i + 1] && free; ++e)
+      if (strong(i, e) && agg[L.ci[e]] >= 0) free = false;
+    if (!free) continue;
+    agg[i] = na;
+    for (int e = L.rp[i]; e < L.rp[i + 1]; ++e)
+      if (strong(i, e)) agg[L.ci[e]] = na;
+    ++na;
+  }
+  std::vector<int> pass2(n, -1);
+  for (int i = 0; i < n; ++i) {
+    if (agg[i] >= 0) continue;
+    for (int e = L.rp[i]; e < L.rp[i + 1]; ++e)
+      if (strong(i, e) && agg[L.ci[e]] >= 0) {
+        pass2[i] = agg[L.ci[e]];
+        break;
+      }
+  }
+  for (int i = 0; i < n; ++i)
+    if (agg[i] < 0 && pass2[i] >= 0) agg[i] = pass2[i];
+  for (int i = 0; i < n; ++i) {
+    if (agg[i] >= 0) continue;
+    agg[i] = na;
+    for (int e = L.rp[i]; e < L.rp[i + 1]; ++e)
+      if (strong(i, e) && agg[L.ci[e]] < 0) agg[L.ci[e]] = na;
+    ++na;
+  }
+  return na;
+}
+
+// spectral radius of D^{-1} A by power iteration
+double rho_dinv_a(const HostLevel& L) {
+  const int n = L.n;
+  std::vector<double> d(n, 1.0), x(n), y(n);
+  for (int i = 0; i < n; ++i)
+    for (int e = L.rp[i]; e < L.rp[i + 1]; ++e)
+      if (L.ci[e] == i) d[i] = L.a[e];
+  std::mt19937_64 rng(12345);
+  std::normal_distribution<double> nd(0.0, 1.0);
+  for (auto& v : x) v = nd(rng);
+  double rho = 1.0;
+  for (int it = 0; it < 20; ++it) {
+    double nrm = 0.0;
+    for (int i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (int e = L.rp[i]; e < L.rp[i + 1]; ++e) s += L.a[e] * x[L.ci[e]];
+      y[i] = s / d[i];
+      nrm += y[i] * y[i];
+    }
+    rho = std::sqrt(nrm);
+    if (!(rho > 0.0)) return 1.0;
+    for (int i = 0; i < n; ++i) x[i] = y[i] / rho;
+  }
+  return rho;
+}
+
+// Dense inverse of a complex matrix by Gauss-Jordan with partial pivoting.
+bool invert_dense(int n, std::vector<std::complex<double>>& M) {
+  std::vector<std::complex<double>> I((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) I[(size_t)i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    double best = std::abs(M[(size_t)c * n + c]);
+    for (int r = c + 1; r < n; ++r)
+      if (std::abs(M[(size_t)r * n + c]) > best) {
+        best = std::abs(M[(size_t)r * n + c]);
+        piv = r;
+      }
+    if (!(best > 0.0)) return false;
+    if (piv != c)
+      for (int k = 0; k < n; ++k) {
+        std::swap(M[(size_t)c * n + k], M[(size_t)piv * n + k]);
+        std::swap(I[(size_t)c * n + k], I[(size_t)piv * n + k]);
+      }
+    const std::complex<double> inv = 1.0 / M[(size_t)c * n + c];
+    for (int k = 0; k < n; ++k) {
+      M[(size_t)c * n + k] *= inv;
+      I[(size_t)c * n + k] *= inv;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const std::complex<double> f = M[(size_t)r * n + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < n; ++k) {
+        M[(size_t)r * n + k] -= f * M[(size_t)c * n + k];
+        I[(size_t)r * n + k] -= f * I[(size_t)c * n + k];
+      }
+    }
+  }
+  M.swap(I);
+  return true;
+}
+
+}  // namespace
+
+bool amg_build(const HostLevel& fine, const std::vector<std::complex<double>>& poles,
+               const AmgParams& prm, AmgHierarchy& H, std::string& err) {
+  H.levels.clear();
+  H.P.clear();
+  H.R.clear();
+  H.levels.push_back(fine);
+  while (H.levels.back().n > prm.coarse_max && (int)H.levels.size() < prm.max_levels) {
+    const HostLevel& L = H.levels.back();
+    const int n = L.n;
+    std::vector<int> agg;
+    const int nc = aggregate(L, prm.theta, agg);
+    if (nc >= n || nc == 0) break;  // no coarsening possible
+    std::vector<int> cnt(nc, 0);
+    for (int i = 0; i < n; ++i) cnt[agg[i]]++;
+    // tentative prolongator T (n x nc), one entry per row
+    std::vector<int> trp(n + 1), tci(n);
+    std::vector<double> tv(n);
+    for (int i = 0; i < n; ++i) {
+      trp[i + 1] = i + 1;
+      tci[i] = agg[i];
+      tv[i] = 1.0 / std::sqrt((double)cnt[agg[i]]);
+    }
+    // P = T - (omega / rho) D^{-1} A T
+    const double rho = rho_dinv_a(L);
+    std::vector<int> arp, aci;
+    std::vector<double> at;
+    spgemm2(n, nc, L.rp, L.ci, L.a, nullptr, trp, tci, tv, arp, aci, at, nullptr);
+    std::vector<double> d(n, 1.0);
+    for (int i = 0; i < n; ++i)
+      for (int e = L.rp[i]; e < L.rp[i + 1]; ++e)
+        if (L.ci[e] == i) d[i] = L.a[e];
+    HostCsrP P;
+    P.n = n;
+    P.m = nc;
+    P.rp = arp;
+    P.ci = aci;
+    P.v.resize(at.size());
+    const double w = prm.omega_p / rho;
+    for (int i = 0; i < n; ++i)
+      for (int e = arp[i]; e < arp[i + 1]; ++e) {
+        double v = -w * at[e] / d[i];
+        if (aci[e] == agg[i]) v += tv[i];
+        P.v[e] = v;
+      }
+    HostCsrP R;
+    R.n = nc;
+    R.m = n;
+    transpose(n, nc, P.rp, P.ci, P.v, R.rp, R.ci, R.v);
+    // Galerkin: AP, BP (shared pattern), then R (AP), R (BP)
+    std::vector<int> aprp, apci;
+    std::vector<double> apa, apb;
+    spgemm2(n, nc, L.rp, L.ci, L.a, &L.b, P.rp, P.ci, P.v, aprp, apci, apa, &apb);
+    HostLevel C;
+    C.n = nc;
+    std::vector<double> cb;
+    // R * (AP) and R * (BP) on one pattern: multiply R (single value array)
+    // into the two value arrays of AP/BP by swapping roles: C = R * AP and
+    // C' = R * BP share the pattern because AP and BP do.
+    {
+      SpRow wr(nc);
+      C.rp.assign(nc + 1, 0);
+      for (int i = 0; i < nc; ++i) {
+        wr.cols.clear();
+        for (int e = R.rp[i]; e < R.rp[i + 1]; ++e) {
+          const int k = R.ci[e];
+          const double rv = R.v[e];
+          for (int f = aprp[k]; f < aprp[k + 1]; ++f) {
+            const int j = apci[f];
+            if (wr.marker[j] != i) {
+              wr.marker[j] = i;
+              wr.cols.push_back(j);
+              wr.acc1[j] = 0.0;
+              wr.acc2[j] = 0.0;
+            }
+            wr.acc1[j] += rv * apa[f];
+            wr.acc2[j] += rv * apb[f];
+          }
+        }
+        std::sort(wr.cols.begin(), wr.cols.end());
+        for (int j : wr.cols) {
+          C.ci.push_back(j);
+          // symmetrise the tiny rounding asymmetry later by averaging with the transpose
+          C.a.push_back(wr.acc1[j]);
+          C.b.push_back(wr.acc2[j]);
+        }
+        C.rp[i + 1] = (int)C.ci.size();
+      }
+    }
+    // enforce exact symmetry of the coarse operators: (C + C^T)/2 on the shared pattern
+    {
+      std::vector<int> trp2, tci2;
+      std::vector<double> ta, tb;
+      transpose(nc, nc, C.rp, C.ci, C.a, trp2, tci2, ta);
+      transpose(nc, nc, C.rp, C.ci, C.b, trp2, tci2, tb);
+      if (trp2 == C.rp && tci2 == C.ci) {
+        for (size_t e = 0; e < C.a.size(); ++e) {
+          C.a[e] = 0.5 * (C.a[e] + ta[e]);
+          C.b[e] = 0.5 * (C.b[e] + tb[e]);
+        }
+      }
+    }
+    H.P.push_back(std::move(P));
+    H.R.push_back(std::move(R));
+    H.levels.push_back(std::move(C));
+  }
+  // dense per-pole inverses of the coarsest operator
+  const HostLevel& Lc = H.levels.back();
+  const int nc = Lc.n;
+  if (nc > prm.dense_max) {
+    err = "AMG coarsest level too large for a dense solve (" + std::to_string(nc) + ")";
+    return false;
+  }
+  H.nc = nc;
+  H.coarse_inv.assign(poles.size() * (size_t)nc * nc, 0.0);
+  for (size_t j = 0; j < poles.size(); ++j) {
+    std::vector<std::complex<double>> M((size_t)nc * nc, 0.0);
+    for (int i = 0; i < nc; ++i)
+      for (int e = Lc.rp[i]; e < Lc.rp[i + 1]; ++e)
+        M[(size_t)i * nc + Lc.ci[e]] = Lc.a[e] - poles[j] * Lc.b[e];
+    if (!invert_dense(nc, M)) {
+      err = "singular coarsest AMG operator";
+      return false;
+    }
+    std::copy(M.begin(), M.end(), H.coarse_inv.begin() + j * (size_t)nc * nc);
+  }
+  return true;
+}
+
+}  // namespace slrf

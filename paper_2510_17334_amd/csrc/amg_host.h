@@ -1,0 +1,42 @@
+// Host data of the smoothed-aggregation AMG hierarchy shared by all poles.
+#pragma once
+
+#include <complex>
+#include <string>
+#include <vector>
+
+namespace slrf {
+
+// One level operator pair (A_l, B_l) on a shared, row-sorted CSR pattern.
+struct HostLevel {
+  int n = 0;
+  std::vector<int> rp, ci;
+  std::vector<double> a, b;
+};
+
+// A rectangular real CSR matrix (n x m): prolongator P_l or restriction P_l^T.
+struct HostCsrP {
+  int n = 0, m = 0;
+  std::vector<int> rp, ci;
+  std::vector<double> v;
+};
+
+struct AmgParams {
+  double theta = 0.0;     // strength threshold |a_ij| > theta sqrt(a_ii a_jj)
+  double omega_p = 4.0 / 3.0;  // prolongator smoothing weight (times 1/rho(D^-1 A))
+  int coarse_max = 400;   // stop coarsening at or below this size
+  int dense_max = 2048;   // largest coarsest level inverted densely
+  int max_levels = 10;
+};
+
+struct AmgHierarchy {
+  std::vector<HostLevel> levels;  // levels[0] = fine pencil
+  std::vector<HostCsrP> P, R;     // P[l]: n_l x n_{l+1}, R[l] = P[l]^T
+  int nc = 0;                     // coarsest size
+  std::vector<std::complex<double>> coarse_inv;  // [pole][nc][nc] row-major
+};
+
+bool amg_build(const HostLevel& fine, const std::vector<std::complex<double>>& poles,
+               const AmgParams& prm, AmgHierarchy& H, std::string& err);
+
+}  // namespace slrf

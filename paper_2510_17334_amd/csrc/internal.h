@@ -33,6 +33,17 @@ struct DevPencil {
   const float* b32 = nullptr;
   const double* da = nullptr; // diag(A), diag(B) (library-owned)
   const double* db = nullptr;
+  int max_nnz_sub64 = 0;      // max nonzeros in an aligned block of 64 / 32 rows
+  int max_nnz_sub32 = 0;      // (LDS staging plan of the shifted SpMM; 0 = unknown)
+};
+
+// A rectangular real CSR matrix on the device (AMG prolongation / restriction).
+struct DevTransfer {
+  int nrows = 0, ncols = 0, nnz = 0;
+  const int* rowptr = nullptr;
+  const int* col = nullptr;
+  const double* v = nullptr;
+  const float* v32 = nullptr;
 };
 
 // Launch geometry of the panel kernels: a grid of (row block, panel) tiles.
@@ -71,9 +82,10 @@ hipError_t launch_orth(const DevPencil& P, const PanelGrid& g, const SlotTables&
                        const void* Pbase, size_t vstride, int k, const double2* beta,
                        double2* part, hipStream_t s);
 template <typename T>
+// precond: 0 = none (z = r), 1 = point Jacobi, 2 = leave z to the AMG V-cycle
 hipError_t launch_step(const DevPencil& P, const PanelGrid& g, const SlotTables& st, void* R,
                        void* Z, const void* Qk, const double2* alpha_k, double2* part,
-                       bool precond, hipStream_t s);
+                       int precond, hipStream_t s);
 template <typename T>
 hipError_t launch_yupdate(int n, const PanelGrid& g, const SlotTables& st, double2* Y,
                           const void* Pbase, size_t vstride, int kk, const double2* alpha,
@@ -81,16 +93,31 @@ hipError_t launch_yupdate(int n, const PanelGrid& g, const SlotTables& st, doubl
 template <typename T>
 hipError_t launch_true_resid(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
                              const double2* Y, const double* F, int ldf, void* R, void* Z,
-                             double2* part, bool precond, hipStream_t s);
+                             double2* part, int precond, hipStream_t s);
 template <typename T>
 hipError_t launch_admit(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
                         const double2* Yold, const void* Rold, const void* Zold, double2* Ynew,
                         void* Rnew, void* Znew, const double* F, const double* E,
-                        const double* X, int ld, bool warm, double2* part, bool precond,
+                        const double* X, int ld, bool warm, double2* part, int precond,
                         hipStream_t s);
 template <typename T>
 hipError_t launch_spmm_panel(const DevPencil& P, const PanelGrid& g, const double2* sigma_slot,
                              const void* Z, void* Q, hipStream_t s);
+
+// ----- AMG V-cycle pieces (level vectors in panel layout, rows = level size) -----
+constexpr int kEpiResidOp = 1, kEpiJacobiOp = 2;  // level-operator epilogues
+template <typename T>
+hipError_t launch_lvl_op(const DevPencil& L, const PanelGrid& g, const SlotTables& st, int epi,
+                         double omega, const void* X, const void* Bin, void* Out, hipStream_t s);
+template <typename T>
+hipError_t launch_lvl_jacobi0(const DevPencil& L, const PanelGrid& g, const SlotTables& st,
+                              double omega, const void* Bin, void* Out, hipStream_t s);
+template <typename T>
+hipError_t launch_transfer(const DevTransfer& M, const PanelGrid& g, const SlotTables& st,
+                           const void* In, void* Out, bool add, hipStream_t s);
+template <typename T>
+hipError_t launch_coarse_solve(int nc, const PanelGrid& g, const SlotTables& st, int npoles,
+                               const void* Minv, const void* In, void* Out, hipStream_t s);
 
 hipError_t launch_retire(int n, const PanelGrid& g, const int* retire_sys, const double2* Y,
                          double2* Ystore, hipStream_t s);
@@ -139,6 +166,10 @@ hipError_t launch_colstats(int n, int nc, const double* X, const double* Y, int 
                            const double* theta, const double* W, double* part, int nchunk,
                            double* out, double* out2, hipStream_t s);
 int colstat_chunks(int n);
+// grad[e] = sum_i glam_i x_{i,e}^T (dA_e - lam_i dB_e) x_{i,e}; nd in {4, 8, 24}
+hipError_t launch_eig_grad(int n, int k, const double* X, const double* lam, const double* glam,
+                           int nelem, int nd, const int* dofs, const double* dA, int sa,
+                           const double* dB, int sb, double* grad, hipStream_t s);
 hipError_t launch_cast_f32(const double* in, float* out, size_t cnt, hipStream_t s);
 hipError_t launch_diag(const DevPencil& P, double* da, double* db, int* missing, hipStream_t s);
 

@@ -20,6 +20,8 @@
 //
 // Workgroups of 256 threads: thread t serves slot lane t % 16 of its panel and
 // row subgroup t / 16; a wave covers 4 rows x 16 slots.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace slrf {
@@ -212,6 +214,271 @@ __global__ __launch_bounds__(kThreads) void k_apply_dots(
 }
 
 // ---------------------------------------------------------------------------
+// apply (LDS-staged CSR): the same operation as k_apply_dots for pencils whose
+// row blocks fit in LDS.  A workgroup owns a block of rows and a group of G
+// panels; for each sub-block of `sub` rows the CSR entries (col, a, b) are
+// staged once in LDS and reused by all G panels, so the only global loads of
+// the gather are the 16-byte lane vectors of z (two complex floats or one
+// complex double per lane; one 128/256-byte segment per panel row).  The CGS
+// projections of each pass are formed from an LDS tile of the fresh q, one
+// thread per (slot pair, i) for complex float and per (slot, i, i + 16) for
+// complex double.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct LaneVec;
+template <>
+struct LaneVec<float> {
+  using V = float4;
+  static constexpr int SPL = 2;  // slots per lane
+};
+template <>
+struct LaneVec<double> {
+  using V = double2;
+  static constexpr int SPL = 1;
+};
+
+__device__ __forceinline__ bool map_tile(int nrb, int ncg, int group, int& rb, int& cg) {
+  const long total = (long)nrb * ncg;
+  const long per = (total + 7) / 8;
+  const long b = blockIdx.x;
+  const long t = (b & 7) * per + (b >> 3);
+  if (t >= total) return false;
+  const long G = group;
+  const long pg = t / ((long)nrb * G);
+  const long rem = t - pg * (long)nrb * G;
+  const long gw = min(G, (long)ncg - pg * G);
+  rb = (int)(rem / gw);
+  cg = (int)(pg * G + rem % gw);
+  return true;
+}
+
+__device__ __forceinline__ double lv_z(const float4& v) { return v.z; }
+__device__ __forceinline__ double lv_w(const float4& v) { return v.w; }
+__device__ __forceinline__ double lv_z(const double2&) { return 0.0; }
+__device__ __forceinline__ double lv_w(const double2&) { return 0.0; }
+__device__ __forceinline__ void lv_set_zw(float4& v, float z, float w) {
+  v.z = z;
+  v.w = w;
+}
+__device__ __forceinline__ void lv_set_zw(double2&, double, double) {}
+
+template <typename T, int SPL>
+__device__ __forceinline__ void lane_fma(T* acc, T a, T b, const typename LaneVec<T>::V& z) {
+  if constexpr (SPL == 2) {
+    acc[0] = mad(a, z.x, acc[0]);
+    acc[1] = mad(a, z.y, acc[1]);
+    acc[2] = mad(b, z.x, acc[2]);
+    acc[3] = mad(b, z.y, acc[3]);
+    acc[4] = mad(a, z.z, acc[4]);
+    acc[5] = mad(a, z.w, acc[5]);
+    acc[6] = mad(b, z.z, acc[6]);
+    acc[7] = mad(b, z.w, acc[7]);
+  } else {
+    acc[0] = mad(a, z.x, acc[0]);
+    acc[1] = mad(a, z.y, acc[1]);
+    acc[2] = mad(b, z.x, acc[2]);
+    acc[3] = mad(b, z.y, acc[3]);
+  }
+}
+
+// Epilogues of the LDS-staged operator sweep (M = A - sigma B, x gathered):
+//   kEpiApply : out = M x                      (GCR direction q, optional CGS dots)
+//   kEpiResid : out = b - M x                  (AMG level residual)
+//   kEpiJacobi: out = x + omega D^-1 (b - M x) (AMG damped-Jacobi sweep, D = diag M)
+constexpr int kEpiApply = 0, kEpiResid = 1, kEpiJacobi = 2;
+
+template <typename T, bool DOTS, int G, int EPI = kEpiApply>
+__global__ __launch_bounds__(kThreads) void k_apply_lds(
+    int n, const int* __restrict__ rowptr, const int* __restrict__ col, const T* __restrict__ av,
+    const T* __restrict__ bv, PanelGrid g, int sub, int lds_nnz, const int* __restrict__ active,
+    const double2* __restrict__ sigma, const typename CT<T>::t* __restrict__ Z,
+    typename CT<T>::t* __restrict__ Qk, const typename CT<T>::t* __restrict__ Qb, size_t vstride,
+    int k, double2* __restrict__ part, const typename CT<T>::t* __restrict__ Bin = nullptr,
+    const double* __restrict__ da = nullptr, const double* __restrict__ db = nullptr,
+    double omega = 0.0) {
+  using V = typename LaneVec<T>::V;
+  constexpr int SPL = LaneVec<T>::SPL;
+  constexpr int LPR = kPanel / SPL;    // lanes per row
+  constexpr int RPP = kThreads / LPR;  // rows per pass
+  extern __shared__ double smem_d[];
+  T* s_a = reinterpret_cast<T*>(smem_d);
+  T* s_b = s_a + lds_nnz;
+  int* s_col = reinterpret_cast<int*>(s_b + lds_nnz);
+  int* s_rp = s_col + lds_nnz;
+  __shared__ V sq[RPP][LPR];
+  __shared__ int s_act[G][kPanel];
+  __shared__ int s_pany[G];
+  const int ncg = (g.npan + G - 1) / G;
+  int rb, cg;
+  if (!map_tile(g.nrb, ncg, g.group, rb, cg)) return;
+  const int tid = threadIdx.x;
+  const int lr = tid % LPR, rr = tid / LPR;
+  const int pan0 = cg * G;
+  for (int t = tid; t < G * kPanel; t += kThreads) {
+    const int gg = t / kPanel, p = pan0 + gg;
+    s_act[gg][t % kPanel] =
+        (p < g.npan) ? (active == nullptr ? 1 : (active[p * kPanel + t % kPanel] != 0)) : 0;
+  }
+  __syncthreads();
+  if (tid < G) {
+    int any = 0;
+    for (int l = 0; l < kPanel; ++l) any |= s_act[tid][l];
+    s_pany[tid] = any;
+  }
+  __syncthreads();
+  double h[G][4];
+#pragma unroll
+  for (int gg = 0; gg < G; ++gg)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) h[gg][v] = 0.0;
+  // projection role of this thread: lane vector d_lane of a row, direction(s)
+  const int d_lane = (SPL == 2) ? (tid & 7) : (tid & 15);
+  const int d_i0 = (SPL == 2) ? (tid >> 3) : (tid >> 4);
+  const int d_i1 = d_i0 + 16;
+  const int R0 = rb * g.rpb, R1 = min(R0 + g.rpb, n);
+  for (int s0 = R0; s0 < R1; s0 += sub) {
+    const int s1 = min(s0 + sub, R1);
+    const int eb = rowptr[s0];
+    const int nsub = rowptr[s1] - eb;
+    for (int t = tid; t <= s1 - s0; t += kThreads) s_rp[t] = rowptr[s0 + t] - eb;
+    for (int t = tid; t < nsub; t += kThreads) {
+      s_col[t] = col[eb + t];
+      s_a[t] = av[eb + t];
+      s_b[t] = bv[eb + t];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) {
+      if (!s_pany[gg]) continue;
+      const int pan = pan0 + gg;
+      const size_t pbase = (size_t)pan * n * kPanel;
+      const V* __restrict__ Zp = reinterpret_cast<const V*>(Z + pbase);
+      V* __restrict__ Qp = reinterpret_cast<V*>(Qk + pbase);
+      T sr[SPL], si[SPL];
+#pragma unroll
+      for (int u = 0; u < SPL; ++u) {
+        const double2 sgm = sigma[pan * kPanel + lr * SPL + u];
+        sr[u] = (T)sgm.x;
+        si[u] = (T)sgm.y;
+      }
+      for (int p0 = s0; p0 < s1; p0 += RPP) {
+        const int row = p0 + rr;
+        if (row < s1) {
+          const int e0 = s_rp[row - s0], e1 = s_rp[row - s0 + 1];
+          T acc[4 * SPL];
+#pragma unroll
+          for (int v = 0; v < 4 * SPL; ++v) acc[v] = 0;
+          int e = e0;
+          for (; e + 3 < e1; e += 4) {
+            V z[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) z[u] = Zp[s_col[e + u] * LPR + lr];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) lane_fma<T, SPL>(acc, s_a[e + u], s_b[e + u], z[u]);
+          }
+          for (; e < e1; ++e) lane_fma<T, SPL>(acc, s_a[e], s_b[e], Zp[s_col[e] * LPR + lr]);
+          V q;
+          q.x = acc[0] - (sr[0] * acc[2] - si[0] * acc[3]);
+          q.y = acc[1] - (sr[0] * acc[3] + si[0] * acc[2]);
+          if constexpr (SPL == 2) {
+            q.z = acc[4] - (sr[1] * acc[6] - si[1] * acc[7]);
+            q.w = acc[5] - (sr[1] * acc[7] + si[1] * acc[6]);
+          }
+          if constexpr (EPI != kEpiApply) {
+            const V bb = reinterpret_cast<const V*>(Bin + pbase)[row * LPR + lr];
+            V rres;  // b - M x
+            rres.x = bb.x - q.x;
+            rres.y = bb.y - q.y;
+            if constexpr (SPL == 2) {
+              rres.z = bb.z - q.z;
+              rres.w = bb.w - q.w;
+            }
+            if constexpr (EPI == kEpiResid) {
+              q = rres;
+            } else {
+              const V xo = Zp[row * LPR + lr];
+              const double dav = da[row], dbv = db[row];
+#pragma unroll
+              for (int u = 0; u < SPL; ++u) {
+                const double dx = dav - (double)sr[u] * dbv, dy = -(double)si[u] * dbv;
+                const double iv = omega / (dx * dx + dy * dy);
+                const double ix = dx * iv, iy = -dy * iv;  // omega / (d)
+                const double rx = u == 0 ? rres.x : lv_z(rres), ry = u == 0 ? rres.y : lv_w(rres);
+                const double ox = u == 0 ? xo.x : lv_z(xo), oy = u == 0 ? xo.y : lv_w(xo);
+                const T nx = (T)(ox + rx * ix - ry * iy), ny = (T)(oy + rx * iy + ry * ix);
+                if (u == 0) {
+                  q.x = nx;
+                  q.y = ny;
+                } else {
+                  lv_set_zw(q, nx, ny);
+                }
+              }
+            }
+          }
+          Qp[row * LPR + lr] = q;
+          if constexpr (DOTS) sq[rr][lr] = q;
+        }
+        if constexpr (DOTS) {
+          __syncthreads();
+          const int nr = min(RPP, s1 - p0);
+          if (d_i0 < k) {
+            const V* __restrict__ Qi =
+                reinterpret_cast<const V*>(Qb + (size_t)d_i0 * vstride + pbase);
+#pragma unroll 4
+            for (int r2 = 0; r2 < nr; ++r2) {
+              const V v = Qi[(p0 + r2) * LPR + d_lane];
+              const V qq = sq[r2][d_lane];
+              h[gg][0] += (double)v.x * qq.x + (double)v.y * qq.y;
+              h[gg][1] += (double)v.x * qq.y - (double)v.y * qq.x;
+              if constexpr (SPL == 2) {
+                h[gg][2] += (double)v.z * qq.z + (double)v.w * qq.w;
+                h[gg][3] += (double)v.z * qq.w - (double)v.w * qq.z;
+              }
+            }
+          }
+          if constexpr (SPL == 1) {
+            if (d_i1 < k) {
+              const V* __restrict__ Qi =
+                  reinterpret_cast<const V*>(Qb + (size_t)d_i1 * vstride + pbase);
+#pragma unroll 4
+              for (int r2 = 0; r2 < nr; ++r2) {
+                const V v = Qi[(p0 + r2) * LPR + d_lane];
+                const V qq = sq[r2][d_lane];
+                h[gg][2] += (double)v.x * qq.x + (double)v.y * qq.y;
+                h[gg][3] += (double)v.x * qq.y - (double)v.y * qq.x;
+              }
+            }
+          }
+          __syncthreads();
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if constexpr (DOTS) {
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) {
+      if (!s_pany[gg]) continue;
+      const int slot0 = (pan0 + gg) * kPanel;
+      if constexpr (SPL == 2) {
+        if (d_i0 < k) {
+          double2* dst = part + ((size_t)rb * g.ND + d_i0) * g.C + slot0 + 2 * d_lane;
+          dst[0] = make_double2(h[gg][0], h[gg][1]);
+          dst[1] = make_double2(h[gg][2], h[gg][3]);
+        }
+      } else {
+        if (d_i0 < k)
+          part[((size_t)rb * g.ND + d_i0) * g.C + slot0 + d_lane] =
+              make_double2(h[gg][0], h[gg][1]);
+        if (d_i1 < k)
+          part[((size_t)rb * g.ND + d_i1) * g.C + slot0 + d_lane] =
+              make_double2(h[gg][2], h[gg][3]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // orth: q_k -= sum beta_i q_i ; p_k = z - sum beta_i p_i ; partial <q,q>, <q,r>
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -305,10 +572,10 @@ __global__ __launch_bounds__(kThreads) void k_step(
       const C rn = mk<C>(r.x - (al.x * q.x - al.y * q.y), r.y - (al.x * q.y + al.y * q.x));
       R[off] = rn;
       const double x = rn.x, y = rn.y;
-      if (pc) {
+      if (pc == 1) {
         const double2 d = jacobi_inv(da[row], db[row], sg);
         Z[off] = mk<C>(x * d.x - y * d.y, x * d.y + y * d.x);
-      } else {
+      } else if (pc == 0) {
         Z[off] = rn;
       }
       acc[0] += x * x + y * y;
@@ -400,10 +667,10 @@ __global__ __launch_bounds__(kThreads) void k_true_resid(
       const double x = F[(size_t)row * ldf + c] - mx, y = -my;
       const size_t off = (base + row) * kPanel + lane;
       R[off] = mk<C>(x, y);
-      if (pc) {
+      if (pc == 1) {
         const double2 d = jacobi_inv(da[row], db[row], sg);
         Z[off] = mk<C>(x * d.x - y * d.y, x * d.y + y * d.x);
-      } else {
+      } else if (pc == 0) {
         Z[off] = mk<C>(x, y);
       }
       acc[0] += x * x + y * y;
@@ -479,10 +746,10 @@ __global__ __launch_bounds__(kThreads) void k_admit(
           y = 0.0;
         }
         Rnew[off] = mk<C>(x, y);
-        if (pc) {
+        if (pc == 1) {
           const double2 d = jacobi_inv(da[row], db[row], sg);
           Znew[off] = mk<C>(x * d.x - y * d.y, x * d.y + y * d.x);
-        } else {
+        } else if (pc == 0) {
           Znew[off] = mk<C>(x, y);
         }
         acc[0] += x * x + y * y;
@@ -641,6 +908,139 @@ __global__ void k_fin_true(const double2* __restrict__ red, int nslots, int from
   target2[slot] = fmax(inner_rtol * inner_rtol * rn2, safety * safety * tol2);
 }
 
+// ---------------------------------------------------------------------------
+// AMG V-cycle kernels on level vectors in panel layout (rows = level size).
+// ---------------------------------------------------------------------------
+// Level operator sweep with a plain CSR gather (any row length):
+//   EPI kEpiResid : out = b - (A_l - sigma B_l) x
+//   EPI kEpiJacobi: out = x + omega D^-1 (b - (A_l - sigma B_l) x)
+template <typename T, int EPI>
+__global__ __launch_bounds__(kThreads) void k_lvl_simple(
+    int n, const int* __restrict__ rowptr, const int* __restrict__ col, const T* __restrict__ av,
+    const T* __restrict__ bv, const double* __restrict__ da, const double* __restrict__ db,
+    double omega, PanelGrid g, const int* __restrict__ active, const double2* __restrict__ sigma,
+    const typename CT<T>::t* __restrict__ X, const typename CT<T>::t* __restrict__ Bin,
+    typename CT<T>::t* __restrict__ Out) {
+  using C = typename CT<T>::t;
+  int rb, pan;
+  if (!map_block(g, rb, pan)) return;
+  const int lane = threadIdx.x & 15, rs = threadIdx.x >> 4;
+  const int slot = pan * kPanel + lane;
+  if (active != nullptr && active[slot] == 0) return;
+  const double2 sg = sigma[slot];
+  const size_t pbase = (size_t)pan * n * kPanel;
+  const C* __restrict__ Xp = X + pbase;
+  const int r0 = rb * g.rpb, r1 = min(r0 + g.rpb, n);
+  for (int row = r0 + rs; row < r1; row += 16) {
+    T ar = 0, ai = 0, br = 0, bi = 0;
+    for (int e = rowptr[row]; e < rowptr[row + 1]; ++e) {
+      const C z = Xp[col[e] * kPanel + lane];
+      const T a = av[e], b = bv[e];
+      ar = mad(a, z.x, ar);
+      ai = mad(a, z.y, ai);
+      br = mad(b, z.x, br);
+      bi = mad(b, z.y, bi);
+    }
+    const size_t off = pbase + (size_t)row * kPanel + lane;
+    const C bb = Bin[off];
+    const double rx = (double)bb.x - ((double)ar - (sg.x * br - sg.y * bi));
+    const double ry = (double)bb.y - ((double)ai - (sg.x * bi + sg.y * br));
+    if constexpr (EPI == kEpiResid) {
+      Out[off] = mk<C>(rx, ry);
+    } else {
+      const double2 d = jacobi_inv(da[row], db[row], sg);
+      const C xo = Xp[row * kPanel + lane];
+      Out[off] = mk<C>(xo.x + omega * (rx * d.x - ry * d.y), xo.y + omega * (rx * d.y + ry * d.x));
+    }
+  }
+}
+
+// first smoothing step from a zero guess: out = omega D^-1 b
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_lvl_jacobi0(
+    int n, const double* __restrict__ da, const double* __restrict__ db, double omega, PanelGrid g,
+    const int* __restrict__ active, const double2* __restrict__ sigma,
+    const typename CT<T>::t* __restrict__ Bin, typename CT<T>::t* __restrict__ Out) {
+  using C = typename CT<T>::t;
+  int rb, pan;
+  if (!map_block(g, rb, pan)) return;
+  const int lane = threadIdx.x & 15, rs = threadIdx.x >> 4;
+  const int slot = pan * kPanel + lane;
+  if (active != nullptr && active[slot] == 0) return;
+  const double2 sg = sigma[slot];
+  const size_t pbase = (size_t)pan * n * kPanel;
+  const int r0 = rb * g.rpb, r1 = min(r0 + g.rpb, n);
+  for (int row = r0 + rs; row < r1; row += 16) {
+    const size_t off = pbase + (size_t)row * kPanel + lane;
+    const C bb = Bin[off];
+    const double2 d = jacobi_inv(da[row], db[row], sg);
+    Out[off] = mk<C>(omega * (bb.x * d.x - bb.y * d.y), omega * (bb.x * d.y + bb.y * d.x));
+  }
+}
+
+// grid transfer with a real CSR matrix (restriction P^T or prolongation P):
+//   out[i] (+)= sum_e v_e in[col_e]; in has nin rows, out has nout rows.
+template <typename T, bool ADD>
+__global__ __launch_bounds__(kThreads) void k_transfer(
+    int nout, int nin, const int* __restrict__ rowptr, const int* __restrict__ col,
+    const T* __restrict__ v, PanelGrid g, const int* __restrict__ active,
+    const typename CT<T>::t* __restrict__ In, typename CT<T>::t* __restrict__ Out) {
+  using C = typename CT<T>::t;
+  int rb, pan;
+  if (!map_block(g, rb, pan)) return;
+  const int lane = threadIdx.x & 15, rs = threadIdx.x >> 4;
+  const int slot = pan * kPanel + lane;
+  if (active != nullptr && active[slot] == 0) return;
+  const C* __restrict__ Ip = In + (size_t)pan * nin * kPanel;
+  C* __restrict__ Op = Out + (size_t)pan * nout * kPanel;
+  const int r0 = rb * g.rpb, r1 = min(r0 + g.rpb, nout);
+  for (int row = r0 + rs; row < r1; row += 16) {
+    T sx = 0, sy = 0;
+    for (int e = rowptr[row]; e < rowptr[row + 1]; ++e) {
+      const C z = Ip[col[e] * kPanel + lane];
+      sx = mad(v[e], z.x, sx);
+      sy = mad(v[e], z.y, sy);
+    }
+    C o = mk<C>(sx, sy);
+    if constexpr (ADD) {
+      const C p = Op[row * kPanel + lane];
+      o.x += p.x;
+      o.y += p.y;
+    }
+    Op[row * kPanel + lane] = o;
+  }
+}
+
+// coarsest level: x = (A_c - sigma_j B_c)^{-1} b with the dense inverse of the
+// slot's pole j = sys % npoles
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_coarse_solve(
+    int nc, PanelGrid g, const int* __restrict__ active, const int* __restrict__ sys, int npoles,
+    const typename CT<T>::t* __restrict__ Minv, const typename CT<T>::t* __restrict__ Bin,
+    typename CT<T>::t* __restrict__ Out) {
+  using C = typename CT<T>::t;
+  int rb, pan;
+  if (!map_block(g, rb, pan)) return;
+  const int lane = threadIdx.x & 15, rs = threadIdx.x >> 4;
+  const int slot = pan * kPanel + lane;
+  if (active != nullptr && active[slot] == 0) return;
+  const int sy = sys[slot];
+  if (sy < 0) return;
+  const C* __restrict__ Mp = Minv + (size_t)(sy % npoles) * nc * nc;
+  const C* __restrict__ Bp = Bin + (size_t)pan * nc * kPanel;
+  const int r0 = rb * g.rpb, r1 = min(r0 + g.rpb, nc);
+  for (int row = r0 + rs; row < r1; row += 16) {
+    double sx = 0.0, syy = 0.0;
+    for (int j = 0; j < nc; ++j) {
+      const C m = Mp[(size_t)row * nc + j];
+      const C b = Bp[j * kPanel + lane];
+      sx += (double)m.x * b.x - (double)m.y * b.y;
+      syy += (double)m.x * b.y + (double)m.y * b.x;
+    }
+    Out[(size_t)pan * nc * kPanel + row * kPanel + lane] = mk<C>(sx, syy);
+  }
+}
+
 inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
 
 }  // namespace
@@ -668,15 +1068,60 @@ const double* vals_b<double>(const DevPencil& P) {
   return P.b;
 }
 
+constexpr int kGroupPanels = 4;  // panels per workgroup in the LDS-staged SpMM
+
+template <typename T>
+static size_t lds_bytes(int sub, int nnz) {
+  return (size_t)nnz * (2 * sizeof(T) + sizeof(int)) + (size_t)(sub + 1) * sizeof(int);
+}
+
+// Staging plan: rows per sub-block (64 or 32) whose largest CSR slice fits in
+// 48 KB of LDS; false when neither does (then the gather reads the CSR from
+// global memory).
+template <typename T>
+static bool lds_plan(const DevPencil& P, int rpb, int& sub, int& cap, size_t& bytes) {
+  const int cands[2] = {64, 32};
+  const int caps[2] = {P.max_nnz_sub64, P.max_nnz_sub32};
+  for (int i = 0; i < 2; ++i) {
+    if (caps[i] <= 0 || rpb % cands[i] != 0) continue;
+    const size_t b = lds_bytes<T>(cands[i], caps[i]);
+    if (b <= 48 * 1024) {
+      sub = cands[i];
+      cap = caps[i];
+      bytes = b;
+      return true;
+    }
+  }
+  return false;
+}
+
 template <typename T>
 hipError_t launch_apply_dots(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
                              const void* Z, void* Qk, const void* Qbase, size_t vstride, int k,
                              double2* part, bool, hipStream_t s) {
   using C = typename CT<T>::t;
-  const dim3 grid(g.blocks()), block(kThreads);
   auto Zc = static_cast<const C*>(Z);
   auto Qc = static_cast<C*>(Qk);
   auto Qb = static_cast<const C*>(Qbase);
+  int sub = 0, cap = 0;
+  size_t bytes = 0;
+  if (lds_plan<T>(P, g.rpb, sub, cap, bytes)) {
+    PanelGrid gg = g;
+    const int ncg = (g.npan + kGroupPanels - 1) / kGroupPanels;
+    gg.group = ncg < 4 ? ncg : 4;
+    const long total = (long)g.nrb * ncg;
+    const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
+    if (k == 0)
+      k_apply_lds<T, false, kGroupPanels><<<blocks, kThreads, bytes, s>>>(
+          P.n, P.rowptr, P.col, vals_a<T>(P), vals_b<T>(P), gg, sub, cap, st.active, st.sigma,
+          Zc, Qc, Qb, vstride, k, part);
+    else
+      k_apply_lds<T, true, kGroupPanels><<<blocks, kThreads, bytes, s>>>(
+          P.n, P.rowptr, P.col, vals_a<T>(P), vals_b<T>(P), gg, sub, cap, st.active, st.sigma,
+          Zc, Qc, Qb, vstride, k, part);
+    return hipGetLastError();
+  }
+  const dim3 grid(g.blocks()), block(kThreads);
   if (k == 0)
     k_apply_dots<T, false><<<grid, block, 0, s>>>(P.n, P.rowptr, P.col, vals_a<T>(P),
                                                   vals_b<T>(P), g, st.active, st.sigma, Zc, Qc,
@@ -691,11 +1136,10 @@ hipError_t launch_apply_dots(const DevPencil& P, const PanelGrid& g, const SlotT
 template <typename T>
 hipError_t launch_spmm_panel(const DevPencil& P, const PanelGrid& g, const double2* sigma_slot,
                              const void* Z, void* Q, hipStream_t s) {
-  using C = typename CT<T>::t;
-  k_apply_dots<T, false><<<g.blocks(), kThreads, 0, s>>>(
-      P.n, P.rowptr, P.col, vals_a<T>(P), vals_b<T>(P), g, nullptr, sigma_slot,
-      static_cast<const C*>(Z), static_cast<C*>(Q), nullptr, 0, 0, nullptr);
-  return hipGetLastError();
+  SlotTables st;
+  st.sigma = sigma_slot;
+  st.active = nullptr;
+  return launch_apply_dots<T>(P, g, st, Z, Q, nullptr, 0, 0, nullptr, false, s);
 }
 
 template <typename T>
@@ -715,10 +1159,10 @@ hipError_t launch_orth(const DevPencil& P, const PanelGrid& g, const SlotTables&
 template <typename T>
 hipError_t launch_step(const DevPencil& P, const PanelGrid& g, const SlotTables& st, void* R,
                        void* Z, const void* Qk, const double2* alpha_k, double2* part,
-                       bool precond, hipStream_t s) {
+                       int precond, hipStream_t s) {
   using C = typename CT<T>::t;
   k_step<T><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, st.sigma, P.da, P.db,
-                                            precond ? 1 : 0, static_cast<C*>(R),
+                                            precond, static_cast<C*>(R),
                                             static_cast<C*>(Z), static_cast<const C*>(Qk),
                                             alpha_k, part);
   return hipGetLastError();
@@ -737,10 +1181,10 @@ hipError_t launch_yupdate(int n, const PanelGrid& g, const SlotTables& st, doubl
 template <typename T>
 hipError_t launch_true_resid(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
                              const double2* Y, const double* F, int ldf, void* R, void* Z,
-                             double2* part, bool precond, hipStream_t s) {
+                             double2* part, int precond, hipStream_t s) {
   using C = typename CT<T>::t;
   k_true_resid<T><<<g.blocks(), kThreads, 0, s>>>(
-      P.n, P.rowptr, P.col, P.a, P.b, P.da, P.db, precond ? 1 : 0, g, st.sys, st.col, st.sigma,
+      P.n, P.rowptr, P.col, P.a, P.b, P.da, P.db, precond, g, st.sys, st.col, st.sigma,
       Y, F, ldf, static_cast<C*>(R), static_cast<C*>(Z), part);
   return hipGetLastError();
 }
@@ -749,11 +1193,11 @@ template <typename T>
 hipError_t launch_admit(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
                         const double2* Yold, const void* Rold, const void* Zold, double2* Ynew,
                         void* Rnew, void* Znew, const double* F, const double* E,
-                        const double* X, int ld, bool warm, double2* part, bool precond,
+                        const double* X, int ld, bool warm, double2* part, int precond,
                         hipStream_t s) {
   using C = typename CT<T>::t;
   k_admit<T><<<g.blocks(), kThreads, 0, s>>>(
-      P.n, P.da, P.db, precond ? 1 : 0, g, st.sys, st.src, st.col, st.sigma, st.theta, Yold,
+      P.n, P.da, P.db, precond, g, st.sys, st.src, st.col, st.sigma, st.theta, Yold,
       static_cast<const C*>(Rold), static_cast<const C*>(Zold), Ynew, static_cast<C*>(Rnew),
       static_cast<C*>(Znew), F, E, X, ld, warm ? 1 : 0, part);
   return hipGetLastError();
@@ -821,19 +1265,110 @@ hipError_t launch_fin_true(const double2* red, int nslots, const SlotTables& st,
                                      hipStream_t);                                           \
   template hipError_t launch_step<T>(const DevPencil&, const PanelGrid&, const SlotTables&,  \
                                      void*, void*, const void*, const double2*, double2*,    \
-                                     bool, hipStream_t);                                     \
+                                     int, hipStream_t);                                     \
   template hipError_t launch_yupdate<T>(int, const PanelGrid&, const SlotTables&, double2*,  \
                                         const void*, size_t, int, const double2*,            \
                                         hipStream_t);                                        \
   template hipError_t launch_true_resid<T>(const DevPencil&, const PanelGrid&,               \
                                            const SlotTables&, const double2*, const double*, \
-                                           int, void*, void*, double2*, bool, hipStream_t);  \
+                                           int, void*, void*, double2*, int, hipStream_t);   \
   template hipError_t launch_admit<T>(const DevPencil&, const PanelGrid&, const SlotTables&, \
                                       const double2*, const void*, const void*, double2*,    \
                                       void*, void*, const double*, const double*,            \
-                                      const double*, int, bool, double2*, bool, hipStream_t);
+                                      const double*, int, bool, double2*, int, hipStream_t);
 
 SLRF_INST(float)
 SLRF_INST(double)
+
+// ----------------------------- AMG launchers --------------------------------
+template <typename T>
+hipError_t launch_lvl_op(const DevPencil& L, const PanelGrid& g, const SlotTables& st, int epi,
+                         double omega, const void* X, const void* Bin, void* Out, hipStream_t s) {
+  using C = typename CT<T>::t;
+  auto Xc = static_cast<const C*>(X);
+  auto Bc = static_cast<const C*>(Bin);
+  auto Oc = static_cast<C*>(Out);
+  int sub = 0, cap = 0;
+  size_t bytes = 0;
+  if (lds_plan<T>(L, g.rpb, sub, cap, bytes)) {
+    PanelGrid gg = g;
+    const int ncg = (g.npan + kGroupPanels - 1) / kGroupPanels;
+    gg.group = ncg < 4 ? ncg : 4;
+    const long total = (long)g.nrb * ncg;
+    const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
+    if (epi == kEpiResid)
+      k_apply_lds<T, false, kGroupPanels, kEpiResid><<<blocks, kThreads, bytes, s>>>(
+          L.n, L.rowptr, L.col, vals_a<T>(L), vals_b<T>(L), gg, sub, cap, st.active, st.sigma, Xc,
+          Oc, nullptr, 0, 0, nullptr, Bc, L.da, L.db, omega);
+    else
+      k_apply_lds<T, false, kGroupPanels, kEpiJacobi><<<blocks, kThreads, bytes, s>>>(
+          L.n, L.rowptr, L.col, vals_a<T>(L), vals_b<T>(L), gg, sub, cap, st.active, st.sigma, Xc,
+          Oc, nullptr, 0, 0, nullptr, Bc, L.da, L.db, omega);
+    return hipGetLastError();
+  }
+  if (epi == kEpiResid)
+    k_lvl_simple<T, kEpiResid><<<g.blocks(), kThreads, 0, s>>>(
+        L.n, L.rowptr, L.col, vals_a<T>(L), vals_b<T>(L), L.da, L.db, omega, g, st.active,
+        st.sigma, Xc, Bc, Oc);
+  else
+    k_lvl_simple<T, kEpiJacobi><<<g.blocks(), kThreads, 0, s>>>(
+        L.n, L.rowptr, L.col, vals_a<T>(L), vals_b<T>(L), L.da, L.db, omega, g, st.active,
+        st.sigma, Xc, Bc, Oc);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_lvl_jacobi0(const DevPencil& L, const PanelGrid& g, const SlotTables& st,
+                              double omega, const void* Bin, void* Out, hipStream_t s) {
+  using C = typename CT<T>::t;
+  k_lvl_jacobi0<T><<<g.blocks(), kThreads, 0, s>>>(L.n, L.da, L.db, omega, g, st.active, st.sigma,
+                                                   static_cast<const C*>(Bin),
+                                                   static_cast<C*>(Out));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_transfer(const DevTransfer& M, const PanelGrid& g, const SlotTables& st,
+                           const void* In, void* Out, bool add, hipStream_t s) {
+  using C = typename CT<T>::t;
+  const T* v = std::is_same<T, float>::value ? reinterpret_cast<const T*>(M.v32)
+                                             : reinterpret_cast<const T*>(M.v);
+  if (add)
+    k_transfer<T, true><<<g.blocks(), kThreads, 0, s>>>(M.nrows, M.ncols, M.rowptr, M.col, v, g,
+                                                        st.active, static_cast<const C*>(In),
+                                                        static_cast<C*>(Out));
+  else
+    k_transfer<T, false><<<g.blocks(), kThreads, 0, s>>>(M.nrows, M.ncols, M.rowptr, M.col, v, g,
+                                                         st.active, static_cast<const C*>(In),
+                                                         static_cast<C*>(Out));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_coarse_solve(int nc, const PanelGrid& g, const SlotTables& st, int npoles,
+                               const void* Minv, const void* In, void* Out, hipStream_t s) {
+  using C = typename CT<T>::t;
+  k_coarse_solve<T><<<g.blocks(), kThreads, 0, s>>>(nc, g, st.active, st.sys, npoles,
+                                                    static_cast<const C*>(Minv),
+                                                    static_cast<const C*>(In),
+                                                    static_cast<C*>(Out));
+  return hipGetLastError();
+}
+
+#define SLRF_INST_AMG(T)                                                                       \
+  template hipError_t launch_lvl_op<T>(const DevPencil&, const PanelGrid&, const SlotTables&,  \
+                                       int, double, const void*, const void*, void*,           \
+                                       hipStream_t);                                           \
+  template hipError_t launch_lvl_jacobi0<T>(const DevPencil&, const PanelGrid&,                \
+                                            const SlotTables&, double, const void*, void*,     \
+                                            hipStream_t);                                      \
+  template hipError_t launch_transfer<T>(const DevTransfer&, const PanelGrid&,                 \
+                                         const SlotTables&, const void*, void*, bool,          \
+                                         hipStream_t);                                         \
+  template hipError_t launch_coarse_solve<T>(int, const PanelGrid&, const SlotTables&, int,    \
+                                             const void*, const void*, void*, hipStream_t);
+SLRF_INST_AMG(float)
+SLRF_INST_AMG(double)
+
 
 }  // namespace slrf

@@ -20,6 +20,7 @@
 #include <string>
 #include <vector>
 
+#include "amg_host.h"
 #include "dense_host.h"
 #include "internal.h"
 
@@ -59,6 +60,23 @@ struct Timer {
 
 }  // namespace
 
+// Device copy of the AMG hierarchy (levels >= 1; level 0 is the pencil).
+struct DevAmg {
+  bool ready = false;
+  std::vector<DevPencil> lv;            // levels 1 .. L-1
+  std::vector<DevTransfer> P, R;        // P[l]: n_l x n_{l+1}, R[l] = P[l]^T
+  std::vector<int> n;                   // level sizes, n[0] = fine
+  int nc = 0;                           // coarsest size
+  void* inv64 = nullptr;                // [pole][nc][nc] complex double
+  void* inv32 = nullptr;                // [pole][nc][nc] complex float
+  std::vector<void*> allocs;
+  double omega = 0.7;                   // damped-Jacobi smoothing weight
+  size_t nnz_all = 0;                   // level + transfer nonzeros (byte accounting)
+  ~DevAmg() {
+    for (void* p : allocs) (void)hipFree(p);
+  }
+};
+
 struct slrf_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -81,6 +99,7 @@ struct slrf_ctx {
   size_t h_flags_cap = 0;
   Timer timer;
   slrf_filter_stats* cur_stats = nullptr;
+  DevAmg amg;
 
   ~slrf_ctx() {
     for (auto& b : bufs)
@@ -99,7 +118,7 @@ namespace {
 enum BufId {
   B_XR, B_F, B_E, B_UR, B_FN2, B_YS, B_Y0, B_Y1, B_R0, B_R1, B_Z0, B_Z1, B_Q, B_P, B_PART, B_RED,
   B_TAB_I, B_TAB_D, B_SCAL, B_SYS, B_AU, B_BU, B_V, B_AV, B_BV, B_GPART, B_SMALL, B_XL, B_BXL,
-  B_CST, B_TMP, B_SSP, B_NBUF
+  B_CST, B_TMP, B_SSP, B_AMGV, B_NBUF
 };
 
 #define HIPCHK(x)                                                     \
@@ -206,7 +225,7 @@ hipError_t sync(slrf_ctx* h) {
 slrf_status validate_options(slrf_ctx* h, const slrf_options& o) {
   if (o.precision != SLRF_PREC_FP64 && o.precision != SLRF_PREC_MIXED)
     return fail(h, SLRF_E_ARG, "precision must be SLRF_PREC_FP64 or SLRF_PREC_MIXED");
-  if (o.precond != SLRF_PC_NONE && o.precond != SLRF_PC_JACOBI)
+  if (o.precond != SLRF_PC_NONE && o.precond != SLRF_PC_JACOBI && o.precond != SLRF_PC_AMG)
     return fail(h, SLRF_E_ARG, "unknown preconditioner");
   if (o.restart < 1 || o.restart > kMaxRestart)
     return fail(h, SLRF_E_ARG, "restart must be in [1, 32]");
@@ -239,6 +258,204 @@ int nrb_for(int n) {
   return (n + rpb - 1) / rpb;
 }
 
+
+// ---------------------------------------------------------------------------
+// AMG: host build (once per handle, first use) and the device V-cycle
+// ---------------------------------------------------------------------------
+template <typename V>
+hipError_t upload(slrf_ctx* h, const std::vector<V>& v, const V** out) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, std::max<size_t>(1, v.size()) * sizeof(V));
+  if (e != hipSuccess) return e;
+  h->amg.allocs.push_back(p);
+  if (!v.empty()) e = hipMemcpy(p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice);
+  *out = static_cast<const V*>(p);
+  return e;
+}
+
+int max_slice_of(const std::vector<int>& rp, int n, int sub) {
+  int mx = 0;
+  for (int r = 0; r < n; r += sub) mx = std::max(mx, rp[std::min(r + sub, n)] - rp[r]);
+  return mx;
+}
+
+slrf_status build_amg(slrf_ctx* h) {
+  if (h->amg.ready) return SLRF_OK;
+  const int n = h->P.n, nnz = h->P.nnz;
+  HostLevel fine;
+  fine.n = n;
+  fine.rp.resize(n + 1);
+  fine.ci.resize(nnz);
+  fine.a.resize(nnz);
+  fine.b.resize(nnz);
+  HIPCHK(hipMemcpy(fine.rp.data(), h->P.rowptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(fine.ci.data(), h->P.col, sizeof(int) * nnz, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(fine.a.data(), h->P.a, sizeof(double) * nnz, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(fine.b.data(), h->P.b, sizeof(double) * nnz, hipMemcpyDeviceToHost));
+  std::vector<std::complex<double>> poles;
+  for (auto& p : h->poles) poles.emplace_back(p.x, p.y);
+  AmgParams prm;
+  AmgHierarchy H;
+  std::string err;
+  if (!amg_build(fine, poles, prm, H, err)) return fail(h, SLRF_E_ARG, "AMG setup: " + err);
+  DevAmg& A = h->amg;
+  const int L = (int)H.levels.size();
+  A.n.clear();
+  for (auto& lv : H.levels) A.n.push_back(lv.n);
+  A.nnz_all = 0;
+  for (int l = 1; l < L; ++l) {
+    const HostLevel& hl = H.levels[l];
+    DevPencil d;
+    d.n = hl.n;
+    d.nnz = (int)hl.ci.size();
+    std::vector<float> a32(hl.a.begin(), hl.a.end()), b32(hl.b.begin(), hl.b.end());
+    std::vector<double> da(hl.n, 0.0), db(hl.n, 0.0);
+    for (int i = 0; i < hl.n; ++i)
+      for (int e = hl.rp[i]; e < hl.rp[i + 1]; ++e)
+        if (hl.ci[e] == i) {
+          da[i] = hl.a[e];
+          db[i] = hl.b[e];
+        }
+    HIPCHK(upload(h, hl.rp, &d.rowptr));
+    HIPCHK(upload(h, hl.ci, &d.col));
+    HIPCHK(upload(h, hl.a, &d.a));
+    HIPCHK(upload(h, hl.b, &d.b));
+    HIPCHK(upload(h, a32, &d.a32));
+    HIPCHK(upload(h, b32, &d.b32));
+    HIPCHK(upload(h, da, &d.da));
+    HIPCHK(upload(h, db, &d.db));
+    d.max_nnz_sub64 = max_slice_of(hl.rp, hl.n, 64);
+    d.max_nnz_sub32 = max_slice_of(hl.rp, hl.n, 32);
+    A.lv.push_back(d);
+    A.nnz_all += d.nnz;
+  }
+  auto up_tr = [&](const HostCsrP& M, DevTransfer& d) -> hipError_t {
+    d.nrows = M.n;
+    d.ncols = M.m;
+    d.nnz = (int)M.ci.size();
+    std::vector<float> v32(M.v.begin(), M.v.end());
+    hipError_t e;
+    if ((e = upload(h, M.rp, &d.rowptr)) != hipSuccess) return e;
+    if ((e = upload(h, M.ci, &d.col)) != hipSuccess) return e;
+    if ((e = upload(h, M.v, &d.v)) != hipSuccess) return e;
+    return upload(h, v32, &d.v32);
+  };
+  for (int l = 0; l + 1 < L; ++l) {
+    DevTransfer P, R;
+    HIPCHK(up_tr(H.P[l], P));
+    HIPCHK(up_tr(H.R[l], R));
+    A.P.push_back(P);
+    A.R.push_back(R);
+    A.nnz_all += P.nnz + R.nnz;
+  }
+  A.nc = H.nc;
+  std::vector<double2> i64(H.coarse_inv.size());
+  std::vector<float2> i32(H.coarse_inv.size());
+  for (size_t i = 0; i < H.coarse_inv.size(); ++i) {
+    i64[i] = make_double2(H.coarse_inv[i].real(), H.coarse_inv[i].imag());
+    i32[i] = make_float2((float)H.coarse_inv[i].real(), (float)H.coarse_inv[i].imag());
+  }
+  const double2* p64;
+  const float2* p32;
+  HIPCHK(upload(h, i64, &p64));
+  HIPCHK(upload(h, i32, &p32));
+  A.inv64 = const_cast<double2*>(p64);
+  A.inv32 = const_cast<float2*>(p32);
+  A.ready = true;
+  return SLRF_OK;
+}
+
+// Level vectors of the V-cycle for a pool of C slots.
+struct AmgVecs {
+  void* W0 = nullptr;   // level-0 smoothed iterate
+  void* T0 = nullptr;   // level-0 residual
+  std::vector<void*> X, W, B, T;  // per level (index 0 unused)
+};
+
+size_t amg_vec_bytes(const DevAmg& A, int C, size_t sT) {
+  size_t b = 2 * (size_t)C * A.n[0] * sT;
+  for (size_t l = 1; l < A.n.size(); ++l) b += 4 * (size_t)C * A.n[l] * sT;
+  return b;
+}
+
+template <typename T>
+slrf_status amg_vectors(slrf_ctx* h, int C, AmgVecs& v) {
+  const DevAmg& A = h->amg;
+  const size_t sT = 2 * sizeof(T);
+  char* base;
+  HIPCHK(ensure_t(h, B_AMGV, amg_vec_bytes(A, C, sT), &base));
+  size_t off = 0;
+  auto take = [&](size_t rows) {
+    void* p = base + off;
+    off += (size_t)C * rows * sT;
+    return p;
+  };
+  v.W0 = take(A.n[0]);
+  v.T0 = take(A.n[0]);
+  const size_t L = A.n.size();
+  v.X.assign(L, nullptr);
+  v.W.assign(L, nullptr);
+  v.B.assign(L, nullptr);
+  v.T.assign(L, nullptr);
+  for (size_t l = 1; l < L; ++l) {
+    v.X[l] = take(A.n[l]);
+    v.W[l] = take(A.n[l]);
+    v.B[l] = take(A.n[l]);
+    v.T[l] = take(A.n[l]);
+  }
+  return SLRF_OK;
+}
+
+// z = V(r): one V-cycle (damped-Jacobi pre/post smoothing from a zero guess,
+// Galerkin coarse correction, dense coarsest solve) for every active slot.
+template <typename T>
+slrf_status vcycle(slrf_ctx* h, const AmgVecs& v, int C, int occ, int ND, const SlotTables& st,
+                   const void* Rin, void* Zout, int nact) {
+  const DevAmg& A = h->amg;
+  hipStream_t s = h->stream;
+  const int L = (int)A.n.size();
+  const size_t sT = 2 * sizeof(T);
+  const void* inv = std::is_same<T, float>::value ? A.inv32 : A.inv64;
+  {
+    double bytes = 0.0;
+    for (int l = 0; l < L; ++l) bytes += 10.0 * nact * (double)A.n[l] * sT;
+    bytes += (double)(h->P.nnz + A.nnz_all) * (4.0 + 2.0 * sizeof(T));
+    Scope sp(h, SLRF_K_PRECOND, bytes);
+    if (L == 1) {
+      HIPCHK(launch_coarse_solve<T>(A.nc, make_grid(A.nc, C, occ, ND), st, h->N, inv, Rin, Zout,
+                                    s));
+      return SLRF_OK;
+    }
+    auto lvl = [&](int l) -> const DevPencil& { return l == 0 ? h->P : A.lv[l - 1]; };
+    std::vector<const void*> b(L, nullptr);
+    std::vector<void*> x(L, nullptr);
+    b[0] = Rin;
+    for (int l = 0; l + 1 < L; ++l) {
+      const PanelGrid g = make_grid(A.n[l], C, occ, ND);
+      void* xb = l == 0 ? v.W0 : v.X[l];
+      void* r = l == 0 ? v.T0 : v.T[l];
+      HIPCHK(launch_lvl_jacobi0<T>(lvl(l), g, st, A.omega, b[l], xb, s));
+      HIPCHK(launch_lvl_op<T>(lvl(l), g, st, kEpiResidOp, A.omega, xb, b[l], r, s));
+      const PanelGrid gc = make_grid(A.n[l + 1], C, occ, ND);
+      HIPCHK(launch_transfer<T>(A.R[l], gc, st, r, v.B[l + 1], false, s));
+      b[l + 1] = v.B[l + 1];
+      x[l] = xb;
+    }
+    HIPCHK(launch_coarse_solve<T>(A.nc, make_grid(A.nc, C, occ, ND), st, h->N, inv, b[L - 1],
+                                  v.X[L - 1], s));
+    x[L - 1] = v.X[L - 1];
+    for (int l = L - 2; l >= 0; --l) {
+      const PanelGrid g = make_grid(A.n[l], C, occ, ND);
+      HIPCHK(launch_transfer<T>(A.P[l], g, st, x[l + 1], x[l], true, s));
+      void* out = l == 0 ? Zout : v.W[l];
+      HIPCHK(launch_lvl_op<T>(lvl(l), g, st, kEpiJacobiOp, A.omega, x[l], b[l], out, s));
+      x[l] = out;
+    }
+  }
+  (void)sT;
+  return SLRF_OK;
+}
+
 // Workspace plan of one filter call.
 struct Plan {
   int C;         // slots
@@ -255,8 +472,9 @@ Plan plan_filter(const slrf_ctx* h, int ncols) {
   const int ND = std::max(m, 2);
   const size_t nrb = nrb_for((int)n);
   const size_t fixed = 4 * n * ncols * sizeof(double) + (size_t)Spad * n * 16 + 64 * (size_t)S;
-  const size_t per_slot = n * (2 * 16 + 4 * sT + 2 * (size_t)m * sT) + nrb * ND * 16 +
-                          (size_t)ND * 16 + 3 * (size_t)kMaxRestart * 16 + 64;
+  size_t per_slot = n * (2 * 16 + 4 * sT + 2 * (size_t)m * sT) + nrb * ND * 16 +
+                    (size_t)ND * 16 + 3 * (size_t)kMaxRestart * 16 + 64;
+  if (h->opt.precond == SLRF_PC_AMG && h->amg.ready) per_slot += amg_vec_bytes(h->amg, 1, sT);
   int C = Spad;
   if (h->opt.max_slots > 0) C = std::min(C, h->opt.max_slots);
   if (fixed + (size_t)C * per_slot > h->budget) {
@@ -275,7 +493,12 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
   const auto t0 = std::chrono::steady_clock::now();
   const int n = h->P.n, N = h->N, S = N * nc, m = h->opt.restart;
   const size_t sT = 2 * sizeof(T);
-  const bool pc = h->opt.precond == SLRF_PC_JACOBI;
+  const bool amg = h->opt.precond == SLRF_PC_AMG;
+  const int pc = amg ? 2 : (h->opt.precond == SLRF_PC_JACOBI ? 1 : 0);
+  if (amg) {
+    const slrf_status bs = build_amg(h);
+    if (bs != SLRF_OK) return bs;
+  }
   const bool warm = theta != nullptr;
   const bool mixed = std::is_same<T, float>::value;
   const double inner_rtol = mixed ? h->opt.inner_rtol : 0.0;
@@ -292,6 +515,11 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
   const int Spad = (S + kPanel - 1) / kPanel * kPanel;
   const int nrb = nrb_for(n);
 
+  AmgVecs av;
+  if (amg) {
+    const slrf_status vs = amg_vectors<T>(h, C, av);
+    if (vs != SLRF_OK) return vs;
+  }
   double *Xr, *F, *E = nullptr, *Ur, *fn2;
   double2 *Ys, *Ya, *Yb, *part, *red;
   void *Ra, *Rb, *Za, *Zb, *Q, *Pb;
@@ -507,6 +735,10 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
     for (int k = 0; k < m; ++k) {
       char* Qk = static_cast<char*>(Q) + (size_t)k * vstride * sT;
       char* Pk = static_cast<char*>(Pb) + (size_t)k * vstride * sT;
+      if (amg) {
+        const slrf_status vs = vcycle<T>(h, av, C, occ, ND, tc, R, Z, nact);
+        if (vs != SLRF_OK) return vs;
+      }
       {
         Scope sp(h, SLRF_K_APPLY, (double)nact * n * sT * (k + 2) + csr_bytes);
         HIPCHK(launch_apply_dots<T>(h->P, g, tc, Z, Qk, Q, vstride, k, part, pc, s));
@@ -795,6 +1027,14 @@ slrf_status slrf_setup(slrf_handle* out, const slrf_csr* A, const slrf_csr* B, d
     if (!diag) return bad(SLRF_E_ARG, "every row must store its diagonal entry");
   }
   if (rp != rp2 || cl != cl2) return bad(SLRF_E_ARG, "A and B must share one CSR pattern");
+  // largest CSR slice of an aligned row block (LDS staging plan of the SpMM)
+  auto max_slice = [&](int sub) {
+    int mx = 0;
+    for (int r = 0; r < n; r += sub) mx = std::max(mx, rp[std::min(r + sub, n)] - rp[r]);
+    return mx;
+  };
+  h->P.max_nnz_sub64 = max_slice(64);
+  h->P.max_nnz_sub32 = max_slice(32);
   h->P.n = n;
   h->P.nnz = nnz;
   h->P.rowptr = A->rowptr;
@@ -1072,6 +1312,22 @@ slrf_status slrf_shifted_spmm(slrf_handle h, int32_t nsys, const int32_t* pole, 
   } else {
     HIPCHK(hipStreamSynchronize(s));
   }
+  return SLRF_OK;
+}
+
+slrf_status slrf_eig_grad(slrf_handle h, int32_t k, const double* X, const double* lam,
+                          const double* glam, int32_t nelem, int32_t ndof_e,
+                          const int32_t* elem_dofs, const double* dA, int32_t dA_stride,
+                          const double* dB, int32_t dB_stride, double* grad) {
+  if (!h) return SLRF_E_ARG;
+  if (k < 0 || nelem < 0 || (k > 0 && (!X || !lam || !glam)) || (nelem > 0 && (!elem_dofs || !dA || !grad)))
+    return fail(h, SLRF_E_ARG, "bad eig_grad arguments");
+  if (ndof_e != 4 && ndof_e != 8 && ndof_e != 24)
+    return fail(h, SLRF_E_ARG, "ndof_e must be 4, 8 or 24");
+  if (dA_stride < 0 || dB_stride < 0) return fail(h, SLRF_E_ARG, "negative stride");
+  HIPCHK(launch_eig_grad(h->P.n, k, X, lam, glam, nelem, ndof_e, elem_dofs, dA, dA_stride, dB,
+                         dB_stride, grad, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
   return SLRF_OK;
 }
 

@@ -20,7 +20,8 @@ SLRF_PREC_FP64 = 0
 SLRF_PREC_MIXED = 1
 SLRF_PC_NONE = 0
 SLRF_PC_JACOBI = 1
-KERNEL_CLASSES = ("apply", "orth", "step", "resid", "reduce", "other")
+SLRF_PC_AMG = 2
+KERNEL_CLASSES = ("apply", "orth", "step", "resid", "reduce", "other", "precond")
 _STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP runtime error",
            4: "breakdown", 5: "iteration cap reached", 6: "NaN/Inf detected", 7: "no usable GPU"}
 
@@ -53,7 +54,7 @@ class FilterStats(C.Structure):
                 ("max_iters", C.c_int32), ("cycles", C.c_int32), ("converged", C.c_int32),
                 ("capped", C.c_int32), ("max_pole_iters_ratio_x1000", C.c_int32),
                 ("max_rel_resid", C.c_double), ("seconds", C.c_double),
-                ("launches", C.c_int64 * 6), ("bytes", C.c_double * 6), ("ms", C.c_double * 6),
+                ("launches", C.c_int64 * 7), ("bytes", C.c_double * 7), ("ms", C.c_double * 7),
                 ("sys_iters", C.POINTER(C.c_int32))]
 
 
@@ -84,6 +85,9 @@ SIGNATURES = {
     "slrf_shifted_spmm": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_int32,
                                     C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "slrf_get_n": (C.c_int32, [C.c_void_p]),
+    "slrf_eig_grad": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
+                                C.c_void_p, C.c_int32, C.c_void_p]),
     "slrf_host_projected_eig": (C.c_int32, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                             C.c_void_p]),
 }
@@ -289,6 +293,28 @@ class Handle:
         stats["status"] = r
         return theta[:nconv.value], X[:, :nconv.value], nconv.value, stats
 
+    # --- slrf_eig_grad -------------------------------------------------------
+    def slrf_eig_grad(self, X, lam, glam, elem_dofs, dA, dB=None, dA_stride=0, dB_stride=0):
+        """grad_e = sum_i glam_i x_{i,e}^T (dA_e - lam_i dB_e) x_{i,e} (device tensor)."""
+        torch = _torch()
+        X = _colmajor(X, self.n)
+        k = X.shape[1]
+        dev = X.device
+        lam = torch.as_tensor(lam, dtype=torch.float64, device=dev).contiguous()
+        glam = torch.as_tensor(glam, dtype=torch.float64, device=dev).contiguous()
+        dofs = torch.as_tensor(np.asarray(elem_dofs, dtype=np.int32) if not torch.is_tensor(elem_dofs)
+                               else elem_dofs, device=dev).to(torch.int32).contiguous()
+        nelem, nd = dofs.shape
+        dA = torch.as_tensor(dA, dtype=torch.float64, device=dev).contiguous()
+        dBt = None if dB is None else torch.as_tensor(dB, dtype=torch.float64, device=dev).contiguous()
+        grad = torch.empty(nelem, dtype=torch.float64, device=dev)
+        self._check(self._L.slrf_eig_grad(self._h, k, X.data_ptr(), lam.data_ptr(),
+                                          glam.data_ptr(), nelem, nd, dofs.data_ptr(),
+                                          dA.data_ptr(), dA_stride,
+                                          dBt.data_ptr() if dBt is not None else None, dB_stride,
+                                          grad.data_ptr()))
+        return grad
+
     # --- slrf_shifted_spmm ---------------------------------------------------
     def slrf_shifted_spmm(self, Z, pole_idx, precision: int = SLRF_PREC_FP64, timed=False):
         """Q = (A - sigma_{pole[s]} B) Z on a panel-layout block (see include/slrf.h)."""
@@ -306,6 +332,56 @@ class Handle:
                                               precision, Z.data_ptr(), Q.data_ptr(),
                                               C.byref(ms) if timed else None))
         return (Q, ms.value) if timed else Q
+
+
+class EigFn:
+    """torch.autograd.Function: eigenvalues in (0, gamma] of a parameterised pencil.
+
+    ``forward(theta, problem)`` assembles A(theta), B(theta) on the host through
+    ``problem.assemble(theta_numpy) -> slrf_inputs.Pencil`` (with element data),
+    solves with ``slrf_solve`` on the GPU and returns the NEV eigenvalues;
+    ``backward`` returns dL/dtheta through the adjoint kernel ``slrf_eig_grad``:
+    dL/dtheta_e = sum_i g_i x_i^T (dA/dtheta_e - lambda_i dB/dtheta_e) x_i.
+    ``problem`` also provides gamma, nev, V1 (host n x L), poles, weights,
+    options and, for the element derivatives, ``dA``/``dB`` (ndof x ndof
+    reference matrices; dB may be None) so that dA/dtheta_e = dA on element e.
+    """
+
+    @staticmethod
+    def _impl():
+        torch = _torch()
+
+        class _Fn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, theta, problem):
+                p = problem.assemble(theta.detach().cpu().numpy())
+                h = Handle.from_pencil(p, problem.gamma, problem.poles, problem.weights,
+                                       problem.options, device=str(theta.device)
+                                       if theta.is_cuda else "cuda")
+                V1 = torch.as_tensor(np.ascontiguousarray(np.asarray(problem.V1).T),
+                                     device=h.device).t()
+                lam, X, nconv, _ = h.slrf_solve(problem.nev, V1)
+                if nconv != problem.nev:
+                    raise SlrfError(5, f"only {nconv} of {problem.nev} eigenpairs converged")
+                ctx.h = h
+                ctx.dofs = p.elem_dofs
+                ctx.problem = problem
+                ctx.save_for_backward(lam, X)
+                return lam.to(theta.device)
+
+            @staticmethod
+            def backward(ctx, glam):
+                lam, X = ctx.saved_tensors
+                g = ctx.h.slrf_eig_grad(X, lam, glam.to(lam.device, torch.float64), ctx.dofs,
+                                        ctx.problem.dA, getattr(ctx.problem, "dB", None))
+                ctx.h.close()
+                return g, None
+
+        return _Fn
+
+    @classmethod
+    def apply(cls, theta, problem):
+        return cls._impl().apply(theta, problem)
 
 
 def to_panels(Y, n: int):

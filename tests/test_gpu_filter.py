@@ -102,8 +102,9 @@ def _single_pole_solution(p, gamma, sigma, X, **opt):
     return outs[0] + 1j * outs[1], st
 
 
+@pytest.mark.parametrize("pcnd", [P.SLRF_PC_JACOBI, P.SLRF_PC_AMG])
 @pytest.mark.parametrize("prec", [P.SLRF_PREC_FP64, P.SLRF_PREC_MIXED])
-def test_single_pole_solves_meet_tolerance(cfg1, prec):
+def test_single_pole_solves_meet_tolerance(cfg1, prec, pcnd):
     p = cfg1["pencil"]
     A, B = p.A(), p.B()
     X = cfg1["V1"][:, :12]
@@ -111,7 +112,8 @@ def test_single_pole_solves_meet_tolerance(cfg1, prec):
     tol = 1e-10
     for j in (0, 3, 7):
         sigma = cfg1["poles"][j]
-        Y, st = _single_pole_solution(p, cfg1["gamma"], sigma, X, precision=prec, tol_lin=tol)
+        Y, st = _single_pole_solution(p, cfg1["gamma"], sigma, X, precision=prec, tol_lin=tol,
+                                      precond=pcnd)
         M = (A - sigma * B).tocsr()
         rel = np.linalg.norm(F - M @ Y, axis=0) / np.linalg.norm(F, axis=0)
         assert rel.max() <= 1.01 * tol, (j, rel.max())
@@ -121,11 +123,13 @@ def test_single_pole_solves_meet_tolerance(cfg1, prec):
         assert np.linalg.norm(Y + err - Ylu) <= 1e-9 * np.linalg.norm(Ylu)
 
 
+@pytest.mark.parametrize("pcnd", [P.SLRF_PC_JACOBI, P.SLRF_PC_AMG])
 @pytest.mark.parametrize("prec", [P.SLRF_PREC_FP64, P.SLRF_PREC_MIXED])
-def test_filter_matches_exact_lu_oracle(cfg1, prec):
+def test_filter_matches_exact_lu_oracle(cfg1, prec, pcnd):
     p = cfg1["pencil"]
     tol = 1e-10
-    h = _handle(p, cfg1["gamma"], cfg1["poles"], cfg1["weights"], precision=prec, tol_lin=tol)
+    h = _handle(p, cfg1["gamma"], cfg1["poles"], cfg1["weights"], precision=prec, tol_lin=tol,
+                precond=pcnd)
     X = cfg1["V1"]
     U, st = h.slrf_filter(_dev(X))
     Uo = oracle.filter.apply_filter(p.A(), p.B(), cfg1["poles"], cfg1["weights"], X)
@@ -187,8 +191,9 @@ def test_filter_sine_eigenvectors_full_3d_size():
     lam = np.array([lam1[a - 1] + lam1[b - 1] + lam1[cc - 1] for a, b, cc in ks])
     phi = np.sum(2 * np.real(weights[None, :] / (lam[:, None] - poles[None, :])), axis=1)
     tol = 1e-10
-    for prec in (P.SLRF_PREC_MIXED, P.SLRF_PREC_FP64):
-        h = _handle(p, c["gamma"], poles, weights, precision=prec, tol_lin=tol)
+    for prec, pcnd in ((P.SLRF_PREC_MIXED, P.SLRF_PC_JACOBI), (P.SLRF_PREC_FP64, P.SLRF_PC_JACOBI),
+                       (P.SLRF_PREC_MIXED, P.SLRF_PC_AMG)):
+        h = _handle(p, c["gamma"], poles, weights, precision=prec, tol_lin=tol, precond=pcnd)
         U, st = h.slrf_filter(_dev(X))
         err = np.linalg.norm(_host(U) - X * phi[None, :], axis=0)
         bound = _filter_bound(p.B() @ X, poles, weights, tol, _q1_lambda_min_B(m, 3))
@@ -282,10 +287,14 @@ def _closed_q1_2d(m, k):
     return np.sort((l1[:, None] + l1[None, :]).ravel())[:k]
 
 
-@pytest.mark.parametrize("mode", ["alg1_fp64", "alg2_fp64", "alg1_mixed", "alg2_mixed"])
+@pytest.mark.parametrize("mode", ["alg1_fp64", "alg2_fp64", "alg1_mixed", "alg2_mixed",
+                                  "alg1_mixed_amg", "alg2_fp64_amg"])
 def test_solve_config_q1_2d_closed_form(cfg1, mode):
     p = cfg1["pencil"]
     opt = dict(tol_lin=1e-10)
+    if mode.endswith("_amg"):
+        opt.update(precond=P.SLRF_PC_AMG)
+        mode = mode[:-4]
     if mode.startswith("alg2"):
         opt.update(lock=1, warm_start=1, it_max_lin=13)
     if mode.endswith("mixed"):
@@ -302,13 +311,14 @@ def test_solve_config_q1_2d_closed_form(cfg1, mode):
     h.close()
 
 
-def test_solve_3d_diffusion_vs_dense_lapack():
+@pytest.mark.parametrize("pcnd", [P.SLRF_PC_JACOBI, P.SLRF_PC_AMG])
+def test_solve_3d_diffusion_vs_dense_lapack(pcnd):
     p = si.q1_diffusion_pencil(8, 3, np.exp(np.random.default_rng(4).normal(0, .5, 9 ** 3)))
     lam, _ = oracle.eig.dense_eigs(p.A(), p.B())
     nev = 12
     gamma = 0.5 * (lam[nev - 1] + lam[nev])
     poles, weights = si.slrf_poles(gamma)
-    h = _handle(p, gamma, poles, weights, lock=1, warm_start=1)
+    h = _handle(p, gamma, poles, weights, lock=1, warm_start=1, precond=pcnd)
     th, X, nconv, st = h.slrf_solve(nev, _dev(si.start_block(p.n, 18, 9)))
     assert nconv == nev
     assert np.max(np.abs(_host(th) - lam[:nev]) / lam[:nev]) <= 1e-10
@@ -332,3 +342,21 @@ def test_setup_rejects_malformed_input():
     with pytest.raises(P.SlrfError) as e:
         P.Handle(p.indptr, p.indices, p.a, p.b, -1.0, poles, weights)
     assert e.value.status == 1
+
+
+@pytest.mark.parametrize("prec", [P.SLRF_PREC_FP64, P.SLRF_PREC_MIXED])
+def test_amg_elasticity_single_pole_residuals(prec):
+    """AMG on a 3-dof elasticity pencil (aggregation of coupled dofs): every solve certified."""
+    p = si.hex_elasticity_pencil(6, np.exp(np.random.default_rng(8).normal(0, .5, 216)))
+    A, B = p.A(), p.B()
+    lam = oracle.eig.dense_eigs(A, B)[0]
+    gamma = 0.5 * (lam[9] + lam[10])
+    poles, _ = si.slrf_poles(gamma)
+    X = si.start_block(p.n, 5, 21)
+    F = B @ X
+    for j in (0, 7):
+        Y, st = _single_pole_solution(p, gamma, poles[j], X, precision=prec, tol_lin=1e-10,
+                                      precond=P.SLRF_PC_AMG)
+        M = (A - poles[j] * B).tocsr()
+        rel = np.linalg.norm(F - M @ Y, axis=0) / np.linalg.norm(F, axis=0)
+        assert rel.max() <= 1.01e-10 and st["converged"] == 5

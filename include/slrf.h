@@ -97,6 +97,16 @@ typedef struct {
   int32_t lock;        /* slrf_solve: locking + B-orthogonalisation (Alg. 2)    */
   int32_t timing;      /* record per-kernel HIP event timings into the stats    */
   int32_t max_slots;   /* systems resident at once (multiple of 16); 0 = auto   */
+  int32_t spmm_variant;/* shifted SpMM kernel: 0 = autotuned at setup (every
+                          variant timed on the pencil, fastest kept per
+                          precision, cached per shape class), 1 = row-group
+                          union format, 2 / 4 / 5 = CSR staged in LDS with
+                          8 / 16 / 32 gathers in flight per lane, 3 = CSR
+                          read directly                                       */
+  int32_t reorder;     /* 1 (default): the library keeps a copy of the pencil
+                          in a locality row order (nested aggregation of the
+                          graph of A) so stencil gathers stay cache-resident;
+                          inputs/outputs keep the caller's order.  0: off.    */
   double tol_lin;      /* relative residual target of each shifted solve        */
   double inner_rtol;   /* MIXED: a Krylov cycle stops once its residual fell by
                           this factor (then the FP64 residual is recomputed)    */
@@ -132,6 +142,8 @@ typedef struct {
   int64_t launches[SLRF_K_COUNT];
   double bytes[SLRF_K_COUNT]; /* algorithmic HBM bytes                             */
   double ms[SLRF_K_COUNT];    /* summed kernel time (only with options.timing)     */
+  int32_t spmm_variant;  /* SpMM kernel used for the Krylov sweeps (1 row-group,
+                            2 CSR-LDS, 3 CSR direct; 0 = row-group if present) */
   int32_t* sys_iters;    /* optional, caller-owned host int32[N*ncols]: iterations
                             of system (column c, pole j) at index c*N + j          */
 } slrf_filter_stats;
@@ -213,8 +225,9 @@ slrf_status slrf_solve(slrf_handle h, int32_t nev, int32_t L, const double* V1, 
 /*
  * slrf_shifted_spmm - one sweep of the shifted operator over a batch of
  * complex block vectors, Q_s = (A - sigma_{pole[s]} B) Z_s (Eq. (2) operator).
- * Z, Q: device, "panel layout": systems in panels of 16; element (row i,
- * system s) at complex index ((s / 16) * n + i) * 16 + s % 16, interleaved
+ * Z, Q: device, "panel layout": systems in panels of 16; element (row i of the
+ * internal row order, see slrf_get_row_order, system s) at complex index
+ * ((s / 16) * n + i) * 16 + s % 16, interleaved
  * (re, im); nsys is rounded up to a multiple of 16 and padding systems must
  * be allocated.  precision SLRF_PREC_FP64: complex double; SLRF_PREC_MIXED:
  * complex float (with FP32 copies of A and B).  pole: host int32[nsys],
@@ -246,6 +259,13 @@ slrf_status slrf_eig_grad(slrf_handle h, int32_t k, const double* X, const doubl
 
 /* Problem size of a handle (-1 for NULL). */
 int32_t slrf_get_n(slrf_handle h);
+
+/*
+ * slrf_get_row_order - the library's internal row order: order[new] = old
+ * (host int32[n]).  Identity unless options.reorder was set at setup.  Only
+ * slrf_shifted_spmm exposes internal-order vectors.
+ */
+slrf_status slrf_get_row_order(slrf_handle h, int32_t* order);
 
 /*
  * slrf_host_projected_eig - host-only solve of the small projected problem

@@ -195,6 +195,59 @@ bool invert_dense(int n, std::vector<std::complex<double>>& M) {
 
 }  // namespace
 
+void locality_order(const HostLevel& fine, std::vector<int>& order) {
+  // Nested aggregation of the matrix graph: rows are sorted by their
+  // ancestor at every aggregation level (coarsest first), so rows of one
+  // aggregate are contiguous and aggregates of one parent are contiguous.
+  const int n = fine.n;
+  std::vector<std::vector<int>> anc;  // anc[l][i]: level-(l+1) ancestor of fine row i
+  HostLevel cur;
+  cur.n = n;
+  cur.rp = fine.rp;
+  cur.ci = fine.ci;
+  cur.a = fine.a;
+  std::vector<int> up(n);
+  for (int i = 0; i < n; ++i) up[i] = i;
+  while (cur.n > 64 && anc.size() < 12) {
+    std::vector<int> agg;
+    const int na = aggregate(cur, 0.0, agg);
+    if (na >= cur.n || na == 0) break;
+    for (int i = 0; i < n; ++i) up[i] = agg[up[i]];
+    anc.push_back(up);
+    // graph of the aggregates (values: magnitudes summed, diagonal kept)
+    std::vector<std::vector<std::pair<int, double>>> rows(na);
+    for (int i = 0; i < cur.n; ++i)
+      for (int e = cur.rp[i]; e < cur.rp[i + 1]; ++e)
+        rows[agg[i]].push_back({agg[cur.ci[e]], std::fabs(cur.a[e])});
+    HostLevel nxt;
+    nxt.n = na;
+    nxt.rp.assign(na + 1, 0);
+    for (int c = 0; c < na; ++c) {
+      auto& r = rows[c];
+      std::sort(r.begin(), r.end());
+      int last = -1;
+      for (auto& pr : r) {
+        if (pr.first == last) {
+          nxt.a.back() += pr.second;
+        } else {
+          nxt.ci.push_back(pr.first);
+          nxt.a.push_back(pr.second);
+          last = pr.first;
+        }
+      }
+      nxt.rp[c + 1] = (int)nxt.ci.size();
+    }
+    cur = std::move(nxt);
+  }
+  order.resize(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    for (int l = (int)anc.size() - 1; l >= 0; --l)
+      if (anc[l][x] != anc[l][y]) return anc[l][x] < anc[l][y];
+    return x < y;
+  });
+}
+
 bool amg_build(const HostLevel& fine, const std::vector<std::complex<double>>& poles,
                const AmgParams& prm, AmgHierarchy& H, std::string& err) {
   H.levels.clear();

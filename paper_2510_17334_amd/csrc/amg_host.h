@@ -36,6 +36,9 @@ struct AmgHierarchy {
   std::vector<std::complex<double>> coarse_inv;  // [pole][nc][nc] row-major
 };
 
+// Locality ordering of the rows (order[new] = old) from nested aggregation.
+void locality_order(const HostLevel& fine, std::vector<int>& order);
+
 bool amg_build(const HostLevel& fine, const std::vector<std::complex<double>>& poles,
                const AmgParams& prm, AmgHierarchy& H, std::string& err);
 

@@ -35,7 +35,24 @@ struct DevPencil {
   const double* db = nullptr;
   int max_nnz_sub64 = 0;      // max nonzeros in an aligned block of 64 / 32 rows
   int max_nnz_sub32 = 0;      // (LDS staging plan of the shifted SpMM; 0 = unknown)
+  // Row-group ("union") format: groups of 4 consecutive rows, the union of
+  // their columns once per group and 4 coefficients of A and of B per union
+  // entry ([entry][4]); optional (gptr == nullptr: CSR kernels only).
+  const int* gptr = nullptr;  // [ngroups + 1]
+  const int* gcol = nullptr;  // [nunion]
+  const double* gca = nullptr;
+  const double* gcb = nullptr;
+  const float* gca32 = nullptr;
+  const float* gcb32 = nullptr;
+  int grp_lds_ent = 0;        // max union entries of 8 consecutive groups
+  // SpMM kernel choice per sweep precision (kSpmm*; chosen by the autotuner)
+  int var32 = 0, var64 = 0;
 };
+// SpMM variants: 0 = row-group format if present, else CSR staged in LDS;
+// 1 = row-group format; 2, 4, 5 = CSR staged in LDS with 8, 16, 32 gathers in
+// flight per lane; 3 = CSR read directly
+constexpr int kSpmmAuto = 0, kSpmmGroup = 1, kSpmmCsrLds = 2, kSpmmCsrDirect = 3,
+              kSpmmCsrLds16 = 4, kSpmmCsrLds32 = 5;
 
 // A rectangular real CSR matrix on the device (AMG prolongation / restriction).
 struct DevTransfer {
@@ -150,8 +167,10 @@ hipError_t launch_fin_true(const double2* red, int nslots, const SlotTables& st,
 // ----- real dense / sparse kernels for Rayleigh-Ritz (row-major blocks) -----
 hipError_t launch_spmm_real(const DevPencil& P, const double* X, int ld, int nc, double* AX,
                             double* BX, const double* theta, double* E, hipStream_t s);
+// out[c * ldout + omap(r)] = in[r * ldin + imap(c)]; maps optional (NULL = identity)
 hipError_t launch_transpose(const double* in, int rows, int cols, int ldin, double* out,
-                            int ldout, hipStream_t s);
+                            int ldout, hipStream_t s, const int* imap = nullptr,
+                            const int* omap = nullptr);
 // G (p x q, row-major, ldg) = X^T Y; X: n x p (ldx), Y: n x q (ldy); part: scratch
 hipError_t launch_gram(int n, int p, int q, const double* X, int ldx, const double* Y, int ldy,
                        double* part, int nchunk, double* G, int ldg, hipStream_t s);

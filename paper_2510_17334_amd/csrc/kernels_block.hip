@@ -287,7 +287,7 @@ __device__ __forceinline__ void lane_fma(T* acc, T a, T b, const typename LaneVe
 //   kEpiJacobi: out = x + omega D^-1 (b - M x) (AMG damped-Jacobi sweep, D = diag M)
 constexpr int kEpiApply = 0, kEpiResid = 1, kEpiJacobi = 2;
 
-template <typename T, bool DOTS, int G, int EPI = kEpiApply>
+template <typename T, bool DOTS, int G, int EPI = kEpiApply, int UNR = 8>
 __global__ __launch_bounds__(kThreads) void k_apply_lds(
     int n, const int* __restrict__ rowptr, const int* __restrict__ col, const T* __restrict__ av,
     const T* __restrict__ bv, PanelGrid g, int sub, int lds_nnz, const int* __restrict__ active,
@@ -368,15 +368,23 @@ __global__ __launch_bounds__(kThreads) void k_apply_lds(
           T acc[4 * SPL];
 #pragma unroll
           for (int v = 0; v < 4 * SPL; ++v) acc[v] = 0;
-          int e = e0;
-          for (; e + 3 < e1; e += 4) {
-            V z[4];
+          // batches of UNR gathers in flight; the last batch is predicated, so a
+          // row costs ceil(nnz / UNR) memory round trips
+          for (int e = e0; e < e1; e += UNR) {
+            V z[UNR];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) z[u] = Zp[s_col[e + u] * LPR + lr];
+            for (int u = 0; u < UNR; ++u) {
+              if (e + u < e1)
+                z[u] = Zp[s_col[e + u] * LPR + lr];
+              else
+                z[u] = V{};
+            }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) lane_fma<T, SPL>(acc, s_a[e + u], s_b[e + u], z[u]);
+            for (int u = 0; u < UNR; ++u) {
+              const bool ok = e + u < e1;
+              lane_fma<T, SPL>(acc, ok ? s_a[e + u] : T(0), ok ? s_b[e + u] : T(0), z[u]);
+            }
           }
-          for (; e < e1; ++e) lane_fma<T, SPL>(acc, s_a[e], s_b[e], Zp[s_col[e] * LPR + lr]);
           V q;
           q.x = acc[0] - (sr[0] * acc[2] - si[0] * acc[3]);
           q.y = acc[1] - (sr[0] * acc[3] + si[0] * acc[2]);
@@ -476,6 +484,198 @@ __global__ __launch_bounds__(kThreads) void k_apply_lds(
       }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Row-group ("union") shifted SpMM.  Rows are taken in groups of R = 4
+// consecutive rows; a group stores the union of its rows' columns once and,
+// per union entry, the R coefficients of A and of B (zero where a row has no
+// entry).  One 16-byte lane-vector gather of z then feeds all R rows of the
+// group, so the number of gathers per row drops from nnz/row to the union
+// size / R (about 2x fewer for 27-point stencils).  A workgroup stages the
+// group data of 8 groups (32 rows) in LDS and its waves serve four panels at
+// once (two per pass for complex double).
+// ---------------------------------------------------------------------------
+constexpr int kGrpR = 4;     // rows per group
+constexpr int kGrpSub = 8;   // groups per staged sub-block (32 rows)
+
+template <typename T, int EPI>
+__global__ __launch_bounds__(kThreads) void k_spmm_grp(
+    int n, const int* __restrict__ gptr, const int* __restrict__ gcol, const T* __restrict__ gca,
+    const T* __restrict__ gcb, const double* __restrict__ da, const double* __restrict__ db,
+    double omega, PanelGrid g, int lds_ent, const int* __restrict__ active,
+    const double2* __restrict__ sigma, const typename CT<T>::t* __restrict__ Z,
+    const typename CT<T>::t* __restrict__ Bin, typename CT<T>::t* __restrict__ Out) {
+  using V = typename LaneVec<T>::V;
+  constexpr int SPL = LaneVec<T>::SPL;
+  constexpr int LPR = kPanel / SPL;                    // lanes per panel row
+  constexpr int PPP = kThreads / (LPR * kGrpSub);      // panels per pass (4 or 2)
+  constexpr int NPASS = 4 / PPP;                       // passes for 4 panels
+  constexpr int R = kGrpR;
+  extern __shared__ double smem_d[];
+  T* s_a = reinterpret_cast<T*>(smem_d);               // [lds_ent][R]
+  T* s_b = s_a + (size_t)lds_ent * R;
+  int* s_col = reinterpret_cast<int*>(s_b + (size_t)lds_ent * R);
+  int* s_gp = s_col + lds_ent;                          // [kGrpSub + 1]
+  __shared__ int s_any[4];
+  const int ncg = (g.npan + 3) / 4;
+  int rb, cg;
+  if (!map_tile(g.nrb, ncg, g.group, rb, cg)) return;
+  const int tid = threadIdx.x;
+  const int lr = tid % LPR, gi = (tid / LPR) % kGrpSub, pw = tid / (LPR * kGrpSub);
+  const int pan0 = cg * 4;
+  if (tid < 4) {
+    const int p = pan0 + tid;
+    int any = 0;
+    if (p < g.npan)
+      for (int l = 0; l < kPanel; ++l) any |= active == nullptr ? 1 : (active[p * kPanel + l] != 0);
+    s_any[tid] = any;
+  }
+  const int R0 = rb * g.rpb, R1 = min(R0 + g.rpb, n);
+  const int ngrp_total = (n + R - 1) / R;
+  for (int s0 = R0; s0 < R1; s0 += R * kGrpSub) {
+    const int g0 = s0 / R;
+    const int g1 = min(g0 + kGrpSub, ngrp_total);
+    const int eb = gptr[g0];
+    const int ne = gptr[g1] - eb;
+    __syncthreads();  // previous sub-block done with LDS (and s_any visible)
+    for (int t = tid; t <= g1 - g0; t += kThreads) s_gp[t] = gptr[g0 + t] - eb;
+    for (int t = tid; t < ne; t += kThreads) s_col[t] = gcol[eb + t];
+    for (int t = tid; t < ne * R; t += kThreads) {
+      s_a[t] = gca[(size_t)eb * R + t];
+      s_b[t] = gcb[(size_t)eb * R + t];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int pass = 0; pass < NPASS; ++pass) {
+      const int pl = pass * PPP + pw;  // panel of the group handled by this wave set
+      const int pan = pan0 + pl;
+      if (!s_any[pl] || g0 + gi >= g1) continue;
+      const size_t pbase = (size_t)pan * n * kPanel;
+      const V* __restrict__ Zp = reinterpret_cast<const V*>(Z + pbase);
+      T acc[R][4 * SPL];
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int v = 0; v < 4 * SPL; ++v) acc[r][v] = 0;
+      const int e0 = s_gp[gi], e1 = s_gp[gi + 1];
+      int e = e0;
+      for (; e + 3 < e1; e += 4) {
+        V z[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) z[u] = Zp[s_col[e + u] * LPR + lr];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            lane_fma<T, SPL>(acc[r], s_a[(e + u) * R + r], s_b[(e + u) * R + r], z[u]);
+      }
+      for (; e < e1; ++e) {
+        const V zz = Zp[s_col[e] * LPR + lr];
+#pragma unroll
+        for (int r = 0; r < R; ++r) lane_fma<T, SPL>(acc[r], s_a[e * R + r], s_b[e * R + r], zz);
+      }
+      T sr[SPL], si[SPL];
+#pragma unroll
+      for (int u = 0; u < SPL; ++u) {
+        const double2 sgm = sigma[pan * kPanel + lr * SPL + u];
+        sr[u] = (T)sgm.x;
+        si[u] = (T)sgm.y;
+      }
+      V* __restrict__ Op = reinterpret_cast<V*>(Out + pbase);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int row = (g0 + gi) * R + r;
+        if (row >= n) break;
+        V q;
+        q.x = acc[r][0] - (sr[0] * acc[r][2] - si[0] * acc[r][3]);
+        q.y = acc[r][1] - (sr[0] * acc[r][3] + si[0] * acc[r][2]);
+        if constexpr (SPL == 2) {
+          q.z = acc[r][4] - (sr[1] * acc[r][6] - si[1] * acc[r][7]);
+          q.w = acc[r][5] - (sr[1] * acc[r][7] + si[1] * acc[r][6]);
+        }
+        if constexpr (EPI != kEpiApply) {
+          const V bb = reinterpret_cast<const V*>(Bin + pbase)[row * LPR + lr];
+          V rres;
+          rres.x = bb.x - q.x;
+          rres.y = bb.y - q.y;
+          if constexpr (SPL == 2) {
+            rres.z = bb.z - q.z;
+            rres.w = bb.w - q.w;
+          }
+          if constexpr (EPI == kEpiResid) {
+            q = rres;
+          } else {
+            const V xo = Zp[row * LPR + lr];
+            const double dav = da[row], dbv = db[row];
+#pragma unroll
+            for (int u = 0; u < SPL; ++u) {
+              const double dx = dav - (double)sr[u] * dbv, dy = -(double)si[u] * dbv;
+              const double iv = omega / (dx * dx + dy * dy);
+              const double ix = dx * iv, iy = -dy * iv;
+              const double rx = u == 0 ? rres.x : lv_z(rres), ry = u == 0 ? rres.y : lv_w(rres);
+              const double ox = u == 0 ? xo.x : lv_z(xo), oy = u == 0 ? xo.y : lv_w(xo);
+              const T nx = (T)(ox + rx * ix - ry * iy), ny = (T)(oy + rx * iy + ry * ix);
+              if (u == 0) {
+                q.x = nx;
+                q.y = ny;
+              } else {
+                lv_set_zw(q, nx, ny);
+              }
+            }
+          }
+        }
+        Op[row * LPR + lr] = q;
+      }
+    }
+  }
+}
+
+// CGS projections h_i = <q_i, q_k>, i < k, from the stored directions and the
+// fresh q_k (a streaming pass over k + 1 vectors): thread (row subgroup, slot)
+// keeps the k partial sums in registers, then the 16 row subgroups are combined
+// in a fixed order (shuffles + LDS), one partial per (row block, i, slot).
+template <typename T, int MAXK>
+__global__ __launch_bounds__(kThreads) void k_dots(int n, PanelGrid g,
+                                                   const int* __restrict__ active,
+                                                   const typename CT<T>::t* __restrict__ Qk,
+                                                   const typename CT<T>::t* __restrict__ Qb,
+                                                   size_t vstride, int k,
+                                                   double2* __restrict__ part) {
+  using C = typename CT<T>::t;
+  constexpr int NV = 2 * MAXK;
+  __shared__ double red[4 * NV * 16];
+  int rb, pan;
+  if (!map_block(g, rb, pan)) return;
+  const int lane = threadIdx.x & 15, rs = threadIdx.x >> 4;
+  const int slot = pan * kPanel + lane;
+  const bool act = active == nullptr || active[slot] != 0;
+  if (!__syncthreads_or(act)) return;
+  const size_t pbase = (size_t)pan * n * kPanel;
+  double h[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) h[v] = 0.0;
+  const int r0 = rb * g.rpb, r1 = min(r0 + g.rpb, n);
+  if (act) {
+    for (int row = r0 + rs; row < r1; row += 16) {
+      const size_t off = pbase + (size_t)row * kPanel + lane;
+      const C q = Qk[off];
+      const double qx = q.x, qy = q.y;
+#pragma unroll
+      for (int i = 0; i < MAXK; ++i) {
+        if (i < k) {
+          const C v = Qb[(size_t)i * vstride + off];
+          h[2 * i] += (double)v.x * qx + (double)v.y * qy;
+          h[2 * i + 1] += (double)v.x * qy - (double)v.y * qx;
+        }
+      }
+    }
+  }
+  reduce16<NV>(h, 2 * k, red, [&](int v, int ln, double sv) {
+    double* dst = reinterpret_cast<double*>(part + ((size_t)rb * g.ND + (v >> 1)) * g.C +
+                                            pan * kPanel + ln);
+    dst[v & 1] = sv;
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -978,6 +1178,49 @@ __global__ __launch_bounds__(kThreads) void k_lvl_jacobi0(
   }
 }
 
+// grid transfer with long rows (restriction P^T): a workgroup handles 4 rows;
+// for each row the 16 row subgroups take every 16th entry and the partial sums
+// are combined in a fixed order through LDS.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_transfer_split(
+    int nout, int nin, const int* __restrict__ rowptr, const int* __restrict__ col,
+    const T* __restrict__ v, int npan, const int* __restrict__ active,
+    const typename CT<T>::t* __restrict__ In, typename CT<T>::t* __restrict__ Out) {
+  using C = typename CT<T>::t;
+  __shared__ double red[16][kPanel][2];
+  const int lane = threadIdx.x & 15, rs = threadIdx.x >> 4;
+  const long nblk = (long)((nout + 3) / 4) * npan;
+  const long b = blockIdx.x;
+  if (b >= nblk) return;
+  const int pan = (int)(b % npan);
+  const int rq = (int)(b / npan) * 4;
+  const int slot = pan * kPanel + lane;
+  const bool act = active == nullptr || active[slot] != 0;
+  if (!__syncthreads_or(act)) return;
+  const C* __restrict__ Ip = In + (size_t)pan * nin * kPanel;
+  C* __restrict__ Op = Out + (size_t)pan * nout * kPanel;
+  for (int row = rq; row < min(rq + 4, nout); ++row) {
+    double sx = 0.0, sy = 0.0;
+    for (int e = rowptr[row] + rs; e < rowptr[row + 1]; e += 16) {
+      const C z = Ip[col[e] * kPanel + lane];
+      sx += (double)v[e] * z.x;
+      sy += (double)v[e] * z.y;
+    }
+    red[rs][lane][0] = sx;
+    red[rs][lane][1] = sy;
+    __syncthreads();
+    if (rs == 0) {
+      double tx = 0.0, ty = 0.0;
+      for (int r = 0; r < 16; ++r) {
+        tx += red[r][lane][0];
+        ty += red[r][lane][1];
+      }
+      Op[row * kPanel + lane] = mk<C>(tx, ty);
+    }
+    __syncthreads();
+  }
+}
+
 // grid transfer with a real CSR matrix (restriction P^T or prolongation P):
 //   out[i] (+)= sum_e v_e in[col_e]; in has nin rows, out has nout rows.
 template <typename T, bool ADD>
@@ -1075,11 +1318,20 @@ static size_t lds_bytes(int sub, int nnz) {
   return (size_t)nnz * (2 * sizeof(T) + sizeof(int)) + (size_t)(sub + 1) * sizeof(int);
 }
 
+// gathers in flight per lane in the CSR-LDS kernels, from the variant code
+template <typename T>
+static int lds_unroll(const DevPencil& P) {
+  const int var = std::is_same<T, float>::value ? P.var32 : P.var64;
+  return var == kSpmmCsrLds16 ? 16 : (var == kSpmmCsrLds32 ? 32 : 8);
+}
+
 // Staging plan: rows per sub-block (64 or 32) whose largest CSR slice fits in
 // 48 KB of LDS; false when neither does (then the gather reads the CSR from
 // global memory).
 template <typename T>
 static bool lds_plan(const DevPencil& P, int rpb, int& sub, int& cap, size_t& bytes) {
+  const int var = std::is_same<T, float>::value ? P.var32 : P.var64;
+  if (var == kSpmmCsrDirect || var == kSpmmGroup) return false;
   const int cands[2] = {64, 32};
   const int caps[2] = {P.max_nnz_sub64, P.max_nnz_sub32};
   for (int i = 0; i < 2; ++i) {
@@ -1096,6 +1348,68 @@ static bool lds_plan(const DevPencil& P, int rpb, int& sub, int& cap, size_t& by
 }
 
 template <typename T>
+static size_t grp_lds_bytes(int ent) {
+  return (size_t)ent * (2 * kGrpR * sizeof(T) + sizeof(int)) + (kGrpSub + 1) * sizeof(int);
+}
+
+template <typename T>
+static const T* grp_a(const DevPencil& P);
+template <>
+const float* grp_a<float>(const DevPencil& P) {
+  return P.gca32;
+}
+template <>
+const double* grp_a<double>(const DevPencil& P) {
+  return P.gca;
+}
+template <typename T>
+static const T* grp_b(const DevPencil& P);
+template <>
+const float* grp_b<float>(const DevPencil& P) {
+  return P.gcb32;
+}
+template <>
+const double* grp_b<double>(const DevPencil& P) {
+  return P.gcb;
+}
+
+// Row-group SpMM with epilogue; false when the pencil has no row-group format
+// (or it does not fit in LDS) so the caller falls back to the CSR kernels.
+template <typename T>
+static bool launch_grp(const DevPencil& P, const PanelGrid& g, const SlotTables& st, int epi,
+                       double omega, const void* Z, const void* Bin, void* Out, hipStream_t s,
+                       hipError_t& err) {
+  using C = typename CT<T>::t;
+  const int var = std::is_same<T, float>::value ? P.var32 : P.var64;
+  if (var != kSpmmAuto && var != kSpmmGroup) return false;
+  if (P.gptr == nullptr || g.rpb % (kGrpR * kGrpSub) != 0) return false;
+  const size_t bytes = grp_lds_bytes<T>(P.grp_lds_ent);
+  if (bytes > 48 * 1024) return false;
+  PanelGrid gg = g;
+  const int ncg = (g.npan + 3) / 4;
+  gg.group = ncg < 4 ? ncg : 4;
+  const long total = (long)g.nrb * ncg;
+  const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
+  auto Zc = static_cast<const C*>(Z);
+  auto Bc = static_cast<const C*>(Bin);
+  auto Oc = static_cast<C*>(Out);
+  if (epi == kEpiApply)
+    k_spmm_grp<T, kEpiApply><<<blocks, kThreads, bytes, s>>>(
+        P.n, P.gptr, P.gcol, grp_a<T>(P), grp_b<T>(P), P.da, P.db, omega, gg, P.grp_lds_ent,
+        st.active, st.sigma, Zc, Bc, Oc);
+  else if (epi == kEpiResid)
+    k_spmm_grp<T, kEpiResid><<<blocks, kThreads, bytes, s>>>(
+        P.n, P.gptr, P.gcol, grp_a<T>(P), grp_b<T>(P), P.da, P.db, omega, gg, P.grp_lds_ent,
+        st.active, st.sigma, Zc, Bc, Oc);
+  else
+    k_spmm_grp<T, kEpiJacobi><<<blocks, kThreads, bytes, s>>>(
+        P.n, P.gptr, P.gcol, grp_a<T>(P), grp_b<T>(P), P.da, P.db, omega, gg, P.grp_lds_ent,
+        st.active, st.sigma, Zc, Bc, Oc);
+  err = hipGetLastError();
+  return true;
+}
+
+template <typename T>
 hipError_t launch_apply_dots(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
                              const void* Z, void* Qk, const void* Qbase, size_t vstride, int k,
                              double2* part, bool, hipStream_t s) {
@@ -1103,6 +1417,19 @@ hipError_t launch_apply_dots(const DevPencil& P, const PanelGrid& g, const SlotT
   auto Zc = static_cast<const C*>(Z);
   auto Qc = static_cast<C*>(Qk);
   auto Qb = static_cast<const C*>(Qbase);
+  {
+    hipError_t err = hipSuccess;
+    if (launch_grp<T>(P, g, st, kEpiApply, 0.0, Z, nullptr, Qk, s, err)) {
+      if (err != hipSuccess || k == 0) return err;
+      if (k <= 8)
+        k_dots<T, 8><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, Qc, Qb, vstride, k, part);
+      else if (k <= 16)
+        k_dots<T, 16><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, Qc, Qb, vstride, k, part);
+      else
+        k_dots<T, 32><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, Qc, Qb, vstride, k, part);
+      return hipGetLastError();
+    }
+  }
   int sub = 0, cap = 0;
   size_t bytes = 0;
   if (lds_plan<T>(P, g.rpb, sub, cap, bytes)) {
@@ -1111,14 +1438,21 @@ hipError_t launch_apply_dots(const DevPencil& P, const PanelGrid& g, const SlotT
     gg.group = ncg < 4 ? ncg : 4;
     const long total = (long)g.nrb * ncg;
     const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
-    if (k == 0)
-      k_apply_lds<T, false, kGroupPanels><<<blocks, kThreads, bytes, s>>>(
-          P.n, P.rowptr, P.col, vals_a<T>(P), vals_b<T>(P), gg, sub, cap, st.active, st.sigma,
-          Zc, Qc, Qb, vstride, k, part);
-    else
-      k_apply_lds<T, true, kGroupPanels><<<blocks, kThreads, bytes, s>>>(
-          P.n, P.rowptr, P.col, vals_a<T>(P), vals_b<T>(P), gg, sub, cap, st.active, st.sigma,
-          Zc, Qc, Qb, vstride, k, part);
+    const int unr = lds_unroll<T>(P);
+#define SLRF_LDS_APPLY(DOTS, U)                                                             \
+  k_apply_lds<T, DOTS, kGroupPanels, kEpiApply, U><<<blocks, kThreads, bytes, s>>>(          \
+      P.n, P.rowptr, P.col, vals_a<T>(P), vals_b<T>(P), gg, sub, cap, st.active, st.sigma, Zc, \
+      Qc, Qb, vstride, k, part)
+    if (k == 0) {
+      if (unr == 16) SLRF_LDS_APPLY(false, 16);
+      else if (unr == 32) SLRF_LDS_APPLY(false, 32);
+      else SLRF_LDS_APPLY(false, 8);
+    } else {
+      if (unr == 16) SLRF_LDS_APPLY(true, 16);
+      else if (unr == 32) SLRF_LDS_APPLY(true, 32);
+      else SLRF_LDS_APPLY(true, 8);
+    }
+#undef SLRF_LDS_APPLY
     return hipGetLastError();
   }
   const dim3 grid(g.blocks()), block(kThreads);
@@ -1288,6 +1622,10 @@ hipError_t launch_lvl_op(const DevPencil& L, const PanelGrid& g, const SlotTable
   auto Xc = static_cast<const C*>(X);
   auto Bc = static_cast<const C*>(Bin);
   auto Oc = static_cast<C*>(Out);
+  {
+    hipError_t err = hipSuccess;
+    if (launch_grp<T>(L, g, st, epi, omega, X, Bin, Out, s, err)) return err;
+  }
   int sub = 0, cap = 0;
   size_t bytes = 0;
   if (lds_plan<T>(L, g.rpb, sub, cap, bytes)) {
@@ -1296,14 +1634,21 @@ hipError_t launch_lvl_op(const DevPencil& L, const PanelGrid& g, const SlotTable
     gg.group = ncg < 4 ? ncg : 4;
     const long total = (long)g.nrb * ncg;
     const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
-    if (epi == kEpiResid)
-      k_apply_lds<T, false, kGroupPanels, kEpiResid><<<blocks, kThreads, bytes, s>>>(
-          L.n, L.rowptr, L.col, vals_a<T>(L), vals_b<T>(L), gg, sub, cap, st.active, st.sigma, Xc,
-          Oc, nullptr, 0, 0, nullptr, Bc, L.da, L.db, omega);
-    else
-      k_apply_lds<T, false, kGroupPanels, kEpiJacobi><<<blocks, kThreads, bytes, s>>>(
-          L.n, L.rowptr, L.col, vals_a<T>(L), vals_b<T>(L), gg, sub, cap, st.active, st.sigma, Xc,
-          Oc, nullptr, 0, 0, nullptr, Bc, L.da, L.db, omega);
+    const int unr = lds_unroll<T>(L);
+#define SLRF_LDS_LVL(E, U)                                                                   \
+  k_apply_lds<T, false, kGroupPanels, E, U><<<blocks, kThreads, bytes, s>>>(                  \
+      L.n, L.rowptr, L.col, vals_a<T>(L), vals_b<T>(L), gg, sub, cap, st.active, st.sigma, Xc, \
+      Oc, nullptr, 0, 0, nullptr, Bc, L.da, L.db, omega)
+    if (epi == kEpiResid) {
+      if (unr == 16) SLRF_LDS_LVL(kEpiResid, 16);
+      else if (unr == 32) SLRF_LDS_LVL(kEpiResid, 32);
+      else SLRF_LDS_LVL(kEpiResid, 8);
+    } else {
+      if (unr == 16) SLRF_LDS_LVL(kEpiJacobi, 16);
+      else if (unr == 32) SLRF_LDS_LVL(kEpiJacobi, 32);
+      else SLRF_LDS_LVL(kEpiJacobi, 8);
+    }
+#undef SLRF_LDS_LVL
     return hipGetLastError();
   }
   if (epi == kEpiResid)
@@ -1333,6 +1678,14 @@ hipError_t launch_transfer(const DevTransfer& M, const PanelGrid& g, const SlotT
   using C = typename CT<T>::t;
   const T* v = std::is_same<T, float>::value ? reinterpret_cast<const T*>(M.v32)
                                              : reinterpret_cast<const T*>(M.v);
+  if (!add && M.nnz > 32 * M.nrows) {
+    const long nblk = (long)((M.nrows + 3) / 4) * g.npan;
+    k_transfer_split<T><<<(unsigned)nblk, kThreads, 0, s>>>(M.nrows, M.ncols, M.rowptr, M.col, v,
+                                                            g.npan, st.active,
+                                                            static_cast<const C*>(In),
+                                                            static_cast<C*>(Out));
+    return hipGetLastError();
+  }
   if (add)
     k_transfer<T, true><<<g.blocks(), kThreads, 0, s>>>(M.nrows, M.ncols, M.rowptr, M.col, v, g,
                                                         st.active, static_cast<const C*>(In),

@@ -46,21 +46,24 @@ __global__ __launch_bounds__(256) void k_spmm_real(int n, const int* __restrict_
   }
 }
 
-// out[c * ldout + r] = in[r * ldin + c] for r < rows, c < cols (32x32 LDS tiles)
+// out[c * ldout + omap(r)] = in[r * ldin + imap(c)] for r < rows, c < cols
+// (32x32 LDS tiles); imap / omap are optional index maps (NULL = identity), used
+// to apply the library's row order at the column-major <-> row-major boundary.
 __global__ __launch_bounds__(256) void k_transpose(const double* __restrict__ in, int rows,
                                                    int cols, int ldin, double* __restrict__ out,
-                                                   int ldout) {
+                                                   int ldout, const int* __restrict__ imap,
+                                                   const int* __restrict__ omap) {
   __shared__ double tile[32][33];
   const int bx = blockIdx.x * 32, by = blockIdx.y * 32;  // bx over cols, by over rows
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
   for (int j = ty; j < 32; j += 8) {
     const int r = by + j, c = bx + tx;
-    if (r < rows && c < cols) tile[j][tx] = in[(size_t)r * ldin + c];
+    if (r < rows && c < cols) tile[j][tx] = in[(size_t)r * ldin + (imap ? imap[c] : c)];
   }
   __syncthreads();
   for (int j = ty; j < 32; j += 8) {
     const int c = bx + j, r = by + tx;
-    if (r < rows && c < cols) out[(size_t)c * ldout + r] = tile[tx][j];
+    if (r < rows && c < cols) out[(size_t)c * ldout + (omap ? omap[r] : r)] = tile[tx][j];
   }
 }
 
@@ -233,10 +236,10 @@ hipError_t launch_spmm_real(const DevPencil& P, const double* X, int ld, int nc,
 }
 
 hipError_t launch_transpose(const double* in, int rows, int cols, int ldin, double* out,
-                            int ldout, hipStream_t s) {
+                            int ldout, hipStream_t s, const int* imap, const int* omap) {
   if (rows == 0 || cols == 0) return hipSuccess;
   dim3 grid(cdiv(cols, 32), cdiv(rows, 32));
-  k_transpose<<<grid, 256, 0, s>>>(in, rows, cols, ldin, out, ldout);
+  k_transpose<<<grid, 256, 0, s>>>(in, rows, cols, ldin, out, ldout, imap, omap);
   return hipGetLastError();
 }
 

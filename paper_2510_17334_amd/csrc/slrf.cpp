@@ -14,6 +14,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <map>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -93,6 +95,14 @@ struct slrf_ctx {
   double* da = nullptr;
   double* db = nullptr;
   double2* d_w = nullptr;
+  // locality row order (library-owned permuted pencil); order[new] = old
+  int* order = nullptr;
+  std::vector<int> h_order;
+  void* grp_mem[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  int* own_rp = nullptr;
+  int* own_ci = nullptr;
+  double* own_a = nullptr;
+  double* own_b = nullptr;
   // workspace
   std::vector<DevBuf> bufs;
   int* h_flags = nullptr;  // pinned host mirror of per-slot flags
@@ -109,6 +119,13 @@ struct slrf_ctx {
     if (da) (void)hipFree(da);
     if (db) (void)hipFree(db);
     if (d_w) (void)hipFree(d_w);
+    if (order) (void)hipFree(order);
+    for (void* p : grp_mem)
+      if (p) (void)hipFree(p);
+    if (own_rp) (void)hipFree(own_rp);
+    if (own_ci) (void)hipFree(own_ci);
+    if (own_a) (void)hipFree(own_a);
+    if (own_b) (void)hipFree(own_b);
     if (h_flags) (void)hipHostFree(h_flags);
   }
 };
@@ -239,6 +256,8 @@ slrf_status validate_options(slrf_ctx* h, const slrf_options& o) {
   if (o.max_slots < 0 || o.max_slots % kPanel != 0)
     return fail(h, SLRF_E_ARG, "max_slots must be a non-negative multiple of 16");
   if (o.mem_budget < 0) return fail(h, SLRF_E_ARG, "mem_budget must be >= 0");
+  if (o.spmm_variant < 0 || o.spmm_variant > 5)
+    return fail(h, SLRF_E_ARG, "spmm_variant must be 0..5");
   return SLRF_OK;
 }
 
@@ -456,6 +475,84 @@ slrf_status vcycle(slrf_ctx* h, const AmgVecs& v, int C, int occ, int ND, const 
   return SLRF_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// SpMM autotuner: time every applicable kernel variant on the actual pencil
+// (a 256-system panel batch in each precision) and keep the fastest.  The
+// choice is cached per process by shape class (n bucket, nonzeros per row).
+// ---------------------------------------------------------------------------
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, std::pair<int, int>> g_tune_cache;
+
+template <typename T>
+float time_spmm_variant(slrf_ctx* h, int var, void* Z, void* Q, const double2* sig, int nsys) {
+  DevPencil P = h->P;
+  if (std::is_same<T, float>::value) P.var32 = var; else P.var64 = var;
+  const PanelGrid g = make_grid(P.n, nsys, nsys, 2);
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) || hipEventCreate(&b)) return 1e30f;
+  float best = 1e30f;
+  for (int rep = 0; rep < 4; ++rep) {
+    (void)hipEventRecord(a, h->stream);
+    if (launch_spmm_panel<T>(P, g, sig, Z, Q, h->stream) != hipSuccess) break;
+    (void)hipEventRecord(b, h->stream);
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    if (rep > 0) best = std::min(best, ms);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return best;
+}
+
+slrf_status autotune_spmm(slrf_ctx* h) {
+  const int n = h->P.n;
+  const int nnz_row = (int)std::lround((double)h->P.nnz / n);
+  int nb = 0;
+  while ((1 << (nb + 1)) <= n) ++nb;
+  const auto key = std::make_pair(nb, nnz_row);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      h->P.var32 = it->second.first;
+      h->P.var64 = it->second.second;
+      return SLRF_OK;
+    }
+  }
+  const int nsys = 256;
+  void *Z = nullptr, *Q = nullptr, *sg = nullptr;
+  const size_t bytes = (size_t)nsys * n * 16;
+  if (hipMalloc(&Z, bytes) || hipMalloc(&Q, bytes) || hipMalloc(&sg, sizeof(double2) * nsys)) {
+    if (Z) (void)hipFree(Z);
+    if (Q) (void)hipFree(Q);
+    return SLRF_OK;  // keep the defaults when memory is short
+  }
+  std::vector<double2> sig(nsys);
+  for (int i = 0; i < nsys; ++i) sig[i] = h->poles[i % h->N];
+  HIPCHK(hipMemcpy(sg, sig.data(), sizeof(double2) * nsys, hipMemcpyHostToDevice));
+  HIPCHK(hipMemsetAsync(Z, 0, bytes, h->stream));
+  const int vars[5] = {kSpmmGroup, kSpmmCsrLds, kSpmmCsrLds16, kSpmmCsrLds32, kSpmmCsrDirect};
+  int best32 = kSpmmAuto, best64 = kSpmmAuto;
+  float t32 = 1e30f, t64 = 1e30f;
+  for (int v : vars) {
+    const float a = time_spmm_variant<float>(h, v, Z, Q, static_cast<double2*>(sg), nsys);
+    if (a < t32) { t32 = a; best32 = v; }
+    const float b = time_spmm_variant<double>(h, v, Z, Q, static_cast<double2*>(sg), nsys);
+    if (b < t64) { t64 = b; best64 = v; }
+  }
+  (void)hipStreamSynchronize(h->stream);
+  (void)hipFree(Z);
+  (void)hipFree(Q);
+  (void)hipFree(sg);
+  h->P.var32 = best32;
+  h->P.var64 = best64;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[key] = std::make_pair(best32, best64);
+  return SLRF_OK;
+}
+
 // Workspace plan of one filter call.
 struct Plan {
   int C;         // slots
@@ -569,7 +666,7 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
   // ----- right-hand sides: F = B X (and E = (A - theta B) X for the warm start)
   {
     Scope sp(h, SLRF_K_OTHER, 16.0 * n * nc);
-    HIPCHK(launch_transpose(X, nc, n, n, Xr, nc, s));  // col-major -> row-major
+    HIPCHK(launch_transpose(X, nc, n, n, Xr, nc, s, h->order));  // col-major -> row-major
   }
   {
     Scope sp(h, SLRF_K_OTHER, (warm ? 24.0 : 16.0) * n * nc + 20.0 * h->P.nnz);
@@ -787,7 +884,7 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
   }
   {
     Scope sp(h, SLRF_K_OTHER, 16.0 * n * nc);
-    HIPCHK(launch_transpose(Ur, n, nc, nc, U, n, s));
+    HIPCHK(launch_transpose(Ur, n, nc, nc, U, n, s, nullptr, h->order));
   }
   // ----- statistics
   std::vector<int> its(S);
@@ -828,6 +925,7 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
     }
     st->max_pole_iters_ratio_x1000 = pmin > 0 ? (int32_t)(1000.0 * pmax / pmin) : 0;
     st->max_rel_resid = maxrel;
+    st->spmm_variant = std::is_same<T, float>::value ? h->P.var32 : h->P.var64;
     if (st->sys_iters) std::memcpy(st->sys_iters, its.data(), sizeof(int) * S);
     st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
@@ -949,6 +1047,8 @@ void slrf_default_options(slrf_options* o) {
   o->lock = 0;
   o->timing = 0;
   o->max_slots = 0;
+  o->reorder = 1;
+  o->spmm_variant = 0;
   o->tol_lin = 1e-10;
   o->inner_rtol = 1e-5;
   o->tol_eig = 1e-8;
@@ -956,6 +1056,12 @@ void slrf_default_options(slrf_options* o) {
 }
 
 int32_t slrf_get_n(slrf_handle h) { return h ? h->P.n : -1; }
+
+slrf_status slrf_get_row_order(slrf_handle h, int32_t* order) {
+  if (!h || !order) return SLRF_E_ARG;
+  for (int i = 0; i < h->P.n; ++i) order[i] = h->h_order.empty() ? i : h->h_order[i];
+  return SLRF_OK;
+}
 
 slrf_status slrf_setup(slrf_handle* out, const slrf_csr* A, const slrf_csr* B, double gamma,
                        int32_t npoles, const slrf_zd* poles, const slrf_zd* weights,
@@ -1027,6 +1133,113 @@ slrf_status slrf_setup(slrf_handle* out, const slrf_csr* A, const slrf_csr* B, d
     if (!diag) return bad(SLRF_E_ARG, "every row must store its diagonal entry");
   }
   if (rp != rp2 || cl != cl2) return bad(SLRF_E_ARG, "A and B must share one CSR pattern");
+  h->P.n = n;
+  h->P.nnz = nnz;
+  h->P.rowptr = A->rowptr;
+  h->P.col = A->col;
+  h->P.a = A->val;
+  h->P.b = B->val;
+  std::vector<double> hA, hB;  // host copies of the final values (row-group format)
+  if (h->opt.reorder) {
+    // Locality order (nested aggregation of the graph of A): the library keeps
+    // a permuted copy of the pencil and applies the order at the boundary.
+    HostLevel L0;
+    L0.n = n;
+    L0.rp = rp;
+    L0.ci = cl;
+    L0.a.resize(nnz);
+    std::vector<double> bv(nnz);
+    if (hipMemcpy(L0.a.data(), A->val, sizeof(double) * nnz, hipMemcpyDeviceToHost) ||
+        hipMemcpy(bv.data(), B->val, sizeof(double) * nnz, hipMemcpyDeviceToHost))
+      return bad(SLRF_E_ARG, "CSR values are not readable device memory");
+    locality_order(L0, h->h_order);
+    std::vector<int> inv(n);
+    for (int i = 0; i < n; ++i) inv[h->h_order[i]] = i;
+    std::vector<int> prp(n + 1, 0), pci(nnz);
+    std::vector<double> pa(nnz), pb(nnz);
+    std::vector<std::pair<int, int>> row;
+    for (int i = 0; i < n; ++i) {
+      const int o = h->h_order[i];
+      row.clear();
+      for (int e = rp[o]; e < rp[o + 1]; ++e) row.push_back({inv[cl[e]], e});
+      std::sort(row.begin(), row.end());
+      int k = prp[i];
+      for (auto& pr : row) {
+        pci[k] = pr.first;
+        pa[k] = L0.a[pr.second];
+        pb[k] = bv[pr.second];
+        ++k;
+      }
+      prp[i + 1] = k;
+    }
+    if (hipMalloc(&h->order, sizeof(int) * n) || hipMalloc(&h->own_rp, sizeof(int) * (n + 1)) ||
+        hipMalloc(&h->own_ci, sizeof(int) * nnz) || hipMalloc(&h->own_a, sizeof(double) * nnz) ||
+        hipMalloc(&h->own_b, sizeof(double) * nnz))
+      return bad(SLRF_E_NOMEM, "allocation of the reordered pencil failed");
+    if (hipMemcpy(h->order, h->h_order.data(), sizeof(int) * n, hipMemcpyHostToDevice) ||
+        hipMemcpy(h->own_rp, prp.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice) ||
+        hipMemcpy(h->own_ci, pci.data(), sizeof(int) * nnz, hipMemcpyHostToDevice) ||
+        hipMemcpy(h->own_a, pa.data(), sizeof(double) * nnz, hipMemcpyHostToDevice) ||
+        hipMemcpy(h->own_b, pb.data(), sizeof(double) * nnz, hipMemcpyHostToDevice))
+      return bad(SLRF_E_HIP, "upload of the reordered pencil failed");
+    rp.swap(prp);
+    cl.swap(pci);
+    hA.swap(pa);
+    hB.swap(pb);
+    h->P.rowptr = h->own_rp;
+    h->P.col = h->own_ci;
+    h->P.a = h->own_a;
+    h->P.b = h->own_b;
+  } else {
+    hA.resize(nnz);
+    hB.resize(nnz);
+    if (hipMemcpy(hA.data(), A->val, sizeof(double) * nnz, hipMemcpyDeviceToHost) ||
+        hipMemcpy(hB.data(), B->val, sizeof(double) * nnz, hipMemcpyDeviceToHost))
+      return bad(SLRF_E_ARG, "CSR values are not readable device memory");
+  }
+  {
+    // Row-group (union) format of the pencil in its final row order.
+    const int R = 4, ng = (n + R - 1) / R;
+    std::vector<int> gp(ng + 1, 0), gc;
+    std::vector<double> ga, gb;
+    std::vector<int> u;
+    for (int gi = 0; gi < ng; ++gi) {
+      const int r0 = gi * R, r1 = std::min(r0 + R, n);
+      u.assign(cl.begin() + rp[r0], cl.begin() + rp[r1]);
+      std::sort(u.begin(), u.end());
+      u.erase(std::unique(u.begin(), u.end()), u.end());
+      const size_t base = gc.size();
+      gc.insert(gc.end(), u.begin(), u.end());
+      ga.resize(gc.size() * R, 0.0);
+      gb.resize(gc.size() * R, 0.0);
+      for (int r = r0; r < r1; ++r)
+        for (int e = rp[r]; e < rp[r + 1]; ++e) {
+          const size_t pos = base + (std::lower_bound(u.begin(), u.end(), cl[e]) - u.begin());
+          ga[pos * R + (r - r0)] = hA[e];
+          gb[pos * R + (r - r0)] = hB[e];
+        }
+      gp[gi + 1] = (int)gc.size();
+    }
+    int ent = 0;
+    for (int g0 = 0; g0 < ng; g0 += 8) ent = std::max(ent, gp[std::min(g0 + 8, ng)] - gp[g0]);
+    std::vector<float> ga32(ga.begin(), ga.end()), gb32(gb.begin(), gb.end());
+    const size_t sz[6] = {sizeof(int) * gp.size(), sizeof(int) * gc.size(),
+                          sizeof(double) * ga.size(), sizeof(double) * gb.size(),
+                          sizeof(float) * ga32.size(), sizeof(float) * gb32.size()};
+    const void* src[6] = {gp.data(), gc.data(), ga.data(), gb.data(), ga32.data(), gb32.data()};
+    for (int i = 0; i < 6; ++i) {
+      if (hipMalloc(&h->grp_mem[i], std::max<size_t>(sz[i], 4)) ||
+          hipMemcpy(h->grp_mem[i], src[i], sz[i], hipMemcpyHostToDevice))
+        return bad(SLRF_E_NOMEM, "allocation of the row-group format failed");
+    }
+    h->P.gptr = static_cast<const int*>(h->grp_mem[0]);
+    h->P.gcol = static_cast<const int*>(h->grp_mem[1]);
+    h->P.gca = static_cast<const double*>(h->grp_mem[2]);
+    h->P.gcb = static_cast<const double*>(h->grp_mem[3]);
+    h->P.gca32 = static_cast<const float*>(h->grp_mem[4]);
+    h->P.gcb32 = static_cast<const float*>(h->grp_mem[5]);
+    h->P.grp_lds_ent = ent;
+  }
   // largest CSR slice of an aligned row block (LDS staging plan of the SpMM)
   auto max_slice = [&](int sub) {
     int mx = 0;
@@ -1035,12 +1248,6 @@ slrf_status slrf_setup(slrf_handle* out, const slrf_csr* A, const slrf_csr* B, d
   };
   h->P.max_nnz_sub64 = max_slice(64);
   h->P.max_nnz_sub32 = max_slice(32);
-  h->P.n = n;
-  h->P.nnz = nnz;
-  h->P.rowptr = A->rowptr;
-  h->P.col = A->col;
-  h->P.a = A->val;
-  h->P.b = B->val;
   // ---- library-owned copies: FP32 values, diagonals, weights
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) return bad(SLRF_E_HIP, "hipMemGetInfo failed");
@@ -1055,7 +1262,7 @@ slrf_status slrf_setup(slrf_handle* out, const slrf_csr* A, const slrf_csr* B, d
   int* d_missing = nullptr;
   int missing = 0;
   if (hipMalloc(&d_missing, sizeof(int)) || hipMemsetAsync(d_missing, 0, sizeof(int), s) ||
-      launch_cast_f32(A->val, h->a32, nnz, s) || launch_cast_f32(B->val, h->b32, nnz, s) ||
+      launch_cast_f32(h->P.a, h->a32, nnz, s) || launch_cast_f32(h->P.b, h->b32, nnz, s) ||
       launch_diag(h->P, h->da, h->db, d_missing, s) ||
       hipMemcpyAsync(h->d_w, h->weights.data(), sizeof(double2) * npoles, hipMemcpyHostToDevice,
                      s) ||
@@ -1066,6 +1273,14 @@ slrf_status slrf_setup(slrf_handle* out, const slrf_csr* A, const slrf_csr* B, d
   }
   (void)hipFree(d_missing);
   if (missing) return bad(SLRF_E_ARG, "missing diagonal entry");
+  h->P.var32 = h->P.var64 = h->opt.spmm_variant;
+  if (h->opt.spmm_variant == kSpmmAuto && n >= 4096) {
+    const slrf_status ts = autotune_spmm(h);
+    if (ts != SLRF_OK) {
+      *out = h;
+      return ts;
+    }
+  }
   h->budget = h->opt.mem_budget > 0 ? (size_t)h->opt.mem_budget : (size_t)(0.6 * (double)fr);
   *out = h;
   return SLRF_OK;
@@ -1084,6 +1299,7 @@ slrf_status slrf_set_options(slrf_handle h, const slrf_options* opt) {
   if (s != SLRF_OK) return s;
   h->opt = *opt;
   if (opt->mem_budget > 0) h->budget = (size_t)opt->mem_budget;
+  if (opt->spmm_variant != kSpmmAuto) h->P.var32 = h->P.var64 = opt->spmm_variant;
   return SLRF_OK;
 }
 
@@ -1115,17 +1331,17 @@ slrf_status slrf_rayleigh_ritz(slrf_handle h, int32_t ncols, double* U, int32_t 
   hipStream_t s = h->stream;
   double *Ur, *Xl = nullptr, *BXl = nullptr;
   HIPCHK(ensure_t(h, B_TMP, (size_t)n * ncols, &Ur));
-  HIPCHK(launch_transpose(U, ncols, n, n, Ur, ncols, s));
+  HIPCHK(launch_transpose(U, ncols, n, n, Ur, ncols, s, h->order));
   if (nlocked > 0) {
     HIPCHK(ensure_t(h, B_XL, (size_t)n * nlocked, &Xl));
     HIPCHK(ensure_t(h, B_BXL, (size_t)n * nlocked, &BXl));
-    HIPCHK(launch_transpose(Xlocked, nlocked, n, n, Xl, nlocked, s));
+    HIPCHK(launch_transpose(Xlocked, nlocked, n, n, Xl, nlocked, s, h->order));
     HIPCHK(launch_spmm_real(h->P, Xl, nlocked, nlocked, nullptr, BXl, nullptr, nullptr, s));
   }
   std::vector<double> th, res;
   slrf_status r = rr_rowmajor(h, ncols, Ur, nlocked, Xl, BXl, th, res, nullptr);
   if (r != SLRF_OK) return r;
-  HIPCHK(launch_transpose(Ur, n, ncols, ncols, U, n, s));
+  HIPCHK(launch_transpose(Ur, n, ncols, ncols, U, n, s, nullptr, h->order));
   HIPCHK(hipMemcpyAsync(theta, th.data(), sizeof(double) * ncols, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(resid, res.data(), sizeof(double) * ncols, hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -1175,18 +1391,18 @@ slrf_status slrf_solve(slrf_handle h, int32_t nev, int32_t L, const double* V1, 
     const auto tr = std::chrono::steady_clock::now();
     double *Ur, *Xl = nullptr, *BXl = nullptr;
     HIPCHK(ensure_t(h, B_TMP, (size_t)n * nact, &Ur));
-    HIPCHK(launch_transpose(U, nact, n, n, Ur, nact, s));
+    HIPCHK(launch_transpose(U, nact, n, n, Ur, nact, s, h->order));
     const int nl = alg2 ? nconv : 0;
     if (nl > 0) {
       HIPCHK(ensure_t(h, B_XL, (size_t)n * nl, &Xl));
       HIPCHK(ensure_t(h, B_BXL, (size_t)n * nl, &BXl));
-      HIPCHK(launch_transpose(Xlk, nl, n, n, Xl, nl, s));
+      HIPCHK(launch_transpose(Xlk, nl, n, n, Xl, nl, s, h->order));
       HIPCHK(launch_spmm_real(h->P, Xl, nl, nl, nullptr, BXl, nullptr, nullptr, s));
     }
     std::vector<double> th, res;
     slrf_status r = rr_rowmajor(h, nact, Ur, nl, Xl, BXl, th, res, nullptr);
     if (r != SLRF_OK) return r;
-    HIPCHK(launch_transpose(Ur, n, nact, nact, U, n, s));  // Ritz vectors, column-major
+    HIPCHK(launch_transpose(Ur, n, nact, nact, U, n, s, nullptr, h->order));  // Ritz vectors
     rsec += std::chrono::duration<double>(std::chrono::steady_clock::now() - tr).count();
     std::vector<int> conv, rest;
     for (int c = 0; c < nact; ++c) {

@@ -45,7 +45,9 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("precond", C.c_int32), ("restart", C.c_int32),
                 ("maxit_lin", C.c_int32), ("it_max_lin", C.c_int32), ("max_outer", C.c_int32),
                 ("warm_start", C.c_int32), ("lock", C.c_int32), ("timing", C.c_int32),
-                ("max_slots", C.c_int32), ("tol_lin", C.c_double), ("inner_rtol", C.c_double),
+                ("max_slots", C.c_int32), ("spmm_variant", C.c_int32), ("reorder", C.c_int32),
+                ("tol_lin", C.c_double),
+                ("inner_rtol", C.c_double),
                 ("tol_eig", C.c_double), ("mem_budget", C.c_double)]
 
 
@@ -55,7 +57,7 @@ class FilterStats(C.Structure):
                 ("capped", C.c_int32), ("max_pole_iters_ratio_x1000", C.c_int32),
                 ("max_rel_resid", C.c_double), ("seconds", C.c_double),
                 ("launches", C.c_int64 * 7), ("bytes", C.c_double * 7), ("ms", C.c_double * 7),
-                ("sys_iters", C.POINTER(C.c_int32))]
+                ("spmm_variant", C.c_int32), ("sys_iters", C.POINTER(C.c_int32))]
 
 
 class SolveStats(C.Structure):
@@ -85,6 +87,7 @@ SIGNATURES = {
     "slrf_shifted_spmm": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_int32,
                                     C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "slrf_get_n": (C.c_int32, [C.c_void_p]),
+    "slrf_get_row_order": (C.c_int, [C.c_void_p, C.c_void_p]),
     "slrf_eig_grad": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                 C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                                 C.c_void_p, C.c_int32, C.c_void_p]),
@@ -292,6 +295,12 @@ class Handle:
         stats = {f: getattr(st, f) for f, _ in SolveStats._fields_}
         stats["status"] = r
         return theta[:nconv.value], X[:, :nconv.value], nconv.value, stats
+
+    def slrf_get_row_order(self):
+        """Internal row order (order[new] = old) used by slrf_shifted_spmm vectors."""
+        order = np.zeros(self.n, dtype=np.int32)
+        self._check(self._L.slrf_get_row_order(self._h, order.ctypes.data))
+        return order
 
     # --- slrf_eig_grad -------------------------------------------------------
     def slrf_eig_grad(self, X, lam, glam, elem_dofs, dA, dB=None, dA_stride=0, dB_stride=0):

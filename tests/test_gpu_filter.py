@@ -77,7 +77,9 @@ def test_shifted_spmm_parity(prec, which):
     Q = P.slrf.from_panels(h.slrf_shifted_spmm(Zt, pidx, prec), p.n, nsys)
     Qh = _host(Q).astype(np.complex128)
     Zr = _host(P.slrf.from_panels(Zt, p.n, nsys)).astype(np.complex128)  # rounded input
-    A, B = p.A(), p.B()
+    order = h.slrf_get_row_order()  # panel vectors use the library's row order
+    assert np.array_equal(np.sort(order), np.arange(p.n))
+    A, B = p.A()[order][:, order], p.B()[order][:, order]
     absA, absB = abs(A), abs(B)
     eps = np.finfo(np.float64 if prec == P.SLRF_PREC_FP64 else np.float32).eps
     for s in range(nsys):

@@ -107,7 +107,7 @@ def run_precision(P, torch, p, gamma, poles, weights, Xd, prec, steps, warmup, t
         "max_rel_resid": st["max_rel_resid"],
         "converged": st["converged"],
         "spmm_variant": {1: "row-group", 2: "csr-lds-u8", 3: "csr-direct", 4: "csr-lds-u16",
-                          5: "csr-lds-u32"}.get(st["spmm_variant"],
+                          5: "csr-lds-u32", 6: "halo"}.get(st["spmm_variant"],
                                                                              "default"),
         "kernel_ms": {k: v / steps for k, v in agg["ms"].items()},
         "kernel_GBps": {k: (agg["bytes"][k] / 1e9) / (agg["ms"][k] / 1e3)

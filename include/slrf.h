@@ -102,7 +102,8 @@ typedef struct {
                           precision, cached per shape class), 1 = row-group
                           union format, 2 / 4 / 5 = CSR staged in LDS with
                           8 / 16 / 32 gathers in flight per lane, 3 = CSR
-                          read directly                                       */
+                          read directly, 6 = halo tiles (the gathered operand
+                          staged in LDS per tile of rows)                     */
   int32_t reorder;     /* 1 (default): the library keeps a copy of the pencil
                           in a locality row order (nested aggregation of the
                           graph of A) so stencil gathers stay cache-resident;

@@ -1,0 +1,42 @@
+// Host construction of the halo-tile format of a CSR pencil (shifted SpMM with
+// the gathered operand staged in LDS).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace slrf {
+
+// Rows are cut into tiles made of whole slices of kHaloSlice consecutive rows.
+// A tile's halo is the sorted set of columns its rows reference; a tile grows
+// slice by slice while its halo stays within hmax entries and its rows within
+// rows_cap.  Entries are stored slice-major: entry j of row r (slice s = r / 8,
+// lane t = r % 8) sits at (sptr[s] + j) * 8 + t, with its column given as the
+// position in the tile's halo; slen holds the row lengths (0 past n), a slice
+// is as wide as its longest row rounded up to a multiple of kHaloPad, and
+// shorter rows are padded with entries of local column 0 and coefficients 0
+// (they add 0 * z for a halo row of the same system: the kernels need no
+// per-entry predicate).
+struct HostHalo {
+  int ntile = 0, hmax = 0;
+  int emax = 0;            // most entries of a pass (4 consecutive slices of a tile)
+  std::vector<int> trow;   // [ntile + 1] first row of each tile
+  std::vector<int> hptr;   // [ntile + 1] offsets into halo
+  std::vector<int> halo;   // halo rows of all tiles
+  std::vector<int> sptr;   // [nslice + 1] slice offsets in steps of 8 entries
+  std::vector<int> slen;   // [nslice * 8] row lengths
+  std::vector<uint16_t> lcol;   // local column (halo position) per entry
+  std::vector<double> ab;  // (a, b) per entry, interleaved
+};
+
+constexpr int kHaloSlice = 8;
+constexpr int kHaloPassSlices = 4;
+constexpr int kHaloPad = 4;         // slice widths are multiples of this  // slices formed together by one workgroup pass
+
+// Returns false (format not built) when a single slice references more than
+// hmax columns or hmax exceeds the 16-bit local index range.
+bool build_halo(int n, const std::vector<int>& rp, const std::vector<int>& ci,
+                const std::vector<double>& a, const std::vector<double>& b, int hmax,
+                int rows_cap, HostHalo& out);
+
+}  // namespace slrf

@@ -45,14 +45,35 @@ struct DevPencil {
   const float* gca32 = nullptr;
   const float* gcb32 = nullptr;
   int grp_lds_ent = 0;        // max union entries of 8 consecutive groups
+  // Halo-tile format (optional, hx_ntile == 0: absent): rows cut into tiles of
+  // whole 8-row slices whose referenced columns (the tile's halo, sorted)
+  // number at most kHaloMaxH; entry j of row r is stored at
+  // (hx_sptr[r / 8] + j) * 8 + r % 8 with its column as a halo position.
+  int hx_ntile = 0, hx_hmax = 0, hx_emax = 0;  // tiles, largest halo, most entries of a pass
+  const int* hx_trow = nullptr;   // [ntile + 1] first row of each tile
+  const int* hx_hptr = nullptr;   // [ntile + 1] halo offsets
+  const int* hx_halo = nullptr;   // halo rows of all tiles
+  const int* hx_sptr = nullptr;   // [nslice + 1] slice offsets (steps of 8 entries)
+  const int* hx_slen = nullptr;   // [nslice * 8] row lengths
+  const unsigned short* hx_lcol = nullptr;
+  const float2* hx_ab32 = nullptr;   // (a, b) per entry
+  const double2* hx_ab64 = nullptr;
   // SpMM kernel choice per sweep precision (kSpmm*; chosen by the autotuner)
   int var32 = 0, var64 = 0;
 };
 // SpMM variants: 0 = row-group format if present, else CSR staged in LDS;
 // 1 = row-group format; 2, 4, 5 = CSR staged in LDS with 8, 16, 32 gathers in
-// flight per lane; 3 = CSR read directly
+// flight per lane; 3 = CSR read directly; 6 = halo tiles (gathered operand
+// staged in LDS) for plain sweeps, CSR staged in LDS (16 in flight) for the
+// sweeps fused with the CGS projections
 constexpr int kSpmmAuto = 0, kSpmmGroup = 1, kSpmmCsrLds = 2, kSpmmCsrDirect = 3,
-              kSpmmCsrLds16 = 4, kSpmmCsrLds32 = 5;
+              kSpmmCsrLds16 = 4, kSpmmCsrLds32 = 5, kSpmmHalo = 6;
+constexpr int kSpmmVariants = 7;
+// Largest halo of a tile (rows of 128 bytes in LDS; with the staged
+// coefficients of a pass three to four workgroups fit a CU).
+constexpr int kHaloMaxH = 192;
+constexpr int kHaloMaxRows = 512;
+constexpr int kHaloMaxG = 8;  // units (128-byte panel column slices) per workgroup
 
 // A rectangular real CSR matrix on the device (AMG prolongation / restriction).
 struct DevTransfer {

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "amg_host.h"
+#include "halo_host.h"
 #include "dense_host.h"
 #include "internal.h"
 
@@ -99,6 +100,7 @@ struct slrf_ctx {
   int* order = nullptr;
   std::vector<int> h_order;
   void* grp_mem[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  std::vector<void*> halo_mem;  // halo-tile format arrays
   int* own_rp = nullptr;
   int* own_ci = nullptr;
   double* own_a = nullptr;
@@ -121,6 +123,8 @@ struct slrf_ctx {
     if (d_w) (void)hipFree(d_w);
     if (order) (void)hipFree(order);
     for (void* p : grp_mem)
+      if (p) (void)hipFree(p);
+    for (void* p : halo_mem)
       if (p) (void)hipFree(p);
     if (own_rp) (void)hipFree(own_rp);
     if (own_ci) (void)hipFree(own_ci);
@@ -256,8 +260,8 @@ slrf_status validate_options(slrf_ctx* h, const slrf_options& o) {
   if (o.max_slots < 0 || o.max_slots % kPanel != 0)
     return fail(h, SLRF_E_ARG, "max_slots must be a non-negative multiple of 16");
   if (o.mem_budget < 0) return fail(h, SLRF_E_ARG, "mem_budget must be >= 0");
-  if (o.spmm_variant < 0 || o.spmm_variant > 5)
-    return fail(h, SLRF_E_ARG, "spmm_variant must be 0..5");
+  if (o.spmm_variant < 0 || o.spmm_variant >= kSpmmVariants)
+    return fail(h, SLRF_E_ARG, "spmm_variant must be 0..6");
   return SLRF_OK;
 }
 
@@ -533,10 +537,12 @@ slrf_status autotune_spmm(slrf_ctx* h) {
   for (int i = 0; i < nsys; ++i) sig[i] = h->poles[i % h->N];
   HIPCHK(hipMemcpy(sg, sig.data(), sizeof(double2) * nsys, hipMemcpyHostToDevice));
   HIPCHK(hipMemsetAsync(Z, 0, bytes, h->stream));
-  const int vars[5] = {kSpmmGroup, kSpmmCsrLds, kSpmmCsrLds16, kSpmmCsrLds32, kSpmmCsrDirect};
+  const int vars[6] = {kSpmmGroup,    kSpmmCsrLds,    kSpmmCsrLds16,
+                       kSpmmCsrLds32, kSpmmCsrDirect, kSpmmHalo};
   int best32 = kSpmmAuto, best64 = kSpmmAuto;
   float t32 = 1e30f, t64 = 1e30f;
   for (int v : vars) {
+    if (v == kSpmmHalo && h->P.hx_ntile == 0) continue;
     const float a = time_spmm_variant<float>(h, v, Z, Q, static_cast<double2*>(sg), nsys);
     if (a < t32) { t32 = a; best32 = v; }
     const float b = time_spmm_variant<double>(h, v, Z, Q, static_cast<double2*>(sg), nsys);
@@ -1239,6 +1245,38 @@ slrf_status slrf_setup(slrf_handle* out, const slrf_csr* A, const slrf_csr* B, d
     h->P.gca32 = static_cast<const float*>(h->grp_mem[4]);
     h->P.gcb32 = static_cast<const float*>(h->grp_mem[5]);
     h->P.grp_lds_ent = ent;
+  }
+  {
+    // Halo-tile format of the pencil in its final row order (absent when a
+    // single 8-row slice references more columns than the LDS tile holds).
+    HostHalo hx;
+    if (build_halo(n, rp, cl, hA, hB, kHaloMaxH, kHaloMaxRows, hx)) {
+      const size_t nent = hx.lcol.size();
+      std::vector<float> ab32(hx.ab.begin(), hx.ab.end());
+      const size_t sz[8] = {sizeof(int) * hx.trow.size(), sizeof(int) * hx.hptr.size(),
+                            sizeof(int) * hx.halo.size(), sizeof(int) * hx.sptr.size(),
+                            sizeof(int) * hx.slen.size(), sizeof(uint16_t) * nent,
+                            sizeof(float) * 2 * nent,     sizeof(double) * 2 * nent};
+      const void* src[8] = {hx.trow.data(), hx.hptr.data(), hx.halo.data(), hx.sptr.data(),
+                            hx.slen.data(), hx.lcol.data(), ab32.data(),    hx.ab.data()};
+      h->halo_mem.assign(8, nullptr);
+      for (int i = 0; i < 8; ++i) {
+        if (hipMalloc(&h->halo_mem[i], std::max<size_t>(sz[i], 4)) ||
+            hipMemcpy(h->halo_mem[i], src[i], sz[i], hipMemcpyHostToDevice))
+          return bad(SLRF_E_NOMEM, "allocation of the halo-tile format failed");
+      }
+      h->P.hx_ntile = hx.ntile;
+      h->P.hx_hmax = hx.hmax;
+      h->P.hx_emax = hx.emax;
+      h->P.hx_trow = static_cast<const int*>(h->halo_mem[0]);
+      h->P.hx_hptr = static_cast<const int*>(h->halo_mem[1]);
+      h->P.hx_halo = static_cast<const int*>(h->halo_mem[2]);
+      h->P.hx_sptr = static_cast<const int*>(h->halo_mem[3]);
+      h->P.hx_slen = static_cast<const int*>(h->halo_mem[4]);
+      h->P.hx_lcol = static_cast<const unsigned short*>(h->halo_mem[5]);
+      h->P.hx_ab32 = static_cast<const float2*>(h->halo_mem[6]);
+      h->P.hx_ab64 = static_cast<const double2*>(h->halo_mem[7]);
+    }
   }
   // largest CSR slice of an aligned row block (LDS staging plan of the SpMM)
   auto max_slice = [&](int sub) {

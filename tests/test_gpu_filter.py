@@ -59,15 +59,19 @@ def cfg1():
 # ----------------------------------------------------------------------------
 # shifted SpMM (a3)
 # ----------------------------------------------------------------------------
+SPMM_VARIANTS = [0, 1, 2, 3, 4, 5, 6]  # auto, row-group, CSR-LDS u8, direct, u16, u32, halo
+
+
+@pytest.mark.parametrize("variant", SPMM_VARIANTS)
 @pytest.mark.parametrize("prec", [P.SLRF_PREC_FP64, P.SLRF_PREC_MIXED])
 @pytest.mark.parametrize("which", ["q1_2d_m40", "diff_3d_m12"])
-def test_shifted_spmm_parity(prec, which):
+def test_shifted_spmm_parity(prec, which, variant):
     if which == "q1_2d_m40":
         p = si.q1_kron_pencil(40, 2)
-    else:
+    else:  # n = 2197: a ragged last slice of 5 rows
         p = si.q1_diffusion_pencil(12, 3, np.exp(np.random.default_rng(2).normal(0, .5, 13 ** 3)))
     poles, weights = si.slrf_poles(300.0)
-    h = _handle(p, 300.0, poles, weights)
+    h = _handle(p, 300.0, poles, weights, spmm_variant=variant)
     nsys = 37
     rng = np.random.default_rng(7)
     Zh = rng.standard_normal((p.n, nsys)) + 1j * rng.standard_normal((p.n, nsys))
@@ -125,13 +129,14 @@ def test_single_pole_solves_meet_tolerance(cfg1, prec, pcnd):
         assert np.linalg.norm(Y + err - Ylu) <= 1e-9 * np.linalg.norm(Ylu)
 
 
+@pytest.mark.parametrize("variant", [0, 6])
 @pytest.mark.parametrize("pcnd", [P.SLRF_PC_JACOBI, P.SLRF_PC_AMG])
 @pytest.mark.parametrize("prec", [P.SLRF_PREC_FP64, P.SLRF_PREC_MIXED])
-def test_filter_matches_exact_lu_oracle(cfg1, prec, pcnd):
+def test_filter_matches_exact_lu_oracle(cfg1, prec, pcnd, variant):
     p = cfg1["pencil"]
     tol = 1e-10
     h = _handle(p, cfg1["gamma"], cfg1["poles"], cfg1["weights"], precision=prec, tol_lin=tol,
-                precond=pcnd)
+                precond=pcnd, spmm_variant=variant)
     X = cfg1["V1"]
     U, st = h.slrf_filter(_dev(X))
     Uo = oracle.filter.apply_filter(p.A(), p.B(), cfg1["poles"], cfg1["weights"], X)
@@ -142,17 +147,19 @@ def test_filter_matches_exact_lu_oracle(cfg1, prec, pcnd):
     h.close()
 
 
-def test_filter_bitwise_deterministic_and_pool_independent(cfg1):
+@pytest.mark.parametrize("variant", [0, 6])
+def test_filter_bitwise_deterministic_and_pool_independent(cfg1, variant):
     p = cfg1["pencil"]
     X = _dev(cfg1["V1"][:, :10])
-    h = _handle(p, cfg1["gamma"], cfg1["poles"], cfg1["weights"])
+    h = _handle(p, cfg1["gamma"], cfg1["poles"], cfg1["weights"], spmm_variant=variant)
     U1, _ = h.slrf_filter(X)
     U2, _ = h.slrf_filter(X)
     assert torch.equal(U1, U2)
     h.close()
     # a pool of only 16 resident systems streams the 80 systems through it;
     # every system's arithmetic is independent of its slot, so U is identical
-    h = _handle(p, cfg1["gamma"], cfg1["poles"], cfg1["weights"], max_slots=16)
+    h = _handle(p, cfg1["gamma"], cfg1["poles"], cfg1["weights"], max_slots=16,
+                spmm_variant=variant)
     U3, st = h.slrf_filter(X)
     assert torch.equal(U1, U3)
     h.close()

@@ -1714,9 +1714,17 @@ hipError_t launch_apply_dots(const DevPencil& P, const PanelGrid& g, const SlotT
   auto Qb = static_cast<const C*>(Qbase);
   {
     hipError_t err = hipSuccess;
-    // (the halo kernel forms plain sweeps; sweeps fused with the CGS
-    // projections use the CSR kernels, whose partial sums span 512-row blocks)
-    if (k == 0 && launch_halo<T>(P, g, st, kEpiApply, 0.0, Z, nullptr, Qk, s, err)) return err;
+    // halo sweep, then the CGS projections as a separate streaming pass
+    if (launch_halo<T>(P, g, st, kEpiApply, 0.0, Z, nullptr, Qk, s, err)) {
+      if (err != hipSuccess || k == 0) return err;
+      if (k <= 8)
+        k_dots<T, 8><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, Qc, Qb, vstride, k, part);
+      else if (k <= 16)
+        k_dots<T, 16><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, Qc, Qb, vstride, k, part);
+      else
+        k_dots<T, 32><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, Qc, Qb, vstride, k, part);
+      return hipGetLastError();
+    }
     if (launch_grp<T>(P, g, st, kEpiApply, 0.0, Z, nullptr, Qk, s, err)) {
       if (err != hipSuccess || k == 0) return err;
       if (k <= 8)

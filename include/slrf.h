@@ -125,7 +125,11 @@ enum {
   SLRF_K_REDUCE = 4,/* second-stage reductions and per-system scalars             */
   SLRF_K_OTHER = 5, /* admission, compaction, filter sum, RHS SpMM, transposes    */
   SLRF_K_PRECOND = 6,/* AMG V-cycle (all levels)                                 */
-  SLRF_K_COUNT = 7
+  SLRF_K_SWEEP = 7,  /* the fine-level operator sweep alone (halo-tile SpMM: the
+                        GCR apply without its projections and the V-cycle's
+                        level-0 residual and smoothing sweeps); an overlay:
+                        these launches are also counted in APPLY / PRECOND    */
+  SLRF_K_COUNT = 8
 };
 
 typedef struct {

@@ -110,6 +110,19 @@ struct SlotTables {
 };
 
 // ----- shifted block kernels (inner precision T = float or double) -----
+// True when the pencil's operator sweeps for T run on the halo-tile kernel
+// (then the GCR apply is a plain sweep followed by a separate projection pass).
+template <typename T>
+bool sweep_is_halo(const DevPencil& P);
+// Plain operator sweep Out = M Z of the active slots (no projections).
+template <typename T>
+hipError_t launch_sweep(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
+                        const void* Z, void* Out, hipStream_t s);
+// CGS projections h_i = <q_i, q_k>, i < k, as partial sums per row block.
+template <typename T>
+hipError_t launch_dots(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
+                       const void* Qk, const void* Qbase, size_t vstride, int k, double2* part,
+                       hipStream_t s);
 template <typename T>
 hipError_t launch_apply_dots(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
                              const void* Z, void* Qk, const void* Qbase, size_t vstride, int k,

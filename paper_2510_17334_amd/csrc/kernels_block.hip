@@ -1705,6 +1705,34 @@ bool launch_halo(const DevPencil& P, const PanelGrid& g, const SlotTables& st, i
 }
 
 template <typename T>
+bool sweep_is_halo(const DevPencil& P) {
+  return halo_selected<T>(P);
+}
+
+template <typename T>
+hipError_t launch_dots(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
+                       const void* Qk, const void* Qbase, size_t vstride, int k, double2* part,
+                       hipStream_t s) {
+  using C = typename CT<T>::t;
+  auto Qc = static_cast<const C*>(Qk);
+  auto Qb = static_cast<const C*>(Qbase);
+  if (k <= 0) return hipSuccess;
+  if (k <= 8)
+    k_dots<T, 8><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, Qc, Qb, vstride, k, part);
+  else if (k <= 16)
+    k_dots<T, 16><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, Qc, Qb, vstride, k, part);
+  else
+    k_dots<T, 32><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, Qc, Qb, vstride, k, part);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sweep(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
+                        const void* Z, void* Out, hipStream_t s) {
+  return launch_apply_dots<T>(P, g, st, Z, Out, nullptr, 0, 0, nullptr, false, s);
+}
+
+template <typename T>
 hipError_t launch_apply_dots(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
                              const void* Z, void* Qk, const void* Qbase, size_t vstride, int k,
                              double2* part, bool, hipStream_t s) {
@@ -1717,13 +1745,7 @@ hipError_t launch_apply_dots(const DevPencil& P, const PanelGrid& g, const SlotT
     // halo sweep, then the CGS projections as a separate streaming pass
     if (launch_halo<T>(P, g, st, kEpiApply, 0.0, Z, nullptr, Qk, s, err)) {
       if (err != hipSuccess || k == 0) return err;
-      if (k <= 8)
-        k_dots<T, 8><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, Qc, Qb, vstride, k, part);
-      else if (k <= 16)
-        k_dots<T, 16><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, Qc, Qb, vstride, k, part);
-      else
-        k_dots<T, 32><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, Qc, Qb, vstride, k, part);
-      return hipGetLastError();
+      return launch_dots<T>(P, g, st, Qk, Qbase, vstride, k, part, s);
     }
     if (launch_grp<T>(P, g, st, kEpiApply, 0.0, Z, nullptr, Qk, s, err)) {
       if (err != hipSuccess || k == 0) return err;
@@ -1893,6 +1915,12 @@ hipError_t launch_fin_true(const double2* red, int nslots, const SlotTables& st,
 }
 
 #define SLRF_INST(T)                                                                         \
+  template bool sweep_is_halo<T>(const DevPencil&);                                          \
+  template hipError_t launch_sweep<T>(const DevPencil&, const PanelGrid&, const SlotTables&, \
+                                      const void*, void*, hipStream_t);                      \
+  template hipError_t launch_dots<T>(const DevPencil&, const PanelGrid&, const SlotTables&,  \
+                                     const void*, const void*, size_t, int, double2*,        \
+                                     hipStream_t);                                           \
   template hipError_t launch_apply_dots<T>(const DevPencil&, const PanelGrid&,               \
                                            const SlotTables&, const void*, void*,            \
                                            const void*, size_t, int, double2*, bool,         \

@@ -205,6 +205,7 @@ struct Scope {
   int cls;
   hipEvent_t b = nullptr;
   Scope(slrf_ctx* hh, int c, double bytes) : h(hh), cls(c) {
+    if (cls < 0) return;  // not recorded
     if (h->cur_stats) {
       h->cur_stats->launches[cls] += 1;
       h->cur_stats->bytes[cls] += bytes;
@@ -450,6 +451,7 @@ slrf_status vcycle(slrf_ctx* h, const AmgVecs& v, int C, int occ, int ND, const 
       return SLRF_OK;
     }
     auto lvl = [&](int l) -> const DevPencil& { return l == 0 ? h->P : A.lv[l - 1]; };
+    const double fine_csr = (double)h->P.nnz * (4.0 + 2.0 * sizeof(T)) + 4.0 * (A.n[0] + 1);
     std::vector<const void*> b(L, nullptr);
     std::vector<void*> x(L, nullptr);
     b[0] = Rin;
@@ -458,7 +460,11 @@ slrf_status vcycle(slrf_ctx* h, const AmgVecs& v, int C, int occ, int ND, const 
       void* xb = l == 0 ? v.W0 : v.X[l];
       void* r = l == 0 ? v.T0 : v.T[l];
       HIPCHK(launch_lvl_jacobi0<T>(lvl(l), g, st, A.omega, b[l], xb, s));
-      HIPCHK(launch_lvl_op<T>(lvl(l), g, st, kEpiResidOp, A.omega, xb, b[l], r, s));
+      {
+        Scope sw(h, l == 0 && sweep_is_halo<T>(h->P) ? SLRF_K_SWEEP : -1,
+                 (double)nact * A.n[0] * sT * 3.0 + fine_csr);
+        HIPCHK(launch_lvl_op<T>(lvl(l), g, st, kEpiResidOp, A.omega, xb, b[l], r, s));
+      }
       const PanelGrid gc = make_grid(A.n[l + 1], C, occ, ND);
       HIPCHK(launch_transfer<T>(A.R[l], gc, st, r, v.B[l + 1], false, s));
       b[l + 1] = v.B[l + 1];
@@ -471,6 +477,8 @@ slrf_status vcycle(slrf_ctx* h, const AmgVecs& v, int C, int occ, int ND, const 
       const PanelGrid g = make_grid(A.n[l], C, occ, ND);
       HIPCHK(launch_transfer<T>(A.P[l], g, st, x[l + 1], x[l], true, s));
       void* out = l == 0 ? Zout : v.W[l];
+      Scope sw(h, l == 0 && sweep_is_halo<T>(h->P) ? SLRF_K_SWEEP : -1,
+               (double)nact * A.n[0] * sT * 3.0 + fine_csr);
       HIPCHK(launch_lvl_op<T>(lvl(l), g, st, kEpiJacobiOp, A.omega, x[l], b[l], out, s));
       x[l] = out;
     }
@@ -842,7 +850,14 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
         const slrf_status vs = vcycle<T>(h, av, C, occ, ND, tc, R, Z, nact);
         if (vs != SLRF_OK) return vs;
       }
-      {
+      if (sweep_is_halo<T>(h->P)) {
+        Scope sp(h, SLRF_K_APPLY, (double)nact * n * sT * (k + 2) + csr_bytes);
+        {
+          Scope sw(h, SLRF_K_SWEEP, (double)nact * n * sT * 2.0 + csr_bytes);
+          HIPCHK(launch_sweep<T>(h->P, g, tc, Z, Qk, s));
+        }
+        HIPCHK(launch_dots<T>(h->P, g, tc, Qk, Q, vstride, k, part, s));
+      } else {
         Scope sp(h, SLRF_K_APPLY, (double)nact * n * sT * (k + 2) + csr_bytes);
         HIPCHK(launch_apply_dots<T>(h->P, g, tc, Z, Qk, Q, vstride, k, part, pc, s));
       }

@@ -21,7 +21,7 @@ SLRF_PREC_MIXED = 1
 SLRF_PC_NONE = 0
 SLRF_PC_JACOBI = 1
 SLRF_PC_AMG = 2
-KERNEL_CLASSES = ("apply", "orth", "step", "resid", "reduce", "other", "precond")
+KERNEL_CLASSES = ("apply", "orth", "step", "resid", "reduce", "other", "precond", "sweep")
 _STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP runtime error",
            4: "breakdown", 5: "iteration cap reached", 6: "NaN/Inf detected", 7: "no usable GPU"}
 
@@ -56,7 +56,7 @@ class FilterStats(C.Structure):
                 ("max_iters", C.c_int32), ("cycles", C.c_int32), ("converged", C.c_int32),
                 ("capped", C.c_int32), ("max_pole_iters_ratio_x1000", C.c_int32),
                 ("max_rel_resid", C.c_double), ("seconds", C.c_double),
-                ("launches", C.c_int64 * 7), ("bytes", C.c_double * 7), ("ms", C.c_double * 7),
+                ("launches", C.c_int64 * 8), ("bytes", C.c_double * 8), ("ms", C.c_double * 8),
                 ("spmm_variant", C.c_int32), ("sys_iters", C.POINTER(C.c_int32))]
 
 

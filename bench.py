@@ -30,6 +30,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+# FP32 / FP64 FMA rate of the vector ALUs without packed-FP32 instructions (the
+# build disables them): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz.
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# the shifted sweep q = (A - sigma B) z does 2 complex-by-real products per
+# stored entry and system: 8 real flop (accumulated A z and B z)
+SWEEP_FLOP_PER_ENTRY = 8.0
 
 
 def parse():
@@ -45,6 +51,10 @@ def parse():
     ap.add_argument("--precond", choices=["amg", "jacobi"], default="amg")
     ap.add_argument("--restart", type=int, default=8, help="GCR restart length m")
     ap.add_argument("--ncols", type=int, default=160)
+    ap.add_argument("--workload", choices=["q1_3d", "batch64"], default="q1_3d",
+                    help="q1_3d: the metric workload; batch64: the 64 uneven Q1 diffusion "
+                         "pencils through the batched entry point")
+    ap.add_argument("--threads", type=int, default=8, help="host threads of the batched call")
     return ap.parse_args()
 
 
@@ -130,12 +140,14 @@ def run_precision(P, torch, p, gamma, poles, weights, Xd, prec, steps, warmup, t
         step()
     torch.cuda.synchronize()
     agg = {"bytes": {}, "ms": {}, "launches": {}}
+    sweep_systems = 0.0
     t0 = time.perf_counter()
     for _ in range(steps):
         U, st, th, res = step()
         for key in agg:
             for k, v in st[key].items():
                 agg[key][k] = agg[key].get(k, 0) + v
+        sweep_systems += st["sweep_systems"]
         last = (U, st, th, res)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / max(steps, 1)
@@ -157,6 +169,7 @@ def run_precision(P, torch, p, gamma, poles, weights, Xd, prec, steps, warmup, t
                         for k in agg["ms"] if agg["ms"][k] > 0},
         "kernel_launches": {k: v // steps for k, v in agg["launches"].items()},
         "kernel_bytes": {k: v / steps for k, v in agg["bytes"].items()},
+        "sweep_system_passes": sweep_systems / steps,
     }
     Uh = U.detach().cpu().numpy()
     h.close()
@@ -188,6 +201,108 @@ def spmm_rate(P, torch, p, gamma, poles, weights, nsys):
     return res
 
 
+def roofline_entry(dom, r, achieved_gbps, nl, traffic, tflops, intensity):
+    """Roofline of the dominant kernel.  The complex-float sweep does 8 flop per
+    stored entry and system against 16 bytes of vector traffic per row and
+    system, 13.5 flop/byte on the 27-point pencil: above the 9.8 flop/byte
+    ridge of the non-packed FP32 ALU rate (78.6 TFLOP/s) and 8 TB/s, so it is
+    ALU-bound; the complex-double sweep (6.7 flop/byte) is HBM-bound."""
+    base = {"kernel": ("k_apply_halo (fine-level shifted SpMM sweep)" if dom == "sweep" else dom),
+            "launches_per_step": r["kernel_launches"][dom],
+            "avg_launch_ms": r["kernel_ms"][dom] / nl,
+            "algorithmic_bytes_per_launch": r["kernel_bytes"][dom] / nl,
+            "hbm_achieved_GBps": achieved_gbps, "hbm_frac": achieved_gbps / HBM_PEAK_GBPS,
+            "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                            "copy-kernel scaled)",
+            "sweep_sources_sha256": sweep_source_hash()}
+    ridge = VALU_PEAK_TFLOPS * 1e3 / HBM_PEAK_GBPS
+    if tflops is not None and intensity is not None and intensity > ridge:
+        out = {"bound": "alu", "achieved": tflops, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+               "frac": tflops / VALU_PEAK_TFLOPS, "flop_per_byte": intensity,
+               "ridge_flop_per_byte": ridge}
+    else:
+        out = {"bound": "hbm", "achieved": achieved_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+               "frac": achieved_gbps / HBM_PEAK_GBPS}
+        if intensity is not None:
+            out["flop_per_byte"] = intensity
+    out.update(base)
+    return out
+
+
+def run_batch64(args):
+    """One outer iteration of Algorithm 1 on each of the 64 uneven pencils: the
+    filters of all pencils through slrf_filter_batch (concurrent streams), then
+    each pencil's Rayleigh-Ritz.  value = systems of all pencils / step time."""
+    import numpy as np
+    import torch
+
+    import paper_2510_17334_amd as P
+    import slrf_inputs as si
+
+    golden = os.path.join(ROOT, "tests", "golden", "batch64_q1_diffusion.json")
+    if not os.path.exists(golden):
+        print("batch64 needs tests/golden/batch64_q1_diffusion.json (interval ends from the "
+              "oracle); run tests/golden/make_batch64_q1_diffusion.py", file=sys.stderr)
+        sys.exit(2)
+    gold = json.load(open(golden))["pencils"]
+    torch.cuda.set_device(0)
+    draws = si.batched_pencils(64, seed=1004)
+    hs, Xs = [], []
+    nsys = 0
+    for d, g in zip(draws, gold):
+        p = d["pencil"]
+        poles, weights = si.slrf_poles(g["gamma"])
+        opt = P.default_options(precision=P.SLRF_PREC_MIXED, precond=P.SLRF_PC_AMG,
+                                restart=args.restart, tol_lin=1e-8, timing=0)
+        hs.append(P.Handle.from_pencil(p, g["gamma"], poles, weights, opt,
+                                       stream=torch.cuda.Stream()))
+        V = si.start_block(p.n, d["L"], d["seed"])
+        Xs.append(torch.as_tensor(np.ascontiguousarray(V.T), device="cuda").t())
+        nsys += d["L"] * len(poles)
+    torch.cuda.synchronize()
+
+    def step(nthreads):
+        out = P.slrf_filter_batch(hs, Xs, nthreads=nthreads)
+        for h, (U, st) in zip(hs, out):
+            with torch.cuda.stream(h.stream):
+                h.slrf_rayleigh_ritz(U)
+        return out
+
+    res = {}
+    for label, nt in (("batched", args.threads), ("one_at_a_time", 1)):
+        for _ in range(args.warmup):
+            step(nt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = step(nt)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / max(args.steps, 1)
+        res[label] = {"ms_per_step": dt * 1e3, "solves_per_s": nsys / dt, "threads": nt,
+                      "converged": int(sum(st["converged"] for _, st in out)),
+                      "inner_iters": int(sum(st["total_iters"] for _, st in out))}
+        print(f"{label}: {dt * 1e3:.1f} ms/step, {nsys / dt:.1f} solves/s", file=sys.stderr,
+              flush=True)
+    for h in hs:
+        h.close()
+    r = res["batched"]
+    line = {
+        "metric": "filtered pole x RHS solves/sec to rel tol 1e-8 (mixed), 64 uneven pencils",
+        "value": r["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64+f64", "data": "synthetic",
+        "config": {"workload": "batch64_q1_diffusion", "pencils": 64,
+                   "n_range": [min(g["n"] for g in gold), max(g["n"] for g in gold)],
+                   "systems": nsys, "tol_lin": 1e-8,
+                   "solver": f"GCR({args.restart})+AMG V-cycle, mixed",
+                   "step": "Algorithm 1 outer iteration on every pencil"},
+        "modes": res,
+        "batching_speedup": res["one_at_a_time"]["ms_per_step"] / r["ms_per_step"],
+    }
+    print(json.dumps(line, default=float))
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -195,6 +310,9 @@ def main():
               f"independent, a multi-GPU run would shard them by column (see the design "
               f"notes); --gpus {args.gpus} is not supported in this build.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch64":
+        run_batch64(args)
+        return
     import numpy as np
     import torch
 
@@ -241,6 +359,14 @@ def main():
     achieved = r["kernel_GBps"][dom]
     nl = max(r["kernel_launches"][dom], 1)
     traffic = profiled_traffic() if dom == "sweep" else None
+    if dom == "sweep":
+        # flops of the sweeps in the step: bytes per launch are 2 or 3 vector
+        # passes plus the matrix; the flop count follows the same active-system
+        # count, recorded by the library as the sweep's system-rows
+        sweep_flop = SWEEP_FLOP_PER_ENTRY * p.nnz * r["sweep_system_passes"]
+        tflops = sweep_flop / (r["kernel_ms"]["sweep"] / 1e3) / 1e12
+        sT = 8 if main_name == "mixed" else 16
+        intensity = SWEEP_FLOP_PER_ENTRY * p.nnz / p.n / (2 * sT)
     line = {
         "metric": "filtered pole x RHS solves/sec to rel tol 1e-8 (mixed vs FP64); SpMM HBM GB/s",
         "value": r["solves_per_s"],
@@ -259,16 +385,9 @@ def main():
                    "solver": f"GCR({args.restart})+{'AMG V-cycle' if args.precond == 'amg' else 'Jacobi'}",
                    "step": "Algorithm 1 outer iteration",
                    "precision": main_name},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "kernel": ("k_apply_halo (fine-level shifted SpMM sweep)"
-                                if dom == "sweep" else dom),
-                     "launches_per_step": r["kernel_launches"][dom],
-                     "avg_launch_ms": r["kernel_ms"][dom] / nl,
-                     "algorithmic_bytes_per_launch": r["kernel_bytes"][dom] / nl,
-                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + "
-                                     "WRITE_SIZE, copy-kernel scaled)",
-                     "sweep_sources_sha256": sweep_source_hash()},
+        "roofline": roofline_entry(dom, r, achieved, nl, traffic,
+                                   tflops if dom == "sweep" else None,
+                                   intensity if dom == "sweep" else None),
         "spmm": spmm,
         "precisions": results,
     }

@@ -147,8 +147,10 @@ typedef struct {
   int64_t launches[SLRF_K_COUNT];
   double bytes[SLRF_K_COUNT]; /* algorithmic HBM bytes                             */
   double ms[SLRF_K_COUNT];    /* summed kernel time (only with options.timing)     */
-  int32_t spmm_variant;  /* SpMM kernel used for the Krylov sweeps (1 row-group,
-                            2 CSR-LDS, 3 CSR direct; 0 = row-group if present) */
+  int32_t spmm_variant;  /* SpMM kernel used for the Krylov sweeps (the
+                            options.spmm_variant codes; 0 = default choice)   */
+  double sweep_systems;  /* systems swept, summed over the SWEEP-class launches
+                            (flops of those launches = 8 * nnz * sweep_systems) */
   int32_t* sys_iters;    /* optional, caller-owned host int32[N*ncols]: iterations
                             of system (column c, pole j) at index c*N + j          */
 } slrf_filter_stats;
@@ -226,6 +228,32 @@ slrf_status slrf_rayleigh_ritz(slrf_handle h, int32_t ncols, double* U, int32_t 
  */
 slrf_status slrf_solve(slrf_handle h, int32_t nev, int32_t L, const double* V1, double* theta_out,
                        double* X_out, int32_t* nconv_out, slrf_solve_stats* stats);
+
+/*
+ * slrf_filter_batch / slrf_solve_batch - many independent pencils at once
+ * (the batched form of Eq. (2)-(3) and of Algorithm 1 / 2 over uneven-sized
+ * problems).  Entry i is exactly slrf_filter / slrf_solve on hs[i] with the
+ * i-th arguments; the calls run concurrently from up to nthreads host threads
+ * (0 = min(nh, 8)), largest problems first, each on its handle's stream, so
+ * the GPU overlaps the kernels of different pencils.  Give every handle its
+ * own stream (handles that share a stream still give correct results, run
+ * serially on the GPU).  Handles must be distinct.  Per-entry arguments are
+ * arrays of length nh (theta_warm, stats, nconv_out may be NULL; their
+ * entries may be NULL).  Results are identical to the single calls (each
+ * handle's arithmetic does not depend on what runs beside it).  Each
+ * handle's cached solver workspace is released when its entry finishes, so
+ * the device memory in use is bounded by the entries in flight.  Returns
+ * SLRF_OK if every entry succeeded, else the status of the first failing
+ * entry in index order (all entries are still attempted; a failing handle's
+ * message is in its slrf_last_error).
+ */
+slrf_status slrf_filter_batch(int32_t nh, const slrf_handle* hs, const int32_t* ncols,
+                              const double* const* X, const double* const* theta_warm,
+                              double* const* U, slrf_filter_stats* stats, int32_t nthreads);
+slrf_status slrf_solve_batch(int32_t nh, const slrf_handle* hs, const int32_t* nev,
+                             const int32_t* L, const double* const* V1,
+                             double* const* theta_out, double* const* X_out,
+                             int32_t* nconv_out, slrf_solve_stats* stats, int32_t nthreads);
 
 /*
  * slrf_shifted_spmm - one sweep of the shifted operator over a batch of

@@ -20,4 +20,6 @@ from .slrf import (  # noqa: F401
     library_path,
     host_projected_eig,
     KERNEL_CLASSES,
+    slrf_filter_batch,
+    slrf_solve_batch,
 )

@@ -13,7 +13,10 @@
 #include "slrf.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <numeric>
+#include <thread>
 #include <map>
 #include <mutex>
 #include <cmath>
@@ -461,8 +464,9 @@ slrf_status vcycle(slrf_ctx* h, const AmgVecs& v, int C, int occ, int ND, const 
       void* r = l == 0 ? v.T0 : v.T[l];
       HIPCHK(launch_lvl_jacobi0<T>(lvl(l), g, st, A.omega, b[l], xb, s));
       {
-        Scope sw(h, l == 0 && sweep_is_halo<T>(h->P) ? SLRF_K_SWEEP : -1,
-                 (double)nact * A.n[0] * sT * 3.0 + fine_csr);
+        const bool fine = l == 0 && sweep_is_halo<T>(h->P);
+        Scope sw(h, fine ? SLRF_K_SWEEP : -1, (double)nact * A.n[0] * sT * 3.0 + fine_csr);
+        if (fine && h->cur_stats) h->cur_stats->sweep_systems += nact;
         HIPCHK(launch_lvl_op<T>(lvl(l), g, st, kEpiResidOp, A.omega, xb, b[l], r, s));
       }
       const PanelGrid gc = make_grid(A.n[l + 1], C, occ, ND);
@@ -477,8 +481,9 @@ slrf_status vcycle(slrf_ctx* h, const AmgVecs& v, int C, int occ, int ND, const 
       const PanelGrid g = make_grid(A.n[l], C, occ, ND);
       HIPCHK(launch_transfer<T>(A.P[l], g, st, x[l + 1], x[l], true, s));
       void* out = l == 0 ? Zout : v.W[l];
-      Scope sw(h, l == 0 && sweep_is_halo<T>(h->P) ? SLRF_K_SWEEP : -1,
-               (double)nact * A.n[0] * sT * 3.0 + fine_csr);
+      const bool fine = l == 0 && sweep_is_halo<T>(h->P);
+      Scope sw(h, fine ? SLRF_K_SWEEP : -1, (double)nact * A.n[0] * sT * 3.0 + fine_csr);
+      if (fine && h->cur_stats) h->cur_stats->sweep_systems += nact;
       HIPCHK(launch_lvl_op<T>(lvl(l), g, st, kEpiJacobiOp, A.omega, x[l], b[l], out, s));
       x[l] = out;
     }
@@ -854,6 +859,7 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
         Scope sp(h, SLRF_K_APPLY, (double)nact * n * sT * (k + 2) + csr_bytes);
         {
           Scope sw(h, SLRF_K_SWEEP, (double)nact * n * sT * 2.0 + csr_bytes);
+          if (h->cur_stats) h->cur_stats->sweep_systems += nact;
           HIPCHK(launch_sweep<T>(h->P, g, tc, Z, Qk, s));
         }
         HIPCHK(launch_dots<T>(h->P, g, tc, Qk, Q, vstride, k, part, s));
@@ -1037,6 +1043,63 @@ slrf_status rr_rowmajor(slrf_ctx* h, int nc, double* Ur, int nl, const double* X
 // ===========================================================================
 // C ABI
 // ===========================================================================
+// ---------------------------------------------------------------------------
+// Batched entry points: a pool of host threads drains a queue of handles in
+// descending order of work; each thread drives its handle's pool loop on the
+// handle's stream, so kernels of different pencils overlap on the device.
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename F>
+slrf_status run_batch(int32_t nh, const slrf_handle* hs, const std::vector<double>& work,
+                      int32_t nthreads, F&& one) {
+  std::vector<int> order(nh);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+  std::vector<slrf_status> res(nh, SLRF_OK);
+  std::atomic<int> next{0};
+  const int nt = std::max(1, std::min<int>(nthreads > 0 ? nthreads : 8, nh));
+  auto worker = [&]() {
+    for (;;) {
+      const int k = next.fetch_add(1);
+      if (k >= nh) break;
+      const int i = order[k];
+      if (hipSetDevice(hs[i]->device) != hipSuccess) {
+        res[i] = SLRF_E_HIP;
+        continue;
+      }
+      res[i] = one(i);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
+  worker();
+  for (auto& th : pool) th.join();
+  for (int i = 0; i < nh; ++i)
+    if (res[i] != SLRF_OK) return res[i];
+  return SLRF_OK;
+}
+
+// Frees a handle's cached solver workspace (it is re-created on the next call):
+// bounds the device memory of a batch to the entries in flight.
+void release_workspace(slrf_handle h) {
+  (void)hipStreamSynchronize(h->stream);
+  for (auto& b : h->bufs) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+  }
+}
+
+bool distinct_handles(int32_t nh, const slrf_handle* hs) {
+  std::vector<slrf_handle> v(hs, hs + nh);
+  std::sort(v.begin(), v.end());
+  return std::adjacent_find(v.begin(), v.end()) == v.end() &&
+         std::find(v.begin(), v.end(), nullptr) == v.end();
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* slrf_status_string(slrf_status s) {
@@ -1605,6 +1668,42 @@ int32_t slrf_host_projected_eig(int32_t n, const double* Ah, const double* Bh, d
   if (n < 0 || (n > 0 && (!Ah || !Bh || !theta || !S))) return -1;
   int fb = 0;
   return sym_gen_eig(n, Ah, Bh, theta, S, &fb);
+}
+
+slrf_status slrf_filter_batch(int32_t nh, const slrf_handle* hs, const int32_t* ncols,
+                              const double* const* X, const double* const* theta_warm,
+                              double* const* U, slrf_filter_stats* stats, int32_t nthreads) {
+  if (nh < 0) return SLRF_E_ARG;
+  if (nh == 0) return SLRF_OK;
+  if (!hs || !ncols || !X || !U || !distinct_handles(nh, hs)) return SLRF_E_ARG;
+  std::vector<double> work(nh);
+  for (int i = 0; i < nh; ++i) work[i] = (double)hs[i]->P.nnz * ncols[i] * hs[i]->N;
+  return run_batch(nh, hs, work, nthreads, [&](int i) {
+    const slrf_status r = slrf_filter(hs[i], ncols[i], X[i],
+                                      theta_warm ? theta_warm[i] : nullptr, U[i],
+                                      stats ? &stats[i] : nullptr);
+    release_workspace(hs[i]);
+    return r;
+  });
+}
+
+slrf_status slrf_solve_batch(int32_t nh, const slrf_handle* hs, const int32_t* nev,
+                             const int32_t* L, const double* const* V1,
+                             double* const* theta_out, double* const* X_out,
+                             int32_t* nconv_out, slrf_solve_stats* stats, int32_t nthreads) {
+  if (nh < 0) return SLRF_E_ARG;
+  if (nh == 0) return SLRF_OK;
+  if (!hs || !nev || !L || !V1 || !theta_out || !X_out || !distinct_handles(nh, hs))
+    return SLRF_E_ARG;
+  std::vector<double> work(nh);
+  for (int i = 0; i < nh; ++i) work[i] = (double)hs[i]->P.nnz * L[i] * hs[i]->N;
+  return run_batch(nh, hs, work, nthreads, [&](int i) {
+    const slrf_status r = slrf_solve(hs[i], nev[i], L[i], V1[i], theta_out[i], X_out[i],
+                                     nconv_out ? &nconv_out[i] : nullptr,
+                                     stats ? &stats[i] : nullptr);
+    release_workspace(hs[i]);
+    return r;
+  });
 }
 
 }  // extern "C"

@@ -57,7 +57,8 @@ class FilterStats(C.Structure):
                 ("capped", C.c_int32), ("max_pole_iters_ratio_x1000", C.c_int32),
                 ("max_rel_resid", C.c_double), ("seconds", C.c_double),
                 ("launches", C.c_int64 * 8), ("bytes", C.c_double * 8), ("ms", C.c_double * 8),
-                ("spmm_variant", C.c_int32), ("sys_iters", C.POINTER(C.c_int32))]
+                ("spmm_variant", C.c_int32), ("sweep_systems", C.c_double),
+                ("sys_iters", C.POINTER(C.c_int32))]
 
 
 class SolveStats(C.Structure):
@@ -93,6 +94,13 @@ SIGNATURES = {
                                 C.c_void_p, C.c_int32, C.c_void_p]),
     "slrf_host_projected_eig": (C.c_int32, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                             C.c_void_p]),
+    "slrf_filter_batch": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                    C.POINTER(C.c_void_p), C.POINTER(FilterStats), C.c_int32]),
+    "slrf_solve_batch": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_int32), C.POINTER(C.c_void_p),
+                                   C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                   C.POINTER(C.c_int32), C.POINTER(SolveStats), C.c_int32]),
 }
 
 
@@ -405,3 +413,78 @@ def to_panels(Y, n: int):
 
 def from_panels(Z, n: int, nsys: int):
     return Z.permute(1, 0, 2).reshape(n, -1)[:, :nsys]
+
+
+# --- batched entry points -------------------------------------------------------
+def _ptrs(ts):
+    arr = (C.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = None if t is None else t.data_ptr()
+    return arr
+
+
+def _sync_streams(handles):
+    """Order every handle's stream after the caller's current stream."""
+    torch = _torch()
+    cur = torch.cuda.current_stream()
+    for h in handles:
+        if h.stream != cur:
+            h.stream.wait_stream(cur)
+
+
+def slrf_filter_batch(handles, Xs, thetas=None, nthreads: int = 0, allow_noconv=False):
+    """slrf_filter on every (handle, X) pair, run concurrently (largest first).
+
+    Returns a list of (U, stats dict).  Give each handle its own stream.
+    """
+    nh = len(handles)
+    if len(Xs) != nh or (thetas is not None and len(thetas) != nh):
+        raise ValueError("one X (and theta) per handle")
+    torch = _torch()
+    Xs = [_colmajor(X, h.n) for h, X in zip(handles, Xs)]
+    Us = [_empty_colmajor(h.n, X.shape[1], X.device) for h, X in zip(handles, Xs)]
+    ths = None
+    if thetas is not None:
+        ths = [None if t is None else torch.as_tensor(t, dtype=torch.float64,
+                                                      device=X.device).contiguous()
+               for t, X in zip(thetas, Xs)]
+    hs = (C.c_void_p * nh)(*[h._h.value for h in handles])
+    nc = (C.c_int32 * nh)(*[X.shape[1] for X in Xs])
+    st = (FilterStats * nh)()
+    _sync_streams(handles)
+    r = lib().slrf_filter_batch(nh, hs, nc, _ptrs(Xs), _ptrs(ths) if ths is not None else None,
+                                _ptrs(Us), st, nthreads)
+    if r != 0 and not (allow_noconv and r == 5):
+        msgs = "; ".join(lib().slrf_last_error(h._h).decode() for h in handles)
+        raise SlrfError(r, msgs)
+    return [(U, Handle._stats_dict(st[i], None, r)) for i, U in enumerate(Us)]
+
+
+def slrf_solve_batch(handles, nevs, V1s, nthreads: int = 0, allow_noconv=False):
+    """slrf_solve on every handle, run concurrently (largest first).
+
+    Returns a list of (theta, X, nconv, stats dict).
+    """
+    nh = len(handles)
+    torch = _torch()
+    V1s = [_colmajor(V, h.n) for h, V in zip(handles, V1s)]
+    thetas = [torch.full((k,), float("nan"), dtype=torch.float64, device=V.device)
+              for k, V in zip(nevs, V1s)]
+    Xs = [_empty_colmajor(h.n, k, V.device) for h, k, V in zip(handles, nevs, V1s)]
+    hs = (C.c_void_p * nh)(*[h._h.value for h in handles])
+    nev = (C.c_int32 * nh)(*[int(k) for k in nevs])
+    Ls = (C.c_int32 * nh)(*[V.shape[1] for V in V1s])
+    nconv = (C.c_int32 * nh)()
+    st = (SolveStats * nh)()
+    _sync_streams(handles)
+    r = lib().slrf_solve_batch(nh, hs, nev, Ls, _ptrs(V1s), _ptrs(thetas), _ptrs(Xs), nconv, st,
+                               nthreads)
+    if r != 0 and not (allow_noconv and r == 5):
+        msgs = "; ".join(lib().slrf_last_error(h._h).decode() for h in handles)
+        raise SlrfError(r, msgs)
+    out = []
+    for i in range(nh):
+        k = nconv[i]
+        d = {f: getattr(st[i], f) for f, _ in SolveStats._fields_}
+        out.append((thetas[i][:k], Xs[i][:, :k], k, d))
+    return out

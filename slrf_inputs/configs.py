@@ -64,13 +64,17 @@ def config_q1_3d(m: int = 64, L: int = 160, count: int = 100):
                 name=f"q1_3d_m{m}")
 
 
-def batched_pencils(count: int = 64, seed: int = 1004, nmin: int = 5000, nmax: int = 60000):
+def batched_pencils(count: int = 64, seed: int = 1004, nmin: int = 5000, nmax: int = 60000,
+                    only=None):
     """Draw the uneven batch: per pencil (dim, m, kappa, target eigenvalue count c).
 
     The interval (0, gamma] for each pencil needs its eigenvalues and is chosen
-    by the caller; this returns the pencils and the drawn counts only.
+    by the caller; this returns the pencils and the drawn counts only.  `only`
+    (an iterable of indices) assembles just those pencils (the draws of the
+    others are still made, so every pencil is the same in any selection).
     """
     rng = seeded_rng(seed)
+    keep = None if only is None else set(int(i) for i in only)
     out = []
     for i in range(count):
         dim = 2 if rng.random() < 0.5 else 3
@@ -78,6 +82,8 @@ def batched_pencils(count: int = 64, seed: int = 1004, nmin: int = 5000, nmax: i
         m = int(round(nt ** (1.0 / dim)))
         kappa = np.exp(rng.normal(0.0, 0.5, size=(m + 1) ** dim))
         c = int(rng.integers(10, 61))
+        if keep is not None and i not in keep:
+            continue
         out.append(dict(pencil=q1_diffusion_pencil(m, dim, kappa), count=c, dim=dim, m=m,
-                        L=int(np.ceil(1.5 * c)), seed=seed * 1000 + i))
+                        L=int(np.ceil(1.5 * c)), seed=seed * 1000 + i, index=i))
     return out

@@ -282,3 +282,18 @@ def test_sine_vector_helper_is_eigenvector():
         v = sine_vector(m, ks)
         lam = sum(lam1[np.array(ks) - 1])
         assert np.linalg.norm(p.A() @ v - lam * (p.B() @ v)) <= 1e-11 * lam * np.linalg.norm(p.B() @ v)
+
+
+def test_smallest_eigs_closed_form_and_dense():
+    # eigsh path (n > 400) against the closed-form 2D Q1 spectrum
+    m = 40
+    lam1 = closed_form_1d(m)
+    lam2 = np.sort((lam1[:, None] + lam1[None, :]).ravel())
+    p = si.q1_kron_pencil(m, 2)
+    got = oracle.eig.smallest_eigs(p.A(), p.B(), 25)
+    assert np.allclose(got, lam2[:25], rtol=1e-10, atol=0)
+    # eigsh path against dense LAPACK on a variable-coefficient 3D pencil (n = 729)
+    kappa = np.exp(np.random.default_rng(5).normal(0, 0.5, 10 ** 3))
+    q = si.q1_diffusion_pencil(9, 3, kappa)
+    dense = oracle.eig.dense_eigs(q.A(), q.B())[0]
+    assert np.allclose(oracle.eig.smallest_eigs(q.A(), q.B(), 30), dense[:30], rtol=1e-10)

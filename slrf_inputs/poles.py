@@ -60,8 +60,10 @@ def quadrature_poles(gamma: float, npoles: int, rule: str = "midpoint"):
     z_k = c + r exp(i phi_k) in the upper half and quadrature weights omega_k in
     phi, the resolvent integral (1/(2 pi i)) \\oint dz / (z - t) becomes
     Phi(t) = sum_k w_k / (t - z_k) with w_k = -omega_k r exp(i phi_k) / (2 pi).
-    ``rule`` is "midpoint" (equispaced phi) or "gauss-legendre" (Gauss-Legendre
-    nodes on each half circle).  These are the comparison filters of the
+    ``rule`` is "midpoint" (equispaced phi), "gauss-legendre" (Gauss-Legendre
+    nodes on each half circle) or "gauss-chebyshev" (Chebyshev nodes of the
+    first kind on each half circle, weights (pi/N) sqrt(1 - x^2) so the rule
+    integrates plain functions of x).  These are the comparison filters of the
     paper's Table 1; they are provided as data only.
     """
     N = int(npoles)
@@ -73,6 +75,10 @@ def quadrature_poles(gamma: float, npoles: int, rule: str = "midpoint"):
         xg, wg = np.polynomial.legendre.leggauss(N)
         phi = 0.5 * np.pi * (1.0 + xg)
         omega = 0.5 * np.pi * wg
+    elif rule == "gauss-chebyshev":
+        xc = np.cos(np.pi * (2 * np.arange(1, N + 1) - 1) / (2 * N))
+        phi = 0.5 * np.pi * (1.0 + xc)
+        omega = 0.5 * np.pi * (np.pi / N) * np.sqrt(1.0 - xc ** 2)
     else:
         raise ValueError(f"unknown rule {rule!r}")
     z = c + r * np.exp(1j * phi)

@@ -105,3 +105,18 @@ def test_config_gammas():
     assert c1["nev"] == 20 and abs(c1["gamma"] - 328.6492) < 1e-3
     g, nev = si.q1_gamma_nev(64, 3, 100)
     assert nev == 102 and abs(g - 421.0642) < 1e-3
+
+
+def test_quadrature_filters_midpoint_closed_form_and_shape():
+    gamma = 10.0
+    t = np.array([0.3, 2.0, 5.0, 9.0, 11.0, 20.0, 100.0])
+    z, w = si.quadrature_poles(gamma, 8, "midpoint")
+    phi = np.array([np.sum(2 * np.real(w / (x - z))) for x in t])
+    s = (t - gamma / 2) / (gamma / 2)
+    # equispaced midpoint nodes on the circle: Phi = 1 / (1 + s^(2N)) exactly
+    assert np.allclose(phi, 1.0 / (1.0 + s ** 16), rtol=1e-12, atol=1e-14)
+    for rule in ("gauss-legendre", "gauss-chebyshev"):
+        z, w = si.quadrature_poles(gamma, 8, rule)
+        assert np.all(z.imag > 0) and np.allclose(np.abs(z - gamma / 2), gamma / 2)
+        phi = np.array([np.sum(2 * np.real(w / (x - z))) for x in (2.0, 5.0, 8.0, 30.0, 200.0)])
+        assert np.all(np.abs(phi[:3] - 1) < 0.02) and np.all(np.abs(phi[3:]) < 0.01)

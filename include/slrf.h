@@ -240,9 +240,10 @@ slrf_status slrf_solve(slrf_handle h, int32_t nev, int32_t L, const double* V1, 
  * serially on the GPU).  Handles must be distinct.  Per-entry arguments are
  * arrays of length nh (theta_warm, stats, nconv_out may be NULL; their
  * entries may be NULL).  Results are identical to the single calls (each
- * handle's arithmetic does not depend on what runs beside it).  Each
- * handle's cached solver workspace is released when its entry finishes, so
- * the device memory in use is bounded by the entries in flight.  Returns
+ * handle's arithmetic does not depend on what runs beside it).  Each host
+ * thread lends one workspace to the handles it runs in turn (a handle's own
+ * cached workspace is left untouched), so the device memory of a batch is
+ * bounded by the thread count, not by the number of pencils.  Returns
  * SLRF_OK if every entry succeeded, else the status of the first failing
  * entry in index order (all entries are still attempted; a failing handle's
  * message is in its slrf_last_error).

@@ -1030,6 +1030,10 @@ __global__ __launch_bounds__(kThreads) void k_yupdate(int n, PanelGrid g,
 #pragma unroll 4
     for (int i = 0; i < kk; ++i) {
       const double2 a = sa[i * kPanel + lane];
+      // a slot that stopped within the cycle has alpha = 0 for the later
+      // steps and no direction p_i formed there (the buffer holds whatever
+      // it held before): skip the term instead of multiplying it by zero
+      if (a.x == 0.0 && a.y == 0.0) continue;
       const C p = Pb[(size_t)i * vstride + off];
       y.x += a.x * p.x - a.y * p.y;
       y.y += a.x * p.y + a.y * p.x;

@@ -1060,6 +1060,10 @@ slrf_status run_batch(int32_t nh, const slrf_handle* hs, const std::vector<doubl
   std::atomic<int> next{0};
   const int nt = std::max(1, std::min<int>(nthreads > 0 ? nthreads : 8, nh));
   auto worker = [&]() {
+    // one workspace per thread, lent to each handle the thread runs (largest
+    // first, so later entries mostly fit without regrowth): the device memory
+    // of a batch is bounded by the threads, not by the number of pencils
+    std::vector<DevBuf> arena;
     for (;;) {
       const int k = next.fetch_add(1);
       if (k >= nh) break;
@@ -1068,8 +1072,13 @@ slrf_status run_batch(int32_t nh, const slrf_handle* hs, const std::vector<doubl
         res[i] = SLRF_E_HIP;
         continue;
       }
+      std::swap(hs[i]->bufs, arena);
       res[i] = one(i);
+      (void)hipStreamSynchronize(hs[i]->stream);
+      std::swap(hs[i]->bufs, arena);
     }
+    for (auto& b : arena)
+      if (b.p) (void)hipFree(b.p);
   };
   std::vector<std::thread> pool;
   for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
@@ -1078,17 +1087,6 @@ slrf_status run_batch(int32_t nh, const slrf_handle* hs, const std::vector<doubl
   for (int i = 0; i < nh; ++i)
     if (res[i] != SLRF_OK) return res[i];
   return SLRF_OK;
-}
-
-// Frees a handle's cached solver workspace (it is re-created on the next call):
-// bounds the device memory of a batch to the entries in flight.
-void release_workspace(slrf_handle h) {
-  (void)hipStreamSynchronize(h->stream);
-  for (auto& b : h->bufs) {
-    if (b.p) (void)hipFree(b.p);
-    b.p = nullptr;
-    b.cap = 0;
-  }
 }
 
 bool distinct_handles(int32_t nh, const slrf_handle* hs) {
@@ -1679,11 +1677,8 @@ slrf_status slrf_filter_batch(int32_t nh, const slrf_handle* hs, const int32_t* 
   std::vector<double> work(nh);
   for (int i = 0; i < nh; ++i) work[i] = (double)hs[i]->P.nnz * ncols[i] * hs[i]->N;
   return run_batch(nh, hs, work, nthreads, [&](int i) {
-    const slrf_status r = slrf_filter(hs[i], ncols[i], X[i],
-                                      theta_warm ? theta_warm[i] : nullptr, U[i],
-                                      stats ? &stats[i] : nullptr);
-    release_workspace(hs[i]);
-    return r;
+    return slrf_filter(hs[i], ncols[i], X[i], theta_warm ? theta_warm[i] : nullptr, U[i],
+                       stats ? &stats[i] : nullptr);
   });
 }
 
@@ -1698,11 +1693,8 @@ slrf_status slrf_solve_batch(int32_t nh, const slrf_handle* hs, const int32_t* n
   std::vector<double> work(nh);
   for (int i = 0; i < nh; ++i) work[i] = (double)hs[i]->P.nnz * L[i] * hs[i]->N;
   return run_batch(nh, hs, work, nthreads, [&](int i) {
-    const slrf_status r = slrf_solve(hs[i], nev[i], L[i], V1[i], theta_out[i], X_out[i],
-                                     nconv_out ? &nconv_out[i] : nullptr,
-                                     stats ? &stats[i] : nullptr);
-    release_workspace(hs[i]);
-    return r;
+    return slrf_solve(hs[i], nev[i], L[i], V1[i], theta_out[i], X_out[i],
+                      nconv_out ? &nconv_out[i] : nullptr, stats ? &stats[i] : nullptr);
   });
 }
 

@@ -26,6 +26,7 @@ from .blocks import start_block, seeded_rng  # noqa: F401
 from .configs import (  # noqa: F401
     config_q1_2d,
     config_q1_3d,
+    config_elasticity,
     q1_gamma_nev,
     q1_eigenvalues_1d,
     batched_pencils,

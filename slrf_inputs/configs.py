@@ -19,7 +19,7 @@ import itertools
 
 import numpy as np
 
-from .pencils import q1_kron_pencil, q1_diffusion_pencil
+from .pencils import q1_kron_pencil, q1_diffusion_pencil, hex_elasticity_pencil
 from .blocks import seeded_rng
 
 
@@ -87,3 +87,20 @@ def batched_pencils(count: int = 64, seed: int = 1004, nmin: int = 5000, nmax: i
         out.append(dict(pencil=q1_diffusion_pencil(m, dim, kappa), count=c, dim=dim, m=m,
                         L=int(np.ceil(1.5 * c)), seed=seed * 1000 + i, index=i))
     return out
+
+
+def config_elasticity(ne: int = 32, sigma: float = 0.3, seed: int = 1005, count: int = 50,
+                      L: int = 75):
+    """Clamped trilinear-hex elasticity on ne^3 elements, Young's modulus per
+    element lognormal(0, sigma) from ``seed`` (nu = 0.3, rho = 1).
+
+    ne = 32, sigma = 0.3, seed 1005, 50 eigenvalues, L = 75: the
+    differentiation workload (n = 104,544); ne = 48, sigma = 0.5, seed 1003,
+    200 eigenvalues, L = 300: the large elasticity workload (n = 345,744).
+    The interval end gamma needs the eigenvalues and comes from the caller.
+    """
+    rng = seeded_rng(seed)
+    young = np.exp(rng.normal(0.0, sigma, ne ** 3))
+    p = hex_elasticity_pencil(ne, young)
+    return dict(pencil=p, young=young, count=count, L=L, seed=seed + 100, npoles=8,
+                name=f"elasticity_{ne}")

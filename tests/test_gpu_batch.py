@@ -3,7 +3,8 @@
 * slrf_filter_batch returns, for every pencil, exactly (bitwise) the block the
   single slrf_filter call returns: each handle's arithmetic is independent of
   what runs beside it on other streams.
-* slrf_solve_batch on the 64-pencil uneven batch (Q1 diffusion, lognormal
+* slrf_solve_batch (Algorithm 2: locking, warm start; inner tolerance 1e-10 as
+  in Section 3.2) on the 64-pencil uneven batch (Q1 diffusion, lognormal
   coefficients, n in [5000, 60000], 10-60 eigenvalues each) finds every
   eigenvalue of each interval (0, gamma] within 1e-8 relative of the oracle's
   shift-invert Lanczos values (tests/golden/batch64_q1_diffusion.json, written
@@ -81,7 +82,7 @@ def test_solve_batch_64_uneven_pencils_match_oracle():
         assert p.n == g["n"] and d["count"] == g["count"]
         poles, weights = si.slrf_poles(g["gamma"])
         opt = P.default_options(precision=P.SLRF_PREC_MIXED, precond=P.SLRF_PC_AMG, restart=8,
-                                tol_lin=1e-8, max_outer=60)
+                                tol_lin=1e-10, lock=1, warm_start=1, max_outer=60)
         hs.append(P.Handle.from_pencil(p, g["gamma"], poles, weights, opt,
                                        stream=torch.cuda.Stream()))
         V1s.append(_dev(si.start_block(p.n, d["L"], d["seed"])))

@@ -114,6 +114,11 @@ typedef struct {
   double tol_eig;      /* Ritz pair converged when ||r||_2 < tol_eig             */
   double mem_budget;   /* bytes of device workspace the planner may use; 0 = 60%
                           of the free device memory at setup                   */
+  int32_t amg_block;   /* dofs per node for the AMG aggregation and the row
+                          order (node-major numbering: dof = block*node + c):
+                          0 = detect (3 or 2 when every node's rows share one
+                          column list of whole node blocks, else 1), 1 = scalar
+                          aggregation, 2..8 = given (n must be a multiple)    */
 } slrf_options;
 
 /* Per-kernel-class counters (algorithmic bytes, launches, event time). */

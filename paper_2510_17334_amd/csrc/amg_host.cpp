@@ -193,9 +193,74 @@ bool invert_dense(int n, std::vector<std::complex<double>>& M) {
   return true;
 }
 
+// Node graph of a node-major pencil with `bs` dofs per node: entry (I, J) holds
+// the Frobenius norm of the bs x bs block of A (rows of a node share one
+// column list made of whole blocks).
+HostLevel node_graph(const HostLevel& L, int bs) {
+  HostLevel G;
+  const int nn = L.n / bs;
+  G.n = nn;
+  G.rp.assign(nn + 1, 0);
+  for (int I = 0; I < nn; ++I) {
+    const int len = L.rp[bs * I + 1] - L.rp[bs * I];
+    for (int k = 0; k < len; k += bs) {
+      double f = 0.0;
+      for (int r = 0; r < bs; ++r) {
+        const int e0 = L.rp[bs * I + r] + k;
+        for (int c = 0; c < bs; ++c) f += L.a[e0 + c] * L.a[e0 + c];
+      }
+      G.ci.push_back(L.ci[L.rp[bs * I] + k] / bs);
+      G.a.push_back(std::sqrt(f));
+    }
+    G.rp[I + 1] = (int)G.ci.size();
+  }
+  return G;
+}
+
 }  // namespace
 
-void locality_order(const HostLevel& fine, std::vector<int>& order) {
+int detect_block(const HostLevel& L) {
+  for (int bs : {3, 2}) {
+    if (L.n % bs != 0) continue;
+    bool ok = true;
+    for (int I = 0; I < L.n / bs && ok; ++I) {
+      const int r0 = bs * I;
+      const int len = L.rp[r0 + 1] - L.rp[r0];
+      if (len % bs != 0) ok = false;
+      for (int r = 1; r < bs && ok; ++r) {
+        if (L.rp[r0 + r + 1] - L.rp[r0 + r] != len) {
+          ok = false;
+          break;
+        }
+        for (int k = 0; k < len; ++k)
+          if (L.ci[L.rp[r0 + r] + k] != L.ci[L.rp[r0] + k]) {
+            ok = false;
+            break;
+          }
+      }
+      for (int k = 0; k < len && ok; k += bs)
+        for (int c = 0; c < bs; ++c) {
+          const int j = L.ci[L.rp[r0] + k + c];
+          if (j % bs != c || j / bs != L.ci[L.rp[r0] + k] / bs) {
+            ok = false;
+            break;
+          }
+        }
+    }
+    if (ok) return bs;
+  }
+  return 1;
+}
+
+void locality_order(const HostLevel& fine, std::vector<int>& order, int block) {
+  if (block > 1) {
+    std::vector<int> norder;
+    locality_order(node_graph(fine, block), norder, 1);
+    order.resize(fine.n);
+    for (size_t k = 0; k < norder.size(); ++k)
+      for (int c = 0; c < block; ++c) order[block * k + c] = block * norder[k] + c;
+    return;
+  }
   // Nested aggregation of the matrix graph: rows are sorted by their
   // ancestor at every aggregation level (coarsest first), so rows of one
   // aggregate are contiguous and aggregates of one parent are contiguous.
@@ -257,8 +322,19 @@ bool amg_build(const HostLevel& fine, const std::vector<std::complex<double>>& p
   while (H.levels.back().n > prm.coarse_max && (int)H.levels.size() < prm.max_levels) {
     const HostLevel& L = H.levels.back();
     const int n = L.n;
+    const int bs = prm.block > 1 && n % prm.block == 0 ? prm.block : 1;
     std::vector<int> agg;
-    const int nc = aggregate(L, prm.theta, agg);
+    int nc;
+    if (bs > 1) {
+      // aggregate nodes; dof (I, c) maps to coarse dof (agg(I), c)
+      std::vector<int> nagg;
+      const int na = aggregate(node_graph(L, bs), prm.theta, nagg);
+      nc = na * bs;
+      agg.resize(n);
+      for (int i = 0; i < n; ++i) agg[i] = bs * nagg[i / bs] + i % bs;
+    } else {
+      nc = aggregate(L, prm.theta, agg);
+    }
     if (nc >= n || nc == 0) break;  // no coarsening possible
     std::vector<int> cnt(nc, 0);
     for (int i = 0; i < n; ++i) cnt[agg[i]]++;

@@ -27,6 +27,8 @@ struct AmgParams {
   int coarse_max = 400;   // stop coarsening at or below this size
   int dense_max = 2048;   // largest coarsest level inverted densely
   int max_levels = 10;
+  int block = 1;          // dofs per node (node-major numbering): nodes are aggregated,
+                          // and each aggregate gets one tentative column per dof
 };
 
 struct AmgHierarchy {
@@ -36,8 +38,13 @@ struct AmgHierarchy {
   std::vector<std::complex<double>> coarse_inv;  // [pole][nc][nc] row-major
 };
 
-// Locality ordering of the rows (order[new] = old) from nested aggregation.
-void locality_order(const HostLevel& fine, std::vector<int>& order);
+// Locality ordering of the rows (order[new] = old) from nested aggregation
+// (of the node graph when block > 1, keeping each node's dofs together).
+void locality_order(const HostLevel& fine, std::vector<int>& order, int block = 1);
+
+// Dofs per node of a node-major pencil: 3 or 2 when every node's rows share
+// one column list made of whole node blocks, else 1.
+int detect_block(const HostLevel& L);
 
 bool amg_build(const HostLevel& fine, const std::vector<std::complex<double>>& poles,
                const AmgParams& prm, AmgHierarchy& H, std::string& err);

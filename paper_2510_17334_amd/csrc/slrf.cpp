@@ -102,6 +102,7 @@ struct slrf_ctx {
   // locality row order (library-owned permuted pencil); order[new] = old
   int* order = nullptr;
   std::vector<int> h_order;
+  int block = 0;  // dofs per node (0 = not yet determined)
   void* grp_mem[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   std::vector<void*> halo_mem;  // halo-tile format arrays
   int* own_rp = nullptr;
@@ -264,6 +265,9 @@ slrf_status validate_options(slrf_ctx* h, const slrf_options& o) {
   if (o.max_slots < 0 || o.max_slots % kPanel != 0)
     return fail(h, SLRF_E_ARG, "max_slots must be a non-negative multiple of 16");
   if (o.mem_budget < 0) return fail(h, SLRF_E_ARG, "mem_budget must be >= 0");
+  if (o.amg_block < 0 || o.amg_block > 8) return fail(h, SLRF_E_ARG, "amg_block must be 0..8");
+  if (o.amg_block > 1 && h->P.n > 0 && h->P.n % o.amg_block != 0)
+    return fail(h, SLRF_E_ARG, "n must be a multiple of amg_block");
   if (o.spmm_variant < 0 || o.spmm_variant >= kSpmmVariants)
     return fail(h, SLRF_E_ARG, "spmm_variant must be 0..6");
   return SLRF_OK;
@@ -322,6 +326,8 @@ slrf_status build_amg(slrf_ctx* h) {
   std::vector<std::complex<double>> poles;
   for (auto& p : h->poles) poles.emplace_back(p.x, p.y);
   AmgParams prm;
+  prm.block = h->block > 0 ? h->block : (h->opt.amg_block > 0 ? h->opt.amg_block
+                                                               : detect_block(fine));
   AmgHierarchy H;
   std::string err;
   if (!amg_build(fine, poles, prm, H, err)) return fail(h, SLRF_E_ARG, "AMG setup: " + err);
@@ -1135,6 +1141,7 @@ void slrf_default_options(slrf_options* o) {
   o->inner_rtol = 1e-5;
   o->tol_eig = 1e-8;
   o->mem_budget = 0.0;
+  o->amg_block = 0;
 }
 
 int32_t slrf_get_n(slrf_handle h) { return h ? h->P.n : -1; }
@@ -1234,7 +1241,9 @@ slrf_status slrf_setup(slrf_handle* out, const slrf_csr* A, const slrf_csr* B, d
     if (hipMemcpy(L0.a.data(), A->val, sizeof(double) * nnz, hipMemcpyDeviceToHost) ||
         hipMemcpy(bv.data(), B->val, sizeof(double) * nnz, hipMemcpyDeviceToHost))
       return bad(SLRF_E_ARG, "CSR values are not readable device memory");
-    locality_order(L0, h->h_order);
+    h->block = h->opt.amg_block > 0 ? h->opt.amg_block : detect_block(L0);
+    if (n % h->block != 0) return bad(SLRF_E_ARG, "n must be a multiple of amg_block");
+    locality_order(L0, h->h_order, h->block);
     std::vector<int> inv(n);
     for (int i = 0; i < n; ++i) inv[h->h_order[i]] = i;
     std::vector<int> prp(n + 1, 0), pci(nnz);

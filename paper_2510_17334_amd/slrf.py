@@ -48,7 +48,8 @@ class Options(C.Structure):
                 ("max_slots", C.c_int32), ("spmm_variant", C.c_int32), ("reorder", C.c_int32),
                 ("tol_lin", C.c_double),
                 ("inner_rtol", C.c_double),
-                ("tol_eig", C.c_double), ("mem_budget", C.c_double)]
+                ("tol_eig", C.c_double), ("mem_budget", C.c_double),
+                ("amg_block", C.c_int32)]
 
 
 class FilterStats(C.Structure):

@@ -104,7 +104,8 @@ GOLD_E32 = os.path.join(os.path.dirname(__file__), "golden", "elasticity32.json"
 @pytest.mark.skipif(not os.path.exists(GOLD_E32), reason="golden elasticity eigenvalues missing")
 def test_elasticity32_solve_and_gradient_full_size():
     """The differentiation workload at full size (n = 104,544, 50 eigenvalues):
-    mixed Algorithm 2 eigenvalues vs the oracle's shift-invert Lanczos (1e-8),
+    mixed Algorithm 2 eigenvalues vs the oracle's shift-invert Lanczos (1e-8
+    relative after refinement; FP64 residuals of every inner solve 1e-10),
     the adjoint kernel vs the oracle's per-element formula on 20 sampled
     elements (same eigenvectors, 1e-10), and Euler homogeneity over all 32,768
     elements (sum_e E_e dL/dE_e = sum_i lambda_i)."""
@@ -113,8 +114,10 @@ def test_elasticity32_solve_and_gradient_full_size():
     p = c["pencil"]
     assert p.n == gold["n"]
     poles, weights = si.slrf_poles(gold["gamma"])
-    opt = P.default_options(precision=P.SLRF_PREC_MIXED, precond=P.SLRF_PC_AMG, restart=8,
-                            tol_lin=1e-10, lock=1, warm_start=1, max_outer=60)
+    # Algorithm 2 (locking, warm start, It_max-linear = 60); point Jacobi: the
+    # scalar-block aggregation hierarchy lacks the rotation modes elasticity needs
+    opt = P.default_options(precision=P.SLRF_PREC_MIXED, precond=P.SLRF_PC_JACOBI, restart=30,
+                            tol_lin=1e-10, lock=1, warm_start=1, max_outer=60, it_max_lin=60)
     h = P.Handle.from_pencil(p, gold["gamma"], poles, weights, opt)
     V1 = _dev(si.start_block(p.n, c["L"], c["seed"]))
     theta, X, nconv, st = h.slrf_solve(c["count"], V1)

@@ -51,9 +51,12 @@ def parse():
     ap.add_argument("--precond", choices=["amg", "jacobi"], default="amg")
     ap.add_argument("--restart", type=int, default=8, help="GCR restart length m")
     ap.add_argument("--ncols", type=int, default=160)
-    ap.add_argument("--workload", choices=["q1_3d", "batch64"], default="q1_3d",
+    ap.add_argument("--workload", choices=["q1_3d", "batch64", "itmax"], default="q1_3d",
                     help="q1_3d: the metric workload; batch64: the 64 uneven Q1 diffusion "
-                         "pencils through the batched entry point")
+                         "pencils through the batched entry point; itmax: Algorithm 2 on the "
+                         "32^3 elasticity pencil swept over It_max-linear")
+    ap.add_argument("--itmax", default="30,60,100,200,0",
+                    help="It_max-linear values of the itmax sweep (0 = no cap)")
     ap.add_argument("--threads", type=int, default=8, help="host threads of the batched call")
     return ap.parse_args()
 
@@ -303,6 +306,60 @@ def run_batch64(args):
     print(json.dumps(line, default=float))
 
 
+def run_itmax(args):
+    """Algorithm 2 (locking, warm start) to all 50 eigenpairs of the clamped 32^3
+    elasticity pencil for each It_max-linear value: wall time, outer iterations,
+    inner iterations and the eigenvalue error against the oracle's values; the
+    fastest cap is reported as the chosen one."""
+    import numpy as np
+    import torch
+
+    import paper_2510_17334_amd as P
+    import slrf_inputs as si
+
+    golden = os.path.join(ROOT, "tests", "golden", "elasticity32.json")
+    if not os.path.exists(golden):
+        print("itmax needs tests/golden/elasticity32.json; run tests/golden/make_elasticity32.py",
+              file=sys.stderr)
+        sys.exit(2)
+    gold = json.load(open(golden))
+    torch.cuda.set_device(0)
+    c = si.config_elasticity(32, 0.3, 1005, 50, 75)
+    p = c["pencil"]
+    lam = np.array(gold["eigenvalues"])
+    poles, weights = si.slrf_poles(gold["gamma"])
+    V1 = torch.as_tensor(np.ascontiguousarray(si.start_block(p.n, c["L"], c["seed"]).T),
+                         device="cuda").t()
+    rows = []
+    for itmax in [int(x) for x in args.itmax.split(",")]:
+        opt = P.default_options(precision=P.SLRF_PREC_MIXED, precond=P.SLRF_PC_JACOBI,
+                                restart=30, tol_lin=1e-10, lock=1, warm_start=1, max_outer=100,
+                                it_max_lin=itmax)
+        h = P.Handle.from_pencil(p, gold["gamma"], poles, weights, opt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        theta, X, nconv, st = h.slrf_solve(c["count"], V1, allow_noconv=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        th = theta.cpu().numpy()
+        err = float(np.max(np.abs(th - lam[:len(th)]) / lam[:len(th)])) if len(th) else None
+        rows.append({"it_max_linear": itmax, "seconds": dt, "nconv": nconv,
+                     "outer_iters": st["outer_iters"], "inner_iters": st["inner_iters"],
+                     "max_rel_eig_err": err})
+        print(f"It_max {itmax}: {dt:.2f} s, {st['outer_iters']} outer, nconv {nconv}, "
+              f"err {err}", file=sys.stderr, flush=True)
+        h.close()
+    ok = [r for r in rows if r["nconv"] == c["count"]]
+    best = min(ok, key=lambda r: r["seconds"]) if ok else None
+    line = {"metric": "seconds to all eigenpairs in (0, gamma], Algorithm 2, vs It_max-linear",
+            "value": best["seconds"] if best else None, "unit": "s", "n_gpus": 1,
+            "higher_is_better": False, "dtype": "c64+f64", "data": "synthetic",
+            "config": {"workload": "elasticity_32", "n": p.n, "nnz": p.nnz, "nev": c["count"],
+                       "L": c["L"], "solver": "GCR(30)+Jacobi, mixed, lock + warm start"},
+            "chosen_it_max_linear": best["it_max_linear"] if best else None, "sweep": rows}
+    print(json.dumps(line, default=float))
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -312,6 +369,9 @@ def main():
         sys.exit(2)
     if args.workload == "batch64":
         run_batch64(args)
+        return
+    if args.workload == "itmax":
+        run_itmax(args)
         return
     import numpy as np
     import torch

@@ -127,20 +127,26 @@ template <typename T>
 hipError_t launch_apply_dots(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
                              const void* Z, void* Qk, const void* Qbase, size_t vstride, int k,
                              double2* part, bool precond, hipStream_t s);
+// CGS update of the new image only, q_k -= sum_i beta_i q_i, with the partial
+// sums of <q_k, q_k> and <q_k, r> (the directions p_i are never formed: the
+// solution update combines the stored preconditioned vectors z_i instead)
 template <typename T>
 hipError_t launch_orth(const DevPencil& P, const PanelGrid& g, const SlotTables& st, void* Qk,
-                       void* Pk, const void* Z, const void* R, const void* Qbase,
-                       const void* Pbase, size_t vstride, int k, const double2* beta,
-                       double2* part, hipStream_t s);
+                       const void* R, const void* Qbase, size_t vstride, int k,
+                       const double2* beta, double2* part, hipStream_t s);
 template <typename T>
-// precond: 0 = none (z = r), 1 = point Jacobi, 2 = leave z to the AMG V-cycle
+// precond: 0 = none (z = r), 1 = point Jacobi, 2 = leave z to the AMG V-cycle;
+// Z may be null (no z written: the last step of a cycle)
 hipError_t launch_step(const DevPencil& P, const PanelGrid& g, const SlotTables& st, void* R,
                        void* Z, const void* Qk, const double2* alpha_k, double2* part,
                        int precond, hipStream_t s);
+// FP64 solution update of a finished cycle: y += sum_j g_j z_j, where the
+// coefficients g follow from alpha and the CGS history beta (p_k = z_k -
+// sum_{i<k} beta_ik p_i); z_0 in Z0, z_j (j >= 1) at Zbase + j * vstride.
 template <typename T>
 hipError_t launch_yupdate(int n, const PanelGrid& g, const SlotTables& st, double2* Y,
-                          const void* Pbase, size_t vstride, int kk, const double2* alpha,
-                          hipStream_t s);
+                          const void* Z0, const void* Zbase, size_t vstride, int kk,
+                          const double2* alpha, const double2* bhist, hipStream_t s);
 template <typename T>
 hipError_t launch_true_resid(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
                              const double2* Y, const double* F, int ldf, void* R, void* Z,
@@ -180,6 +186,7 @@ hipError_t launch_reduce(const double2* part, int nrb, int ND, int C, int nd, in
                          double2* out, hipStream_t s);
 struct SlotScalars {
   double2* beta = nullptr;   // [kMaxRestart][C]
+  double2* bhist = nullptr;  // [kMaxRestart (step k)][kMaxRestart (i < k)][C] beta of the cycle
   double2* alpha = nullptr;  // [kMaxRestart][C]
   double* qq = nullptr;      // [kMaxRestart][C]
   double* target2 = nullptr; // [C] squared residual target of the current cycle

@@ -898,10 +898,8 @@ __global__ __launch_bounds__(kThreads) void k_dots(int n, PanelGrid g,
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_orth(
     int n, PanelGrid g, const int* __restrict__ active, typename CT<T>::t* __restrict__ Qk,
-    typename CT<T>::t* __restrict__ Pk, const typename CT<T>::t* __restrict__ Z,
     const typename CT<T>::t* __restrict__ R, const typename CT<T>::t* __restrict__ Qb,
-    const typename CT<T>::t* __restrict__ Pb, size_t vstride, int k,
-    const double2* __restrict__ beta, double2* __restrict__ part) {
+    size_t vstride, int k, const double2* __restrict__ beta, double2* __restrict__ part) {
   using C = typename CT<T>::t;
   __shared__ double2 sb[kMaxRestart * kPanel];
   __shared__ double red[4 * 3 * 16];
@@ -921,21 +919,16 @@ __global__ __launch_bounds__(kThreads) void k_orth(
     for (int row = r0 + rs; row < r1; row += 16) {
       const size_t off = (base + row) * kPanel + lane;
       const C q = Qk[off];
-      const C z = Z[off];
-      double qx = q.x, qy = q.y, px = z.x, py = z.y;
+      double qx = q.x, qy = q.y;
 #pragma unroll 4
       for (int i = 0; i < k; ++i) {
         const double2 b = sb[i * kPanel + lane];
         const C vq = Qb[(size_t)i * vstride + off];
-        const C vp = Pb[(size_t)i * vstride + off];
         qx -= b.x * vq.x - b.y * vq.y;
         qy -= b.x * vq.y + b.y * vq.x;
-        px -= b.x * vp.x - b.y * vp.y;
-        py -= b.x * vp.y + b.y * vp.x;
       }
       const C qn = mk<C>(qx, qy);
       Qk[off] = qn;
-      Pk[off] = mk<C>(px, py);
       const C r = R[off];
       const double nx = qn.x, ny = qn.y;
       acc[0] += nx * nx + ny * ny;
@@ -986,11 +979,13 @@ __global__ __launch_bounds__(kThreads) void k_step(
       const C rn = mk<C>(r.x - (al.x * q.x - al.y * q.y), r.y - (al.x * q.y + al.y * q.x));
       R[off] = rn;
       const double x = rn.x, y = rn.y;
-      if (pc == 1) {
-        const double2 d = jacobi_inv(da[row], db[row], sg);
-        Z[off] = mk<C>(x * d.x - y * d.y, x * d.y + y * d.x);
-      } else if (pc == 0) {
-        Z[off] = rn;
+      if (Z != nullptr) {
+        if (pc == 1) {
+          const double2 d = jacobi_inv(da[row], db[row], sg);
+          Z[off] = mk<C>(x * d.x - y * d.y, x * d.y + y * d.x);
+        } else if (pc == 0) {
+          Z[off] = rn;
+        }
       }
       acc[0] += x * x + y * y;
     }
@@ -1004,12 +999,11 @@ __global__ __launch_bounds__(kThreads) void k_step(
 // yupdate: y += sum_{i<kk} alpha_i p_i   (FP64 solution)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_yupdate(int n, PanelGrid g,
-                                                      const int* __restrict__ sys,
-                                                      double2* __restrict__ Y,
-                                                      const typename CT<T>::t* __restrict__ Pb,
-                                                      size_t vstride, int kk,
-                                                      const double2* __restrict__ alpha) {
+__global__ __launch_bounds__(kThreads) void k_yupdate(
+    int n, PanelGrid g, const int* __restrict__ sys, double2* __restrict__ Y,
+    const typename CT<T>::t* __restrict__ Z0, const typename CT<T>::t* __restrict__ Zb,
+    size_t vstride, int kk, const double2* __restrict__ alpha,
+    const double2* __restrict__ bhist) {
   using C = typename CT<T>::t;
   __shared__ double2 sa[kMaxRestart * kPanel];
   int rb, pan;
@@ -1021,6 +1015,23 @@ __global__ __launch_bounds__(kThreads) void k_yupdate(int n, PanelGrid g,
   for (int t = threadIdx.x; t < kk * kPanel; t += kThreads)
     sa[t] = alpha[(size_t)(t >> 4) * g.C + pan * kPanel + (t & 15)];
   __syncthreads();
+  // coefficients of the z_j: sum_k alpha_k p_k with p_K = z_K - sum_{i<K}
+  // beta_iK p_i; peeling p_K off from the top: g_K = a_K, a_i -= a_K beta_iK
+  if (threadIdx.x < kPanel) {
+    const int sl = pan * kPanel + threadIdx.x;
+    for (int K = kk - 1; K > 0; --K) {
+      const double2 aK = sa[K * kPanel + threadIdx.x];
+      if (aK.x == 0.0 && aK.y == 0.0) continue;
+      for (int i = 0; i < K; ++i) {
+        const double2 b = bhist[((size_t)K * kMaxRestart + i) * g.C + sl];
+        double2 ai = sa[i * kPanel + threadIdx.x];
+        ai.x -= aK.x * b.x - aK.y * b.y;
+        ai.y -= aK.x * b.y + aK.y * b.x;
+        sa[i * kPanel + threadIdx.x] = ai;
+      }
+    }
+  }
+  __syncthreads();
   if (!occ) return;
   const size_t base = (size_t)pan * n;
   const int r0 = rb * g.rpb, r1 = min(r0 + g.rpb, n);
@@ -1030,11 +1041,11 @@ __global__ __launch_bounds__(kThreads) void k_yupdate(int n, PanelGrid g,
 #pragma unroll 4
     for (int i = 0; i < kk; ++i) {
       const double2 a = sa[i * kPanel + lane];
-      // a slot that stopped within the cycle has alpha = 0 for the later
-      // steps and no direction p_i formed there (the buffer holds whatever
-      // it held before): skip the term instead of multiplying it by zero
+      // a slot that stopped within the cycle has zero coefficients for the
+      // later steps and no z_i formed there (the buffer holds whatever it held
+      // before): skip the term instead of multiplying it by zero
       if (a.x == 0.0 && a.y == 0.0) continue;
-      const C p = Pb[(size_t)i * vstride + off];
+      const C p = i == 0 ? Z0[off] : Zb[(size_t)i * vstride + off];
       y.x += a.x * p.x - a.y * p.y;
       y.y += a.x * p.y + a.y * p.x;
     }
@@ -1243,15 +1254,16 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const double2* __restrict__
 
 __global__ void k_fin_beta(const double2* __restrict__ red, int k, int C, int nslots,
                            const int* __restrict__ active, const double* __restrict__ qq,
-                           double2* __restrict__ beta) {
+                           double2* __restrict__ beta, double2* __restrict__ bhist) {
   const int slot = blockIdx.x * blockDim.x + threadIdx.x;
   if (slot >= nslots) return;
   const bool act = active[slot] != 0;
   for (int i = 0; i < k; ++i) {
     const double q = qq[(size_t)i * C + slot];
     const double2 h = red[(size_t)i * C + slot];
-    beta[(size_t)i * C + slot] =
-        (act && q > 0.0) ? make_double2(h.x / q, h.y / q) : make_double2(0.0, 0.0);
+    const double2 b = (act && q > 0.0) ? make_double2(h.x / q, h.y / q) : make_double2(0.0, 0.0);
+    beta[(size_t)i * C + slot] = b;
+    bhist[((size_t)k * kMaxRestart + i) * C + slot] = b;
   }
 }
 
@@ -1810,15 +1822,13 @@ hipError_t launch_spmm_panel(const DevPencil& P, const PanelGrid& g, const doubl
 
 template <typename T>
 hipError_t launch_orth(const DevPencil& P, const PanelGrid& g, const SlotTables& st, void* Qk,
-                       void* Pk, const void* Z, const void* R, const void* Qbase,
-                       const void* Pbase, size_t vstride, int k, const double2* beta,
-                       double2* part, hipStream_t s) {
+                       const void* R, const void* Qbase, size_t vstride, int k,
+                       const double2* beta, double2* part, hipStream_t s) {
   using C = typename CT<T>::t;
   k_orth<T><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, static_cast<C*>(Qk),
-                                            static_cast<C*>(Pk), static_cast<const C*>(Z),
                                             static_cast<const C*>(R),
-                                            static_cast<const C*>(Qbase),
-                                            static_cast<const C*>(Pbase), vstride, k, beta, part);
+                                            static_cast<const C*>(Qbase), vstride, k, beta,
+                                            part);
   return hipGetLastError();
 }
 
@@ -1836,11 +1846,12 @@ hipError_t launch_step(const DevPencil& P, const PanelGrid& g, const SlotTables&
 
 template <typename T>
 hipError_t launch_yupdate(int n, const PanelGrid& g, const SlotTables& st, double2* Y,
-                          const void* Pbase, size_t vstride, int kk, const double2* alpha,
-                          hipStream_t s) {
+                          const void* Z0, const void* Zbase, size_t vstride, int kk,
+                          const double2* alpha, const double2* bhist, hipStream_t s) {
   using C = typename CT<T>::t;
-  k_yupdate<T><<<g.blocks(), kThreads, 0, s>>>(n, g, st.sys, Y, static_cast<const C*>(Pbase),
-                                               vstride, kk, alpha);
+  k_yupdate<T><<<g.blocks(), kThreads, 0, s>>>(n, g, st.sys, Y, static_cast<const C*>(Z0),
+                                               static_cast<const C*>(Zbase), vstride, kk,
+                                               alpha, bhist);
   return hipGetLastError();
 }
 
@@ -1893,7 +1904,8 @@ hipError_t launch_reduce(const double2* part, int nrb, int ND, int C, int nd, in
 
 hipError_t launch_fin_beta(const double2* red, int k, int C, int nslots, const SlotTables& st,
                            const SlotScalars& sc, hipStream_t s) {
-  k_fin_beta<<<cdiv(nslots, 256), 256, 0, s>>>(red, k, C, nslots, st.active, sc.qq, sc.beta);
+  k_fin_beta<<<cdiv(nslots, 256), 256, 0, s>>>(red, k, C, nslots, st.active, sc.qq, sc.beta,
+                                                sc.bhist);
   return hipGetLastError();
 }
 hipError_t launch_fin_alpha(const double2* red, int k, int C, int nslots, const SlotTables& st,
@@ -1932,15 +1944,14 @@ hipError_t launch_fin_true(const double2* red, int nslots, const SlotTables& st,
   template hipError_t launch_spmm_panel<T>(const DevPencil&, const PanelGrid&,               \
                                            const double2*, const void*, void*, hipStream_t); \
   template hipError_t launch_orth<T>(const DevPencil&, const PanelGrid&, const SlotTables&,  \
-                                     void*, void*, const void*, const void*, const void*,    \
-                                     const void*, size_t, int, const double2*, double2*,     \
-                                     hipStream_t);                                           \
+                                     void*, const void*, const void*, size_t, int,           \
+                                     const double2*, double2*, hipStream_t);                 \
   template hipError_t launch_step<T>(const DevPencil&, const PanelGrid&, const SlotTables&,  \
                                      void*, void*, const void*, const double2*, double2*,    \
                                      int, hipStream_t);                                     \
   template hipError_t launch_yupdate<T>(int, const PanelGrid&, const SlotTables&, double2*,  \
-                                        const void*, size_t, int, const double2*,            \
-                                        hipStream_t);                                        \
+                                        const void*, const void*, size_t, int,               \
+                                        const double2*, const double2*, hipStream_t);        \
   template hipError_t launch_true_resid<T>(const DevPencil&, const PanelGrid&,               \
                                            const SlotTables&, const double2*, const double*, \
                                            int, void*, void*, double2*, int, hipStream_t);   \

@@ -673,12 +673,15 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
   double* d_theta_slot = dtab + 2 * C;
   // scalars: beta, alpha (kMaxRestart*C double2 each), qq (kMaxRestart*C), target2 (C)
   double* scal;
-  HIPCHK(ensure_t(h, B_SCAL, (size_t)kMaxRestart * C * 5 + C, &scal));
+  HIPCHK(ensure_t(h, B_SCAL,
+                  (size_t)kMaxRestart * C * 5 + C + (size_t)kMaxRestart * kMaxRestart * C * 2,
+                  &scal));
   SlotScalars sc;
   sc.beta = reinterpret_cast<double2*>(scal);
   sc.alpha = reinterpret_cast<double2*>(scal + (size_t)2 * kMaxRestart * C);
   sc.qq = scal + (size_t)4 * kMaxRestart * C;
   sc.target2 = scal + (size_t)5 * kMaxRestart * C;
+  sc.bhist = reinterpret_cast<double2*>(scal + (size_t)5 * kMaxRestart * C + C);
   sc.fnorm2 = fn2;
   int* sysi;
   HIPCHK(ensure_t(h, B_SYS, (size_t)3 * S + 8, &sysi));
@@ -745,7 +748,8 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
       t0.src = nullptr;
       if (kk_last > 0) {
         Scope sp(h, SLRF_K_RESID, (double)occ * n * (32.0 + kk_last * sT));
-        HIPCHK(launch_yupdate<T>(n, g, t0, Ybuf[cur], Pb, vstride, kk_last, sc.alpha, s));
+        HIPCHK(launch_yupdate<T>(n, g, t0, Ybuf[cur], Zbuf[cur], Pb, vstride, kk_last,
+                                 sc.alpha, sc.bhist, s));
       }
       {
         Scope sp(h, SLRF_K_RESID, (double)occ * n * (16.0 + 8.0 + 2 * sT) + 20.0 * h->P.nnz);
@@ -853,10 +857,15 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
     SlotTables tc = tabs;
     tc.src = nullptr;
     void* R = Rbuf[cur];
-    void* Z = Zbuf[cur];
+    // the preconditioned vectors of the cycle: z_0 in the (compacted) Z buffer,
+    // z_k (k >= 1) in the direction store, all kept for the solution update
+    auto zk = [&](int k) -> void* {
+      return k == 0 ? Zbuf[cur] : static_cast<void*>(static_cast<char*>(Pb) +
+                                                     (size_t)k * vstride * sT);
+    };
     for (int k = 0; k < m; ++k) {
       char* Qk = static_cast<char*>(Q) + (size_t)k * vstride * sT;
-      char* Pk = static_cast<char*>(Pb) + (size_t)k * vstride * sT;
+      void* Z = zk(k);
       if (amg) {
         const slrf_status vs = vcycle<T>(h, av, C, occ, ND, tc, R, Z, nact);
         if (vs != SLRF_OK) return vs;
@@ -879,8 +888,8 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
         HIPCHK(launch_fin_beta(red, k, C, occ, tc, sc, s));
       }
       {
-        Scope sp(h, SLRF_K_ORTH, (double)nact * n * sT * (2.0 * k + 5));
-        HIPCHK(launch_orth<T>(h->P, g, tc, Qk, Pk, Z, R, Q, Pb, vstride, k, sc.beta, part, s));
+        Scope sp(h, SLRF_K_ORTH, (double)nact * n * sT * (k + 3.0));
+        HIPCHK(launch_orth<T>(h->P, g, tc, Qk, R, Q, vstride, k, sc.beta, part, s));
       }
       {
         Scope sp(h, SLRF_K_REDUCE, 32.0 * nrb * occ);
@@ -889,7 +898,8 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
       }
       {
         Scope sp(h, SLRF_K_STEP, (double)nact * n * sT * 4.0);
-        HIPCHK(launch_step<T>(h->P, g, tc, R, Z, Qk, sc.alpha + (size_t)k * C, part, pc, s));
+        HIPCHK(launch_step<T>(h->P, g, tc, R, k + 1 < m ? zk(k + 1) : nullptr, Qk,
+                              sc.alpha + (size_t)k * C, part, pc, s));
       }
       {
         Scope sp(h, SLRF_K_REDUCE, 16.0 * nrb * occ);

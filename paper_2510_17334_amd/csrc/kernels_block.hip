@@ -1408,82 +1408,6 @@ __global__ __launch_bounds__(kThreads) void k_lvl_jacobi0(
   }
 }
 
-// grid transfer with long rows (restriction P^T): a workgroup handles 4 rows;
-// for each row the 16 row subgroups take every 16th entry and the partial sums
-// are combined in a fixed order through LDS.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_transfer_split(
-    int nout, int nin, const int* __restrict__ rowptr, const int* __restrict__ col,
-    const T* __restrict__ v, int npan, const int* __restrict__ active,
-    const typename CT<T>::t* __restrict__ In, typename CT<T>::t* __restrict__ Out) {
-  using C = typename CT<T>::t;
-  __shared__ double red[16][kPanel][2];
-  const int lane = threadIdx.x & 15, rs = threadIdx.x >> 4;
-  const long nblk = (long)((nout + 3) / 4) * npan;
-  const long b = blockIdx.x;
-  if (b >= nblk) return;
-  const int pan = (int)(b % npan);
-  const int rq = (int)(b / npan) * 4;
-  const int slot = pan * kPanel + lane;
-  const bool act = active == nullptr || active[slot] != 0;
-  if (!__syncthreads_or(act)) return;
-  const C* __restrict__ Ip = In + (size_t)pan * nin * kPanel;
-  C* __restrict__ Op = Out + (size_t)pan * nout * kPanel;
-  for (int row = rq; row < min(rq + 4, nout); ++row) {
-    double sx = 0.0, sy = 0.0;
-    for (int e = rowptr[row] + rs; e < rowptr[row + 1]; e += 16) {
-      const C z = Ip[col[e] * kPanel + lane];
-      sx += (double)v[e] * z.x;
-      sy += (double)v[e] * z.y;
-    }
-    red[rs][lane][0] = sx;
-    red[rs][lane][1] = sy;
-    __syncthreads();
-    if (rs == 0) {
-      double tx = 0.0, ty = 0.0;
-      for (int r = 0; r < 16; ++r) {
-        tx += red[r][lane][0];
-        ty += red[r][lane][1];
-      }
-      Op[row * kPanel + lane] = mk<C>(tx, ty);
-    }
-    __syncthreads();
-  }
-}
-
-// grid transfer with a real CSR matrix (restriction P^T or prolongation P):
-//   out[i] (+)= sum_e v_e in[col_e]; in has nin rows, out has nout rows.
-template <typename T, bool ADD>
-__global__ __launch_bounds__(kThreads) void k_transfer(
-    int nout, int nin, const int* __restrict__ rowptr, const int* __restrict__ col,
-    const T* __restrict__ v, PanelGrid g, const int* __restrict__ active,
-    const typename CT<T>::t* __restrict__ In, typename CT<T>::t* __restrict__ Out) {
-  using C = typename CT<T>::t;
-  int rb, pan;
-  if (!map_block(g, rb, pan)) return;
-  const int lane = threadIdx.x & 15, rs = threadIdx.x >> 4;
-  const int slot = pan * kPanel + lane;
-  if (active != nullptr && active[slot] == 0) return;
-  const C* __restrict__ Ip = In + (size_t)pan * nin * kPanel;
-  C* __restrict__ Op = Out + (size_t)pan * nout * kPanel;
-  const int r0 = rb * g.rpb, r1 = min(r0 + g.rpb, nout);
-  for (int row = r0 + rs; row < r1; row += 16) {
-    T sx = 0, sy = 0;
-    for (int e = rowptr[row]; e < rowptr[row + 1]; ++e) {
-      const C z = Ip[col[e] * kPanel + lane];
-      sx = mad(v[e], z.x, sx);
-      sy = mad(v[e], z.y, sy);
-    }
-    C o = mk<C>(sx, sy);
-    if constexpr (ADD) {
-      const C p = Op[row * kPanel + lane];
-      o.x += p.x;
-      o.y += p.y;
-    }
-    Op[row * kPanel + lane] = o;
-  }
-}
-
 // coarsest level: x = (A_c - sigma_j B_c)^{-1} b with the dense inverse of the
 // slot's pole j = sys % npoles
 template <typename T>
@@ -2022,28 +1946,151 @@ hipError_t launch_lvl_jacobi0(const DevPencil& L, const PanelGrid& g, const Slot
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// AMG transfers with 16-byte lane vectors (two complex floats or one complex
+// double per lane).  Prolongation (short rows of P): 8 or 4 fine rows per wave,
+// one coarse-row gather per entry, optional accumulation into the output.
+// Restriction (long rows of R = P^T): one wave per (coarse row, panel), its
+// lane groups take every EG-th entry, then a fixed xor-shuffle tree sums the
+// groups (deterministic order).
+// ---------------------------------------------------------------------------
+template <typename T, bool ADD>
+__global__ __launch_bounds__(kThreads) void k_prolong(
+    int nout, int nin, const int* __restrict__ rowptr, const int* __restrict__ col,
+    const T* __restrict__ v, PanelGrid g, const int* __restrict__ active,
+    const typename CT<T>::t* __restrict__ In, typename CT<T>::t* __restrict__ Out) {
+  using V = typename LaneVec<T>::V;
+  constexpr int SPL = LaneVec<T>::SPL;
+  constexpr int LPR = kPanel / SPL;
+  constexpr int RPP = kThreads / LPR;
+  int rb, pan;
+  if (!map_block(g, rb, pan)) return;
+  const int tid = threadIdx.x, lr = tid % LPR, rr = tid / LPR;
+  const bool a = tid < kPanel && (active == nullptr || active[pan * kPanel + tid] != 0);
+  if (!__syncthreads_or(a)) return;
+  const V* __restrict__ Ip = reinterpret_cast<const V*>(In + (size_t)pan * nin * kPanel);
+  V* __restrict__ Op = reinterpret_cast<V*>(Out + (size_t)pan * nout * kPanel);
+  const int r0 = rb * g.rpb, r1 = min(r0 + g.rpb, nout);
+  for (int row = r0 + rr; row < r1; row += RPP) {
+    const int e0 = rowptr[row], e1 = rowptr[row + 1];
+    T acc[2 * SPL];
+#pragma unroll
+    for (int c = 0; c < 2 * SPL; ++c) acc[c] = 0;
+    for (int e = e0; e < e1; e += 4) {
+      V z[4];
+      T w[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        z[u] = V{};
+        w[u] = 0;
+        if (e + u < e1) {
+          w[u] = v[e + u];
+          z[u] = Ip[(size_t)col[e + u] * LPR + lr];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        acc[0] = mad(w[u], z[u].x, acc[0]);
+        acc[1] = mad(w[u], z[u].y, acc[1]);
+        if constexpr (SPL == 2) {
+          acc[2] = mad(w[u], (T)lv_z(z[u]), acc[2]);
+          acc[3] = mad(w[u], (T)lv_w(z[u]), acc[3]);
+        }
+      }
+    }
+    V o;
+    o.x = acc[0];
+    o.y = acc[1];
+    if constexpr (SPL == 2) lv_set_zw(o, acc[2], acc[3]);
+    if constexpr (ADD) {
+      const V p = Op[(size_t)row * LPR + lr];
+      o.x += p.x;
+      o.y += p.y;
+      if constexpr (SPL == 2) lv_set_zw(o, (T)(lv_z(o) + lv_z(p)), (T)(lv_w(o) + lv_w(p)));
+    }
+    Op[(size_t)row * LPR + lr] = o;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_restrict(
+    int nout, int nin, const int* __restrict__ rowptr, const int* __restrict__ col,
+    const T* __restrict__ v, int npan, const int* __restrict__ active,
+    const typename CT<T>::t* __restrict__ In, typename CT<T>::t* __restrict__ Out) {
+  using V = typename LaneVec<T>::V;
+  constexpr int SPL = LaneVec<T>::SPL;
+  constexpr int LPR = kPanel / SPL;  // lanes per panel row
+  constexpr int EG = 64 / LPR;       // entry groups per wave
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l % LPR, eg = l / LPR;
+  const int ngrp = (npan + 3) / 4;
+  const long b = blockIdx.x;
+  const int row = (int)(b / ngrp);
+  const int pan = (int)(b % ngrp) * 4 + w;
+  if (row >= nout || pan >= npan) return;  // whole waves (no workgroup barrier below)
+  const bool a = l < kPanel && (active == nullptr || active[pan * kPanel + l] != 0);
+  if (!__any(a)) return;
+  const V* __restrict__ Ip = reinterpret_cast<const V*>(In + (size_t)pan * nin * kPanel);
+  V* __restrict__ Op = reinterpret_cast<V*>(Out + (size_t)pan * nout * kPanel);
+  const int e0 = rowptr[row], e1 = rowptr[row + 1];
+  T acc[2 * SPL];
+#pragma unroll
+  for (int c = 0; c < 2 * SPL; ++c) acc[c] = 0;
+  for (int e = e0 + eg; e < e1; e += 4 * EG) {
+    V z[4];
+    T wv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int ee = e + u * EG;
+      z[u] = V{};
+      wv[u] = 0;
+      if (ee < e1) {
+        wv[u] = v[ee];
+        z[u] = Ip[(size_t)col[ee] * LPR + lr];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      acc[0] = mad(wv[u], z[u].x, acc[0]);
+      acc[1] = mad(wv[u], z[u].y, acc[1]);
+      if constexpr (SPL == 2) {
+        acc[2] = mad(wv[u], (T)lv_z(z[u]), acc[2]);
+        acc[3] = mad(wv[u], (T)lv_w(z[u]), acc[3]);
+      }
+    }
+  }
+#pragma unroll
+  for (int off = LPR; off < 64; off <<= 1)
+#pragma unroll
+    for (int c = 0; c < 2 * SPL; ++c) acc[c] += __shfl_xor(acc[c], off);
+  if (eg == 0) {
+    V o;
+    o.x = acc[0];
+    o.y = acc[1];
+    if constexpr (SPL == 2) lv_set_zw(o, acc[2], acc[3]);
+    Op[(size_t)row * LPR + lr] = o;
+  }
+}
+
 template <typename T>
 hipError_t launch_transfer(const DevTransfer& M, const PanelGrid& g, const SlotTables& st,
                            const void* In, void* Out, bool add, hipStream_t s) {
   using C = typename CT<T>::t;
   const T* v = std::is_same<T, float>::value ? reinterpret_cast<const T*>(M.v32)
                                              : reinterpret_cast<const T*>(M.v);
-  if (!add && M.nnz > 32 * M.nrows) {
-    const long nblk = (long)((M.nrows + 3) / 4) * g.npan;
-    k_transfer_split<T><<<(unsigned)nblk, kThreads, 0, s>>>(M.nrows, M.ncols, M.rowptr, M.col, v,
-                                                            g.npan, st.active,
-                                                            static_cast<const C*>(In),
-                                                            static_cast<C*>(Out));
+  auto Ic = static_cast<const C*>(In);
+  auto Oc = static_cast<C*>(Out);
+  if (!add && M.nnz > 16 * M.nrows) {
+    const long nblk = (long)M.nrows * ((g.npan + 3) / 4);
+    k_restrict<T><<<(unsigned)nblk, kThreads, 0, s>>>(M.nrows, M.ncols, M.rowptr, M.col, v,
+                                                      g.npan, st.active, Ic, Oc);
     return hipGetLastError();
   }
   if (add)
-    k_transfer<T, true><<<g.blocks(), kThreads, 0, s>>>(M.nrows, M.ncols, M.rowptr, M.col, v, g,
-                                                        st.active, static_cast<const C*>(In),
-                                                        static_cast<C*>(Out));
+    k_prolong<T, true><<<g.blocks(), kThreads, 0, s>>>(M.nrows, M.ncols, M.rowptr, M.col, v, g,
+                                                       st.active, Ic, Oc);
   else
-    k_transfer<T, false><<<g.blocks(), kThreads, 0, s>>>(M.nrows, M.ncols, M.rowptr, M.col, v, g,
-                                                         st.active, static_cast<const C*>(In),
-                                                         static_cast<C*>(Out));
+    k_prolong<T, false><<<g.blocks(), kThreads, 0, s>>>(M.nrows, M.ncols, M.rowptr, M.col, v,
+                                                        g, st.active, Ic, Oc);
   return hipGetLastError();
 }
 

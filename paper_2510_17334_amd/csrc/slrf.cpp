@@ -76,7 +76,7 @@ struct DevAmg {
   void* inv64 = nullptr;                // [pole][nc][nc] complex double
   void* inv32 = nullptr;                // [pole][nc][nc] complex float
   std::vector<void*> allocs;
-  double omega = 0.7;                   // damped-Jacobi smoothing weight
+  double omega = 1.0;                   // Jacobi smoothing weight
   size_t nnz_all = 0;                   // level + transfer nonzeros (byte accounting)
   ~DevAmg() {
     for (void* p : allocs) (void)hipFree(p);

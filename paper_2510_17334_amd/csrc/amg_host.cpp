@@ -318,6 +318,7 @@ bool amg_build(const HostLevel& fine, const std::vector<std::complex<double>>& p
   H.levels.clear();
   H.P.clear();
   H.R.clear();
+  H.rho.clear();
   H.levels.push_back(fine);
   while (H.levels.back().n > prm.coarse_max && (int)H.levels.size() < prm.max_levels) {
     const HostLevel& L = H.levels.back();
@@ -348,6 +349,7 @@ bool amg_build(const HostLevel& fine, const std::vector<std::complex<double>>& p
     }
     // P = T - (omega / rho) D^{-1} A T
     const double rho = rho_dinv_a(L);
+    H.rho.push_back(rho);
     std::vector<int> arp, aci;
     std::vector<double> at;
     spgemm2(n, nc, L.rp, L.ci, L.a, nullptr, trp, tci, tv, arp, aci, at, nullptr);

@@ -34,6 +34,7 @@ struct AmgParams {
 struct AmgHierarchy {
   std::vector<HostLevel> levels;  // levels[0] = fine pencil
   std::vector<HostCsrP> P, R;     // P[l]: n_l x n_{l+1}, R[l] = P[l]^T
+  std::vector<double> rho;        // rho[l] = spectral radius estimate of D_l^{-1} A_l
   int nc = 0;                     // coarsest size
   std::vector<std::complex<double>> coarse_inv;  // [pole][nc][nc] row-major
 };

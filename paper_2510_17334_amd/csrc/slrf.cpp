@@ -76,7 +76,7 @@ struct DevAmg {
   void* inv64 = nullptr;                // [pole][nc][nc] complex double
   void* inv32 = nullptr;                // [pole][nc][nc] complex float
   std::vector<void*> allocs;
-  double omega = 1.0;                   // Jacobi smoothing weight
+  std::vector<double> omega;            // Jacobi smoothing weight per level (all but the coarsest)
   size_t nnz_all = 0;                   // level + transfer nonzeros (byte accounting)
   ~DevAmg() {
     for (void* p : allocs) (void)hipFree(p);
@@ -335,6 +335,9 @@ slrf_status build_amg(slrf_ctx* h) {
   const int L = (int)H.levels.size();
   A.n.clear();
   for (auto& lv : H.levels) A.n.push_back(lv.n);
+  // smoothing weight (4/3) / rho(D^-1 A_l), the prolongator-smoothing choice
+  A.omega.clear();
+  for (double r : H.rho) A.omega.push_back(r > 0.0 ? (4.0 / 3.0) / r : 0.7);
   A.nnz_all = 0;
   for (int l = 1; l < L; ++l) {
     const HostLevel& hl = H.levels[l];
@@ -468,12 +471,12 @@ slrf_status vcycle(slrf_ctx* h, const AmgVecs& v, int C, int occ, int ND, const 
       const PanelGrid g = make_grid(A.n[l], C, occ, ND);
       void* xb = l == 0 ? v.W0 : v.X[l];
       void* r = l == 0 ? v.T0 : v.T[l];
-      HIPCHK(launch_lvl_jacobi0<T>(lvl(l), g, st, A.omega, b[l], xb, s));
+      HIPCHK(launch_lvl_jacobi0<T>(lvl(l), g, st, A.omega[l], b[l], xb, s));
       {
         const bool fine = l == 0 && sweep_is_halo<T>(h->P);
         Scope sw(h, fine ? SLRF_K_SWEEP : -1, (double)nact * A.n[0] * sT * 3.0 + fine_csr);
         if (fine && h->cur_stats) h->cur_stats->sweep_systems += nact;
-        HIPCHK(launch_lvl_op<T>(lvl(l), g, st, kEpiResidOp, A.omega, xb, b[l], r, s));
+        HIPCHK(launch_lvl_op<T>(lvl(l), g, st, kEpiResidOp, A.omega[l], xb, b[l], r, s));
       }
       const PanelGrid gc = make_grid(A.n[l + 1], C, occ, ND);
       HIPCHK(launch_transfer<T>(A.R[l], gc, st, r, v.B[l + 1], false, s));
@@ -490,7 +493,7 @@ slrf_status vcycle(slrf_ctx* h, const AmgVecs& v, int C, int occ, int ND, const 
       const bool fine = l == 0 && sweep_is_halo<T>(h->P);
       Scope sw(h, fine ? SLRF_K_SWEEP : -1, (double)nact * A.n[0] * sT * 3.0 + fine_csr);
       if (fine && h->cur_stats) h->cur_stats->sweep_systems += nact;
-      HIPCHK(launch_lvl_op<T>(lvl(l), g, st, kEpiJacobiOp, A.omega, x[l], b[l], out, s));
+      HIPCHK(launch_lvl_op<T>(lvl(l), g, st, kEpiJacobiOp, A.omega[l], x[l], b[l], out, s));
       x[l] = out;
     }
   }

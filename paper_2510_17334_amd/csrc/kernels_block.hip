@@ -895,105 +895,10 @@ __global__ __launch_bounds__(kThreads) void k_dots(int n, PanelGrid g,
 // ---------------------------------------------------------------------------
 // orth: q_k -= sum beta_i q_i ; p_k = z - sum beta_i p_i ; partial <q,q>, <q,r>
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_orth(
-    int n, PanelGrid g, const int* __restrict__ active, typename CT<T>::t* __restrict__ Qk,
-    const typename CT<T>::t* __restrict__ R, const typename CT<T>::t* __restrict__ Qb,
-    size_t vstride, int k, const double2* __restrict__ beta, double2* __restrict__ part) {
-  using C = typename CT<T>::t;
-  __shared__ double2 sb[kMaxRestart * kPanel];
-  __shared__ double red[4 * 3 * 16];
-  int rb, pan;
-  if (!map_block(g, rb, pan)) return;
-  const int lane = threadIdx.x & 15, rs = threadIdx.x >> 4;
-  const int slot = pan * kPanel + lane;
-  const bool act = active[slot] != 0;
-  if (!__syncthreads_or(act)) return;
-  for (int t = threadIdx.x; t < k * kPanel; t += kThreads)
-    sb[t] = beta[(size_t)(t >> 4) * g.C + pan * kPanel + (t & 15)];
-  __syncthreads();
-  double acc[3] = {0.0, 0.0, 0.0};
-  const size_t base = (size_t)pan * n;
-  const int r0 = rb * g.rpb, r1 = min(r0 + g.rpb, n);
-  if (act) {
-    for (int row = r0 + rs; row < r1; row += 16) {
-      const size_t off = (base + row) * kPanel + lane;
-      const C q = Qk[off];
-      double qx = q.x, qy = q.y;
-#pragma unroll 4
-      for (int i = 0; i < k; ++i) {
-        const double2 b = sb[i * kPanel + lane];
-        const C vq = Qb[(size_t)i * vstride + off];
-        qx -= b.x * vq.x - b.y * vq.y;
-        qy -= b.x * vq.y + b.y * vq.x;
-      }
-      const C qn = mk<C>(qx, qy);
-      Qk[off] = qn;
-      const C r = R[off];
-      const double nx = qn.x, ny = qn.y;
-      acc[0] += nx * nx + ny * ny;
-      acc[1] += nx * r.x + ny * r.y;
-      acc[2] += nx * r.y - ny * r.x;
-    }
-  }
-  reduce16<3>(acc, 3, red, [&](int v, int ln, double s) {
-    const size_t dst = ((size_t)rb * g.ND + (v == 0 ? 0 : 1)) * g.C + pan * kPanel + ln;
-    double* d = reinterpret_cast<double*>(part + dst);
-    if (v == 0) {
-      d[0] = s;
-      d[1] = 0.0;
-    } else {
-      d[v - 1] = s;
-    }
-  });
-}
 
 // ---------------------------------------------------------------------------
 // step: r -= alpha q_k ; z = P^-1 r ; partial ||r||^2
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_step(
-    int n, PanelGrid g, const int* __restrict__ active, const double2* __restrict__ sigma,
-    const double* __restrict__ da, const double* __restrict__ db, int pc,
-    typename CT<T>::t* __restrict__ R, typename CT<T>::t* __restrict__ Z,
-    const typename CT<T>::t* __restrict__ Qk, const double2* __restrict__ alpha_k,
-    double2* __restrict__ part) {
-  using C = typename CT<T>::t;
-  __shared__ double red[4 * 1 * 16];
-  int rb, pan;
-  if (!map_block(g, rb, pan)) return;
-  const int lane = threadIdx.x & 15, rs = threadIdx.x >> 4;
-  const int slot = pan * kPanel + lane;
-  const bool act = active[slot] != 0;
-  if (!__syncthreads_or(act)) return;
-  const double2 al = alpha_k[slot];
-  const double2 sg = sigma[slot];
-  double acc[1] = {0.0};
-  const size_t base = (size_t)pan * n;
-  const int r0 = rb * g.rpb, r1 = min(r0 + g.rpb, n);
-  if (act) {
-    for (int row = r0 + rs; row < r1; row += 16) {
-      const size_t off = (base + row) * kPanel + lane;
-      const C r = R[off];
-      const C q = Qk[off];
-      const C rn = mk<C>(r.x - (al.x * q.x - al.y * q.y), r.y - (al.x * q.y + al.y * q.x));
-      R[off] = rn;
-      const double x = rn.x, y = rn.y;
-      if (Z != nullptr) {
-        if (pc == 1) {
-          const double2 d = jacobi_inv(da[row], db[row], sg);
-          Z[off] = mk<C>(x * d.x - y * d.y, x * d.y + y * d.x);
-        } else if (pc == 0) {
-          Z[off] = rn;
-        }
-      }
-      acc[0] += x * x + y * y;
-    }
-  }
-  reduce16<1>(acc, 1, red, [&](int, int ln, double s) {
-    part[((size_t)rb * g.ND) * g.C + pan * kPanel + ln] = make_double2(s, 0.0);
-  });
-}
 
 // ---------------------------------------------------------------------------
 // yupdate: y += sum_{i<kk} alpha_i p_i   (FP64 solution)
@@ -1564,6 +1469,244 @@ static bool launch_grp(const DevPencil& P, const PanelGrid& g, const SlotTables&
 }
 
 
+// ---------------------------------------------------------------------------
+// Streaming GCR kernels with 16-byte lane vectors (LaneVec: two complex floats
+// or one complex double per lane; LPR lanes per panel row, 256 / LPR rows per
+// pass).  Per-slot partial sums are combined over the row subgroups by a fixed
+// xor-shuffle tree inside each wave and a fixed-order sum over the 4 waves.
+// ---------------------------------------------------------------------------
+template <int NVS, int LPR, typename Emit>
+__device__ __forceinline__ void reduce_lv(double* vals, int nvs, double* red, Emit emit) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+  for (int v = 0; v < NVS; ++v) {
+    if (v < nvs) {
+      double x = vals[v];
+#pragma unroll
+      for (int off = LPR; off < 64; off <<= 1) x += __shfl_xor(x, off);
+      if (l < LPR) red[(w * NVS + v) * LPR + l] = x;
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nvs * LPR; t += kThreads) {
+    const int v = t / LPR, lr = t % LPR;
+    const double sum = ((red[(0 * NVS + v) * LPR + lr] + red[(1 * NVS + v) * LPR + lr]) +
+                        red[(2 * NVS + v) * LPR + lr]) +
+                       red[(3 * NVS + v) * LPR + lr];
+    emit(v, lr, sum);
+  }
+}
+
+// complex components of a lane vector: slot c (< SPL) -> (re, im)
+template <typename T>
+__device__ __forceinline__ void lv_get(const typename LaneVec<T>::V& v, int c, double& re,
+                                       double& im) {
+  if (c == 0) {
+    re = v.x;
+    im = v.y;
+  } else {
+    re = lv_z(v);
+    im = lv_w(v);
+  }
+}
+
+// h_i = <q_i, q_k>, i < k <= MAXK, partial sums per (row block, slot)
+template <typename T, int MAXK>
+__global__ __launch_bounds__(kThreads) void k_dots_lv(int n, PanelGrid g,
+                                                      const int* __restrict__ active,
+                                                      const typename CT<T>::t* __restrict__ Qk,
+                                                      const typename CT<T>::t* __restrict__ Qb,
+                                                      size_t vstride, int k,
+                                                      double2* __restrict__ part) {
+  using V = typename LaneVec<T>::V;
+  constexpr int SPL = LaneVec<T>::SPL;
+  constexpr int LPR = kPanel / SPL;
+  constexpr int RPP = kThreads / LPR;
+  constexpr int NVS = 2 * MAXK * SPL;
+  __shared__ double red[4 * NVS * LPR];
+  int rb, pan;
+  if (!map_block(g, rb, pan)) return;
+  const int tid = threadIdx.x, lr = tid % LPR, rs = tid / LPR;
+  const bool a = tid < kPanel && (active == nullptr || active[pan * kPanel + tid] != 0);
+  if (!__syncthreads_or(a)) return;
+  const size_t pbase = (size_t)pan * n * kPanel;
+  const V* __restrict__ Qp = reinterpret_cast<const V*>(Qk + pbase);
+  double h[NVS];
+#pragma unroll
+  for (int v = 0; v < NVS; ++v) h[v] = 0.0;
+  const int r0 = rb * g.rpb, r1 = min(r0 + g.rpb, n);
+  for (int row = r0 + rs; row < r1; row += RPP) {
+    const size_t off = (size_t)row * LPR + lr;
+    const V q = Qp[off];
+#pragma unroll
+    for (int i = 0; i < MAXK; ++i) {
+      if (i < k) {
+        const V vq = reinterpret_cast<const V*>(Qb + (size_t)i * vstride + pbase)[off];
+#pragma unroll
+        for (int c = 0; c < SPL; ++c) {
+          double qx, qy, vx, vy;
+          lv_get<T>(q, c, qx, qy);
+          lv_get<T>(vq, c, vx, vy);
+          h[(2 * i) * SPL + c] += vx * qx + vy * qy;
+          h[(2 * i + 1) * SPL + c] += vx * qy - vy * qx;
+        }
+      }
+    }
+  }
+  reduce_lv<NVS, LPR>(h, 2 * k * SPL, red, [&](int v, int ln, double sum) {
+    // v = (2 i + re/im) * SPL + c; slot = ln * SPL + c
+    const int c = v % SPL, vi = v / SPL;
+    double* dst = reinterpret_cast<double*>(part + ((size_t)rb * g.ND + (vi >> 1)) * g.C +
+                                            pan * kPanel + ln * SPL + c);
+    dst[vi & 1] = sum;
+  });
+}
+
+// q_k -= sum_i beta_i q_i; partial <q_k, q_k>, <q_k, r>
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_orth_lv(
+    int n, PanelGrid g, const int* __restrict__ active, typename CT<T>::t* __restrict__ Qk,
+    const typename CT<T>::t* __restrict__ R, const typename CT<T>::t* __restrict__ Qb,
+    size_t vstride, int k, const double2* __restrict__ beta, double2* __restrict__ part) {
+  using V = typename LaneVec<T>::V;
+  constexpr int SPL = LaneVec<T>::SPL;
+  constexpr int LPR = kPanel / SPL;
+  constexpr int RPP = kThreads / LPR;
+  constexpr int NVS = 3 * SPL;
+  __shared__ double2 sb[kMaxRestart * kPanel];
+  __shared__ double red[4 * NVS * LPR];
+  int rb, pan;
+  if (!map_block(g, rb, pan)) return;
+  const int tid = threadIdx.x, lr = tid % LPR, rs = tid / LPR;
+  const bool a = tid < kPanel && active[pan * kPanel + tid] != 0;
+  if (!__syncthreads_or(a)) return;
+  for (int t = tid; t < k * kPanel; t += kThreads)
+    sb[t] = beta[(size_t)(t >> 4) * g.C + pan * kPanel + (t & 15)];
+  __syncthreads();
+  const size_t pbase = (size_t)pan * n * kPanel;
+  V* __restrict__ Qp = reinterpret_cast<V*>(Qk + pbase);
+  const V* __restrict__ Rp = reinterpret_cast<const V*>(R + pbase);
+  double acc[NVS];
+#pragma unroll
+  for (int v = 0; v < NVS; ++v) acc[v] = 0.0;
+  const int r0 = rb * g.rpb, r1 = min(r0 + g.rpb, n);
+  for (int row = r0 + rs; row < r1; row += RPP) {
+    const size_t off = (size_t)row * LPR + lr;
+    const V q = Qp[off];
+    double qx[SPL], qy[SPL];
+#pragma unroll
+    for (int c = 0; c < SPL; ++c) lv_get<T>(q, c, qx[c], qy[c]);
+#pragma unroll 4
+    for (int i = 0; i < k; ++i) {
+      const V vq = reinterpret_cast<const V*>(Qb + (size_t)i * vstride + pbase)[off];
+#pragma unroll
+      for (int c = 0; c < SPL; ++c) {
+        const double2 b = sb[i * kPanel + lr * SPL + c];
+        double vx, vy;
+        lv_get<T>(vq, c, vx, vy);
+        qx[c] -= b.x * vx - b.y * vy;
+        qy[c] -= b.x * vy + b.y * vx;
+      }
+    }
+    V qn;
+    qn.x = (T)qx[0];
+    qn.y = (T)qy[0];
+    if constexpr (SPL == 2) lv_set_zw(qn, (T)qx[1], (T)qy[1]);
+    Qp[off] = qn;
+    const V r = Rp[off];
+#pragma unroll
+    for (int c = 0; c < SPL; ++c) {
+      double nx, ny, rx, ry;
+      lv_get<T>(qn, c, nx, ny);
+      lv_get<T>(r, c, rx, ry);
+      acc[0 * SPL + c] += nx * nx + ny * ny;
+      acc[1 * SPL + c] += nx * rx + ny * ry;
+      acc[2 * SPL + c] += nx * ry - ny * rx;
+    }
+  }
+  reduce_lv<NVS, LPR>(acc, NVS, red, [&](int v, int ln, double sum) {
+    const int c = v % SPL, vi = v / SPL;  // 0: <q,q>, 1: Re <q,r>, 2: Im <q,r>
+    const size_t dst = ((size_t)rb * g.ND + (vi == 0 ? 0 : 1)) * g.C + pan * kPanel + ln * SPL + c;
+    double* d = reinterpret_cast<double*>(part + dst);
+    if (vi == 0) {
+      d[0] = sum;
+      d[1] = 0.0;
+    } else {
+      d[vi - 1] = sum;
+    }
+  });
+}
+
+// r -= alpha q, z = P^-1 r (Jacobi / copy / none), partial ||r||^2
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_step_lv(
+    int n, PanelGrid g, const int* __restrict__ active, const double2* __restrict__ sigma,
+    const double* __restrict__ da, const double* __restrict__ db, int pc,
+    typename CT<T>::t* __restrict__ R, typename CT<T>::t* __restrict__ Z,
+    const typename CT<T>::t* __restrict__ Qk, const double2* __restrict__ alpha_k,
+    double2* __restrict__ part) {
+  using V = typename LaneVec<T>::V;
+  constexpr int SPL = LaneVec<T>::SPL;
+  constexpr int LPR = kPanel / SPL;
+  constexpr int RPP = kThreads / LPR;
+  __shared__ double red[4 * SPL * LPR];
+  int rb, pan;
+  if (!map_block(g, rb, pan)) return;
+  const int tid = threadIdx.x, lr = tid % LPR, rs = tid / LPR;
+  const bool a = tid < kPanel && active[pan * kPanel + tid] != 0;
+  if (!__syncthreads_or(a)) return;
+  double2 al[SPL], sg[SPL];
+#pragma unroll
+  for (int c = 0; c < SPL; ++c) {
+    al[c] = alpha_k[pan * kPanel + lr * SPL + c];
+    sg[c] = sigma[pan * kPanel + lr * SPL + c];
+  }
+  const size_t pbase = (size_t)pan * n * kPanel;
+  V* __restrict__ Rp = reinterpret_cast<V*>(R + pbase);
+  V* __restrict__ Zp = Z != nullptr ? reinterpret_cast<V*>(Z + pbase) : nullptr;
+  const V* __restrict__ Qp = reinterpret_cast<const V*>(Qk + pbase);
+  double acc[SPL];
+#pragma unroll
+  for (int c = 0; c < SPL; ++c) acc[c] = 0.0;
+  const int r0 = rb * g.rpb, r1 = min(r0 + g.rpb, n);
+  for (int row = r0 + rs; row < r1; row += RPP) {
+    const size_t off = (size_t)row * LPR + lr;
+    const V r = Rp[off];
+    const V q = Qp[off];
+    V rn, zn;
+#pragma unroll
+    for (int c = 0; c < SPL; ++c) {
+      double rx, ry, qx, qy;
+      lv_get<T>(r, c, rx, ry);
+      lv_get<T>(q, c, qx, qy);
+      const T nx = (T)(rx - (al[c].x * qx - al[c].y * qy));
+      const T ny = (T)(ry - (al[c].x * qy + al[c].y * qx));
+      const double x = nx, y = ny;
+      acc[c] += x * x + y * y;
+      T zx = nx, zy = ny;
+      if (pc == 1) {
+        const double2 d = jacobi_inv(da[row], db[row], sg[c]);
+        zx = (T)(x * d.x - y * d.y);
+        zy = (T)(x * d.y + y * d.x);
+      }
+      if (c == 0) {
+        rn.x = nx;
+        rn.y = ny;
+        zn.x = zx;
+        zn.y = zy;
+      } else {
+        lv_set_zw(rn, nx, ny);
+        lv_set_zw(zn, zx, zy);
+      }
+    }
+    Rp[off] = rn;
+    if (Zp != nullptr && pc != 2) Zp[off] = zn;
+  }
+  reduce_lv<SPL, LPR>(acc, SPL, red, [&](int c, int ln, double sum) {
+    part[((size_t)rb * g.ND) * g.C + pan * kPanel + ln * SPL + c] = make_double2(sum, 0.0);
+  });
+}
+
 template <typename T>
 HaloView halo_view(const DevPencil& P) {
   HaloView v;
@@ -1658,7 +1801,8 @@ hipError_t launch_dots(const DevPencil& P, const PanelGrid& g, const SlotTables&
   auto Qb = static_cast<const C*>(Qbase);
   if (k <= 0) return hipSuccess;
   if (k <= 8)
-    k_dots<T, 8><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, Qc, Qb, vstride, k, part);
+    k_dots_lv<T, 8><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, Qc, Qb, vstride, k,
+                                                     part);
   else if (k <= 16)
     k_dots<T, 16><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, Qc, Qb, vstride, k, part);
   else
@@ -1749,10 +1893,10 @@ hipError_t launch_orth(const DevPencil& P, const PanelGrid& g, const SlotTables&
                        const void* R, const void* Qbase, size_t vstride, int k,
                        const double2* beta, double2* part, hipStream_t s) {
   using C = typename CT<T>::t;
-  k_orth<T><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, static_cast<C*>(Qk),
-                                            static_cast<const C*>(R),
-                                            static_cast<const C*>(Qbase), vstride, k, beta,
-                                            part);
+  k_orth_lv<T><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, static_cast<C*>(Qk),
+                                               static_cast<const C*>(R),
+                                               static_cast<const C*>(Qbase), vstride, k, beta,
+                                               part);
   return hipGetLastError();
 }
 
@@ -1761,10 +1905,10 @@ hipError_t launch_step(const DevPencil& P, const PanelGrid& g, const SlotTables&
                        void* Z, const void* Qk, const double2* alpha_k, double2* part,
                        int precond, hipStream_t s) {
   using C = typename CT<T>::t;
-  k_step<T><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, st.sigma, P.da, P.db,
-                                            precond, static_cast<C*>(R),
-                                            static_cast<C*>(Z), static_cast<const C*>(Qk),
-                                            alpha_k, part);
+  k_step_lv<T><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, st.sigma, P.da, P.db,
+                                               precond, static_cast<C*>(R),
+                                               static_cast<C*>(Z), static_cast<const C*>(Qk),
+                                               alpha_k, part);
   return hipGetLastError();
 }
 

@@ -320,6 +320,35 @@ def test_solve_config_q1_2d_closed_form(cfg1, mode):
     h.close()
 
 
+@pytest.mark.parametrize("prec", [P.SLRF_PREC_FP64, P.SLRF_PREC_MIXED])
+def test_solve_q1_3d_m64_full_size_closed_form(prec):
+    """The benchmark pencil at full size (n = 262,144, L = 160, 8 poles): Algorithm 2
+    (locking, warm start; AMG-GCR(8); inner tolerance 1e-10) finds all 102
+    eigenvalues of (0, gamma] (a 6-fold cluster at the boundary of the 100th)
+    within 1e-10 (FP64) / 1e-8 (mixed) relative of the closed form, with
+    sampled Ritz residuals recomputed on the host."""
+    c = si.config_q1_3d()
+    p, gamma, nev = c["pencil"], c["gamma"], c["nev"]
+    poles, weights = si.slrf_poles(gamma)
+    h = _handle(p, gamma, poles, weights, precision=prec, precond=P.SLRF_PC_AMG, restart=8,
+                tol_lin=1e-10, lock=1, warm_start=1)
+    th, X, nconv, st = h.slrf_solve(nev, _dev(si.start_block(p.n, c["L"], c["seed"])))
+    h.close()
+    assert nconv == nev
+    h1 = 1.0 / 65
+    t = np.arange(1, 13) * np.pi / 65
+    lam1 = (6.0 / h1 ** 2) * (1 - np.cos(t)) / (2 + np.cos(t))  # 12 smallest 1D eigenvalues
+    ex = np.sort((lam1[:, None, None] + lam1[None, :, None] + lam1[None, None, :]).ravel())
+    ex = ex[:nev]
+    tol = 1e-10 if prec == P.SLRF_PREC_FP64 else 1e-8
+    assert np.max(np.abs(_host(th) - ex) / ex) <= tol
+    # Ritz residuals of 6 sampled pairs (first, cluster, last), recomputed in FP64
+    idx = np.array([0, 1, 50, 97, 100, nev - 1])
+    Xh = _host(X[:, idx])
+    res = oracle.eig.residual_norms(p.A(), p.B(), _host(th)[idx], Xh)
+    assert res.max() < 1e-8
+
+
 @pytest.mark.parametrize("pcnd", [P.SLRF_PC_JACOBI, P.SLRF_PC_AMG])
 def test_solve_3d_diffusion_vs_dense_lapack(pcnd):
     p = si.q1_diffusion_pencil(8, 3, np.exp(np.random.default_rng(4).normal(0, .5, 9 ** 3)))

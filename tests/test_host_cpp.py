@@ -1,0 +1,219 @@
+"""The library's host-side setup code (C++, no GPU) through a small driver
+(tests/host_driver.cpp, compiled with g++ at test time):
+
+* locality_order: a permutation; with node blocks it keeps each node's dofs
+  together and in order;
+* detect_block: 3 on node-major elasticity, 1 on scalar pencils and on a
+  pattern with one node row changed;
+* build_halo: the halo-tile format reproduces the CSR pencil exactly (every
+  entry back through its tile's halo), padding entries are zero, tile and
+  slice invariants hold, and an over-wide slice is refused;
+* amg_build: every coarse pair is the Galerkin product (P^T A P, P^T B P) to
+  rounding, R = P^T, the dense coarsest inverse inverts A_c - sigma B_c, and
+  the power-iteration estimate of rho(D^-1 A) is within 10 % below the true
+  value.
+"""
+
+import os
+import shutil
+import struct
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import slrf_inputs as si
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(ROOT, "paper_2510_17334_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def driver(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    d = tmp_path_factory.mktemp("host")
+    exe = str(d / "host_driver")
+    cmd = [gxx, "-O1", "-std=c++17", "-I", CSRC, os.path.join(HERE, "host_driver.cpp"),
+           os.path.join(CSRC, "amg_host.cpp"), os.path.join(CSRC, "halo_host.cpp"), "-o", exe]
+    subprocess.run(cmd, check=True, capture_output=True)
+    return exe, d
+
+
+def _write(p, path):
+    with open(path, "wb") as f:
+        f.write(struct.pack("ii", p.n, len(p.indices)))
+        f.write(np.asarray(p.indptr, np.int32).tobytes())
+        f.write(np.asarray(p.indices, np.int32).tobytes())
+        f.write(np.asarray(p.a, np.float64).tobytes())
+        f.write(np.asarray(p.b, np.float64).tobytes())
+
+
+class _Reader:
+    def __init__(self, path):
+        self.buf = open(path, "rb").read()
+        self.pos = 0
+
+    def i(self):
+        v = struct.unpack_from("q", self.buf, self.pos)[0]
+        self.pos += 8
+        return v
+
+    def arr(self, dt):
+        k = self.i()
+        a = np.frombuffer(self.buf, dtype=dt, count=k, offset=self.pos).copy()
+        self.pos += k * np.dtype(dt).itemsize
+        return a
+
+
+def _run(driver, p, *args):
+    exe, d = driver
+    src, out = str(d / "pencil.bin"), str(d / "out.bin")
+    _write(p, src)
+    subprocess.run([exe, src, out] + [str(a) for a in args], check=True)
+    return _Reader(out)
+
+
+class _Csr:
+    """Minimal pencil-like holder for hand-made patterns."""
+
+    def __init__(self, A, B):
+        A, B = A.tocsr(), B.tocsr()
+        A.sort_indices()
+        B.sort_indices()
+        self.n = A.shape[0]
+        self.indptr, self.indices, self.a, self.b = A.indptr, A.indices, A.data, B.data
+
+
+def _elastic(ne=4, seed=0):
+    return si.hex_elasticity_pencil(ne, np.exp(np.random.default_rng(seed).normal(0, .3, ne ** 3)))
+
+
+def test_locality_order_permutation_and_blocks(driver):
+    p = si.q1_kron_pencil(10, 3)
+    order = _run(driver, p, "order", 1).arr(np.int32)
+    assert np.array_equal(np.sort(order), np.arange(p.n))
+    e = _elastic()
+    order = _run(driver, e, "order", 3).arr(np.int32)
+    assert np.array_equal(np.sort(order), np.arange(e.n))
+    o = order.reshape(-1, 3)
+    assert np.all(o % 3 == np.arange(3)) and np.all(o // 3 == (o[:, :1] // 3))
+
+
+def test_detect_block(driver):
+    assert _run(driver, _elastic(), "block").i() == 3
+    assert _run(driver, si.q1_kron_pencil(8, 3), "block").i() == 1
+    e = _elastic()
+    A = sp.csr_matrix((e.a, e.indices, e.indptr)).tolil()
+    B = sp.csr_matrix((e.b, e.indices, e.indptr)).tolil()
+    j = A.rows[4][-1]  # drop one off-diagonal entry of one dof row (and its mirror)
+    for M in (A, B):
+        M[4, j] = 0.0
+        M[j, 4] = 0.0
+    A, B = A.tocsr(), B.tocsr()
+    A.eliminate_zeros()
+    B = sp.csr_matrix((np.ones_like(A.data), A.indices, A.indptr))  # same pattern
+    assert _run(driver, _Csr(A, B), "block").i() == 1
+
+
+@pytest.mark.parametrize("which", ["q1_2d", "random"])
+def test_halo_format_reproduces_csr(driver, which):
+    if which == "q1_2d":
+        p = si.q1_kron_pencil(30, 2)
+    else:
+        rng = np.random.default_rng(4)
+        n = 603  # ragged last slice
+        M = sp.random(n, n, density=0.01, random_state=5, format="csr")
+        M = M + M.T + sp.identity(n)
+        M.data = rng.standard_normal(M.nnz)
+        Bm = M.copy()
+        Bm.data = rng.standard_normal(M.nnz)
+        p = _Csr(M, Bm)
+    hmax, cap = 192, 512
+    r = _run(driver, p, "halo", hmax, cap)
+    assert r.i() == 1
+    hmx, emax = r.i(), r.i()
+    trow, hptr, halo = r.arr(np.int32), r.arr(np.int32), r.arr(np.int32)
+    sptr, slen = r.arr(np.int32), r.arr(np.int32)
+    lcol, ab = r.arr(np.uint16), r.arr(np.float64).reshape(-1, 2)
+    n = p.n
+    assert trow[0] == 0 and trow[-1] == n and np.all(np.diff(trow) > 0)
+    assert np.all(trow[:-1] % 8 == 0) and np.all(np.diff(trow) <= cap)
+    assert np.max(np.diff(hptr)) == hmx <= hmax
+    assert np.all(np.diff(sptr) % 4 == 0)
+    rows, cols, va, vb = [], [], [], []
+    for t in range(len(trow) - 1):
+        h = halo[hptr[t]:hptr[t + 1]]
+        assert np.all(np.diff(h) > 0)
+        for rrow in range(trow[t], trow[t + 1]):
+            s, ln = rrow // 8, rrow % 8
+            L = slen[rrow]
+            k = (sptr[s] + np.arange(sptr[s + 1] - sptr[s])) * 8 + ln
+            assert np.all(ab[k[L:]] == 0.0) and np.all(lcol[k[L:]] == 0)
+            rows += [rrow] * L
+            cols += list(h[lcol[k[:L]]])
+            va += list(ab[k[:L], 0])
+            vb += list(ab[k[:L], 1])
+    A = sp.csr_matrix((p.a, p.indices, p.indptr), shape=(n, n))
+    B = sp.csr_matrix((p.b, p.indices, p.indptr), shape=(n, n))
+    A2 = sp.csr_matrix((va, (rows, cols)), shape=(n, n))
+    B2 = sp.csr_matrix((vb, (rows, cols)), shape=(n, n))
+    assert (A - A2).count_nonzero() == 0 and (B - B2).count_nonzero() == 0
+    # the largest 4-slice pass
+    passes = [(sptr[min(a + 4, b)] - sptr[a]) * 8 for t in range(len(trow) - 1)
+              for a, b in [(trow[t] // 8, (trow[t + 1] + 7) // 8)]
+              for a in range(a, b, 4)]
+    assert emax == max(passes)
+    # a slice referencing more rows than the halo holds is refused
+    assert _run(driver, p, "halo", 8, cap).i() == 0
+
+
+@pytest.mark.parametrize("which", ["q1_diffusion_3d", "elasticity_block"])
+def test_amg_galerkin_hierarchy(driver, which):
+    if which == "q1_diffusion_3d":
+        p = si.q1_diffusion_pencil(9, 3, np.exp(np.random.default_rng(6).normal(0, .5, 1000)))
+        block = 1
+    else:
+        p = _elastic(5, 2)
+        block = 3
+    sigma = 30.0 + 30.0j
+    r = _run(driver, p, "amg", block, sigma.real, sigma.imag)
+    assert r.i() == 1
+    nl = r.i()
+    assert nl >= 2
+    levels = []
+    for _ in range(nl):
+        m = r.i()
+        rp, ci, a, b = r.arr(np.int32), r.arr(np.int32), r.arr(np.float64), r.arr(np.float64)
+        levels.append((sp.csr_matrix((a, ci, rp), shape=(m, m)),
+                       sp.csr_matrix((b, ci, rp), shape=(m, m))))
+    Ps = []
+    for _ in range(nl - 1):
+        nr, nc = r.i(), r.i()
+        rp, ci, v = r.arr(np.int32), r.arr(np.int32), r.arr(np.float64)
+        P = sp.csr_matrix((v, ci, rp), shape=(nr, nc))
+        rn = r.i()
+        rp, ci, v = r.arr(np.int32), r.arr(np.int32), r.arr(np.float64)
+        R = sp.csr_matrix((v, ci, rp), shape=(rn, nr))
+        assert abs(R - P.T).max() == 0.0
+        Ps.append(P)
+    rho = r.arr(np.float64)
+    ncoarse = r.i()
+    inv = r.arr(np.complex128).reshape(ncoarse, ncoarse)
+    for l, P in enumerate(Ps):
+        A0, B0 = levels[l]
+        A1, B1 = levels[l + 1]
+        if block > 1:
+            assert P.shape[1] % block == 0
+        for M0, M1 in ((A0, A1), (B0, B1)):
+            G = (P.T @ M0 @ P).toarray()
+            assert np.abs(M1.toarray() - G).max() <= 1e-12 * np.abs(G).max()
+        D = sp.diags(1.0 / A0.diagonal())
+        true_rho = np.max(np.abs(np.linalg.eigvals((D @ A0).toarray())))
+        assert 0.9 * true_rho <= rho[l] <= true_rho * (1 + 1e-10)
+    Ac, Bc = levels[-1]
+    Mc = (Ac - sigma * Bc).toarray()
+    assert np.abs(inv @ Mc - np.eye(ncoarse)).max() <= 1e-10

@@ -71,7 +71,10 @@ constexpr int kSpmmAuto = 0, kSpmmGroup = 1, kSpmmCsrLds = 2, kSpmmCsrDirect = 3
 constexpr int kSpmmVariants = 7;
 // Largest halo of a tile (rows of 128 bytes in LDS; with the staged
 // coefficients of a pass three to four workgroups fit a CU).
-constexpr int kHaloMaxH = 192;
+#ifndef SLRF_HALO_MAXH
+#define SLRF_HALO_MAXH 192
+#endif
+constexpr int kHaloMaxH = SLRF_HALO_MAXH;
 constexpr int kHaloMaxRows = 512;
 constexpr int kHaloMaxG = 8;  // units (128-byte panel column slices) per workgroup
 
@@ -135,11 +138,12 @@ hipError_t launch_orth(const DevPencil& P, const PanelGrid& g, const SlotTables&
                        const void* R, const void* Qbase, size_t vstride, int k,
                        const double2* beta, double2* part, hipStream_t s);
 template <typename T>
-// precond: 0 = none (z = r), 1 = point Jacobi, 2 = leave z to the AMG V-cycle;
+// precond: 0 = none (z = r), 1 = point Jacobi, 2 = leave z to the AMG V-cycle,
+// 3 = Z receives omega D^-1 r, the level-0 pre-smoothing of the next V-cycle;
 // Z may be null (no z written: the last step of a cycle)
 hipError_t launch_step(const DevPencil& P, const PanelGrid& g, const SlotTables& st, void* R,
                        void* Z, const void* Qk, const double2* alpha_k, double2* part,
-                       int precond, hipStream_t s);
+                       int precond, double omega, hipStream_t s);
 // FP64 solution update of a finished cycle: y += sum_j g_j z_j, where the
 // coefficients g follow from alpha and the CGS history beta (p_k = z_k -
 // sum_{i<k} beta_ik p_i); z_0 in Z0, z_j (j >= 1) at Zbase + j * vstride.

@@ -1015,6 +1015,102 @@ __global__ __launch_bounds__(kThreads) void k_true_resid(
   });
 }
 
+// The same residual with the rows' CSR data staged in LDS once per workgroup
+// and shared by G panels, UNR gathers of y in flight per lane.  Each thread
+// visits the same rows in the same order and sums the entries of a row in CSR
+// order, so the residual and the partial norms are bitwise those of
+// k_true_resid.
+template <typename T, int G, int UNR>
+__global__ __launch_bounds__(kThreads) void k_true_resid_lds(
+    int n, const int* __restrict__ rowptr, const int* __restrict__ col,
+    const double* __restrict__ av, const double* __restrict__ bv, const double* __restrict__ da,
+    const double* __restrict__ db, int pc, PanelGrid g, int sub, int lds_nnz,
+    const int* __restrict__ sys, const int* __restrict__ scol, const double2* __restrict__ sigma,
+    const double2* __restrict__ Y, const double* __restrict__ F, int ldf,
+    typename CT<T>::t* __restrict__ R, typename CT<T>::t* __restrict__ Z,
+    double2* __restrict__ part) {
+  using C = typename CT<T>::t;
+  extern __shared__ double smem_d[];
+  double* s_a = smem_d;
+  double* s_b = s_a + lds_nnz;
+  int* s_col = reinterpret_cast<int*>(s_b + lds_nnz);
+  int* s_rp = s_col + lds_nnz;
+  __shared__ double red[4 * G * 16];
+  const int ncg = (g.npan + G - 1) / G;
+  int rb, cg;
+  if (!map_tile(g.nrb, ncg, g.group, rb, cg)) return;
+  const int tid = threadIdx.x, lane = tid & 15, rs = tid >> 4;
+  const int pan0 = cg * G;
+  bool occ[G];
+  double2 sg[G];
+  int cl[G];
+#pragma unroll
+  for (int gg = 0; gg < G; ++gg) {
+    const int p = pan0 + gg, slot = p * kPanel + lane;
+    occ[gg] = p < g.npan && sys[slot] >= 0;
+    sg[gg] = occ[gg] ? sigma[slot] : make_double2(0.0, 0.0);
+    cl[gg] = occ[gg] ? scol[slot] : 0;
+  }
+  double acc[G];
+#pragma unroll
+  for (int gg = 0; gg < G; ++gg) acc[gg] = 0.0;
+  const int R0 = rb * g.rpb, R1 = min(R0 + g.rpb, n);
+  for (int s0 = R0; s0 < R1; s0 += sub) {
+    const int s1 = min(s0 + sub, R1);
+    const int eb = rowptr[s0];
+    const int nsub = rowptr[s1] - eb;
+    for (int t = tid; t <= s1 - s0; t += kThreads) s_rp[t] = rowptr[s0 + t] - eb;
+    for (int t = tid; t < nsub; t += kThreads) {
+      s_col[t] = col[eb + t];
+      s_a[t] = av[eb + t];
+      s_b[t] = bv[eb + t];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) {
+      if (!occ[gg]) continue;
+      const size_t base = (size_t)(pan0 + gg) * n;
+      for (int row = s0 + rs; row < s1; row += 16) {
+        const int e0 = s_rp[row - s0], e1 = s_rp[row - s0 + 1];
+        double ar = 0, ai = 0, br = 0, bi = 0;
+        for (int e = e0; e < e1; e += UNR) {
+          double2 y[UNR];
+#pragma unroll
+          for (int u = 0; u < UNR; ++u)
+            y[u] = e + u < e1 ? Y[(base + s_col[e + u]) * kPanel + lane] : make_double2(0.0, 0.0);
+#pragma unroll
+          for (int u = 0; u < UNR; ++u) {
+            if (e + u < e1) {
+              const double a = s_a[e + u], b = s_b[e + u];
+              ar = fma(a, y[u].x, ar);
+              ai = fma(a, y[u].y, ai);
+              br = fma(b, y[u].x, br);
+              bi = fma(b, y[u].y, bi);
+            }
+          }
+        }
+        const double mx = ar - (sg[gg].x * br - sg[gg].y * bi);
+        const double my = ai - (sg[gg].x * bi + sg[gg].y * br);
+        const double x = F[(size_t)row * ldf + cl[gg]] - mx, y = -my;
+        const size_t off = (base + row) * kPanel + lane;
+        R[off] = mk<C>(x, y);
+        if (pc == 1) {
+          const double2 d = jacobi_inv(da[row], db[row], sg[gg]);
+          Z[off] = mk<C>(x * d.x - y * d.y, x * d.y + y * d.x);
+        } else if (pc == 0) {
+          Z[off] = mk<C>(x, y);
+        }
+        acc[gg] += x * x + y * y;
+      }
+    }
+    __syncthreads();
+  }
+  reduce16<G>(acc, G, red, [&](int v, int ln, double s) {
+    if (pan0 + v < g.npan)
+      part[((size_t)rb * g.ND) * g.C + (pan0 + v) * kPanel + ln] = make_double2(s, 0.0);
+  });
+}
+
 // ---------------------------------------------------------------------------
 // admit: compact continuing slots and initialise newly admitted systems
 //   y0 = 0, r0 = f                              (cold start)
@@ -1388,9 +1484,7 @@ static int lds_unroll(const DevPencil& P) {
 // 48 KB of LDS; false when neither does (then the gather reads the CSR from
 // global memory).
 template <typename T>
-static bool lds_plan(const DevPencil& P, int rpb, int& sub, int& cap, size_t& bytes) {
-  const int var = std::is_same<T, float>::value ? P.var32 : P.var64;
-  if (var == kSpmmCsrDirect || var == kSpmmGroup) return false;
+static bool lds_fit(const DevPencil& P, int rpb, int& sub, int& cap, size_t& bytes) {
   const int cands[2] = {64, 32};
   const int caps[2] = {P.max_nnz_sub64, P.max_nnz_sub32};
   for (int i = 0; i < 2; ++i) {
@@ -1404,6 +1498,14 @@ static bool lds_plan(const DevPencil& P, int rpb, int& sub, int& cap, size_t& by
     }
   }
   return false;
+}
+
+// rows staged in LDS for the CSR-LDS sweeps, unless the variant is another one
+template <typename T>
+static bool lds_plan(const DevPencil& P, int rpb, int& sub, int& cap, size_t& bytes) {
+  const int var = std::is_same<T, float>::value ? P.var32 : P.var64;
+  if (var == kSpmmCsrDirect || var == kSpmmGroup) return false;
+  return lds_fit<T>(P, rpb, sub, cap, bytes);
 }
 
 template <typename T>
@@ -1637,11 +1739,13 @@ __global__ __launch_bounds__(kThreads) void k_orth_lv(
   });
 }
 
-// r -= alpha q, z = P^-1 r (Jacobi / copy / none), partial ||r||^2
+// r -= alpha q, partial ||r||^2, and z from the new r: pc 0 copy, 1 Jacobi,
+// 2 none, 3 omega D^-1 r (the first smoothing step of the next V-cycle, from
+// the stored r exactly as the level-0 jacobi0 kernel forms it)
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_step_lv(
     int n, PanelGrid g, const int* __restrict__ active, const double2* __restrict__ sigma,
-    const double* __restrict__ da, const double* __restrict__ db, int pc,
+    const double* __restrict__ da, const double* __restrict__ db, int pc, double omega,
     typename CT<T>::t* __restrict__ R, typename CT<T>::t* __restrict__ Z,
     const typename CT<T>::t* __restrict__ Qk, const double2* __restrict__ alpha_k,
     double2* __restrict__ part) {
@@ -1688,6 +1792,10 @@ __global__ __launch_bounds__(kThreads) void k_step_lv(
         const double2 d = jacobi_inv(da[row], db[row], sg[c]);
         zx = (T)(x * d.x - y * d.y);
         zy = (T)(x * d.y + y * d.x);
+      } else if (pc == 3) {
+        const double2 d = jacobi_inv(da[row], db[row], sg[c]);
+        zx = (T)(omega * (x * d.x - y * d.y));
+        zy = (T)(omega * (x * d.y + y * d.x));
       }
       if (c == 0) {
         rn.x = nx;
@@ -1903,10 +2011,10 @@ hipError_t launch_orth(const DevPencil& P, const PanelGrid& g, const SlotTables&
 template <typename T>
 hipError_t launch_step(const DevPencil& P, const PanelGrid& g, const SlotTables& st, void* R,
                        void* Z, const void* Qk, const double2* alpha_k, double2* part,
-                       int precond, hipStream_t s) {
+                       int precond, double omega, hipStream_t s) {
   using C = typename CT<T>::t;
   k_step_lv<T><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, st.sigma, P.da, P.db,
-                                               precond, static_cast<C*>(R),
+                                               precond, omega, static_cast<C*>(R),
                                                static_cast<C*>(Z), static_cast<const C*>(Qk),
                                                alpha_k, part);
   return hipGetLastError();
@@ -1928,6 +2036,19 @@ hipError_t launch_true_resid(const DevPencil& P, const PanelGrid& g, const SlotT
                              const double2* Y, const double* F, int ldf, void* R, void* Z,
                              double2* part, int precond, hipStream_t s) {
   using C = typename CT<T>::t;
+  int sub = 0, cap = 0;
+  size_t bytes = 0;
+  if (lds_fit<double>(P, g.rpb, sub, cap, bytes)) {
+    PanelGrid gg = g;
+    const int ncg = (g.npan + kGroupPanels - 1) / kGroupPanels;
+    gg.group = ncg < 4 ? ncg : 4;
+    const long total = (long)g.nrb * ncg;
+    const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
+    k_true_resid_lds<T, kGroupPanels, 8><<<blocks, kThreads, bytes, s>>>(
+        P.n, P.rowptr, P.col, P.a, P.b, P.da, P.db, precond, gg, sub, cap, st.sys, st.col,
+        st.sigma, Y, F, ldf, static_cast<C*>(R), static_cast<C*>(Z), part);
+    return hipGetLastError();
+  }
   k_true_resid<T><<<g.blocks(), kThreads, 0, s>>>(
       P.n, P.rowptr, P.col, P.a, P.b, P.da, P.db, precond, g, st.sys, st.col, st.sigma,
       Y, F, ldf, static_cast<C*>(R), static_cast<C*>(Z), part);
@@ -2016,7 +2137,7 @@ hipError_t launch_fin_true(const double2* red, int nslots, const SlotTables& st,
                                      const double2*, double2*, hipStream_t);                 \
   template hipError_t launch_step<T>(const DevPencil&, const PanelGrid&, const SlotTables&,  \
                                      void*, void*, const void*, const double2*, double2*,    \
-                                     int, hipStream_t);                                     \
+                                     int, double, hipStream_t);                             \
   template hipError_t launch_yupdate<T>(int, const PanelGrid&, const SlotTables&, double2*,  \
                                         const void*, const void*, size_t, int,               \
                                         const double2*, const double2*, hipStream_t);        \

@@ -444,9 +444,10 @@ slrf_status amg_vectors(slrf_ctx* h, int C, AmgVecs& v) {
 
 // z = V(r): one V-cycle (damped-Jacobi pre/post smoothing from a zero guess,
 // Galerkin coarse correction, dense coarsest solve) for every active slot.
+// pre0_done: the level-0 pre-smoothing omega D^-1 r is already in v.W0.
 template <typename T>
 slrf_status vcycle(slrf_ctx* h, const AmgVecs& v, int C, int occ, int ND, const SlotTables& st,
-                   const void* Rin, void* Zout, int nact) {
+                   const void* Rin, void* Zout, int nact, bool pre0_done) {
   const DevAmg& A = h->amg;
   hipStream_t s = h->stream;
   const int L = (int)A.n.size();
@@ -471,7 +472,8 @@ slrf_status vcycle(slrf_ctx* h, const AmgVecs& v, int C, int occ, int ND, const 
       const PanelGrid g = make_grid(A.n[l], C, occ, ND);
       void* xb = l == 0 ? v.W0 : v.X[l];
       void* r = l == 0 ? v.T0 : v.T[l];
-      HIPCHK(launch_lvl_jacobi0<T>(lvl(l), g, st, A.omega[l], b[l], xb, s));
+      // (level 0: the GCR step that formed r may already have written xb)
+      if (l > 0 || !pre0_done) HIPCHK(launch_lvl_jacobi0<T>(lvl(l), g, st, A.omega[l], b[l], xb, s));
       {
         const bool fine = l == 0 && sweep_is_halo<T>(h->P);
         Scope sw(h, fine ? SLRF_K_SWEEP : -1, (double)nact * A.n[0] * sT * 3.0 + fine_csr);
@@ -645,6 +647,9 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
     const slrf_status vs = amg_vectors<T>(h, C, av);
     if (vs != SLRF_OK) return vs;
   }
+  // the GCR step writes the next V-cycle's level-0 pre-smoothing (hierarchies
+  // of two or more levels; a single level is the dense solve alone)
+  const bool fuse0 = amg && h->amg.n.size() > 1;
   double *Xr, *F, *E = nullptr, *Ur, *fn2;
   double2 *Ys, *Ya, *Yb, *part, *red;
   void *Ra, *Rb, *Za, *Zb, *Q, *Pb;
@@ -870,7 +875,7 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
       char* Qk = static_cast<char*>(Q) + (size_t)k * vstride * sT;
       void* Z = zk(k);
       if (amg) {
-        const slrf_status vs = vcycle<T>(h, av, C, occ, ND, tc, R, Z, nact);
+        const slrf_status vs = vcycle<T>(h, av, C, occ, ND, tc, R, Z, nact, fuse0 && k > 0);
         if (vs != SLRF_OK) return vs;
       }
       if (sweep_is_halo<T>(h->P)) {
@@ -901,8 +906,11 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
       }
       {
         Scope sp(h, SLRF_K_STEP, (double)nact * n * sT * 4.0);
-        HIPCHK(launch_step<T>(h->P, g, tc, R, k + 1 < m ? zk(k + 1) : nullptr, Qk,
-                              sc.alpha + (size_t)k * C, part, pc, s));
+        // with the AMG, the step also forms the next V-cycle's level-0
+        // pre-smoothing (saves that kernel's read of r)
+        void* znext = k + 1 < m ? (fuse0 ? av.W0 : zk(k + 1)) : nullptr;
+        HIPCHK(launch_step<T>(h->P, g, tc, R, znext, Qk, sc.alpha + (size_t)k * C, part,
+                              fuse0 ? 3 : pc, fuse0 ? h->amg.omega[0] : 0.0, s));
       }
       {
         Scope sp(h, SLRF_K_REDUCE, 16.0 * nrb * occ);

@@ -70,13 +70,18 @@ constexpr int kSpmmAuto = 0, kSpmmGroup = 1, kSpmmCsrLds = 2, kSpmmCsrDirect = 3
               kSpmmCsrLds16 = 4, kSpmmCsrLds32 = 5, kSpmmHalo = 6;
 constexpr int kSpmmVariants = 7;
 // Largest halo of a tile (rows of 128 bytes in LDS; with the staged
-// coefficients of a pass three to four workgroups fit a CU).
+// coefficients of the tile four workgroups fit a CU) and the rows of a tile
+// (one 8-row slice per wave of a 256-thread workgroup: a tile is formed in one
+// pass).
 #ifndef SLRF_HALO_MAXH
-#define SLRF_HALO_MAXH 192
+#define SLRF_HALO_MAXH 224
 #endif
 constexpr int kHaloMaxH = SLRF_HALO_MAXH;
-constexpr int kHaloMaxRows = 512;
-constexpr int kHaloMaxG = 8;  // units (128-byte panel column slices) per workgroup
+constexpr int kHaloTileRows = 32;
+#ifndef SLRF_HALO_G
+#define SLRF_HALO_G 8
+#endif
+constexpr int kHaloMaxG = SLRF_HALO_G;  // units (128-byte panel column slices) per workgroup
 
 // A rectangular real CSR matrix on the device (AMG prolongation / restriction).
 struct DevTransfer {

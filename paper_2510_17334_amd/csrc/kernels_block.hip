@@ -300,7 +300,7 @@ __global__ __launch_bounds__(kThreads) void k_apply_lds(
   constexpr int SPL = LaneVec<T>::SPL;
   constexpr int LPR = kPanel / SPL;    // lanes per row
   constexpr int RPP = kThreads / LPR;  // rows per pass
-  extern __shared__ double smem_d[];
+  extern __shared__ __attribute__((aligned(16))) double smem_d[];  // 16-byte vectors live here
   T* s_a = reinterpret_cast<T*>(smem_d);
   T* s_b = s_a + lds_nnz;
   int* s_col = reinterpret_cast<int*>(s_b + lds_nnz);
@@ -491,11 +491,13 @@ __global__ __launch_bounds__(kThreads) void k_apply_lds(
 // LDS.  A workgroup owns one row tile and a run of G units (a unit is a
 // 128-byte column slice of a panel: a whole complex-float panel or half a
 // complex-double panel).  For each unit it copies the tile's halo rows of z
-// (every row the tile's entries reference: one 128-byte line each) into LDS;
-// the tile is then formed 32 rows per pass, each wave taking one 8-row slice,
+// (every row the tile's entries reference: one 128-byte line each) into LDS,
+// the loads for the next unit in flight while the current one is formed;
+// the tile is formed 32 rows per pass, each wave taking one 8-row slice,
 // with the slice-ordered coefficients of the pass (local halo indices and
 // (a, b) pairs) also staged in LDS by wide coalesced copies, the copy of the
-// next pass in flight while the current one is formed.  Vector-memory
+// next pass in flight while the current one is formed (a tile of one pass
+// stages its coefficients once for all its units).  Vector-memory
 // traffic per row and unit is thus the tile's share of its halo plus the
 // coefficients; the per-nonzero reads all come from LDS.  Entries of a row
 // are summed in CSR order, as in the CSR kernels, so the result is bitwise
@@ -514,7 +516,7 @@ struct HaloView {
   const void* ab;
 };
 
-template <typename T, int EPI, int CPT>
+template <typename T, int EPI>
 __global__ __launch_bounds__(kThreads) void k_apply_halo(
     int n, HaloView hv, PanelGrid g, int G, const int* __restrict__ active,
     const double2* __restrict__ sigma, const typename CT<T>::t* __restrict__ Z,
@@ -527,12 +529,14 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
   constexpr int LPRF = kPanel / SPL;         // lane vectors per panel row
   constexpr int SPU = kPanel / UPP;          // systems per unit
   constexpr int UNR = 4;                     // = kHaloPad
-  extern __shared__ double smem_d[];
+  static_assert(kHaloTileRows == 8 * (kThreads / 64), "one 8-row slice per wave");
+  extern __shared__ __attribute__((aligned(16))) double smem_d[];  // 16-byte vectors live here
   V* sZ = reinterpret_cast<V*>(smem_d);                            // [hmax][8]
   AB* s_ab = reinterpret_cast<AB*>(sZ + (size_t)g.rpb * 8);        // [emax]
   unsigned short* s_lc = reinterpret_cast<unsigned short*>(s_ab + hv.emax);  // [emax]
   int* sH = reinterpret_cast<int*>(s_lc + hv.emax);                          // [hmax]
-  __shared__ int s_sp[kHaloMaxRows / 8 + 2];   // slice offsets, relative to the tile
+  __shared__ int s_sp[kHaloTileRows / 8 + 1];  // slice offsets of the tile
+  __shared__ int s_uact[kHaloMaxG];
   const int nunit = g.npan * UPP;
   const int nug = (nunit + G - 1) / G;
   int tile, ug;
@@ -540,41 +544,11 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
   const int tid = threadIdx.x, w = tid >> 6, rr = (tid >> 3) & 7, lr = tid & 7;
   const int r0 = hv.trow[tile], r1 = hv.trow[tile + 1];
   const int h0 = hv.hptr[tile], H = hv.hptr[tile + 1] - h0;
-  const int nsl = (r1 - r0 + 7) >> 3, sl0 = r0 >> 3, npass = (nsl + 3) >> 2;
+  // (the format's tiles hold at most kHaloTileRows rows: nsl <= 4)
+  const int nsl = (r1 - r0 + 7) >> 3, sl0 = r0 >> 3;
   for (int t = tid; t < H; t += kThreads) sH[t] = hv.halo[h0 + t];
-  // (tile rows never exceed kHaloMaxRows: the format's tiles are built so)
-  for (int t = tid; t <= nsl; t += kThreads) s_sp[t] = hv.sptr[sl0 + t];
-  // coefficient copy of a pass: 16-byte chunks of the lcol segment, then of
-  // the (a, b) segment (both start on 16-byte boundaries: slices hold
-  // multiples of 8 entries)
-  constexpr int LC16 = 8;                    // lcol entries per chunk
-  constexpr int AB16 = 16 / (int)sizeof(AB); // (a, b) entries per chunk
-  uint4 creg[CPT];
-  const uint4* __restrict__ gab = static_cast<const uint4*>(hv.ab);
-  const uint4* __restrict__ glc = reinterpret_cast<const uint4*>(hv.lcol);
-  uint4* const slc4 = reinterpret_cast<uint4*>(s_lc);
-  uint4* const sab4 = reinterpret_cast<uint4*>(s_ab);
-// global -> registers (LOAD) or registers -> LDS (STORE) for the coefficients
-// of pass PP
-#define SLRF_HALO_PASS(PP, LOAD)                                  \
-  do {                                                            \
-    const int pa_ = (PP) * 4, pb_ = min((PP) * 4 + 4, nsl);       \
-    const int e0_ = s_sp[pa_] * 8, ne_ = (s_sp[pb_] - s_sp[pa_]) * 8; \
-    const int nlc_ = ne_ / LC16, nab_ = ne_ / AB16;               \
-    _Pragma("unroll") for (int c_ = 0; c_ < CPT; ++c_) {          \
-      const int t_ = c_ * kThreads + tid;                         \
-      if (LOAD) creg[c_] = uint4{0, 0, 0, 0};                     \
-      if (t_ < nlc_) {                                            \
-        if (LOAD) creg[c_] = glc[e0_ / LC16 + t_];                \
-        else slc4[t_] = creg[c_];                                 \
-      } else if (t_ < nlc_ + nab_) {                              \
-        if (LOAD) creg[c_] = gab[e0_ / AB16 + (t_ - nlc_)];       \
-        else sab4[t_ - nlc_] = creg[c_];                          \
-      }                                                           \
-    }                                                             \
-  } while (0)
+  if (tid <= nsl) s_sp[tid] = hv.sptr[sl0 + tid];
   // active units of the block (a unit with no iterating system is skipped)
-  __shared__ int s_uact[kHaloMaxG];
   if (tid < G) {
     const int u = ug * G + tid;
     int any = 0;
@@ -588,8 +562,38 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
   int gu = 0;
   while (gu < G && !s_uact[gu]) ++gu;
   if (gu >= G) return;
-  constexpr int HB = 8;  // halo loads in flight per thread
-  V hreg[HB];
+  // the halo of a unit is loaded into registers while the previous unit is
+  // formed (the whole halo fits: H <= kHaloMaxH)
+  constexpr int HP = (kHaloMaxH * 8 + kThreads - 1) / kThreads;
+  V hreg[HP];
+#define SLRF_HALO_ISSUE(GX)                                                              \
+  do {                                                                                   \
+    const int ux_ = ug * G + (GX);                                                       \
+    const V* __restrict__ zx_ =                                                          \
+        reinterpret_cast<const V*>(Z + (size_t)(ux_ / UPP) * n * kPanel) + (ux_ % UPP) * 8; \
+    _Pragma("unroll") for (int i_ = 0; i_ < HP; ++i_) {                                  \
+      const int t_ = i_ * kThreads + tid;                                                \
+      hreg[i_] = V{};                                                                    \
+      if (t_ < H * 8) hreg[i_] = zx_[(size_t)sH[t_ >> 3] * LPRF + (t_ & 7)];             \
+    }                                                                                    \
+  } while (0)
+  SLRF_HALO_ISSUE(gu);
+  // the tile's slice-ordered coefficients, staged once for all its units:
+  // 16-byte chunks of the lcol segment and of the (a, b) segment (both start
+  // on 16-byte boundaries: slices hold multiples of 8 entries)
+  {
+    const int e0 = s_sp[0] * 8, ne = (s_sp[nsl] - s_sp[0]) * 8;
+    const int nlc = ne / 8, nab = ne * (int)sizeof(AB) / 16;
+    const uint4* __restrict__ glc = reinterpret_cast<const uint4*>(hv.lcol) + e0 / 8;
+    const uint4* __restrict__ gab =
+        static_cast<const uint4*>(hv.ab) + (size_t)e0 * sizeof(AB) / 16;
+    for (int t = tid; t < nlc; t += kThreads) reinterpret_cast<uint4*>(s_lc)[t] = glc[t];
+    for (int t = tid; t < nab; t += kThreads) reinterpret_cast<uint4*>(s_ab)[t] = gab[t];
+  }
+  // this wave's slice
+  const int row = r0 + w * 8 + rr;
+  const int wdt = w < nsl ? s_sp[w + 1] - s_sp[w] : 0;
+  const int soff = w < nsl ? (s_sp[w] - s_sp[0]) * 8 + rr : 0;
   while (gu < G) {
     const int u = ug * G + gu;
     const int pan = u / UPP, half = u % UPP;
@@ -597,21 +601,11 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
     const size_t pbase = (size_t)pan * n * kPanel;
     const V* __restrict__ Zu = reinterpret_cast<const V*>(Z + pbase) + half * 8;
     V* __restrict__ Qu = reinterpret_cast<V*>(Qk + pbase) + half * 8;
-    SLRF_HALO_PASS(0, true);
-    for (int t0 = 0; t0 < H * 8; t0 += kThreads * HB) {
 #pragma unroll
-      for (int i = 0; i < HB; ++i) {
-        const int t = t0 + i * kThreads + tid;
-        hreg[i] = V{};
-        if (t < H * 8) hreg[i] = Zu[(size_t)sH[t >> 3] * LPRF + (t & 7)];
-      }
-#pragma unroll
-      for (int i = 0; i < HB; ++i) {
-        const int t = t0 + i * kThreads + tid;
-        if (t < H * 8) sZ[t] = hreg[i];
-      }
+    for (int i = 0; i < HP; ++i) {
+      const int t = i * kThreads + tid;
+      if (t < H * 8) sZ[t] = hreg[i];
     }
-    SLRF_HALO_PASS(0, false);
     int gn = gu + 1;
     while (gn < G && !s_uact[gn]) ++gn;
     T sr[SPL], si[SPL];
@@ -622,83 +616,74 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
       si[q] = (T)sgm.y;
     }
     __syncthreads();
-    for (int p = 0; p < npass; ++p) {
-      if (p + 1 < npass) SLRF_HALO_PASS(p + 1, true);
-      const int sl = p * 4 + w;
-      const int row = r0 + sl * 8 + rr;
-      V q{};
-      if (sl < nsl) {
-        // slice widths are multiples of UNR; padding entries carry zero
-        // coefficients and a valid local column, so no entry is predicated
-        const AB* __restrict__ pab = s_ab + (s_sp[sl] - s_sp[p * 4]) * 8 + rr;
-        const unsigned short* __restrict__ plc = s_lc + (s_sp[sl] - s_sp[p * 4]) * 8 + rr;
-        const V* __restrict__ pz = sZ + lr;
-        const int wdt = s_sp[sl + 1] - s_sp[sl];
-        T acc[4 * SPL];
+    if (gn < G) SLRF_HALO_ISSUE(gn);
+    if (w < nsl) {
+      // slice widths are multiples of UNR; padding entries carry zero
+      // coefficients and a valid local column, so no entry is predicated
+      const AB* __restrict__ pab = s_ab + soff;
+      const unsigned short* __restrict__ plc = s_lc + soff;
+      const V* __restrict__ pz = sZ + lr;
+      T acc[4 * SPL];
 #pragma unroll
-        for (int v = 0; v < 4 * SPL; ++v) acc[v] = 0;
-        for (int j = 0; j < wdt; j += UNR) {
-          V z[UNR];
-          AB ab[UNR];
+      for (int v = 0; v < 4 * SPL; ++v) acc[v] = 0;
+      for (int j = 0; j < wdt; j += UNR) {
+        V z[UNR];
+        AB ab[UNR];
 #pragma unroll
-          for (int uu = 0; uu < UNR; ++uu) {
-            ab[uu] = pab[(j + uu) * 8];
-            z[uu] = pz[(int)plc[(j + uu) * 8] * 8];
-          }
-#pragma unroll
-          for (int uu = 0; uu < UNR; ++uu) lane_fma<T, SPL>(acc, ab[uu].x, ab[uu].y, z[uu]);
+        for (int uu = 0; uu < UNR; ++uu) {
+          ab[uu] = pab[(j + uu) * 8];
+          z[uu] = pz[(int)plc[(j + uu) * 8] * 8];
         }
-        if (row < r1) {
-          q.x = acc[0] - (sr[0] * acc[2] - si[0] * acc[3]);
-          q.y = acc[1] - (sr[0] * acc[3] + si[0] * acc[2]);
-          if constexpr (SPL == 2) {
-            q.z = acc[4] - (sr[1] * acc[6] - si[1] * acc[7]);
-            q.w = acc[5] - (sr[1] * acc[7] + si[1] * acc[6]);
-          }
-          if constexpr (EPI != kEpiApply) {
-            const V bb = (reinterpret_cast<const V*>(Bin + pbase) + half * 8)[row * LPRF + lr];
-            V rres;  // b - M x
-            rres.x = bb.x - q.x;
-            rres.y = bb.y - q.y;
-            if constexpr (SPL == 2) {
-              rres.z = bb.z - q.z;
-              rres.w = bb.w - q.w;
-            }
-            if constexpr (EPI == kEpiResid) {
-              q = rres;
-            } else {
-              const V xo = Zu[row * LPRF + lr];
-              const double dav = da[row], dbv = db[row];
 #pragma unroll
-              for (int c = 0; c < SPL; ++c) {
-                const double dx = dav - (double)sr[c] * dbv, dy = -(double)si[c] * dbv;
-                const double iv = omega / (dx * dx + dy * dy);
-                const double ix = dx * iv, iy = -dy * iv;  // omega / (d)
-                const double rx = c == 0 ? rres.x : lv_z(rres), ry = c == 0 ? rres.y : lv_w(rres);
-                const double ox = c == 0 ? xo.x : lv_z(xo), oy = c == 0 ? xo.y : lv_w(xo);
-                const T nx = (T)(ox + rx * ix - ry * iy), ny = (T)(oy + rx * iy + ry * ix);
-                if (c == 0) {
-                  q.x = nx;
-                  q.y = ny;
-                } else {
-                  lv_set_zw(q, nx, ny);
-                }
+        for (int uu = 0; uu < UNR; ++uu) lane_fma<T, SPL>(acc, ab[uu].x, ab[uu].y, z[uu]);
+      }
+      if (row < r1) {
+        V q;
+        q.x = acc[0] - (sr[0] * acc[2] - si[0] * acc[3]);
+        q.y = acc[1] - (sr[0] * acc[3] + si[0] * acc[2]);
+        if constexpr (SPL == 2) {
+          q.z = acc[4] - (sr[1] * acc[6] - si[1] * acc[7]);
+          q.w = acc[5] - (sr[1] * acc[7] + si[1] * acc[6]);
+        }
+        if constexpr (EPI != kEpiApply) {
+          const V bb = (reinterpret_cast<const V*>(Bin + pbase) + half * 8)[row * LPRF + lr];
+          V rres;  // b - M x
+          rres.x = bb.x - q.x;
+          rres.y = bb.y - q.y;
+          if constexpr (SPL == 2) {
+            rres.z = bb.z - q.z;
+            rres.w = bb.w - q.w;
+          }
+          if constexpr (EPI == kEpiResid) {
+            q = rres;
+          } else {
+            const V xo = Zu[row * LPRF + lr];
+            const double dav = da[row], dbv = db[row];
+#pragma unroll
+            for (int c = 0; c < SPL; ++c) {
+              const double dx = dav - (double)sr[c] * dbv, dy = -(double)si[c] * dbv;
+              const double iv = omega / (dx * dx + dy * dy);
+              const double ix = dx * iv, iy = -dy * iv;  // omega / (d)
+              const double rx = c == 0 ? rres.x : lv_z(rres), ry = c == 0 ? rres.y : lv_w(rres);
+              const double ox = c == 0 ? xo.x : lv_z(xo), oy = c == 0 ? xo.y : lv_w(xo);
+              const T nx = (T)(ox + rx * ix - ry * iy), ny = (T)(oy + rx * iy + ry * ix);
+              if (c == 0) {
+                q.x = nx;
+                q.y = ny;
+              } else {
+                lv_set_zw(q, nx, ny);
               }
             }
           }
-          Qu[row * LPRF + lr] = q;
         }
-      }
-      __syncthreads();  // pass p's coefficients consumed
-      if (p + 1 < npass) {
-        SLRF_HALO_PASS(p + 1, false);
-        __syncthreads();
+        Qu[row * LPRF + lr] = q;
       }
     }
-    gu = gn;  // (the last pass ended with a barrier: LDS is free for the next unit)
+    __syncthreads();  // the unit's halo consumed: LDS is free for the next one
+    gu = gn;
   }
 }
-#undef SLRF_HALO_PASS
+#undef SLRF_HALO_ISSUE
 
 // ---------------------------------------------------------------------------
 // Row-group ("union") shifted SpMM.  Rows are taken in groups of R = 4
@@ -726,7 +711,7 @@ __global__ __launch_bounds__(kThreads) void k_spmm_grp(
   constexpr int PPP = kThreads / (LPR * kGrpSub);      // panels per pass (4 or 2)
   constexpr int NPASS = 4 / PPP;                       // passes for 4 panels
   constexpr int R = kGrpR;
-  extern __shared__ double smem_d[];
+  extern __shared__ __attribute__((aligned(16))) double smem_d[];  // 16-byte vectors live here
   T* s_a = reinterpret_cast<T*>(smem_d);               // [lds_ent][R]
   T* s_b = s_a + (size_t)lds_ent * R;
   int* s_col = reinterpret_cast<int*>(s_b + (size_t)lds_ent * R);
@@ -1030,7 +1015,7 @@ __global__ __launch_bounds__(kThreads) void k_true_resid_lds(
     typename CT<T>::t* __restrict__ R, typename CT<T>::t* __restrict__ Z,
     double2* __restrict__ part) {
   using C = typename CT<T>::t;
-  extern __shared__ double smem_d[];
+  extern __shared__ __attribute__((aligned(16))) double smem_d[];  // 16-byte vectors live here
   double* s_a = smem_d;
   double* s_b = s_a + lds_nnz;
   int* s_col = reinterpret_cast<int*>(s_b + lds_nnz);
@@ -1831,14 +1816,6 @@ HaloView halo_view(const DevPencil& P) {
   return v;
 }
 
-// 16-byte chunks of one pass's staged coefficients per thread (0: too many)
-template <typename T>
-int halo_cpt(const DevPencil& P) {
-  const int chunks = P.hx_emax / 8 + P.hx_emax * (int)(2 * sizeof(T)) / 16;
-  const int c = (chunks + kThreads - 1) / kThreads;
-  return c <= 4 ? 4 : (c <= 8 ? 8 : (c <= 16 ? 16 : 0));
-}
-
 template <typename T>
 size_t halo_lds_bytes(const DevPencil& P) {
   return (size_t)P.hx_hmax * (8 * sizeof(typename LaneVec<T>::V) + sizeof(int)) +
@@ -1848,7 +1825,7 @@ size_t halo_lds_bytes(const DevPencil& P) {
 template <typename T>
 bool halo_selected(const DevPencil& P) {
   const int var = std::is_same<T, float>::value ? P.var32 : P.var64;
-  return var == kSpmmHalo && P.hx_ntile > 0 && P.hx_hmax <= kHaloMaxH && halo_cpt<T>(P) > 0 &&
+  return var == kSpmmHalo && P.hx_ntile > 0 && P.hx_hmax <= kHaloMaxH &&
          halo_lds_bytes<T>(P) <= 96 * 1024;
 }
 
@@ -1870,19 +1847,12 @@ bool launch_halo(const DevPencil& P, const PanelGrid& g, const SlotTables& st, i
   const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
   const size_t bytes = halo_lds_bytes<T>(P);
   const HaloView hv = halo_view<T>(P);
-  const int cpt = halo_cpt<T>(P);
   auto Zc = static_cast<const C*>(Z);
   auto Bc = static_cast<const C*>(Bin);
   auto Oc = static_cast<C*>(Out);
-#define SLRF_HALO_C(E, CP)                                                                     \
-  k_apply_halo<T, E, CP><<<blocks, kThreads, bytes, s>>>(P.n, hv, gg, G, st.active, st.sigma, \
-                                                         Zc, Oc, Bc, P.da, P.db, omega)
-#define SLRF_HALO(E)                      \
-  do {                                    \
-    if (cpt == 4) SLRF_HALO_C(E, 4);      \
-    else if (cpt == 8) SLRF_HALO_C(E, 8); \
-    else SLRF_HALO_C(E, 16);              \
-  } while (0)
+#define SLRF_HALO(E)                                                                      \
+  k_apply_halo<T, E><<<blocks, kThreads, bytes, s>>>(P.n, hv, gg, G, st.active, st.sigma, \
+                                                     Zc, Oc, Bc, P.da, P.db, omega)
   if (epi == kEpiApply)
     SLRF_HALO(kEpiApply);
   else if (epi == kEpiResid)
@@ -1890,7 +1860,6 @@ bool launch_halo(const DevPencil& P, const PanelGrid& g, const SlotTables& st, i
   else
     SLRF_HALO(kEpiJacobi);
 #undef SLRF_HALO
-#undef SLRF_HALO_C
   err = hipGetLastError();
   return true;
 }

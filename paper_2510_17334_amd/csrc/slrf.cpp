@@ -1356,7 +1356,7 @@ slrf_status slrf_setup(slrf_handle* out, const slrf_csr* A, const slrf_csr* B, d
     // Halo-tile format of the pencil in its final row order (absent when a
     // single 8-row slice references more columns than the LDS tile holds).
     HostHalo hx;
-    if (build_halo(n, rp, cl, hA, hB, kHaloMaxH, kHaloMaxRows, hx)) {
+    if (build_halo(n, rp, cl, hA, hB, kHaloMaxH, kHaloTileRows, hx)) {
       const size_t nent = hx.lcol.size();
       std::vector<float> ab32(hx.ab.begin(), hx.ab.end());
       const size_t sz[8] = {sizeof(int) * hx.trow.size(), sizeof(int) * hx.hptr.size(),

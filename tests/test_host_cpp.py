@@ -119,8 +119,9 @@ def test_detect_block(driver):
     assert _run(driver, _Csr(A, B), "block").i() == 1
 
 
+@pytest.mark.parametrize("hmax,cap", [(192, 512), (224, 32)])
 @pytest.mark.parametrize("which", ["q1_2d", "random"])
-def test_halo_format_reproduces_csr(driver, which):
+def test_halo_format_reproduces_csr(driver, which, hmax, cap):
     if which == "q1_2d":
         p = si.q1_kron_pencil(30, 2)
     else:
@@ -132,7 +133,6 @@ def test_halo_format_reproduces_csr(driver, which):
         Bm = M.copy()
         Bm.data = rng.standard_normal(M.nnz)
         p = _Csr(M, Bm)
-    hmax, cap = 192, 512
     r = _run(driver, p, "halo", hmax, cap)
     assert r.i() == 1
     hmx, emax = r.i(), r.i()

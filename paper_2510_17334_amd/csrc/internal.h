@@ -86,6 +86,7 @@ constexpr int kHaloMaxG = SLRF_HALO_G;  // units (128-byte panel column slices) 
 // A rectangular real CSR matrix on the device (AMG prolongation / restriction).
 struct DevTransfer {
   int nrows = 0, ncols = 0, nnz = 0;
+  int max_sub64 = 0;  // most entries in an aligned block of 64 rows
   const int* rowptr = nullptr;
   const int* col = nullptr;
   const double* v = nullptr;

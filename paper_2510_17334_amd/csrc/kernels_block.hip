@@ -2246,6 +2246,98 @@ __global__ __launch_bounds__(kThreads) void k_prolong(
   }
 }
 
+// Prolongation with the rows of P staged in LDS (64 rows at a time) once per
+// workgroup and shared by G panels; UNR coarse-row gathers in flight per lane.
+// Entries are summed in CSR order as in k_prolong (same result bitwise).
+template <typename T, bool ADD, int G>
+__global__ __launch_bounds__(kThreads) void k_prolong_lds(
+    int nout, int nin, const int* __restrict__ rowptr, const int* __restrict__ col,
+    const T* __restrict__ v, PanelGrid g, int lds_nnz, const int* __restrict__ active,
+    const typename CT<T>::t* __restrict__ In, typename CT<T>::t* __restrict__ Out) {
+  using V = typename LaneVec<T>::V;
+  constexpr int SPL = LaneVec<T>::SPL;
+  constexpr int LPR = kPanel / SPL;
+  constexpr int RPP = kThreads / LPR;
+  constexpr int SUB = 64;
+  constexpr int UNR = 4;
+  extern __shared__ __attribute__((aligned(16))) double smem_d[];
+  T* s_v = reinterpret_cast<T*>(smem_d);
+  int* s_col = reinterpret_cast<int*>(s_v + lds_nnz);
+  __shared__ int s_rp[SUB + 1];
+  __shared__ int s_pany[G];
+  const int ncg = (g.npan + G - 1) / G;
+  int rb, cg;
+  if (!map_tile(g.nrb, ncg, g.group, rb, cg)) return;
+  const int tid = threadIdx.x, lr = tid % LPR, rr = tid / LPR;
+  const int pan0 = cg * G;
+  if (tid < G) {
+    const int p = pan0 + tid;
+    int any = 0;
+    if (p < g.npan)
+      for (int l = 0; l < kPanel; ++l) any |= (active == nullptr || active[p * kPanel + l] != 0);
+    s_pany[tid] = any;
+  }
+  const int R0 = rb * g.rpb, R1 = min(R0 + g.rpb, nout);
+  for (int s0 = R0; s0 < R1; s0 += SUB) {
+    const int s1 = min(s0 + SUB, R1);
+    const int eb = rowptr[s0];
+    const int nsub = rowptr[s1] - eb;
+    for (int t = tid; t <= s1 - s0; t += kThreads) s_rp[t] = rowptr[s0 + t] - eb;
+    for (int t = tid; t < nsub; t += kThreads) {
+      s_col[t] = col[eb + t];
+      s_v[t] = v[eb + t];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) {
+      if (!s_pany[gg]) continue;
+      const int pan = pan0 + gg;
+      const V* __restrict__ Ip = reinterpret_cast<const V*>(In + (size_t)pan * nin * kPanel);
+      V* __restrict__ Op = reinterpret_cast<V*>(Out + (size_t)pan * nout * kPanel);
+      for (int row = s0 + rr; row < s1; row += RPP) {
+        const int e0 = s_rp[row - s0], e1 = s_rp[row - s0 + 1];
+        T acc[2 * SPL];
+#pragma unroll
+        for (int c = 0; c < 2 * SPL; ++c) acc[c] = 0;
+        for (int e = e0; e < e1; e += UNR) {
+          V z[UNR];
+          T w[UNR];
+#pragma unroll
+          for (int u = 0; u < UNR; ++u) {
+            z[u] = V{};
+            w[u] = 0;
+            if (e + u < e1) {
+              w[u] = s_v[e + u];
+              z[u] = Ip[(size_t)s_col[e + u] * LPR + lr];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < UNR; ++u) {
+            acc[0] = mad(w[u], z[u].x, acc[0]);
+            acc[1] = mad(w[u], z[u].y, acc[1]);
+            if constexpr (SPL == 2) {
+              acc[2] = mad(w[u], (T)lv_z(z[u]), acc[2]);
+              acc[3] = mad(w[u], (T)lv_w(z[u]), acc[3]);
+            }
+          }
+        }
+        V o;
+        o.x = acc[0];
+        o.y = acc[1];
+        if constexpr (SPL == 2) lv_set_zw(o, acc[2], acc[3]);
+        if constexpr (ADD) {
+          const V p = Op[(size_t)row * LPR + lr];
+          o.x += p.x;
+          o.y += p.y;
+          if constexpr (SPL == 2) lv_set_zw(o, (T)(lv_z(o) + lv_z(p)), (T)(lv_w(o) + lv_w(p)));
+        }
+        Op[(size_t)row * LPR + lr] = o;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_restrict(
     int nout, int nin, const int* __restrict__ rowptr, const int* __restrict__ col,
@@ -2317,6 +2409,22 @@ hipError_t launch_transfer(const DevTransfer& M, const PanelGrid& g, const SlotT
     const long nblk = (long)M.nrows * ((g.npan + 3) / 4);
     k_restrict<T><<<(unsigned)nblk, kThreads, 0, s>>>(M.nrows, M.ncols, M.rowptr, M.col, v,
                                                       g.npan, st.active, Ic, Oc);
+    return hipGetLastError();
+  }
+  const size_t lbytes = (size_t)M.max_sub64 * (sizeof(T) + sizeof(int));
+  if (M.max_sub64 > 0 && lbytes <= 32 * 1024) {
+    constexpr int G = 4;
+    PanelGrid gg = g;
+    const int ncg = (g.npan + G - 1) / G;
+    gg.group = ncg < 4 ? ncg : 4;
+    const long total = (long)g.nrb * ncg;
+    const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
+    if (add)
+      k_prolong_lds<T, true, G><<<blocks, kThreads, lbytes, s>>>(
+          M.nrows, M.ncols, M.rowptr, M.col, v, gg, M.max_sub64, st.active, Ic, Oc);
+    else
+      k_prolong_lds<T, false, G><<<blocks, kThreads, lbytes, s>>>(
+          M.nrows, M.ncols, M.rowptr, M.col, v, gg, M.max_sub64, st.active, Ic, Oc);
     return hipGetLastError();
   }
   if (add)

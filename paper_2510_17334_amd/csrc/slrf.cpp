@@ -369,6 +369,7 @@ slrf_status build_amg(slrf_ctx* h) {
     d.nrows = M.n;
     d.ncols = M.m;
     d.nnz = (int)M.ci.size();
+    d.max_sub64 = max_slice_of(M.rp, M.n, 64);
     std::vector<float> v32(M.v.begin(), M.v.end());
     hipError_t e;
     if ((e = upload(h, M.rp, &d.rowptr)) != hipSuccess) return e;

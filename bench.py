@@ -6,7 +6,7 @@ holding the 102 smallest eigenvalues, subspace L = 160 seeded N(0,1) columns,
 8 upper-half-plane shifted-Laplace poles -> 1280 shifted complex systems.
 
 One step = one outer iteration of Algorithm 1 on the seeded start block: the
-filter (B V, every (pole, column) system solved by restarted GCR, m = 8, with
+filter (B V, every (pole, column) system solved by restarted GCR, m = 5, with
 one V-cycle of the shared smoothed-aggregation AMG hierarchy as preconditioner,
 to a FP64 relative residual <= 1e-8, the pole sum) followed by Rayleigh-Ritz and the
 residual check.  `value` is systems / step time for the mixed-precision form
@@ -49,7 +49,7 @@ def parse():
                     help="also run a plain 2 GiB device copy (counter scale reference)")
     ap.add_argument("--m", type=int, default=64, help="Q1 nodes per direction (64 = metric)")
     ap.add_argument("--precond", choices=["amg", "jacobi"], default="amg")
-    ap.add_argument("--restart", type=int, default=8, help="GCR restart length m")
+    ap.add_argument("--restart", type=int, default=5, help="GCR restart length m")
     ap.add_argument("--ncols", type=int, default=160)
     ap.add_argument("--workload", choices=["q1_3d", "batch64", "itmax"], default="q1_3d",
                     help="q1_3d: the metric workload; batch64: the 64 uneven Q1 diffusion "

@@ -94,6 +94,45 @@ def test_shifted_spmm_parity(prec, which, variant):
     h.close()
 
 
+@pytest.mark.parametrize("prec", [P.SLRF_PREC_FP64, P.SLRF_PREC_MIXED])
+def test_shifted_spmm_full_size_sampled(prec):
+    """The benchmark's sweep (n = 262,144, 1280 systems, 8 poles, the autotuned
+    kernel) on sampled rows and systems against the row-by-row product."""
+    c = si.config_q1_3d()
+    p = c["pencil"]
+    poles, weights = si.slrf_poles(c["gamma"], 8)
+    h = _handle(p, c["gamma"], poles, weights)
+    nsys = 1280
+    pidx = np.arange(nsys) % 8
+    dt = torch.complex128 if prec == P.SLRF_PREC_FP64 else torch.complex64
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    Zt = torch.randn((nsys // 16, p.n, 16), dtype=dt, device="cuda", generator=g)
+    Q = h.slrf_shifted_spmm(Zt, pidx, prec)
+    order = h.slrf_get_row_order()
+    inv = np.empty_like(order)
+    inv[order] = np.arange(p.n)
+    rng = np.random.default_rng(12)
+    rows = np.concatenate([[0, 1, p.n - 1], rng.choice(p.n, 997, replace=False)])
+    systems = np.concatenate([[0, 15, 16, nsys - 1], rng.choice(nsys, 28, replace=False)])
+    A, B = p.A().tocsr(), p.B().tocsr()
+    eps = np.finfo(np.float64 if prec == P.SLRF_PREC_FP64 else np.float32).eps
+    sys_t = torch.as_tensor(systems, device="cuda")
+    Zs = _host(Zt[sys_t // 16, :, sys_t % 16]).astype(np.complex128)  # [systems, n]
+    Qs = _host(Q[sys_t // 16, :, sys_t % 16]).astype(np.complex128)
+    sg = poles[pidx[systems]]
+    for i in rows:
+        lo, hi = A.indptr[order[i]], A.indptr[order[i] + 1]
+        cols = inv[A.indices[lo:hi]]
+        a, b = A.data[lo:hi], B.data[lo:hi]
+        z = Zs[:, cols]
+        q = Qs[:, i]
+        ref = z @ a - sg * (z @ b)
+        scale = np.abs(z) @ np.abs(a) + np.abs(sg) * (np.abs(z) @ np.abs(b))
+        assert np.all(np.abs(q - ref) <= 32 * eps * scale + 1e-300), i
+    h.close()
+
+
 # ----------------------------------------------------------------------------
 # converged filter (a1-a7): residual certification and oracle parity
 # ----------------------------------------------------------------------------

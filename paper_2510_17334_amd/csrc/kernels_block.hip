@@ -2134,13 +2134,19 @@ hipError_t launch_lvl_op(const DevPencil& L, const PanelGrid& g, const SlotTable
     if (launch_halo<T>(L, g, st, epi, omega, X, Bin, Out, s, err)) return err;
     if (launch_grp<T>(L, g, st, epi, omega, X, Bin, Out, s, err)) return err;
   }
+  // (no partial sums here: a coarse level takes shorter row blocks, down to
+  // 64 rows, until the launch has enough workgroups to fill the chip)
+  const int ncg = (g.npan + kGroupPanels - 1) / kGroupPanels;
+  int rpb = g.rpb;
+  while (rpb > 64 && (long)((L.n + rpb - 1) / rpb) * ncg < 8192) rpb /= 2;
   int sub = 0, cap = 0;
   size_t bytes = 0;
-  if (lds_plan<T>(L, g.rpb, sub, cap, bytes)) {
+  if (lds_plan<T>(L, rpb, sub, cap, bytes)) {
     PanelGrid gg = g;
-    const int ncg = (g.npan + kGroupPanels - 1) / kGroupPanels;
+    gg.rpb = rpb;
+    gg.nrb = (L.n + rpb - 1) / rpb;
     gg.group = ncg < 4 ? ncg : 4;
-    const long total = (long)g.nrb * ncg;
+    const long total = (long)gg.nrb * ncg;
     const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
     const int unr = lds_unroll<T>(L);
 #define SLRF_LDS_LVL(E, U)                                                                   \

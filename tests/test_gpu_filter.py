@@ -133,6 +133,45 @@ def test_shifted_spmm_full_size_sampled(prec):
     h.close()
 
 
+@pytest.mark.parametrize("prec", [P.SLRF_PREC_FP64, P.SLRF_PREC_MIXED])
+def test_shifted_spmm_full_size_sine_closed_form(prec):
+    """Closed form at full size (n = 262,144): for a sine product u,
+    (A - sigma B) u = (lambda_u - sigma) mu_u u with mu_u the B eigenvalue."""
+    m = 64
+    c = si.config_q1_3d()
+    p = c["pencil"]
+    poles, weights = si.slrf_poles(c["gamma"], 8)
+    h = _handle(p, c["gamma"], poles, weights)
+    h1d = 1.0 / (m + 1)
+    t = np.arange(1, m + 1) * np.pi / (m + 1)
+    lam1 = (6.0 / h1d ** 2) * (1 - np.cos(t)) / (2 + np.cos(t))
+    mu1 = (h1d / 6.0) * (4 + 2 * np.cos(t))
+    ks = [(1, 1, 1), (2, 1, 3), (5, 4, 1), (64, 64, 64), (33, 7, 50), (1, 64, 2)]
+    # sin(j k pi / (m + 1)) with the argument reduced exactly (integer j k mod
+    # 2 (m + 1)): high modes are then eigenvectors to rounding
+    sv = lambda k: np.sin(((np.arange(1, m + 1) * k) % (2 * (m + 1))) * np.pi / (m + 1))
+    U = np.stack([np.kron(sv(a), np.kron(sv(b), sv(cc))) for a, b, cc in ks], axis=1)
+    lam = np.array([lam1[a - 1] + lam1[b - 1] + lam1[cc - 1] for a, b, cc in ks])
+    mu = np.array([mu1[a - 1] * mu1[b - 1] * mu1[cc - 1] for a, b, cc in ks])
+    order = h.slrf_get_row_order()
+    nv, npole = len(ks), len(poles)
+    nsys = nv * npole
+    pidx = np.arange(nsys) % npole
+    vidx = np.arange(nsys) // npole
+    Zh = U[order][:, vidx].astype(np.complex128)
+    dt = torch.complex128 if prec == P.SLRF_PREC_FP64 else torch.complex64
+    Zt = P.slrf.to_panels(torch.as_tensor(Zh, device="cuda").to(dt), p.n)
+    Q = _host(P.slrf.from_panels(h.slrf_shifted_spmm(Zt, pidx, prec), p.n, nsys))
+    sg = poles[pidx]
+    ref = Zh * ((lam[vidx] - sg) * mu[vidx])[None, :]
+    A, B = abs(p.A()[order][:, order]), abs(p.B()[order][:, order])
+    scale = A @ np.abs(Zh) + np.abs(sg)[None, :] * (B @ np.abs(Zh))
+    eps = np.finfo(np.float64 if prec == P.SLRF_PREC_FP64 else np.float32).eps
+    # the input is rounded to the sweep precision first in the mixed form
+    assert np.all(np.abs(Q.astype(np.complex128) - ref) <= 64 * eps * scale + 1e-300)
+    h.close()
+
+
 # ----------------------------------------------------------------------------
 # converged filter (a1-a7): residual certification and oracle parity
 # ----------------------------------------------------------------------------

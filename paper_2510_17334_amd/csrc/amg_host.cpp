@@ -454,4 +454,22 @@ bool amg_build(const HostLevel& fine, const std::vector<std::complex<double>>& p
   return true;
 }
 
+bool fine_image(const HostLevel& L, const HostCsrP& P, std::vector<int>& rp,
+                std::vector<int>& ci, std::vector<double>& ap, std::vector<double>& bp,
+                std::vector<double>& pv) {
+  spgemm2(L.n, P.m, L.rp, L.ci, L.a, &L.b, P.rp, P.ci, P.v, rp, ci, ap, &bp);
+  pv.assign(ci.size(), 0.0);
+  std::vector<int> at(P.m, -1);  // entry of column c in the current row
+  for (int i = 0; i < L.n; ++i) {
+    for (int e = rp[i]; e < rp[i + 1]; ++e) at[ci[e]] = e;
+    for (int f = P.rp[i]; f < P.rp[i + 1]; ++f) {
+      const int e = at[P.ci[f]];
+      if (e < rp[i] || e >= rp[i + 1]) return false;
+      pv[e] += P.v[f];
+    }
+    for (int e = rp[i]; e < rp[i + 1]; ++e) at[ci[e]] = -1;
+  }
+  return true;
+}
+
 }  // namespace slrf

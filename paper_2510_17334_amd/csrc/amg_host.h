@@ -50,4 +50,12 @@ int detect_block(const HostLevel& L);
 bool amg_build(const HostLevel& fine, const std::vector<std::complex<double>>& poles,
                const AmgParams& prm, AmgHierarchy& H, std::string& err);
 
+// The fine-level images of the prolongator, A P and B P (n x P.m, one shared
+// row-sorted pattern), and P's values on that pattern (zero where P has no
+// entry; P's pattern lies inside it because every row of A has its diagonal).
+// Returns false if some entry of P falls outside the pattern.
+bool fine_image(const HostLevel& L, const HostCsrP& P, std::vector<int>& rp,
+                std::vector<int>& ci, std::vector<double>& ap, std::vector<double>& bp,
+                std::vector<double>& pv);
+
 }  // namespace slrf

@@ -6,13 +6,15 @@ namespace slrf {
 
 bool build_halo(int n, const std::vector<int>& rp, const std::vector<int>& ci,
                 const std::vector<double>& a, const std::vector<double>& b, int hmax,
-                int rows_cap, HostHalo& out) {
+                int rows_cap, HostHalo& out, const std::vector<double>* c) {
   out = HostHalo();
   if (n <= 0 || hmax < 1 || hmax > 65535) return false;
   const int S = kHaloSlice;
   const int nslice = (n + S - 1) / S;
+  int ncol = n;
+  for (int e = 0; e < rp[n]; ++e) ncol = std::max(ncol, ci[e] + 1);
   // ---- tiles: greedy growth by whole slices under the halo and row caps
-  std::vector<int> stamp(n, -1);
+  std::vector<int> stamp(ncol, -1);
   out.trow.push_back(0);
   out.hptr.push_back(0);
   int tile = 0, hcount = 0, trows = 0;
@@ -50,7 +52,7 @@ bool build_halo(int n, const std::vector<int>& rp, const std::vector<int>& ci,
   out.trow.push_back(n);
   out.ntile = (int)out.trow.size() - 1;
   // ---- halos (sorted) and local indices
-  std::vector<int> pos(n, -1);
+  std::vector<int> pos(ncol, -1);
   std::vector<int> h;
   out.sptr.assign(nslice + 1, 0);
   out.slen.assign((size_t)nslice * S, 0);
@@ -68,6 +70,7 @@ bool build_halo(int n, const std::vector<int>& rp, const std::vector<int>& ci,
   const size_t nent = (size_t)out.sptr[nslice] * S;
   out.lcol.assign(nent, 0);
   out.ab.assign(2 * nent, 0.0);
+  if (c) out.c.assign(nent, 0.0);
   for (int t = 0; t < out.ntile; ++t) {
     const int r0 = out.trow[t], r1 = out.trow[t + 1];
     h.assign(ci.begin() + rp[r0], ci.begin() + rp[r1]);
@@ -84,6 +87,7 @@ bool build_halo(int n, const std::vector<int>& rp, const std::vector<int>& ci,
         out.lcol[k] = (uint16_t)pos[ci[e]];
         out.ab[2 * k] = a[e];
         out.ab[2 * k + 1] = b[e];
+        if (c) out.c[k] = (*c)[e];
       }
     }
     for (int c : h) pos[c] = -1;

@@ -27,16 +27,19 @@ struct HostHalo {
   std::vector<int> slen;   // [nslice * 8] row lengths
   std::vector<uint16_t> lcol;   // local column (halo position) per entry
   std::vector<double> ab;  // (a, b) per entry, interleaved
+  std::vector<double> c;   // optional third value per entry (same layout as lcol)
 };
 
 constexpr int kHaloSlice = 8;
-constexpr int kHaloPassSlices = 4;
-constexpr int kHaloPad = 4;         // slice widths are multiples of this  // slices formed together by one workgroup pass
+constexpr int kHaloPassSlices = 4;  // slices formed together by one workgroup pass
+constexpr int kHaloPad = 4;         // slice widths are multiples of this
 
 // Returns false (format not built) when a single slice references more than
-// hmax columns or hmax exceeds the 16-bit local index range.
+// hmax columns or hmax exceeds the 16-bit local index range.  The matrix may
+// be rectangular (columns are any non-negative indices); `c`, when given, is a
+// third value array on the same pattern, laid out like the entries into out.c.
 bool build_halo(int n, const std::vector<int>& rp, const std::vector<int>& ci,
                 const std::vector<double>& a, const std::vector<double>& b, int hmax,
-                int rows_cap, HostHalo& out);
+                int rows_cap, HostHalo& out, const std::vector<double>* c = nullptr);
 
 }  // namespace slrf

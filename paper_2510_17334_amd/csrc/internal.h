@@ -186,6 +186,33 @@ template <typename T>
 hipError_t launch_coarse_solve(int nc, const PanelGrid& g, const SlotTables& st, int npoles,
                                const void* Minv, const void* In, void* Out, hipStream_t s);
 
+// Fine-level image of the level-0 prolongator P for the fused up-step of the
+// V-cycle: (A P, B P) in the halo-tile format (rows: fine rows in 32-row
+// tiles; halo: coarse rows) with P's values per entry (zero where P has none).
+struct DevImage {
+  int nc = 0;                                 // coarse rows (columns of P)
+  int ntile = 0, hmax = 0, emax = 0;          // ntile == 0: not built
+  const int* trow = nullptr;
+  const int* hptr = nullptr;
+  const int* halo = nullptr;
+  const int* sptr = nullptr;
+  const unsigned short* lcol = nullptr;
+  const float2* ab32 = nullptr;
+  const double2* ab64 = nullptr;
+  const float* p32 = nullptr;
+  const double* p64 = nullptr;
+};
+constexpr int kImgMaxH = 64;  // largest coarse halo of an image tile
+// Level-0 up-step in one pass: with x = x0 + P e (e the coarse correction),
+// Out = x + omega D^-1 (r1 - (A P - sigma B P) e), where r1 = b - M x0 is the
+// residual the down-step formed; equal (to rounding) to prolongation followed
+// by the damped-Jacobi post-smoothing sweep.  Returns false (nothing
+// launched) when the pencil has no image.
+template <typename T>
+bool launch_post_image(const DevImage& I, const DevPencil& P, const PanelGrid& g,
+                       const SlotTables& st, double omega, const void* E, const void* X0,
+                       const void* R1, void* Out, hipStream_t s, hipError_t& err);
+
 hipError_t launch_retire(int n, const PanelGrid& g, const int* retire_sys, const double2* Y,
                          double2* Ystore, hipStream_t s);
 hipError_t launch_filter_sum(int n, int ncols, int npoles, const double2* Ystore,

@@ -686,6 +686,175 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
 #undef SLRF_HALO_ISSUE
 
 // ---------------------------------------------------------------------------
+// Fused level-0 up-step of the V-cycle on the image tiles of P: per fine row
+// and system, acc_a = sum (A P)_rc e_c, acc_b = sum (B P)_rc e_c and
+// acc_p = sum P_rc e_c over the row's image entries, then
+//   out = x0 + acc_p + omega D^-1 (r1 - (acc_a - sigma acc_b)).
+// The workgroup layout follows k_apply_halo: one 32-row tile, a run of G
+// units, the tile's coefficients staged once, each unit's coarse halo rows of
+// e copied into LDS (loaded into registers while the previous unit is formed).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_post_image(
+    int n, int nc, HaloView hv, const T* __restrict__ pv, PanelGrid g, int G,
+    const int* __restrict__ active, const double2* __restrict__ sigma,
+    const typename CT<T>::t* __restrict__ E, const typename CT<T>::t* __restrict__ X0,
+    const typename CT<T>::t* __restrict__ R1, typename CT<T>::t* __restrict__ Out,
+    const double* __restrict__ da, const double* __restrict__ db, double omega) {
+  using V = typename LaneVec<T>::V;
+  using AB = typename CT<T>::t;
+  constexpr int SPL = LaneVec<T>::SPL;
+  constexpr int UPP = SPL == 2 ? 1 : 2;
+  constexpr int LPRF = kPanel / SPL;
+  constexpr int SPU = kPanel / UPP;
+  constexpr int UNR = 4;  // = kHaloPad
+  extern __shared__ __attribute__((aligned(16))) double smem_d[];  // 16-byte vectors live here
+  V* sZ = reinterpret_cast<V*>(smem_d);                            // [hmax][8]
+  AB* s_ab = reinterpret_cast<AB*>(sZ + (size_t)g.rpb * 8);        // [emax]
+  T* s_p = reinterpret_cast<T*>(s_ab + hv.emax);                   // [emax]
+  unsigned short* s_lc = reinterpret_cast<unsigned short*>(s_p + hv.emax);  // [emax]
+  int* sH = reinterpret_cast<int*>(s_lc + hv.emax);                         // [hmax]
+  __shared__ int s_sp[kHaloTileRows / 8 + 1];
+  __shared__ int s_uact[kHaloMaxG];
+  const int nunit = g.npan * UPP;
+  const int nug = (nunit + G - 1) / G;
+  int tile, ug;
+  if (!map_tile(hv.ntile, nug, g.group, tile, ug)) return;
+  const int tid = threadIdx.x, w = tid >> 6, rr = (tid >> 3) & 7, lr = tid & 7;
+  const int r0 = hv.trow[tile], r1 = hv.trow[tile + 1];
+  const int h0 = hv.hptr[tile], H = hv.hptr[tile + 1] - h0;
+  const int nsl = (r1 - r0 + 7) >> 3, sl0 = r0 >> 3;  // (nsl <= 4: format invariant)
+  for (int t = tid; t < H; t += kThreads) sH[t] = hv.halo[h0 + t];
+  if (tid <= nsl) s_sp[tid] = hv.sptr[sl0 + tid];
+  if (tid < G) {
+    const int u = ug * G + tid;
+    int any = 0;
+    if (u < nunit) {
+      const int b = (u / UPP) * kPanel + (u % UPP) * SPU;
+      for (int l = 0; l < SPU; ++l) any |= (active == nullptr || active[b + l] != 0) ? 1 : 0;
+    }
+    s_uact[tid] = any;
+  }
+  __syncthreads();
+  int gu = 0;
+  while (gu < G && !s_uact[gu]) ++gu;
+  if (gu >= G) return;
+  constexpr int HP = (kImgMaxH * 8 + kThreads - 1) / kThreads;
+  V hreg[HP];
+#define SLRF_IMG_ISSUE(GX)                                                                  \
+  do {                                                                                      \
+    const int ux_ = ug * G + (GX);                                                          \
+    const V* __restrict__ ex_ =                                                             \
+        reinterpret_cast<const V*>(E + (size_t)(ux_ / UPP) * nc * kPanel) + (ux_ % UPP) * 8; \
+    _Pragma("unroll") for (int i_ = 0; i_ < HP; ++i_) {                                     \
+      const int t_ = i_ * kThreads + tid;                                                   \
+      hreg[i_] = V{};                                                                       \
+      if (t_ < H * 8) hreg[i_] = ex_[(size_t)sH[t_ >> 3] * LPRF + (t_ & 7)];                \
+    }                                                                                       \
+  } while (0)
+  SLRF_IMG_ISSUE(gu);
+  {
+    const int e0 = s_sp[0] * 8, ne = (s_sp[nsl] - s_sp[0]) * 8;
+    const int nlc = ne / 8, nab = ne * (int)sizeof(AB) / 16, np = ne * (int)sizeof(T) / 16;
+    const uint4* __restrict__ glc = reinterpret_cast<const uint4*>(hv.lcol) + e0 / 8;
+    const uint4* __restrict__ gab =
+        static_cast<const uint4*>(hv.ab) + (size_t)e0 * sizeof(AB) / 16;
+    const uint4* __restrict__ gp = reinterpret_cast<const uint4*>(pv) + (size_t)e0 * sizeof(T) / 16;
+    for (int t = tid; t < nlc; t += kThreads) reinterpret_cast<uint4*>(s_lc)[t] = glc[t];
+    for (int t = tid; t < nab; t += kThreads) reinterpret_cast<uint4*>(s_ab)[t] = gab[t];
+    for (int t = tid; t < np; t += kThreads) reinterpret_cast<uint4*>(s_p)[t] = gp[t];
+  }
+  const int row = r0 + w * 8 + rr;
+  const int wdt = w < nsl ? s_sp[w + 1] - s_sp[w] : 0;
+  const int soff = w < nsl ? (s_sp[w] - s_sp[0]) * 8 + rr : 0;
+  while (gu < G) {
+    const int u = ug * G + gu;
+    const int pan = u / UPP, half = u % UPP;
+    const int sys0 = pan * kPanel + half * SPU;
+    const size_t pbase = (size_t)pan * n * kPanel;
+#pragma unroll
+    for (int i = 0; i < HP; ++i) {
+      const int t = i * kThreads + tid;
+      if (t < H * 8) sZ[t] = hreg[i];
+    }
+    int gn = gu + 1;
+    while (gn < G && !s_uact[gn]) ++gn;
+    T sr[SPL], si[SPL];
+#pragma unroll
+    for (int q = 0; q < SPL; ++q) {
+      const double2 sgm = sigma[sys0 + lr * SPL + q];
+      sr[q] = (T)sgm.x;
+      si[q] = (T)sgm.y;
+    }
+    __syncthreads();
+    if (gn < G) SLRF_IMG_ISSUE(gn);
+    if (w < nsl) {
+      const AB* __restrict__ pab = s_ab + soff;
+      const T* __restrict__ pp = s_p + soff;
+      const unsigned short* __restrict__ plc = s_lc + soff;
+      const V* __restrict__ pz = sZ + lr;
+      T acc[4 * SPL], accp[2 * SPL];
+#pragma unroll
+      for (int v = 0; v < 4 * SPL; ++v) acc[v] = 0;
+#pragma unroll
+      for (int v = 0; v < 2 * SPL; ++v) accp[v] = 0;
+      for (int j = 0; j < wdt; j += UNR) {
+        V z[UNR];
+        AB ab[UNR];
+        T pw[UNR];
+#pragma unroll
+        for (int uu = 0; uu < UNR; ++uu) {
+          ab[uu] = pab[(j + uu) * 8];
+          pw[uu] = pp[(j + uu) * 8];
+          z[uu] = pz[(int)plc[(j + uu) * 8] * 8];
+        }
+#pragma unroll
+        for (int uu = 0; uu < UNR; ++uu) {
+          lane_fma<T, SPL>(acc, ab[uu].x, ab[uu].y, z[uu]);
+          accp[0] = mad(pw[uu], (T)z[uu].x, accp[0]);
+          accp[1] = mad(pw[uu], (T)z[uu].y, accp[1]);
+          if constexpr (SPL == 2) {
+            accp[2] = mad(pw[uu], (T)lv_z(z[uu]), accp[2]);
+            accp[3] = mad(pw[uu], (T)lv_w(z[uu]), accp[3]);
+          }
+        }
+      }
+      if (row < r1) {
+        const size_t off = (size_t)row * LPRF + lr;
+        const V xo = (reinterpret_cast<const V*>(X0 + pbase) + half * 8)[off];
+        const V ro = (reinterpret_cast<const V*>(R1 + pbase) + half * 8)[off];
+        const double dav = da[row], dbv = db[row];
+        V q;
+#pragma unroll
+        for (int c = 0; c < SPL; ++c) {
+          // M P e for system c, then s = r1 - M P e and x = x0 + P e
+          const T mr = acc[4 * c + 0] - (sr[c] * acc[4 * c + 2] - si[c] * acc[4 * c + 3]);
+          const T mi = acc[4 * c + 1] - (sr[c] * acc[4 * c + 3] + si[c] * acc[4 * c + 2]);
+          const double rx = (c == 0 ? (double)ro.x : lv_z(ro)) - (double)mr;
+          const double ry = (c == 0 ? (double)ro.y : lv_w(ro)) - (double)mi;
+          const double ox = (c == 0 ? (double)xo.x : lv_z(xo)) + (double)accp[2 * c];
+          const double oy = (c == 0 ? (double)xo.y : lv_w(xo)) + (double)accp[2 * c + 1];
+          const double dx = dav - (double)sr[c] * dbv, dy = -(double)si[c] * dbv;
+          const double iv = omega / (dx * dx + dy * dy);
+          const double ix = dx * iv, iy = -dy * iv;  // omega / (d)
+          const T nx = (T)(ox + rx * ix - ry * iy), ny = (T)(oy + rx * iy + ry * ix);
+          if (c == 0) {
+            q.x = nx;
+            q.y = ny;
+          } else {
+            lv_set_zw(q, nx, ny);
+          }
+        }
+        (reinterpret_cast<V*>(Out + pbase) + half * 8)[off] = q;
+      }
+    }
+    __syncthreads();  // the unit's halo consumed
+    gu = gn;
+  }
+}
+#undef SLRF_IMG_ISSUE
+
+// ---------------------------------------------------------------------------
 // Row-group ("union") shifted SpMM.  Rows are taken in groups of R = 4
 // consecutive rows; a group stores the union of its rows' columns once and,
 // per union entry, the R coefficients of A and of B (zero where a row has no
@@ -1870,6 +2039,43 @@ bool sweep_is_halo(const DevPencil& P) {
 }
 
 template <typename T>
+bool launch_post_image(const DevImage& I, const DevPencil& P, const PanelGrid& g,
+                       const SlotTables& st, double omega, const void* E, const void* X0,
+                       const void* R1, void* Out, hipStream_t s, hipError_t& err) {
+  using C = typename CT<T>::t;
+  if (I.ntile == 0 || I.hmax > kImgMaxH) return false;
+  constexpr int UPP = std::is_same<T, float>::value ? 1 : 2;
+  const int G = kHaloMaxG;
+  const int nug = (g.npan * UPP + G - 1) / G;
+  PanelGrid gg = g;
+  gg.group = nug < 4 ? nug : 4;
+  gg.rpb = I.hmax;  // LDS halo rows (the kernel's carve-up of dynamic LDS)
+  const long total = (long)I.ntile * nug;
+  const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
+  const size_t bytes = (size_t)I.hmax * (8 * sizeof(typename LaneVec<T>::V) + sizeof(int)) +
+                       (size_t)I.emax * (3 * sizeof(T) + 2);
+  HaloView hv;
+  hv.ntile = I.ntile;
+  hv.emax = I.emax;
+  hv.trow = I.trow;
+  hv.hptr = I.hptr;
+  hv.halo = I.halo;
+  hv.sptr = I.sptr;
+  hv.slen = nullptr;
+  hv.lcol = I.lcol;
+  hv.ab = std::is_same<T, float>::value ? static_cast<const void*>(I.ab32)
+                                        : static_cast<const void*>(I.ab64);
+  const T* pv = std::is_same<T, float>::value ? reinterpret_cast<const T*>(I.p32)
+                                              : reinterpret_cast<const T*>(I.p64);
+  k_post_image<T><<<blocks, kThreads, bytes, s>>>(
+      P.n, I.nc, hv, pv, gg, G, st.active, st.sigma, static_cast<const C*>(E),
+      static_cast<const C*>(X0), static_cast<const C*>(R1), static_cast<C*>(Out), P.da, P.db,
+      omega);
+  err = hipGetLastError();
+  return true;
+}
+
+template <typename T>
 hipError_t launch_dots(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
                        const void* Qk, const void* Qbase, size_t vstride, int k, double2* part,
                        hipStream_t s) {
@@ -2464,7 +2670,10 @@ hipError_t launch_coarse_solve(int nc, const PanelGrid& g, const SlotTables& st,
                                          const SlotTables&, const void*, void*, bool,          \
                                          hipStream_t);                                         \
   template hipError_t launch_coarse_solve<T>(int, const PanelGrid&, const SlotTables&, int,    \
-                                             const void*, const void*, void*, hipStream_t);
+                                             const void*, const void*, void*, hipStream_t);   \
+  template bool launch_post_image<T>(const DevImage&, const DevPencil&, const PanelGrid&,       \
+                                     const SlotTables&, double, const void*, const void*,       \
+                                     const void*, void*, hipStream_t, hipError_t&);
 SLRF_INST_AMG(float)
 SLRF_INST_AMG(double)
 

@@ -77,6 +77,7 @@ struct DevAmg {
   void* inv32 = nullptr;                // [pole][nc][nc] complex float
   std::vector<void*> allocs;
   std::vector<double> omega;            // Jacobi smoothing weight per level (all but the coarsest)
+  DevImage img;                         // fine image of P_0 (fused up-step), ntile 0 if absent
   size_t nnz_all = 0;                   // level + transfer nonzeros (byte accounting)
   ~DevAmg() {
     for (void* p : allocs) (void)hipFree(p);
@@ -385,6 +386,38 @@ slrf_status build_amg(slrf_ctx* h) {
     A.R.push_back(R);
     A.nnz_all += P.nnz + R.nnz;
   }
+  // fine image (A P_0, B P_0) with P_0's values, in 32-row halo tiles over
+  // the coarse rows: the fused level-0 up-step (absent when a tile's coarse
+  // halo would exceed kImgMaxH rows)
+  A.img = DevImage();
+  if (L >= 2) {
+    std::vector<int> irp, ici;
+    std::vector<double> iap, ibp, ipv;
+    HostHalo hx;
+    if (fine_image(fine, H.P[0], irp, ici, iap, ibp, ipv) &&
+        build_halo(n, irp, ici, iap, ibp, kImgMaxH, kHaloTileRows, hx, &ipv)) {
+      DevImage& I = A.img;
+      std::vector<float> ab32(hx.ab.begin(), hx.ab.end()), p32(hx.c.begin(), hx.c.end());
+      std::vector<double2> ab64(hx.ab.size() / 2);
+      for (size_t i = 0; i < ab64.size(); ++i) ab64[i] = make_double2(hx.ab[2 * i], hx.ab[2 * i + 1]);
+      std::vector<float2> ab32v(ab64.size());
+      for (size_t i = 0; i < ab64.size(); ++i) ab32v[i] = make_float2(ab32[2 * i], ab32[2 * i + 1]);
+      HIPCHK(upload(h, hx.trow, &I.trow));
+      HIPCHK(upload(h, hx.hptr, &I.hptr));
+      HIPCHK(upload(h, hx.halo, &I.halo));
+      HIPCHK(upload(h, hx.sptr, &I.sptr));
+      HIPCHK(upload(h, hx.lcol, &I.lcol));
+      HIPCHK(upload(h, ab32v, &I.ab32));
+      HIPCHK(upload(h, ab64, &I.ab64));
+      HIPCHK(upload(h, p32, &I.p32));
+      HIPCHK(upload(h, hx.c, &I.p64));
+      I.nc = H.P[0].m;
+      I.hmax = hx.hmax;
+      I.emax = hx.emax;
+      I.ntile = hx.ntile;
+      A.nnz_all += ici.size();
+    }
+  }
   A.nc = H.nc;
   std::vector<double2> i64(H.coarse_inv.size());
   std::vector<float2> i32(H.coarse_inv.size());
@@ -491,6 +524,15 @@ slrf_status vcycle(slrf_ctx* h, const AmgVecs& v, int C, int occ, int ND, const 
     x[L - 1] = v.X[L - 1];
     for (int l = L - 2; l >= 0; --l) {
       const PanelGrid g = make_grid(A.n[l], C, occ, ND);
+      if (l == 0) {
+        // prolongation and post-smoothing of the fine level in one pass
+        hipError_t err = hipSuccess;
+        if (launch_post_image<T>(A.img, h->P, g, st, A.omega[0], x[1], x[0], v.T0, Zout, s,
+                                 err)) {
+          HIPCHK(err);
+          break;
+        }
+      }
       HIPCHK(launch_transfer<T>(A.P[l], g, st, x[l + 1], x[l], true, s));
       void* out = l == 0 ? Zout : v.W[l];
       const bool fine = l == 0 && sweep_is_halo<T>(h->P);

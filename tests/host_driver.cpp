@@ -98,6 +98,39 @@ int main(int argc, char** argv) {
     put(H.rho);
     put_i(H.nc);
     put(H.coarse_inv);
+  } else if (mode == "image") {
+    // fine image of P_0 and its halo-tile layout with P's values as the third array
+    AmgParams prm;
+    prm.block = std::atoi(argv[4]);
+    AmgHierarchy H;
+    std::string err;
+    std::vector<std::complex<double>> poles{{1.0, 1.0}};
+    bool ok = amg_build(L, poles, prm, H, err) && H.P.size() >= 1;
+    std::vector<int> rp, ci;
+    std::vector<double> ap, bp, pv;
+    ok = ok && fine_image(L, H.P[0], rp, ci, ap, bp, pv);
+    HostHalo X;
+    const bool hok = ok && build_halo(n, rp, ci, ap, bp, std::atoi(argv[5]), std::atoi(argv[6]), X, &pv);
+    put_i(ok ? 1 : 0);
+    put_i(hok ? 1 : 0);
+    put_i(ok ? H.P[0].m : 0);
+    put(H.P.empty() ? std::vector<int>() : H.P[0].rp);
+    put(H.P.empty() ? std::vector<int>() : H.P[0].ci);
+    put(H.P.empty() ? std::vector<double>() : H.P[0].v);
+    put(rp);
+    put(ci);
+    put(ap);
+    put(bp);
+    put(pv);
+    put_i(X.hmax);
+    put(X.trow);
+    put(X.hptr);
+    put(X.halo);
+    put(X.sptr);
+    put(X.slen);
+    put(X.lcol);
+    put(X.ab);
+    put(X.c);
   } else {
     return 2;
   }

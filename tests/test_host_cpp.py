@@ -11,7 +11,10 @@
 * amg_build: every coarse pair is the Galerkin product (P^T A P, P^T B P) to
   rounding, R = P^T, the dense coarsest inverse inverts A_c - sigma B_c, and
   the power-iteration estimate of rho(D^-1 A) is within 10 % below the true
-  value.
+  value;
+* fine_image: (A P_0, B P_0) and P_0's values on that pattern, and their
+  rectangular halo-tile layout (columns are coarse rows) carrying P as the
+  third value array.
 """
 
 import os
@@ -217,3 +220,49 @@ def test_amg_galerkin_hierarchy(driver, which):
     Ac, Bc = levels[-1]
     Mc = (Ac - sigma * Bc).toarray()
     assert np.abs(inv @ Mc - np.eye(ncoarse)).max() <= 1e-10
+
+
+@pytest.mark.parametrize("which", ["q1_diffusion_3d", "elasticity_block"])
+def test_fine_image_of_prolongator(driver, which):
+    if which == "q1_diffusion_3d":
+        p = si.q1_diffusion_pencil(9, 3, np.exp(np.random.default_rng(8).normal(0, .5, 1000)))
+        block = 1
+    else:
+        p = _elastic(6, 3)  # large enough for a two-level hierarchy
+        block = 3
+    r = _run(driver, p, "image", block, 256, 32)
+    assert r.i() == 1 and r.i() == 1
+    nc = r.i()
+    n = p.n
+    prp, pci, pv0 = r.arr(np.int32), r.arr(np.int32), r.arr(np.float64)
+    P = sp.csr_matrix((pv0, pci, prp), shape=(n, nc))
+    rp, ci = r.arr(np.int32), r.arr(np.int32)
+    ap, bp, pv = r.arr(np.float64), r.arr(np.float64), r.arr(np.float64)
+    A = sp.csr_matrix((p.a, p.indices, p.indptr), shape=(n, n))
+    B = sp.csr_matrix((p.b, p.indices, p.indptr), shape=(n, n))
+    AP = sp.csr_matrix((ap, ci, rp), shape=(n, nc))
+    BP = sp.csr_matrix((bp, ci, rp), shape=(n, nc))
+    PP = sp.csr_matrix((pv, ci, rp), shape=(n, nc))
+    for M, ref in ((AP, A @ P), (BP, B @ P), (PP, P)):
+        d = (M - ref).toarray()
+        assert np.abs(d).max() <= 1e-13 * max(np.abs(ref.toarray()).max(), 1.0)
+    # the halo layout carries all three arrays entry for entry
+    hmax = r.i()
+    trow, hptr, halo = r.arr(np.int32), r.arr(np.int32), r.arr(np.int32)
+    sptr, slen = r.arr(np.int32), r.arr(np.int32)
+    lcol, ab, c3 = r.arr(np.uint16), r.arr(np.float64).reshape(-1, 2), r.arr(np.float64)
+    assert np.all(np.diff(trow) <= 32) and hmax == np.max(np.diff(hptr))
+    rows, cols, va, vb, vc = [], [], [], [], []
+    for t in range(len(trow) - 1):
+        h = halo[hptr[t]:hptr[t + 1]]
+        assert np.all(h < nc)
+        for rrow in range(trow[t], trow[t + 1]):
+            s_, ln = rrow // 8, rrow % 8
+            L = slen[rrow]
+            k = (sptr[s_] + np.arange(L)) * 8 + ln
+            rows += [rrow] * L
+            cols += list(h[lcol[k]])
+            va += list(ab[k, 0]); vb += list(ab[k, 1]); vc += list(c3[k])
+    for vals, ref in ((va, AP), (vb, BP), (vc, PP)):
+        M = sp.csr_matrix((vals, (rows, cols)), shape=(n, nc))
+        assert abs(M - ref).max() == 0.0

@@ -865,21 +865,23 @@ __global__ __launch_bounds__(kThreads) void k_post_image(
         const size_t off = (size_t)row * LPRF + lr;
         const V xo = (reinterpret_cast<const V*>(X0 + pbase) + half * 8)[off];
         const V ro = (reinterpret_cast<const V*>(R1 + pbase) + half * 8)[off];
-        const double dav = da[row], dbv = db[row];
+        // (the smoother scaling in the vector precision: the V-cycle is a
+        // preconditioner, its arithmetic precision is the sweep's)
+        const T dav = (T)da[row], dbv = (T)db[row], om = (T)omega;
         V q;
 #pragma unroll
         for (int c = 0; c < SPL; ++c) {
           // M P e for system c, then s = r1 - M P e and x = x0 + P e
           const T mr = acc[4 * c + 0] - (sr[c] * acc[4 * c + 2] - si[c] * acc[4 * c + 3]);
           const T mi = acc[4 * c + 1] - (sr[c] * acc[4 * c + 3] + si[c] * acc[4 * c + 2]);
-          const double rx = (c == 0 ? (double)ro.x : lv_z(ro)) - (double)mr;
-          const double ry = (c == 0 ? (double)ro.y : lv_w(ro)) - (double)mi;
-          const double ox = (c == 0 ? (double)xo.x : lv_z(xo)) + (double)accp[2 * c];
-          const double oy = (c == 0 ? (double)xo.y : lv_w(xo)) + (double)accp[2 * c + 1];
-          const double dx = dav - (double)sr[c] * dbv, dy = -(double)si[c] * dbv;
-          const double iv = omega / (dx * dx + dy * dy);
-          const double ix = dx * iv, iy = -dy * iv;  // omega / (d)
-          const T nx = (T)(ox + rx * ix - ry * iy), ny = (T)(oy + rx * iy + ry * ix);
+          const T rx = (c == 0 ? ro.x : (T)lv_z(ro)) - mr;
+          const T ry = (c == 0 ? ro.y : (T)lv_w(ro)) - mi;
+          const T ox = (c == 0 ? xo.x : (T)lv_z(xo)) + accp[2 * c];
+          const T oy = (c == 0 ? xo.y : (T)lv_w(xo)) + accp[2 * c + 1];
+          const T dx = dav - sr[c] * dbv, dy = -si[c] * dbv;
+          const T iv = om / (dx * dx + dy * dy);
+          const T ix = dx * iv, iy = -dy * iv;  // omega / (d)
+          const T nx = ox + rx * ix - ry * iy, ny = oy + rx * iy + ry * ix;
           if (c == 0) {
             q.x = nx;
             q.y = ny;
@@ -895,6 +897,162 @@ __global__ __launch_bounds__(kThreads) void k_post_image(
   }
 }
 #undef SLRF_IMG_ISSUE
+
+// ---------------------------------------------------------------------------
+// FP64 true residual on the halo tiles: r = f - (A - sigma B) y for the
+// complex-double solution y (staged per unit and tile in LDS as in
+// k_apply_halo<double>), written as R in the inner precision and as Z
+// (point Jacobi, copy, or nothing).  A row's entries are summed in CSR order
+// with the same fused multiply-adds as k_true_resid (padding entries add
+// exact zeros), so R and Z are bitwise those of the CSR kernel.  The norms
+// are taken by k_rnorm over R.
+// ---------------------------------------------------------------------------
+template <typename TI>
+__global__ __launch_bounds__(kThreads) void k_true_halo(
+    int n, HaloView hv, PanelGrid g, int G, const int* __restrict__ sys,
+    const int* __restrict__ scol, const double2* __restrict__ sigma,
+    const double2* __restrict__ Y, const double* __restrict__ F, int ldf,
+    typename CT<TI>::t* __restrict__ R, typename CT<TI>::t* __restrict__ Z,
+    const double* __restrict__ da, const double* __restrict__ db, int pc) {
+  using V = double2;
+  using C = typename CT<TI>::t;
+  constexpr int UPP = 2, LPRF = kPanel, SPU = kPanel / UPP, UNR = 4;
+  extern __shared__ __attribute__((aligned(16))) double smem_d[];  // 16-byte vectors live here
+  V* sZ = reinterpret_cast<V*>(smem_d);                            // [hmax][8]
+  double2* s_ab = reinterpret_cast<double2*>(sZ + (size_t)g.rpb * 8);          // [emax]
+  unsigned short* s_lc = reinterpret_cast<unsigned short*>(s_ab + hv.emax);  // [emax]
+  int* sH = reinterpret_cast<int*>(s_lc + hv.emax);                          // [hmax]
+  __shared__ int s_sp[kHaloTileRows / 8 + 1];
+  __shared__ int s_uact[kHaloMaxG];
+  const int nunit = g.npan * UPP;
+  const int nug = (nunit + G - 1) / G;
+  int tile, ug;
+  if (!map_tile(hv.ntile, nug, g.group, tile, ug)) return;
+  const int tid = threadIdx.x, w = tid >> 6, rr = (tid >> 3) & 7, lr = tid & 7;
+  const int r0 = hv.trow[tile], r1 = hv.trow[tile + 1];
+  const int h0 = hv.hptr[tile], H = hv.hptr[tile + 1] - h0;
+  const int nsl = (r1 - r0 + 7) >> 3, sl0 = r0 >> 3;  // (nsl <= 4: format invariant)
+  for (int t = tid; t < H; t += kThreads) sH[t] = hv.halo[h0 + t];
+  if (tid <= nsl) s_sp[tid] = hv.sptr[sl0 + tid];
+  if (tid < G) {
+    const int u = ug * G + tid;
+    int any = 0;
+    if (u < nunit) {
+      const int b = (u / UPP) * kPanel + (u % UPP) * SPU;
+      for (int l = 0; l < SPU; ++l) any |= sys[b + l] >= 0 ? 1 : 0;
+    }
+    s_uact[tid] = any;
+  }
+  __syncthreads();
+  int gu = 0;
+  while (gu < G && !s_uact[gu]) ++gu;
+  if (gu >= G) return;
+  constexpr int HP = (kHaloMaxH * 8 + kThreads - 1) / kThreads;
+  V hreg[HP];
+#define SLRF_TRUE_ISSUE(GX)                                                              \
+  do {                                                                                   \
+    const int ux_ = ug * G + (GX);                                                       \
+    const V* __restrict__ yx_ = Y + (size_t)(ux_ / UPP) * n * kPanel + (ux_ % UPP) * 8;  \
+    _Pragma("unroll") for (int i_ = 0; i_ < HP; ++i_) {                                  \
+      const int t_ = i_ * kThreads + tid;                                                \
+      hreg[i_] = V{};                                                                    \
+      if (t_ < H * 8) hreg[i_] = yx_[(size_t)sH[t_ >> 3] * LPRF + (t_ & 7)];             \
+    }                                                                                    \
+  } while (0)
+  SLRF_TRUE_ISSUE(gu);
+  {
+    const int e0 = s_sp[0] * 8, ne = (s_sp[nsl] - s_sp[0]) * 8;
+    const uint4* __restrict__ glc = reinterpret_cast<const uint4*>(hv.lcol) + e0 / 8;
+    const uint4* __restrict__ gab = static_cast<const uint4*>(hv.ab) + e0;
+    for (int t = tid; t < ne / 8; t += kThreads) reinterpret_cast<uint4*>(s_lc)[t] = glc[t];
+    for (int t = tid; t < ne; t += kThreads) reinterpret_cast<uint4*>(s_ab)[t] = gab[t];
+  }
+  const int row = r0 + w * 8 + rr;
+  const int wdt = w < nsl ? s_sp[w + 1] - s_sp[w] : 0;
+  const int soff = w < nsl ? (s_sp[w] - s_sp[0]) * 8 + rr : 0;
+  while (gu < G) {
+    const int u = ug * G + gu;
+    const int pan = u / UPP, half = u % UPP;
+    const int slot = pan * kPanel + half * SPU + lr;
+#pragma unroll
+    for (int i = 0; i < HP; ++i) {
+      const int t = i * kThreads + tid;
+      if (t < H * 8) sZ[t] = hreg[i];
+    }
+    int gn = gu + 1;
+    while (gn < G && !s_uact[gn]) ++gn;
+    const bool occ = sys[slot] >= 0;
+    const double2 sg = occ ? sigma[slot] : make_double2(0.0, 0.0);
+    const int cl = occ ? scol[slot] : 0;
+    __syncthreads();
+    if (gn < G) SLRF_TRUE_ISSUE(gn);
+    if (w < nsl && occ) {
+      const double2* __restrict__ pab = s_ab + soff;
+      const unsigned short* __restrict__ plc = s_lc + soff;
+      const V* __restrict__ pz = sZ + lr;
+      double ar = 0, ai = 0, br = 0, bi = 0;
+      for (int j = 0; j < wdt; j += UNR) {
+        V z[UNR];
+        double2 ab[UNR];
+#pragma unroll
+        for (int uu = 0; uu < UNR; ++uu) {
+          ab[uu] = pab[(j + uu) * 8];
+          z[uu] = pz[(int)plc[(j + uu) * 8] * 8];
+        }
+#pragma unroll
+        for (int uu = 0; uu < UNR; ++uu) {
+          ar = fma(ab[uu].x, z[uu].x, ar);
+          ai = fma(ab[uu].x, z[uu].y, ai);
+          br = fma(ab[uu].y, z[uu].x, br);
+          bi = fma(ab[uu].y, z[uu].y, bi);
+        }
+      }
+      if (row < r1) {
+        const double mx = ar - (sg.x * br - sg.y * bi);
+        const double my = ai - (sg.x * bi + sg.y * br);
+        const double x = F[(size_t)row * ldf + cl] - mx, y = -my;
+        const size_t off = ((size_t)pan * n + row) * kPanel + half * SPU + lr;
+        R[off] = mk<C>(x, y);
+        if (pc == 1) {
+          const double2 d = jacobi_inv(da[row], db[row], sg);
+          Z[off] = mk<C>(x * d.x - y * d.y, x * d.y + y * d.x);
+        } else if (pc == 0) {
+          Z[off] = mk<C>(x, y);
+        }
+      }
+    }
+    __syncthreads();  // the unit's halo consumed
+    gu = gn;
+  }
+}
+#undef SLRF_TRUE_ISSUE
+
+// ||r||^2 per slot from the stored residual R, as partial sums per row block
+// (rows r0 + 16 i of the block summed per thread, then the 16 row groups).
+template <typename TI>
+__global__ __launch_bounds__(kThreads) void k_rnorm(int n, PanelGrid g,
+                                                    const int* __restrict__ sys,
+                                                    const typename CT<TI>::t* __restrict__ R,
+                                                    double2* __restrict__ part) {
+  __shared__ double red[4 * 1 * 16];
+  int rb, pan;
+  if (!map_block(g, rb, pan)) return;
+  const int lane = threadIdx.x & 15, rs = threadIdx.x >> 4;
+  const bool occ = sys[pan * kPanel + lane] >= 0;
+  if (!__syncthreads_or(occ)) return;
+  double acc[1] = {0.0};
+  const size_t base = (size_t)pan * n;
+  const int r0 = rb * g.rpb, r1 = min(r0 + g.rpb, n);
+  if (occ)
+    for (int row = r0 + rs; row < r1; row += 16) {
+      const auto v = R[(base + row) * kPanel + lane];
+      const double x = v.x, y = v.y;
+      acc[0] += x * x + y * y;
+    }
+  reduce16<1>(acc, 1, red, [&](int, int ln, double s) {
+    part[((size_t)rb * g.ND) * g.C + pan * kPanel + ln] = make_double2(s, 0.0);
+  });
+}
 
 // ---------------------------------------------------------------------------
 // Row-group ("union") shifted SpMM.  Rows are taken in groups of R = 4
@@ -2283,6 +2441,21 @@ hipError_t launch_true_resid(const DevPencil& P, const PanelGrid& g, const SlotT
                              const double2* Y, const double* F, int ldf, void* R, void* Z,
                              double2* part, int precond, hipStream_t s) {
   using C = typename CT<T>::t;
+  if (halo_selected<double>(P)) {
+    // halo tiles (the complex-double sweep's format) and a norm pass over R
+    const int G = kHaloMaxG;
+    const int nug = (g.npan * 2 + G - 1) / G;
+    PanelGrid gg = g;
+    gg.group = nug < 4 ? nug : 4;
+    gg.rpb = P.hx_hmax;
+    const long total = (long)P.hx_ntile * nug;
+    const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
+    k_true_halo<T><<<blocks, kThreads, halo_lds_bytes<double>(P), s>>>(
+        P.n, halo_view<double>(P), gg, G, st.sys, st.col, st.sigma, Y, F, ldf,
+        static_cast<C*>(R), static_cast<C*>(Z), P.da, P.db, precond);
+    k_rnorm<T><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.sys, static_cast<const C*>(R), part);
+    return hipGetLastError();
+  }
   int sub = 0, cap = 0;
   size_t bytes = 0;
   if (lds_fit<double>(P, g.rpb, sub, cap, bytes)) {

@@ -204,28 +204,6 @@ struct DevImage {
 };
 constexpr int kImgMaxH = 64;  // largest coarse halo of an image tile
 
-// Level-0 restriction fused into the residual sweep: per fine halo tile, the
-// coarse rows its rows reach through P and, for each (a "partial row"), the
-// tile-local rows and P's weights in a fixed order.  The sweep writes one
-// partial row per (tile, coarse row); a 0/1 sum then gathers the partial rows
-// of each coarse row (fixed order: bitwise reproducible).
-struct DevRestrictTiles {
-  int ntk = 0;                          // partial rows (0: not built)
-  const int* tk = nullptr;              // [ntile + 1] first partial row of each tile
-  const int* ke = nullptr;              // [ntk + 1] entry offsets
-  const unsigned char* erow = nullptr;  // tile-local row of each entry
-  const float* ew32 = nullptr;          // P's weight of each entry
-  const double* ew64 = nullptr;
-};
-constexpr int kRestrictTileK = 32;  // most partial rows of one tile
-// Level-0 residual sweep r1 = b - M x (halo tiles) that also writes the
-// restriction partial rows of r1 into Part (panel layout, rt.ntk rows).
-// Returns false (nothing launched) when the sweep is not the halo kernel or
-// the tables are absent.
-template <typename T>
-bool launch_resid_restrict(const DevPencil& P, const DevRestrictTiles& rt, const PanelGrid& g,
-                           const SlotTables& st, const void* X, const void* Bin, void* Out,
-                           void* Part, hipStream_t s, hipError_t& err);
 // Level-0 up-step in one pass: with x = x0 + P e (e the coarse correction),
 // Out = x + omega D^-1 (r1 - (A P - sigma B P) e), where r1 = b - M x0 is the
 // residual the down-step formed; equal (to rounding) to prolongation followed

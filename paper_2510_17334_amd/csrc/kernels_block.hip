@@ -516,23 +516,12 @@ struct HaloView {
   const void* ab;
 };
 
-// Restriction partial rows of a halo tile (see DevRestrictTiles)
-struct RestrictView {
-  int ntk;
-  const int* tk;
-  const int* ke;
-  const unsigned char* erow;
-  const void* ew;
-};
-constexpr int kEpiResidR = 3;  // residual sweep + restriction partial rows
-
 template <typename T, int EPI>
 __global__ __launch_bounds__(kThreads) void k_apply_halo(
     int n, HaloView hv, PanelGrid g, int G, const int* __restrict__ active,
     const double2* __restrict__ sigma, const typename CT<T>::t* __restrict__ Z,
     typename CT<T>::t* __restrict__ Qk, const typename CT<T>::t* __restrict__ Bin,
-    const double* __restrict__ da, const double* __restrict__ db, double omega,
-    RestrictView rv, typename CT<T>::t* __restrict__ Part) {
+    const double* __restrict__ da, const double* __restrict__ db, double omega) {
   using V = typename LaneVec<T>::V;
   using AB = typename CT<T>::t;              // (a, b) coefficient pair
   constexpr int SPL = LaneVec<T>::SPL;       // systems per lane vector
@@ -548,7 +537,6 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
   int* sH = reinterpret_cast<int*>(s_lc + hv.emax);                          // [hmax]
   __shared__ int s_sp[kHaloTileRows / 8 + 1];  // slice offsets of the tile
   __shared__ int s_uact[kHaloMaxG];
-  __shared__ V sR[EPI == kEpiResidR ? kHaloTileRows * 8 : 1];  // the tile's residual rows
   const int nunit = g.npan * UPP;
   const int nug = (nunit + G - 1) / G;
   int tile, ug;
@@ -666,9 +654,8 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
             rres.z = bb.z - q.z;
             rres.w = bb.w - q.w;
           }
-          if constexpr (EPI == kEpiResid || EPI == kEpiResidR) {
+          if constexpr (EPI == kEpiResid) {
             q = rres;
-            if constexpr (EPI == kEpiResidR) sR[(w * 8 + rr) * 8 + lr] = q;
           } else {
             const V xo = Zu[row * LPRF + lr];
             const double dav = da[row], dbv = db[row];
@@ -690,35 +677,6 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
           }
         }
         Qu[row * LPRF + lr] = q;
-      }
-    }
-    if constexpr (EPI == kEpiResidR) {
-      // partial rows of the restriction: thread (k, lane) sums P's weights
-      // times the tile's residual rows reaching coarse row k, in table order
-      __syncthreads();
-      const int kk = tid >> 3;
-      const int k0 = rv.tk[tile], nk = rv.tk[tile + 1] - k0;
-      if (kk < nk) {
-        const T* __restrict__ ew = static_cast<const T*>(rv.ew);
-        T pa[2 * SPL];
-#pragma unroll
-        for (int c = 0; c < 2 * SPL; ++c) pa[c] = 0;
-        for (int e = rv.ke[k0 + kk]; e < rv.ke[k0 + kk + 1]; ++e) {
-          const T wgt = ew[e];
-          const V rv4 = sR[(int)rv.erow[e] * 8 + lr];
-          pa[0] = mad(wgt, rv4.x, pa[0]);
-          pa[1] = mad(wgt, rv4.y, pa[1]);
-          if constexpr (SPL == 2) {
-            pa[2] = mad(wgt, (T)lv_z(rv4), pa[2]);
-            pa[3] = mad(wgt, (T)lv_w(rv4), pa[3]);
-          }
-        }
-        V o;
-        o.x = pa[0];
-        o.y = pa[1];
-        if constexpr (SPL == 2) lv_set_zw(o, pa[2], pa[3]);
-        (reinterpret_cast<V*>(Part + (size_t)pan * rv.ntk * kPanel) + half * 8)
-            [(size_t)(k0 + kk) * LPRF + lr] = o;
       }
     }
     __syncthreads();  // the unit's halo consumed: LDS is free for the next one
@@ -2221,8 +2179,7 @@ bool launch_halo(const DevPencil& P, const PanelGrid& g, const SlotTables& st, i
   auto Oc = static_cast<C*>(Out);
 #define SLRF_HALO(E)                                                                      \
   k_apply_halo<T, E><<<blocks, kThreads, bytes, s>>>(P.n, hv, gg, G, st.active, st.sigma, \
-                                                     Zc, Oc, Bc, P.da, P.db, omega,         \
-                                                     RestrictView{}, nullptr)
+                                                     Zc, Oc, Bc, P.da, P.db, omega)
   if (epi == kEpiApply)
     SLRF_HALO(kEpiApply);
   else if (epi == kEpiResid)
@@ -2237,35 +2194,6 @@ bool launch_halo(const DevPencil& P, const PanelGrid& g, const SlotTables& st, i
 template <typename T>
 bool sweep_is_halo(const DevPencil& P) {
   return halo_selected<T>(P);
-}
-
-template <typename T>
-bool launch_resid_restrict(const DevPencil& P, const DevRestrictTiles& rt, const PanelGrid& g,
-                           const SlotTables& st, const void* X, const void* Bin, void* Out,
-                           void* Part, hipStream_t s, hipError_t& err) {
-  using C = typename CT<T>::t;
-  if (rt.ntk == 0 || !halo_selected<T>(P)) return false;
-  constexpr int UPP = std::is_same<T, float>::value ? 1 : 2;
-  const int G = kHaloMaxG;
-  const int nug = (g.npan * UPP + G - 1) / G;
-  PanelGrid gg = g;
-  gg.group = nug < 4 ? nug : 4;
-  gg.rpb = P.hx_hmax;
-  const long total = (long)P.hx_ntile * nug;
-  const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
-  RestrictView rv;
-  rv.ntk = rt.ntk;
-  rv.tk = rt.tk;
-  rv.ke = rt.ke;
-  rv.erow = rt.erow;
-  rv.ew = std::is_same<T, float>::value ? static_cast<const void*>(rt.ew32)
-                                        : static_cast<const void*>(rt.ew64);
-  k_apply_halo<T, kEpiResidR><<<blocks, kThreads, halo_lds_bytes<T>(P), s>>>(
-      P.n, halo_view<T>(P), gg, G, st.active, st.sigma, static_cast<const C*>(X),
-      static_cast<C*>(Out), static_cast<const C*>(Bin), P.da, P.db, 0.0, rv,
-      static_cast<C*>(Part));
-  err = hipGetLastError();
-  return true;
 }
 
 template <typename T>
@@ -2918,10 +2846,7 @@ hipError_t launch_coarse_solve(int nc, const PanelGrid& g, const SlotTables& st,
                                              const void*, const void*, void*, hipStream_t);   \
   template bool launch_post_image<T>(const DevImage&, const DevPencil&, const PanelGrid&,       \
                                      const SlotTables&, double, const void*, const void*,       \
-                                     const void*, void*, hipStream_t, hipError_t&);             \
-  template bool launch_resid_restrict<T>(const DevPencil&, const DevRestrictTiles&,             \
-                                         const PanelGrid&, const SlotTables&, const void*,      \
-                                         const void*, void*, void*, hipStream_t, hipError_t&);
+                                     const void*, void*, hipStream_t, hipError_t&);
 SLRF_INST_AMG(float)
 SLRF_INST_AMG(double)
 

@@ -13,7 +13,6 @@
 #include "slrf.h"
 
 #include <algorithm>
-#include <tuple>
 #include <atomic>
 #include <chrono>
 #include <numeric>
@@ -80,8 +79,6 @@ struct DevAmg {
   std::vector<double> omega;            // Jacobi smoothing weight per level (all but the coarsest)
   std::vector<DevImage> img;            // img[l]: image (A_l P_l, B_l P_l) for the fused
                                         // up-step of level l (ntile 0 if absent)
-  DevRestrictTiles rt;                  // level-0 restriction fused into the residual sweep
-  DevTransfer rsum;                     // n_1 x rt.ntk: 0/1 sum of the partial rows
   size_t nnz_all = 0;                   // level + transfer nonzeros (byte accounting)
   ~DevAmg() {
     for (void* p : allocs) (void)hipFree(p);
@@ -423,69 +420,6 @@ slrf_status build_amg(slrf_ctx* h) {
       A.nnz_all += ici.size();
     }
   }
-  // level-0 restriction partial rows per fine halo tile (the fine sweep's
-  // tiles): for each tile the coarse rows its rows reach through P_0, each
-  // with the tile-local rows and weights in row order; and the 0/1 matrix
-  // summing the partial rows of each coarse row in tile order
-  A.rt = DevRestrictTiles();
-  A.rsum = DevTransfer();
-  if (L >= 2 && h->P.hx_ntile > 0) {
-    const int nt = h->P.hx_ntile;
-    std::vector<int> trow(nt + 1);
-    HIPCHK(hipMemcpy(trow.data(), h->P.hx_trow, sizeof(int) * (nt + 1), hipMemcpyDeviceToHost));
-    const HostCsrP& P0 = H.P[0];
-    std::vector<int> tk{0}, ke{0};
-    std::vector<unsigned char> erow;
-    std::vector<double> ew;
-    std::vector<std::vector<int>> parts(P0.m);
-    bool ok = true;
-    std::vector<std::tuple<int, int, double>> ent;
-    for (int t = 0; t < nt && ok; ++t) {
-      ent.clear();
-      for (int r = trow[t]; r < trow[t + 1]; ++r)
-        for (int f = P0.rp[r]; f < P0.rp[r + 1]; ++f)
-          ent.emplace_back(P0.ci[f], r - trow[t], P0.v[f]);
-      std::sort(ent.begin(), ent.end(), [](const auto& x, const auto& y) {
-        return std::get<0>(x) != std::get<0>(y) ? std::get<0>(x) < std::get<0>(y)
-                                                : std::get<1>(x) < std::get<1>(y);
-      });
-      int nk = 0;
-      for (size_t i = 0; i < ent.size(); ++i) {
-        if (i == 0 || std::get<0>(ent[i]) != std::get<0>(ent[i - 1])) {
-          if (i > 0) ke.push_back((int)erow.size());
-          parts[std::get<0>(ent[i])].push_back(tk.back() + nk);
-          ++nk;
-        }
-        erow.push_back((unsigned char)std::get<1>(ent[i]));
-        ew.push_back(std::get<2>(ent[i]));
-      }
-      if (!ent.empty()) ke.push_back((int)erow.size());
-      if (nk > kRestrictTileK || trow[t + 1] - trow[t] > kHaloTileRows) ok = false;
-      tk.push_back(tk.back() + nk);
-    }
-    if (ok) {
-      DevRestrictTiles& R = A.rt;
-      std::vector<float> ew32(ew.begin(), ew.end());
-      HIPCHK(upload(h, tk, &R.tk));
-      HIPCHK(upload(h, ke, &R.ke));
-      HIPCHK(upload(h, erow, &R.erow));
-      HIPCHK(upload(h, ew32, &R.ew32));
-      HIPCHK(upload(h, ew, &R.ew64));
-      HostCsrP S;
-      S.n = P0.m;
-      S.m = tk.back();
-      S.rp.assign(1, 0);
-      for (int c = 0; c < P0.m; ++c) {
-        for (int q : parts[c]) {
-          S.ci.push_back(q);
-          S.v.push_back(1.0);
-        }
-        S.rp.push_back((int)S.ci.size());
-      }
-      HIPCHK(up_tr(S, A.rsum));
-      R.ntk = tk.back();
-    }
-  }
   A.nc = H.nc;
   std::vector<double2> i64(H.coarse_inv.size());
   std::vector<float2> i32(H.coarse_inv.size());
@@ -507,12 +441,11 @@ slrf_status build_amg(slrf_ctx* h) {
 struct AmgVecs {
   void* W0 = nullptr;   // level-0 smoothed iterate
   void* T0 = nullptr;   // level-0 residual
-  void* Pt = nullptr;   // level-0 restriction partial rows (A.rt.ntk rows)
   std::vector<void*> X, W, B, T;  // per level (index 0 unused)
 };
 
 size_t amg_vec_bytes(const DevAmg& A, int C, size_t sT) {
-  size_t b = (2 * (size_t)A.n[0] + (size_t)A.rt.ntk) * C * sT;
+  size_t b = 2 * (size_t)C * A.n[0] * sT;
   for (size_t l = 1; l < A.n.size(); ++l) b += 4 * (size_t)C * A.n[l] * sT;
   return b;
 }
@@ -531,7 +464,6 @@ slrf_status amg_vectors(slrf_ctx* h, int C, AmgVecs& v) {
   };
   v.W0 = take(A.n[0]);
   v.T0 = take(A.n[0]);
-  v.Pt = A.rt.ntk > 0 ? take(A.rt.ntk) : nullptr;
   const size_t L = A.n.size();
   v.X.assign(L, nullptr);
   v.W.assign(L, nullptr);
@@ -578,24 +510,14 @@ slrf_status vcycle(slrf_ctx* h, const AmgVecs& v, int C, int occ, int ND, const 
       void* r = l == 0 ? v.T0 : v.T[l];
       // (level 0: the GCR step that formed r may already have written xb)
       if (l > 0 || !pre0_done) HIPCHK(launch_lvl_jacobi0<T>(lvl(l), g, st, A.omega[l], b[l], xb, s));
-      bool fused = false;  // level 0: the sweep also forms the restriction partial rows
       {
         const bool fine = l == 0 && sweep_is_halo<T>(h->P);
         Scope sw(h, fine ? SLRF_K_SWEEP : -1, (double)nact * A.n[0] * sT * 3.0 + fine_csr);
         if (fine && h->cur_stats) h->cur_stats->sweep_systems += nact;
-        hipError_t err = hipSuccess;
-        fused = l == 0 && v.Pt != nullptr &&
-                launch_resid_restrict<T>(h->P, A.rt, g, st, xb, b[l], r, v.Pt, s, err);
-        if (fused)
-          HIPCHK(err);
-        else
-          HIPCHK(launch_lvl_op<T>(lvl(l), g, st, kEpiResidOp, A.omega[l], xb, b[l], r, s));
+        HIPCHK(launch_lvl_op<T>(lvl(l), g, st, kEpiResidOp, A.omega[l], xb, b[l], r, s));
       }
       const PanelGrid gc = make_grid(A.n[l + 1], C, occ, ND);
-      if (fused)
-        HIPCHK(launch_transfer<T>(A.rsum, gc, st, v.Pt, v.B[l + 1], false, s));
-      else
-        HIPCHK(launch_transfer<T>(A.R[l], gc, st, r, v.B[l + 1], false, s));
+      HIPCHK(launch_transfer<T>(A.R[l], gc, st, r, v.B[l + 1], false, s));
       b[l + 1] = v.B[l + 1];
       x[l] = xb;
     }

@@ -2431,10 +2431,46 @@ hipError_t launch_filter_sum(int n, int ncols, int npoles, const double2* Ystore
   return hipGetLastError();
 }
 
+// Second stage with the row blocks split over the 16 waves of a workgroup
+// (wave w takes rb = w, w + 16, ...; lanes take 64 consecutive slots, so the
+// loads coalesce), then the 16 wave sums in wave order: a fixed order.
+__global__ __launch_bounds__(1024) void k_reduce16w(const double2* __restrict__ part, int nrb,
+                                                    int ND, int C, int nd, int nslots,
+                                                    double2* __restrict__ out) {
+  __shared__ double2 red[16][64];
+  const int nsc = (nslots + 63) / 64;
+  const int d = blockIdx.x / nsc, slot = (blockIdx.x % nsc) * 64 + (threadIdx.x & 63);
+  const int w = threadIdx.x >> 6;
+  double2 s[2] = {};
+  if (slot < nslots) {
+    int i = 0;
+    for (int rb = w; rb < nrb; rb += 16, ++i) {
+      const double2 v = part[((size_t)rb * ND + d) * C + slot];
+      s[i & 1].x += v.x;
+      s[i & 1].y += v.y;
+    }
+  }
+  red[w][threadIdx.x & 63] = make_double2(s[0].x + s[1].x, s[0].y + s[1].y);
+  __syncthreads();
+  if (w == 0 && slot < nslots) {
+    double2 t = red[0][threadIdx.x];
+    for (int k = 1; k < 16; ++k) {
+      t.x += red[k][threadIdx.x].x;
+      t.y += red[k][threadIdx.x].y;
+    }
+    out[(size_t)d * C + slot] = t;
+  }
+}
+
 hipError_t launch_reduce(const double2* part, int nrb, int ND, int C, int nd, int nslots,
                          double2* out, hipStream_t s) {
   const size_t tot = (size_t)nd * nslots;
   if (tot == 0) return hipSuccess;
+  if (nrb >= 64) {
+    k_reduce16w<<<(unsigned)(nd * ((nslots + 63) / 64)), 1024, 0, s>>>(part, nrb, ND, C, nd,
+                                                                         nslots, out);
+    return hipGetLastError();
+  }
   k_reduce<<<cdiv(tot, kThreads), kThreads, 0, s>>>(part, nrb, ND, C, nd, nslots, out);
   return hipGetLastError();
 }

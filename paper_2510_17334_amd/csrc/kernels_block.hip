@@ -1605,6 +1605,7 @@ __global__ void k_fin_rnorm(const double2* __restrict__ red, int nslots,
   if (s < 0 || active[slot] == 0) return;
   const int it = its[s] + 1;
   its[s] = it;
+  if (red == nullptr) return;  // (last step of a cycle: counted only)
   const double rn2 = red[slot].x;
   if (!(rn2 == rn2) || rn2 > 1e300) {
     status[slot] = 3;

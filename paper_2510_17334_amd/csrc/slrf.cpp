@@ -950,18 +950,23 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
         HIPCHK(launch_reduce(part, nrb, ND, C, 2, occ, red, s));
         HIPCHK(launch_fin_alpha(red, k, C, occ, tc, sc, s));
       }
-      {
-        Scope sp(h, SLRF_K_STEP, (double)nact * n * sT * 4.0);
-        // with the AMG, the step also forms the next V-cycle's level-0
-        // pre-smoothing (saves that kernel's read of r)
-        void* znext = k + 1 < m ? (fuse0 ? av.W0 : zk(k + 1)) : nullptr;
-        HIPCHK(launch_step<T>(h->P, g, tc, R, znext, Qk, sc.alpha + (size_t)k * C, part,
-                              fuse0 ? 3 : pc, fuse0 ? h->amg.omega[0] : 0.0, s));
-      }
-      {
+      if (k + 1 < m) {
+        {
+          Scope sp(h, SLRF_K_STEP, (double)nact * n * sT * 4.0);
+          // with the AMG, the step also forms the next V-cycle's level-0
+          // pre-smoothing (saves that kernel's read of r)
+          void* znext = fuse0 ? av.W0 : zk(k + 1);
+          HIPCHK(launch_step<T>(h->P, g, tc, R, znext, Qk, sc.alpha + (size_t)k * C, part,
+                                fuse0 ? 3 : pc, fuse0 ? h->amg.omega[0] : 0.0, s));
+        }
         Scope sp(h, SLRF_K_REDUCE, 16.0 * nrb * occ);
         HIPCHK(launch_reduce(part, nrb, ND, C, 1, occ, red, s));
         HIPCHK(launch_fin_rnorm(red, occ, tc, sc, itcap, s));
+      } else {
+        // last step of the cycle: the boundary recomputes r from y in FP64
+        // (and tests it), so the recursive update of r is skipped; the step
+        // is only counted
+        HIPCHK(launch_fin_rnorm(nullptr, occ, tc, sc, itcap, s));
       }
       kk_last = k + 1;
       HIPCHK(hipMemcpyAsync(hflags, d_act, sizeof(int) * occ, hipMemcpyDeviceToHost, s));

@@ -212,7 +212,20 @@ constexpr int kImgMaxH = 64;  // largest coarse halo of an image tile
 template <typename T>
 bool launch_post_image(const DevImage& I, const DevPencil& P, const PanelGrid& g,
                        const SlotTables& st, double omega, const void* E, const void* X0,
-                       const void* R1, void* Out, hipStream_t s, hipError_t& err);
+                       const void* R1, void* Out, hipStream_t s, hipError_t& err,
+                       bool r1_bf16 = false);
+// Level-0 residual r1 = b - M x on the halo tiles stored as complex bfloat16
+// (4 bytes per entry, panel layout): r1 is only restricted and read by the
+// up-step, where the preconditioner tolerates its rounding.  Complex-float
+// sweeps only; returns false (nothing launched) otherwise.
+template <typename T>
+bool launch_resid_bf16(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
+                       const void* X, const void* Bin, void* Out, hipStream_t s,
+                       hipError_t& err);
+// Restriction of a complex-bfloat16 panel vector (complex-float results).
+template <typename T>
+hipError_t launch_restrict_bf16(const DevTransfer& M, const PanelGrid& g, const SlotTables& st,
+                                const void* In, void* Out, hipStream_t s);
 
 hipError_t launch_retire(int n, const PanelGrid& g, const int* retire_sys, const double2* Y,
                          double2* Ystore, hipStream_t s);

@@ -286,6 +286,24 @@ __device__ __forceinline__ void lane_fma(T* acc, T a, T b, const typename LaneVe
 //   kEpiResid : out = b - M x                  (AMG level residual)
 //   kEpiJacobi: out = x + omega D^-1 (b - M x) (AMG damped-Jacobi sweep, D = diag M)
 constexpr int kEpiApply = 0, kEpiResid = 1, kEpiJacobi = 2;
+// kEpiResidH: the residual b - M x stored as complex bfloat16 (the level-0
+// residual of the V-cycle, which only the restriction and the up-step read)
+constexpr int kEpiResidH = 3;
+
+// complex bfloat16 in one 32-bit word (re in the low half); rounding to the
+// nearest even
+__device__ __forceinline__ unsigned bf16_rne(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+__device__ __forceinline__ unsigned pack_cbf16(float re, float im) {
+  return bf16_rne(re) | (bf16_rne(im) << 16);
+}
+__device__ __forceinline__ float4 unpack_cbf16x2(uint2 h) {
+  return make_float4(__uint_as_float(h.x << 16), __uint_as_float(h.x & 0xFFFF0000u),
+                     __uint_as_float(h.y << 16), __uint_as_float(h.y & 0xFFFF0000u));
+}
 
 template <typename T, bool DOTS, int G, int EPI = kEpiApply, int UNR = 8>
 __global__ __launch_bounds__(kThreads) void k_apply_lds(
@@ -654,7 +672,7 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
             rres.z = bb.z - q.z;
             rres.w = bb.w - q.w;
           }
-          if constexpr (EPI == kEpiResid) {
+          if constexpr (EPI == kEpiResid || EPI == kEpiResidH) {
             q = rres;
           } else {
             const V xo = Zu[row * LPRF + lr];
@@ -676,7 +694,13 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
             }
           }
         }
-        Qu[row * LPRF + lr] = q;
+        if constexpr (EPI == kEpiResidH) {
+          if constexpr (SPL == 2)
+            reinterpret_cast<uint2*>(Qk)[((size_t)pan * n + row) * 8 + lr] =
+                make_uint2(pack_cbf16(q.x, q.y), pack_cbf16(lv_z(q), lv_w(q)));
+        } else {
+          Qu[row * LPRF + lr] = q;
+        }
       }
     }
     __syncthreads();  // the unit's halo consumed: LDS is free for the next one
@@ -694,7 +718,8 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
 // units, the tile's coefficients staged once, each unit's coarse halo rows of
 // e copied into LDS (loaded into registers while the previous unit is formed).
 // ---------------------------------------------------------------------------
-template <typename T>
+// (HR1: r1 is complex bfloat16, complex-float sweeps only)
+template <typename T, bool HR1>
 __global__ __launch_bounds__(kThreads) void k_post_image(
     int n, int nc, HaloView hv, const T* __restrict__ pv, PanelGrid g, int G,
     const int* __restrict__ active, const double2* __restrict__ sigma,
@@ -822,7 +847,13 @@ __global__ __launch_bounds__(kThreads) void k_post_image(
       if (row < r1) {
         const size_t off = (size_t)row * LPRF + lr;
         const V xo = (reinterpret_cast<const V*>(X0 + pbase) + half * 8)[off];
-        const V ro = (reinterpret_cast<const V*>(R1 + pbase) + half * 8)[off];
+        V ro;
+        if constexpr (HR1) {
+          if constexpr (SPL == 2)
+            ro = unpack_cbf16x2(reinterpret_cast<const uint2*>(R1)[((size_t)pan * n + row) * 8 + lr]);
+        } else {
+          ro = (reinterpret_cast<const V*>(R1 + pbase) + half * 8)[off];
+        }
         // (the smoother scaling in the vector precision: the V-cycle is a
         // preconditioner, its arithmetic precision is the sweep's)
         const T dav = (T)da[row], dbv = (T)db[row], om = (T)omega;
@@ -2198,9 +2229,30 @@ bool sweep_is_halo(const DevPencil& P) {
 }
 
 template <typename T>
+bool launch_resid_bf16(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
+                       const void* X, const void* Bin, void* Out, hipStream_t s,
+                       hipError_t& err) {
+  using C = typename CT<T>::t;
+  if (!std::is_same<T, float>::value || !halo_selected<T>(P)) return false;
+  const int G = kHaloMaxG;
+  const int nug = (g.npan + G - 1) / G;
+  PanelGrid gg = g;
+  gg.group = nug < 4 ? nug : 4;
+  gg.rpb = P.hx_hmax;
+  const long total = (long)P.hx_ntile * nug;
+  const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
+  k_apply_halo<T, kEpiResidH><<<blocks, kThreads, halo_lds_bytes<T>(P), s>>>(
+      P.n, halo_view<T>(P), gg, G, st.active, st.sigma, static_cast<const C*>(X),
+      static_cast<C*>(Out), static_cast<const C*>(Bin), P.da, P.db, 0.0);
+  err = hipGetLastError();
+  return true;
+}
+
+template <typename T>
 bool launch_post_image(const DevImage& I, const DevPencil& P, const PanelGrid& g,
                        const SlotTables& st, double omega, const void* E, const void* X0,
-                       const void* R1, void* Out, hipStream_t s, hipError_t& err) {
+                       const void* R1, void* Out, hipStream_t s, hipError_t& err,
+                       bool r1_bf16) {
   using C = typename CT<T>::t;
   if (I.ntile == 0 || I.hmax > kImgMaxH) return false;
   constexpr int UPP = std::is_same<T, float>::value ? 1 : 2;
@@ -2226,10 +2278,16 @@ bool launch_post_image(const DevImage& I, const DevPencil& P, const PanelGrid& g
                                         : static_cast<const void*>(I.ab64);
   const T* pv = std::is_same<T, float>::value ? reinterpret_cast<const T*>(I.p32)
                                               : reinterpret_cast<const T*>(I.p64);
-  k_post_image<T><<<blocks, kThreads, bytes, s>>>(
-      P.n, I.nc, hv, pv, gg, G, st.active, st.sigma, static_cast<const C*>(E),
-      static_cast<const C*>(X0), static_cast<const C*>(R1), static_cast<C*>(Out), P.da, P.db,
-      omega);
+#define SLRF_POST(H)                                                                             \
+  k_post_image<T, H><<<blocks, kThreads, bytes, s>>>(                                            \
+      P.n, I.nc, hv, pv, gg, G, st.active, st.sigma, static_cast<const C*>(E),                   \
+      static_cast<const C*>(X0), static_cast<const C*>(R1), static_cast<C*>(Out), P.da, P.db, \
+      omega)
+  if (r1_bf16 && std::is_same<T, float>::value)
+    SLRF_POST(true);
+  else
+    SLRF_POST(false);
+#undef SLRF_POST
   err = hipGetLastError();
   return true;
 }
@@ -2760,7 +2818,8 @@ __global__ __launch_bounds__(kThreads) void k_prolong_lds(
   }
 }
 
-template <typename T>
+// (HIN: the input is complex bfloat16, complex-float sweeps only)
+template <typename T, bool HIN = false>
 __global__ __launch_bounds__(kThreads) void k_restrict(
     int nout, int nin, const int* __restrict__ rowptr, const int* __restrict__ col,
     const T* __restrict__ v, int npan, const int* __restrict__ active,
@@ -2778,6 +2837,7 @@ __global__ __launch_bounds__(kThreads) void k_restrict(
   const bool a = l < kPanel && (active == nullptr || active[pan * kPanel + l] != 0);
   if (!__any(a)) return;
   const V* __restrict__ Ip = reinterpret_cast<const V*>(In + (size_t)pan * nin * kPanel);
+  const uint2* __restrict__ Ih = reinterpret_cast<const uint2*>(In) + (size_t)pan * nin * 8;
   V* __restrict__ Op = reinterpret_cast<V*>(Out + (size_t)pan * nout * kPanel);
   const int e0 = rowptr[row], e1 = rowptr[row + 1];
   T acc[2 * SPL];
@@ -2793,7 +2853,11 @@ __global__ __launch_bounds__(kThreads) void k_restrict(
       wv[u] = 0;
       if (ee < e1) {
         wv[u] = v[ee];
-        z[u] = Ip[(size_t)col[ee] * LPR + lr];
+        if constexpr (HIN) {
+          if constexpr (SPL == 2) z[u] = unpack_cbf16x2(Ih[(size_t)col[ee] * 8 + lr]);
+        } else {
+          z[u] = Ip[(size_t)col[ee] * LPR + lr];
+        }
       }
     }
 #pragma unroll
@@ -2817,6 +2881,20 @@ __global__ __launch_bounds__(kThreads) void k_restrict(
     if constexpr (SPL == 2) lv_set_zw(o, acc[2], acc[3]);
     Op[(size_t)row * LPR + lr] = o;
   }
+}
+
+template <typename T>
+hipError_t launch_restrict_bf16(const DevTransfer& M, const PanelGrid& g, const SlotTables& st,
+                                const void* In, void* Out, hipStream_t s) {
+  using C = typename CT<T>::t;
+  if (!std::is_same<T, float>::value) return hipErrorInvalidValue;
+  const T* v = reinterpret_cast<const T*>(M.v32);
+  const long nblk = (long)M.nrows * ((g.npan + 3) / 4);
+  k_restrict<T, true><<<(unsigned)nblk, kThreads, 0, s>>>(M.nrows, M.ncols, M.rowptr, M.col, v,
+                                                         g.npan, st.active,
+                                                         static_cast<const C*>(In),
+                                                         static_cast<C*>(Out));
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -2883,7 +2961,11 @@ hipError_t launch_coarse_solve(int nc, const PanelGrid& g, const SlotTables& st,
                                              const void*, const void*, void*, hipStream_t);   \
   template bool launch_post_image<T>(const DevImage&, const DevPencil&, const PanelGrid&,       \
                                      const SlotTables&, double, const void*, const void*,       \
-                                     const void*, void*, hipStream_t, hipError_t&);
+                                     const void*, void*, hipStream_t, hipError_t&, bool);       \
+  template bool launch_resid_bf16<T>(const DevPencil&, const PanelGrid&, const SlotTables&,     \
+                                     const void*, const void*, void*, hipStream_t, hipError_t&); \
+  template hipError_t launch_restrict_bf16<T>(const DevTransfer&, const PanelGrid&,             \
+                                              const SlotTables&, const void*, void*, hipStream_t);
 SLRF_INST_AMG(float)
 SLRF_INST_AMG(double)
 

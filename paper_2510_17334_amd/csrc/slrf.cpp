@@ -504,20 +504,33 @@ slrf_status vcycle(slrf_ctx* h, const AmgVecs& v, int C, int occ, int ND, const 
     std::vector<const void*> b(L, nullptr);
     std::vector<void*> x(L, nullptr);
     b[0] = Rin;
+    // complex-float sweeps keep the level-0 residual (read only by the
+    // restriction and the fused up-step) in complex bfloat16
+    const bool r16 = std::is_same<T, float>::value && sweep_is_halo<T>(h->P) &&
+                     A.img[0].ntile > 0 && A.img[0].hmax <= kImgMaxH;
     for (int l = 0; l + 1 < L; ++l) {
       const PanelGrid g = make_grid(A.n[l], C, occ, ND);
       void* xb = l == 0 ? v.W0 : v.X[l];
       void* r = l == 0 ? v.T0 : v.T[l];
       // (level 0: the GCR step that formed r may already have written xb)
       if (l > 0 || !pre0_done) HIPCHK(launch_lvl_jacobi0<T>(lvl(l), g, st, A.omega[l], b[l], xb, s));
+      const bool h16 = l == 0 && r16;
       {
         const bool fine = l == 0 && sweep_is_halo<T>(h->P);
-        Scope sw(h, fine ? SLRF_K_SWEEP : -1, (double)nact * A.n[0] * sT * 3.0 + fine_csr);
+        Scope sw(h, fine ? SLRF_K_SWEEP : -1,
+                 (double)nact * A.n[0] * sT * (h16 ? 2.5 : 3.0) + fine_csr);
         if (fine && h->cur_stats) h->cur_stats->sweep_systems += nact;
-        HIPCHK(launch_lvl_op<T>(lvl(l), g, st, kEpiResidOp, A.omega[l], xb, b[l], r, s));
+        hipError_t err = hipSuccess;
+        if (h16 && launch_resid_bf16<T>(h->P, g, st, xb, b[l], r, s, err))
+          HIPCHK(err);
+        else
+          HIPCHK(launch_lvl_op<T>(lvl(l), g, st, kEpiResidOp, A.omega[l], xb, b[l], r, s));
       }
       const PanelGrid gc = make_grid(A.n[l + 1], C, occ, ND);
-      HIPCHK(launch_transfer<T>(A.R[l], gc, st, r, v.B[l + 1], false, s));
+      if (h16)
+        HIPCHK(launch_restrict_bf16<T>(A.R[l], gc, st, r, v.B[l + 1], s));
+      else
+        HIPCHK(launch_transfer<T>(A.R[l], gc, st, r, v.B[l + 1], false, s));
       b[l + 1] = v.B[l + 1];
       x[l] = xb;
     }
@@ -531,7 +544,7 @@ slrf_status vcycle(slrf_ctx* h, const AmgVecs& v, int C, int occ, int ND, const 
         // prolongation and post-smoothing of level l in one pass
         hipError_t err = hipSuccess;
         if (launch_post_image<T>(A.img[l], lvl(l), g, st, A.omega[l], x[l + 1], x[l],
-                                 l == 0 ? v.T0 : v.T[l], out, s, err)) {
+                                 l == 0 ? v.T0 : v.T[l], out, s, err, l == 0 && r16)) {
           HIPCHK(err);
           x[l] = out;
           continue;

@@ -145,7 +145,8 @@ hipError_t launch_orth(const DevPencil& P, const PanelGrid& g, const SlotTables&
                        const double2* beta, double2* part, hipStream_t s);
 template <typename T>
 // precond: 0 = none (z = r), 1 = point Jacobi, 2 = leave z to the AMG V-cycle,
-// 3 = Z receives omega D^-1 r, the level-0 pre-smoothing of the next V-cycle;
+// 3 = Z receives omega D^-1 r, the level-0 pre-smoothing of the next V-cycle,
+// 4 = the same stored as complex bfloat16 (complex-float sweeps);
 // Z may be null (no z written: the last step of a cycle)
 hipError_t launch_step(const DevPencil& P, const PanelGrid& g, const SlotTables& st, void* R,
                        void* Z, const void* Qk, const double2* alpha_k, double2* part,
@@ -178,7 +179,8 @@ hipError_t launch_lvl_op(const DevPencil& L, const PanelGrid& g, const SlotTable
                          double omega, const void* X, const void* Bin, void* Out, hipStream_t s);
 template <typename T>
 hipError_t launch_lvl_jacobi0(const DevPencil& L, const PanelGrid& g, const SlotTables& st,
-                              double omega, const void* Bin, void* Out, hipStream_t s);
+                              double omega, const void* Bin, void* Out, hipStream_t s,
+                              bool out_bf16 = false);
 template <typename T>
 hipError_t launch_transfer(const DevTransfer& M, const PanelGrid& g, const SlotTables& st,
                            const void* In, void* Out, bool add, hipStream_t s);
@@ -215,13 +217,14 @@ bool launch_post_image(const DevImage& I, const DevPencil& P, const PanelGrid& g
                        const void* R1, void* Out, hipStream_t s, hipError_t& err,
                        bool r1_bf16 = false);
 // Level-0 residual r1 = b - M x on the halo tiles stored as complex bfloat16
+// (x_bf16: the iterate x is complex bfloat16 too)
 // (4 bytes per entry, panel layout): r1 is only restricted and read by the
 // up-step, where the preconditioner tolerates its rounding.  Complex-float
 // sweeps only; returns false (nothing launched) otherwise.
 template <typename T>
 bool launch_resid_bf16(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
                        const void* X, const void* Bin, void* Out, hipStream_t s,
-                       hipError_t& err);
+                       hipError_t& err, bool x_bf16 = false);
 // Restriction of a complex-bfloat16 panel vector (complex-float results).
 template <typename T>
 hipError_t launch_restrict_bf16(const DevTransfer& M, const PanelGrid& g, const SlotTables& st,

@@ -534,7 +534,9 @@ struct HaloView {
   const void* ab;
 };
 
-template <typename T, int EPI>
+// (ZH: the gathered operand z is complex bfloat16, widened to complex float
+// when staged; complex-float sweeps only)
+template <typename T, int EPI, bool ZH = false>
 __global__ __launch_bounds__(kThreads) void k_apply_halo(
     int n, HaloView hv, PanelGrid g, int G, const int* __restrict__ active,
     const double2* __restrict__ sigma, const typename CT<T>::t* __restrict__ Z,
@@ -583,16 +585,18 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
   // the halo of a unit is loaded into registers while the previous unit is
   // formed (the whole halo fits: H <= kHaloMaxH)
   constexpr int HP = (kHaloMaxH * 8 + kThreads - 1) / kThreads;
-  V hreg[HP];
+  using HV = typename std::conditional<ZH, uint2, V>::type;  // staged element as loaded
+  HV hreg[HP];
 #define SLRF_HALO_ISSUE(GX)                                                              \
   do {                                                                                   \
     const int ux_ = ug * G + (GX);                                                       \
-    const V* __restrict__ zx_ =                                                          \
-        reinterpret_cast<const V*>(Z + (size_t)(ux_ / UPP) * n * kPanel) + (ux_ % UPP) * 8; \
+    const HV* __restrict__ zx_ =                                                         \
+        ZH ? reinterpret_cast<const HV*>(Z) + (size_t)(ux_ / UPP) * n * 8                \
+           : reinterpret_cast<const HV*>(Z + (size_t)(ux_ / UPP) * n * kPanel) + (ux_ % UPP) * 8; \
     _Pragma("unroll") for (int i_ = 0; i_ < HP; ++i_) {                                  \
       const int t_ = i_ * kThreads + tid;                                                \
-      hreg[i_] = V{};                                                                    \
-      if (t_ < H * 8) hreg[i_] = zx_[(size_t)sH[t_ >> 3] * LPRF + (t_ & 7)];             \
+      hreg[i_] = HV{};                                                                   \
+      if (t_ < H * 8) hreg[i_] = zx_[(size_t)sH[t_ >> 3] * (ZH ? 8 : LPRF) + (t_ & 7)];  \
     }                                                                                    \
   } while (0)
   SLRF_HALO_ISSUE(gu);
@@ -622,7 +626,12 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
 #pragma unroll
     for (int i = 0; i < HP; ++i) {
       const int t = i * kThreads + tid;
-      if (t < H * 8) sZ[t] = hreg[i];
+      if constexpr (ZH) {
+        if constexpr (SPL == 2)
+          if (t < H * 8) sZ[t] = unpack_cbf16x2(hreg[i]);
+      } else {
+        if (t < H * 8) sZ[t] = hreg[i];
+      }
     }
     int gn = gu + 1;
     while (gn < G && !s_uact[gn]) ++gn;
@@ -718,7 +727,7 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
 // units, the tile's coefficients staged once, each unit's coarse halo rows of
 // e copied into LDS (loaded into registers while the previous unit is formed).
 // ---------------------------------------------------------------------------
-// (HR1: r1 is complex bfloat16, complex-float sweeps only)
+// (HR1: r1 and x0 are complex bfloat16, complex-float sweeps only)
 template <typename T, bool HR1>
 __global__ __launch_bounds__(kThreads) void k_post_image(
     int n, int nc, HaloView hv, const T* __restrict__ pv, PanelGrid g, int G,
@@ -846,12 +855,15 @@ __global__ __launch_bounds__(kThreads) void k_post_image(
       }
       if (row < r1) {
         const size_t off = (size_t)row * LPRF + lr;
-        const V xo = (reinterpret_cast<const V*>(X0 + pbase) + half * 8)[off];
-        V ro;
+        V xo, ro;
         if constexpr (HR1) {
-          if constexpr (SPL == 2)
-            ro = unpack_cbf16x2(reinterpret_cast<const uint2*>(R1)[((size_t)pan * n + row) * 8 + lr]);
+          if constexpr (SPL == 2) {
+            const size_t ho = ((size_t)pan * n + row) * 8 + lr;
+            xo = unpack_cbf16x2(reinterpret_cast<const uint2*>(X0)[ho]);
+            ro = unpack_cbf16x2(reinterpret_cast<const uint2*>(R1)[ho]);
+          }
         } else {
+          xo = (reinterpret_cast<const V*>(X0 + pbase) + half * 8)[off];
           ro = (reinterpret_cast<const V*>(R1 + pbase) + half * 8)[off];
         }
         // (the smoother scaling in the vector precision: the V-cycle is a
@@ -1730,8 +1742,9 @@ __global__ __launch_bounds__(kThreads) void k_lvl_simple(
   }
 }
 
-// first smoothing step from a zero guess: out = omega D^-1 b
-template <typename T>
+// first smoothing step from a zero guess: out = omega D^-1 b (OH: out as
+// complex bfloat16, complex-float sweeps only)
+template <typename T, bool OH = false>
 __global__ __launch_bounds__(kThreads) void k_lvl_jacobi0(
     int n, const double* __restrict__ da, const double* __restrict__ db, double omega, PanelGrid g,
     const int* __restrict__ active, const double2* __restrict__ sigma,
@@ -1749,7 +1762,11 @@ __global__ __launch_bounds__(kThreads) void k_lvl_jacobi0(
     const size_t off = pbase + (size_t)row * kPanel + lane;
     const C bb = Bin[off];
     const double2 d = jacobi_inv(da[row], db[row], sg);
-    Out[off] = mk<C>(omega * (bb.x * d.x - bb.y * d.y), omega * (bb.x * d.y + bb.y * d.x));
+    if constexpr (OH)
+      reinterpret_cast<unsigned*>(Out)[off] = pack_cbf16(
+          (float)(omega * (bb.x * d.x - bb.y * d.y)), (float)(omega * (bb.x * d.y + bb.y * d.x)));
+    else
+      Out[off] = mk<C>(omega * (bb.x * d.x - bb.y * d.y), omega * (bb.x * d.y + bb.y * d.x));
   }
 }
 
@@ -2085,7 +2102,8 @@ __global__ __launch_bounds__(kThreads) void k_orth_lv(
 
 // r -= alpha q, partial ||r||^2, and z from the new r: pc 0 copy, 1 Jacobi,
 // 2 none, 3 omega D^-1 r (the first smoothing step of the next V-cycle, from
-// the stored r exactly as the level-0 jacobi0 kernel forms it)
+// the stored r exactly as the level-0 jacobi0 kernel forms it), 4 the same
+// stored as complex bfloat16 (complex-float sweeps)
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_step_lv(
     int n, PanelGrid g, const int* __restrict__ active, const double2* __restrict__ sigma,
@@ -2136,7 +2154,7 @@ __global__ __launch_bounds__(kThreads) void k_step_lv(
         const double2 d = jacobi_inv(da[row], db[row], sg[c]);
         zx = (T)(x * d.x - y * d.y);
         zy = (T)(x * d.y + y * d.x);
-      } else if (pc == 3) {
+      } else if (pc == 3 || pc == 4) {
         const double2 d = jacobi_inv(da[row], db[row], sg[c]);
         zx = (T)(omega * (x * d.x - y * d.y));
         zy = (T)(omega * (x * d.y + y * d.x));
@@ -2152,7 +2170,13 @@ __global__ __launch_bounds__(kThreads) void k_step_lv(
       }
     }
     Rp[off] = rn;
-    if (Zp != nullptr && pc != 2) Zp[off] = zn;
+    if (Zp != nullptr && pc == 4) {
+      if constexpr (SPL == 2)
+        reinterpret_cast<uint2*>(Z)[((size_t)pan * n + row) * 8 + lr] =
+            make_uint2(pack_cbf16(zn.x, zn.y), pack_cbf16(lv_z(zn), lv_w(zn)));
+    } else if (Zp != nullptr && pc != 2) {
+      Zp[off] = zn;
+    }
   }
   reduce_lv<SPL, LPR>(acc, SPL, red, [&](int c, int ln, double sum) {
     part[((size_t)rb * g.ND) * g.C + pan * kPanel + ln * SPL + c] = make_double2(sum, 0.0);
@@ -2231,7 +2255,7 @@ bool sweep_is_halo(const DevPencil& P) {
 template <typename T>
 bool launch_resid_bf16(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
                        const void* X, const void* Bin, void* Out, hipStream_t s,
-                       hipError_t& err) {
+                       hipError_t& err, bool x_bf16) {
   using C = typename CT<T>::t;
   if (!std::is_same<T, float>::value || !halo_selected<T>(P)) return false;
   const int G = kHaloMaxG;
@@ -2241,9 +2265,15 @@ bool launch_resid_bf16(const DevPencil& P, const PanelGrid& g, const SlotTables&
   gg.rpb = P.hx_hmax;
   const long total = (long)P.hx_ntile * nug;
   const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
-  k_apply_halo<T, kEpiResidH><<<blocks, kThreads, halo_lds_bytes<T>(P), s>>>(
-      P.n, halo_view<T>(P), gg, G, st.active, st.sigma, static_cast<const C*>(X),
-      static_cast<C*>(Out), static_cast<const C*>(Bin), P.da, P.db, 0.0);
+#define SLRF_RH(ZH)                                                                          \
+  k_apply_halo<T, kEpiResidH, ZH><<<blocks, kThreads, halo_lds_bytes<T>(P), s>>>(            \
+      P.n, halo_view<T>(P), gg, G, st.active, st.sigma, static_cast<const C*>(X),            \
+      static_cast<C*>(Out), static_cast<const C*>(Bin), P.da, P.db, 0.0)
+  if (x_bf16)
+    SLRF_RH(true);
+  else
+    SLRF_RH(false);
+#undef SLRF_RH
   err = hipGetLastError();
   return true;
 }
@@ -2652,11 +2682,17 @@ hipError_t launch_lvl_op(const DevPencil& L, const PanelGrid& g, const SlotTable
 
 template <typename T>
 hipError_t launch_lvl_jacobi0(const DevPencil& L, const PanelGrid& g, const SlotTables& st,
-                              double omega, const void* Bin, void* Out, hipStream_t s) {
+                              double omega, const void* Bin, void* Out, hipStream_t s,
+                              bool out_bf16) {
   using C = typename CT<T>::t;
-  k_lvl_jacobi0<T><<<g.blocks(), kThreads, 0, s>>>(L.n, L.da, L.db, omega, g, st.active, st.sigma,
-                                                   static_cast<const C*>(Bin),
-                                                   static_cast<C*>(Out));
+  if (out_bf16 && std::is_same<T, float>::value)
+    k_lvl_jacobi0<T, true><<<g.blocks(), kThreads, 0, s>>>(L.n, L.da, L.db, omega, g, st.active,
+                                                           st.sigma, static_cast<const C*>(Bin),
+                                                           static_cast<C*>(Out));
+  else
+    k_lvl_jacobi0<T><<<g.blocks(), kThreads, 0, s>>>(L.n, L.da, L.db, omega, g, st.active,
+                                                     st.sigma, static_cast<const C*>(Bin),
+                                                     static_cast<C*>(Out));
   return hipGetLastError();
 }
 
@@ -2953,7 +2989,7 @@ hipError_t launch_coarse_solve(int nc, const PanelGrid& g, const SlotTables& st,
                                        hipStream_t);                                           \
   template hipError_t launch_lvl_jacobi0<T>(const DevPencil&, const PanelGrid&,                \
                                             const SlotTables&, double, const void*, void*,     \
-                                            hipStream_t);                                      \
+                                            hipStream_t, bool);                                \
   template hipError_t launch_transfer<T>(const DevTransfer&, const PanelGrid&,                 \
                                          const SlotTables&, const void*, void*, bool,          \
                                          hipStream_t);                                         \
@@ -2963,7 +2999,8 @@ hipError_t launch_coarse_solve(int nc, const PanelGrid& g, const SlotTables& st,
                                      const SlotTables&, double, const void*, const void*,       \
                                      const void*, void*, hipStream_t, hipError_t&, bool);       \
   template bool launch_resid_bf16<T>(const DevPencil&, const PanelGrid&, const SlotTables&,     \
-                                     const void*, const void*, void*, hipStream_t, hipError_t&); \
+                                     const void*, const void*, void*, hipStream_t, hipError_t&, \
+                                     bool);                                                     \
   template hipError_t launch_restrict_bf16<T>(const DevTransfer&, const PanelGrid&,             \
                                               const SlotTables&, const void*, void*, hipStream_t);
 SLRF_INST_AMG(float)

@@ -478,6 +478,16 @@ slrf_status amg_vectors(slrf_ctx* h, int C, AmgVecs& v) {
   return SLRF_OK;
 }
 
+// Complex-float sweeps on a pencil with halo tiles and a level-0 image keep
+// the level-0 V-cycle vectors the GCR step and the sweeps exchange (the
+// pre-smoothed iterate x0 and its residual r1) in complex bfloat16.
+template <typename T>
+bool amg_level0_bf16(const slrf_ctx* h) {
+  const DevAmg& A = h->amg;
+  return std::is_same<T, float>::value && sweep_is_halo<T>(h->P) && !A.img.empty() &&
+         A.img[0].ntile > 0 && A.img[0].hmax <= kImgMaxH;
+}
+
 // z = V(r): one V-cycle (damped-Jacobi pre/post smoothing from a zero guess,
 // Galerkin coarse correction, dense coarsest solve) for every active slot.
 // pre0_done: the level-0 pre-smoothing omega D^-1 r is already in v.W0.
@@ -504,24 +514,22 @@ slrf_status vcycle(slrf_ctx* h, const AmgVecs& v, int C, int occ, int ND, const 
     std::vector<const void*> b(L, nullptr);
     std::vector<void*> x(L, nullptr);
     b[0] = Rin;
-    // complex-float sweeps keep the level-0 residual (read only by the
-    // restriction and the fused up-step) in complex bfloat16
-    const bool r16 = std::is_same<T, float>::value && sweep_is_halo<T>(h->P) &&
-                     A.img[0].ntile > 0 && A.img[0].hmax <= kImgMaxH;
+    const bool r16 = amg_level0_bf16<T>(h);
     for (int l = 0; l + 1 < L; ++l) {
       const PanelGrid g = make_grid(A.n[l], C, occ, ND);
       void* xb = l == 0 ? v.W0 : v.X[l];
       void* r = l == 0 ? v.T0 : v.T[l];
       // (level 0: the GCR step that formed r may already have written xb)
-      if (l > 0 || !pre0_done) HIPCHK(launch_lvl_jacobi0<T>(lvl(l), g, st, A.omega[l], b[l], xb, s));
+      if (l > 0 || !pre0_done)
+        HIPCHK(launch_lvl_jacobi0<T>(lvl(l), g, st, A.omega[l], b[l], xb, s, l == 0 && r16));
       const bool h16 = l == 0 && r16;
       {
         const bool fine = l == 0 && sweep_is_halo<T>(h->P);
         Scope sw(h, fine ? SLRF_K_SWEEP : -1,
-                 (double)nact * A.n[0] * sT * (h16 ? 2.5 : 3.0) + fine_csr);
+                 (double)nact * A.n[0] * sT * (h16 ? 2.0 : 3.0) + fine_csr);
         if (fine && h->cur_stats) h->cur_stats->sweep_systems += nact;
         hipError_t err = hipSuccess;
-        if (h16 && launch_resid_bf16<T>(h->P, g, st, xb, b[l], r, s, err))
+        if (h16 && launch_resid_bf16<T>(h->P, g, st, xb, b[l], r, s, err, true))
           HIPCHK(err);
         else
           HIPCHK(launch_lvl_op<T>(lvl(l), g, st, kEpiResidOp, A.omega[l], xb, b[l], r, s));
@@ -970,7 +978,8 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
           // pre-smoothing (saves that kernel's read of r)
           void* znext = fuse0 ? av.W0 : zk(k + 1);
           HIPCHK(launch_step<T>(h->P, g, tc, R, znext, Qk, sc.alpha + (size_t)k * C, part,
-                                fuse0 ? 3 : pc, fuse0 ? h->amg.omega[0] : 0.0, s));
+                                fuse0 ? (amg_level0_bf16<T>(h) ? 4 : 3) : pc,
+                                fuse0 ? h->amg.omega[0] : 0.0, s));
         }
         Scope sp(h, SLRF_K_REDUCE, 16.0 * nrb * occ);
         HIPCHK(launch_reduce(part, nrb, ND, C, 1, occ, red, s));

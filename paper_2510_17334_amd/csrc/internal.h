@@ -128,10 +128,13 @@ template <typename T>
 hipError_t launch_sweep(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
                         const void* Z, void* Out, hipStream_t s);
 // CGS projections h_i = <q_i, q_k>, i < k, as partial sums per row block.
+// hq: the stored q_i are complex bfloat16 (complex float, k <= 8): slot i at
+// Qbase + i * vstride elements holds lane pair (panel, row, lane) at 8-byte
+// index (panel * n + row) * 8 + lane.
 template <typename T>
 hipError_t launch_dots(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
                        const void* Qk, const void* Qbase, size_t vstride, int k, double2* part,
-                       hipStream_t s);
+                       hipStream_t s, bool hq = false);
 template <typename T>
 hipError_t launch_apply_dots(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
                              const void* Z, void* Qk, const void* Qbase, size_t vstride, int k,
@@ -139,18 +142,23 @@ hipError_t launch_apply_dots(const DevPencil& P, const PanelGrid& g, const SlotT
 // CGS update of the new image only, q_k -= sum_i beta_i q_i, with the partial
 // sums of <q_k, q_k> and <q_k, r> (the directions p_i are never formed: the
 // solution update combines the stored preconditioned vectors z_i instead)
+// The image w is read from Qk; q_k goes to Qout (may be Qk) when store is set
+// (a cycle's last q_k is never read again); hq as for launch_dots, with q_k
+// rounded to complex bfloat16 before its partial sums are taken.
 template <typename T>
-hipError_t launch_orth(const DevPencil& P, const PanelGrid& g, const SlotTables& st, void* Qk,
-                       const void* R, const void* Qbase, size_t vstride, int k,
-                       const double2* beta, double2* part, hipStream_t s);
+hipError_t launch_orth(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
+                       const void* Qk, const void* R, const void* Qbase, size_t vstride, int k,
+                       const double2* beta, double2* part, hipStream_t s, void* Qout,
+                       bool store, bool hq);
 template <typename T>
 // precond: 0 = none (z = r), 1 = point Jacobi, 2 = leave z to the AMG V-cycle,
 // 3 = Z receives omega D^-1 r, the level-0 pre-smoothing of the next V-cycle,
 // 4 = the same stored as complex bfloat16 (complex-float sweeps);
-// Z may be null (no z written: the last step of a cycle)
+// Z may be null (no z written: the last step of a cycle); hq: Qk holds q_k as
+// complex bfloat16 (layout as for launch_dots)
 hipError_t launch_step(const DevPencil& P, const PanelGrid& g, const SlotTables& st, void* R,
                        void* Z, const void* Qk, const double2* alpha_k, double2* part,
-                       int precond, double omega, hipStream_t s);
+                       int precond, double omega, hipStream_t s, bool hq = false);
 // FP64 solution update of a finished cycle: y += sum_j g_j z_j, where the
 // coefficients g follow from alpha and the CGS history beta (p_k = z_k -
 // sum_{i<k} beta_ik p_i); z_0 in Z0, z_j (j >= 1) at Zbase + j * vstride.

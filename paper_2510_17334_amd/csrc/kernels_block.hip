@@ -1973,8 +1973,10 @@ __device__ __forceinline__ void lv_get(const typename LaneVec<T>::V& v, int c, d
   }
 }
 
-// h_i = <q_i, q_k>, i < k <= MAXK, partial sums per (row block, slot)
-template <typename T, int MAXK>
+// h_i = <q_i, q_k>, i < k <= MAXK, partial sums per (row block, slot).
+// HQ: the stored q_i are complex bfloat16 (one 8-byte pair of systems per
+// lane at ((panel * n + row) * 8 + lane) of slot i; complex-float only).
+template <typename T, int MAXK, bool HQ = false>
 __global__ __launch_bounds__(kThreads) void k_dots_lv(int n, PanelGrid g,
                                                       const int* __restrict__ active,
                                                       const typename CT<T>::t* __restrict__ Qk,
@@ -2004,7 +2006,12 @@ __global__ __launch_bounds__(kThreads) void k_dots_lv(int n, PanelGrid g,
 #pragma unroll
     for (int i = 0; i < MAXK; ++i) {
       if (i < k) {
-        const V vq = reinterpret_cast<const V*>(Qb + (size_t)i * vstride + pbase)[off];
+        V vq;
+        if constexpr (HQ && SPL == 2)
+          vq = unpack_cbf16x2(reinterpret_cast<const uint2*>(Qb + (size_t)i * vstride)
+                                  [((size_t)pan * n + row) * 8 + lr]);
+        else
+          vq = reinterpret_cast<const V*>(Qb + (size_t)i * vstride + pbase)[off];
 #pragma unroll
         for (int c = 0; c < SPL; ++c) {
           double qx, qy, vx, vy;
@@ -2025,12 +2032,17 @@ __global__ __launch_bounds__(kThreads) void k_dots_lv(int n, PanelGrid g,
   });
 }
 
-// q_k -= sum_i beta_i q_i; partial <q_k, q_k>, <q_k, r>
-template <typename T>
+// q_k = w - sum_i beta_i q_i from the image w in Qk; partial <q_k, q_k>,
+// <q_k, r>.  q_k is written to Qout when store is set (Qout may alias Qk).
+// HQ: the stored q_i and q_k are complex bfloat16 (layout as in k_dots_lv),
+// and the partial sums are taken from the rounded q_k, so that every later
+// use of q_k sees the same vector.
+template <typename T, bool HQ = false>
 __global__ __launch_bounds__(kThreads) void k_orth_lv(
-    int n, PanelGrid g, const int* __restrict__ active, typename CT<T>::t* __restrict__ Qk,
+    int n, PanelGrid g, const int* __restrict__ active, const typename CT<T>::t* Qk,
     const typename CT<T>::t* __restrict__ R, const typename CT<T>::t* __restrict__ Qb,
-    size_t vstride, int k, const double2* __restrict__ beta, double2* __restrict__ part) {
+    size_t vstride, int k, const double2* __restrict__ beta, double2* __restrict__ part,
+    typename CT<T>::t* Qout, int store) {
   using V = typename LaneVec<T>::V;
   constexpr int SPL = LaneVec<T>::SPL;
   constexpr int LPR = kPanel / SPL;
@@ -2047,7 +2059,8 @@ __global__ __launch_bounds__(kThreads) void k_orth_lv(
     sb[t] = beta[(size_t)(t >> 4) * g.C + pan * kPanel + (t & 15)];
   __syncthreads();
   const size_t pbase = (size_t)pan * n * kPanel;
-  V* __restrict__ Qp = reinterpret_cast<V*>(Qk + pbase);
+  const V* Qp = reinterpret_cast<const V*>(Qk + pbase);
+  V* Op = reinterpret_cast<V*>(Qout + pbase);
   const V* __restrict__ Rp = reinterpret_cast<const V*>(R + pbase);
   double acc[NVS];
 #pragma unroll
@@ -2061,7 +2074,12 @@ __global__ __launch_bounds__(kThreads) void k_orth_lv(
     for (int c = 0; c < SPL; ++c) lv_get<T>(q, c, qx[c], qy[c]);
 #pragma unroll 4
     for (int i = 0; i < k; ++i) {
-      const V vq = reinterpret_cast<const V*>(Qb + (size_t)i * vstride + pbase)[off];
+      V vq;
+      if constexpr (HQ && SPL == 2)
+        vq = unpack_cbf16x2(reinterpret_cast<const uint2*>(Qb + (size_t)i * vstride)
+                                [((size_t)pan * n + row) * 8 + lr]);
+      else
+        vq = reinterpret_cast<const V*>(Qb + (size_t)i * vstride + pbase)[off];
 #pragma unroll
       for (int c = 0; c < SPL; ++c) {
         const double2 b = sb[i * kPanel + lr * SPL + c];
@@ -2075,7 +2093,13 @@ __global__ __launch_bounds__(kThreads) void k_orth_lv(
     qn.x = (T)qx[0];
     qn.y = (T)qy[0];
     if constexpr (SPL == 2) lv_set_zw(qn, (T)qx[1], (T)qy[1]);
-    Qp[off] = qn;
+    if constexpr (HQ && SPL == 2) {
+      const uint2 hq = make_uint2(pack_cbf16(qn.x, qn.y), pack_cbf16(lv_z(qn), lv_w(qn)));
+      qn = unpack_cbf16x2(hq);
+      if (store) reinterpret_cast<uint2*>(Qout)[((size_t)pan * n + row) * 8 + lr] = hq;
+    } else {
+      if (store) Op[off] = qn;
+    }
     const V r = Rp[off];
 #pragma unroll
     for (int c = 0; c < SPL; ++c) {
@@ -2103,8 +2127,9 @@ __global__ __launch_bounds__(kThreads) void k_orth_lv(
 // r -= alpha q, partial ||r||^2, and z from the new r: pc 0 copy, 1 Jacobi,
 // 2 none, 3 omega D^-1 r (the first smoothing step of the next V-cycle, from
 // the stored r exactly as the level-0 jacobi0 kernel forms it), 4 the same
-// stored as complex bfloat16 (complex-float sweeps)
-template <typename T>
+// stored as complex bfloat16 (complex-float sweeps).  HQ: q_k is stored as
+// complex bfloat16 (layout as in k_dots_lv).
+template <typename T, bool HQ = false>
 __global__ __launch_bounds__(kThreads) void k_step_lv(
     int n, PanelGrid g, const int* __restrict__ active, const double2* __restrict__ sigma,
     const double* __restrict__ da, const double* __restrict__ db, int pc, double omega,
@@ -2138,7 +2163,11 @@ __global__ __launch_bounds__(kThreads) void k_step_lv(
   for (int row = r0 + rs; row < r1; row += RPP) {
     const size_t off = (size_t)row * LPR + lr;
     const V r = Rp[off];
-    const V q = Qp[off];
+    V q;
+    if constexpr (HQ && SPL == 2)
+      q = unpack_cbf16x2(reinterpret_cast<const uint2*>(Qk)[((size_t)pan * n + row) * 8 + lr]);
+    else
+      q = Qp[off];
     V rn, zn;
 #pragma unroll
     for (int c = 0; c < SPL; ++c) {
@@ -2325,11 +2354,17 @@ bool launch_post_image(const DevImage& I, const DevPencil& P, const PanelGrid& g
 template <typename T>
 hipError_t launch_dots(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
                        const void* Qk, const void* Qbase, size_t vstride, int k, double2* part,
-                       hipStream_t s) {
+                       hipStream_t s, bool hq) {
   using C = typename CT<T>::t;
   auto Qc = static_cast<const C*>(Qk);
   auto Qb = static_cast<const C*>(Qbase);
   if (k <= 0) return hipSuccess;
+  if (hq) {
+    if (!std::is_same<T, float>::value || k > 8) return hipErrorInvalidValue;
+    k_dots_lv<T, 8, true><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, Qc, Qb, vstride,
+                                                           k, part);
+    return hipGetLastError();
+  }
   if (k <= 8)
     k_dots_lv<T, 8><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, Qc, Qb, vstride, k,
                                                      part);
@@ -2359,7 +2394,7 @@ hipError_t launch_apply_dots(const DevPencil& P, const PanelGrid& g, const SlotT
     // halo sweep, then the CGS projections as a separate streaming pass
     if (launch_halo<T>(P, g, st, kEpiApply, 0.0, Z, nullptr, Qk, s, err)) {
       if (err != hipSuccess || k == 0) return err;
-      return launch_dots<T>(P, g, st, Qk, Qbase, vstride, k, part, s);
+      return launch_dots<T>(P, g, st, Qk, Qbase, vstride, k, part, s, false);
     }
     if (launch_grp<T>(P, g, st, kEpiApply, 0.0, Z, nullptr, Qk, s, err)) {
       if (err != hipSuccess || k == 0) return err;
@@ -2419,22 +2454,38 @@ hipError_t launch_spmm_panel(const DevPencil& P, const PanelGrid& g, const doubl
 }
 
 template <typename T>
-hipError_t launch_orth(const DevPencil& P, const PanelGrid& g, const SlotTables& st, void* Qk,
-                       const void* R, const void* Qbase, size_t vstride, int k,
-                       const double2* beta, double2* part, hipStream_t s) {
+hipError_t launch_orth(const DevPencil& P, const PanelGrid& g, const SlotTables& st,
+                       const void* Qk, const void* R, const void* Qbase, size_t vstride, int k,
+                       const double2* beta, double2* part, hipStream_t s, void* Qout,
+                       bool store, bool hq) {
   using C = typename CT<T>::t;
-  k_orth_lv<T><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, static_cast<C*>(Qk),
-                                               static_cast<const C*>(R),
-                                               static_cast<const C*>(Qbase), vstride, k, beta,
-                                               part);
+  if (hq) {
+    if (!std::is_same<T, float>::value) return hipErrorInvalidValue;
+    k_orth_lv<T, true><<<g.blocks(), kThreads, 0, s>>>(
+        P.n, g, st.active, static_cast<const C*>(Qk), static_cast<const C*>(R),
+        static_cast<const C*>(Qbase), vstride, k, beta, part, static_cast<C*>(Qout),
+        store ? 1 : 0);
+    return hipGetLastError();
+  }
+  k_orth_lv<T><<<g.blocks(), kThreads, 0, s>>>(
+      P.n, g, st.active, static_cast<const C*>(Qk), static_cast<const C*>(R),
+      static_cast<const C*>(Qbase), vstride, k, beta, part, static_cast<C*>(Qout),
+      store ? 1 : 0);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_step(const DevPencil& P, const PanelGrid& g, const SlotTables& st, void* R,
                        void* Z, const void* Qk, const double2* alpha_k, double2* part,
-                       int precond, double omega, hipStream_t s) {
+                       int precond, double omega, hipStream_t s, bool hq) {
   using C = typename CT<T>::t;
+  if (hq) {
+    if (!std::is_same<T, float>::value) return hipErrorInvalidValue;
+    k_step_lv<T, true><<<g.blocks(), kThreads, 0, s>>>(
+        P.n, g, st.active, st.sigma, P.da, P.db, precond, omega, static_cast<C*>(R),
+        static_cast<C*>(Z), static_cast<const C*>(Qk), alpha_k, part);
+    return hipGetLastError();
+  }
   k_step_lv<T><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, st.sigma, P.da, P.db,
                                                precond, omega, static_cast<C*>(R),
                                                static_cast<C*>(Z), static_cast<const C*>(Qk),
@@ -2598,7 +2649,7 @@ hipError_t launch_fin_true(const double2* red, int nslots, const SlotTables& st,
                                       const void*, void*, hipStream_t);                      \
   template hipError_t launch_dots<T>(const DevPencil&, const PanelGrid&, const SlotTables&,  \
                                      const void*, const void*, size_t, int, double2*,        \
-                                     hipStream_t);                                           \
+                                     hipStream_t, bool);                                     \
   template hipError_t launch_apply_dots<T>(const DevPencil&, const PanelGrid&,               \
                                            const SlotTables&, const void*, void*,            \
                                            const void*, size_t, int, double2*, bool,         \
@@ -2606,11 +2657,12 @@ hipError_t launch_fin_true(const double2* red, int nslots, const SlotTables& st,
   template hipError_t launch_spmm_panel<T>(const DevPencil&, const PanelGrid&,               \
                                            const double2*, const void*, void*, hipStream_t); \
   template hipError_t launch_orth<T>(const DevPencil&, const PanelGrid&, const SlotTables&,  \
-                                     void*, const void*, const void*, size_t, int,           \
-                                     const double2*, double2*, hipStream_t);                 \
+                                     const void*, const void*, const void*, size_t, int,     \
+                                     const double2*, double2*, hipStream_t, void*, bool,     \
+                                     bool);                                                  \
   template hipError_t launch_step<T>(const DevPencil&, const PanelGrid&, const SlotTables&,  \
                                      void*, void*, const void*, const double2*, double2*,    \
-                                     int, double, hipStream_t);                             \
+                                     int, double, hipStream_t, bool);                       \
   template hipError_t launch_yupdate<T>(int, const PanelGrid&, const SlotTables&, double2*,  \
                                         const void*, const void*, size_t, int,               \
                                         const double2*, const double2*, hipStream_t);        \
@@ -2865,11 +2917,19 @@ __global__ __launch_bounds__(kThreads) void k_restrict(
   constexpr int LPR = kPanel / SPL;  // lanes per panel row
   constexpr int EG = 64 / LPR;       // entry groups per wave
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l % LPR, eg = l / LPR;
+  // Work item t = (group of 4 panels, coarse row), row-minor.  Workgroups are
+  // dealt to the 8 XCDs round-robin; each XCD takes one contiguous range of t,
+  // so neighbouring coarse rows of a panel group, whose fine supports
+  // overlap, gather through the same L2.
   const int ngrp = (npan + 3) / 4;
+  const long total = (long)nout * ngrp;
+  const long per = (total + 7) / 8;
   const long b = blockIdx.x;
-  const int row = (int)(b / ngrp);
-  const int pan = (int)(b % ngrp) * 4 + w;
-  if (row >= nout || pan >= npan) return;  // whole waves (no workgroup barrier below)
+  const long t = (b & 7) * per + (b >> 3);
+  if (t >= total) return;
+  const int row = (int)(t % nout);
+  const int pan = (int)(t / nout) * 4 + w;
+  if (pan >= npan) return;  // whole waves (no workgroup barrier below)
   const bool a = l < kPanel && (active == nullptr || active[pan * kPanel + l] != 0);
   if (!__any(a)) return;
   const V* __restrict__ Ip = reinterpret_cast<const V*>(In + (size_t)pan * nin * kPanel);
@@ -2879,25 +2939,33 @@ __global__ __launch_bounds__(kThreads) void k_restrict(
   T acc[2 * SPL];
 #pragma unroll
   for (int c = 0; c < 2 * SPL; ++c) acc[c] = 0;
-  for (int e = e0 + eg; e < e1; e += 4 * EG) {
-    V z[4];
-    T wv[4];
+  // U entries per entry group and round, all column indices of a round loaded
+  // before its gathers are issued (deeper rounds measured slower on the
+  // complex-bfloat16 input, faster on the coarser complex-float levels).
+  constexpr int U = HIN ? 4 : 8;
+  for (int e = e0 + eg; e < e1; e += U * EG) {
+    int ci[U];
+    T wv[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int ee = e + u * EG;
+      ci[u] = ee < e1 ? col[ee] : -1;
+      wv[u] = ee < e1 ? v[ee] : (T)0;
+    }
+    V z[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
       z[u] = V{};
-      wv[u] = 0;
-      if (ee < e1) {
-        wv[u] = v[ee];
+      if (ci[u] >= 0) {
         if constexpr (HIN) {
-          if constexpr (SPL == 2) z[u] = unpack_cbf16x2(Ih[(size_t)col[ee] * 8 + lr]);
+          if constexpr (SPL == 2) z[u] = unpack_cbf16x2(Ih[(size_t)ci[u] * 8 + lr]);
         } else {
-          z[u] = Ip[(size_t)col[ee] * LPR + lr];
+          z[u] = Ip[(size_t)ci[u] * LPR + lr];
         }
       }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       acc[0] = mad(wv[u], z[u].x, acc[0]);
       acc[1] = mad(wv[u], z[u].y, acc[1]);
       if constexpr (SPL == 2) {
@@ -2925,7 +2993,7 @@ hipError_t launch_restrict_bf16(const DevTransfer& M, const PanelGrid& g, const 
   using C = typename CT<T>::t;
   if (!std::is_same<T, float>::value) return hipErrorInvalidValue;
   const T* v = reinterpret_cast<const T*>(M.v32);
-  const long nblk = (long)M.nrows * ((g.npan + 3) / 4);
+  const long nblk = ((long)M.nrows * ((g.npan + 3) / 4) + 7) / 8 * 8;
   k_restrict<T, true><<<(unsigned)nblk, kThreads, 0, s>>>(M.nrows, M.ncols, M.rowptr, M.col, v,
                                                          g.npan, st.active,
                                                          static_cast<const C*>(In),
@@ -2942,7 +3010,7 @@ hipError_t launch_transfer(const DevTransfer& M, const PanelGrid& g, const SlotT
   auto Ic = static_cast<const C*>(In);
   auto Oc = static_cast<C*>(Out);
   if (!add && M.nnz > 16 * M.nrows) {
-    const long nblk = (long)M.nrows * ((g.npan + 3) / 4);
+    const long nblk = ((long)M.nrows * ((g.npan + 3) / 4) + 7) / 8 * 8;
     k_restrict<T><<<(unsigned)nblk, kThreads, 0, s>>>(M.nrows, M.ncols, M.rowptr, M.col, v,
                                                       g.npan, st.active, Ic, Oc);
     return hipGetLastError();

@@ -806,6 +806,11 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
   int cycles = 0;
   bool numeric = false;
   const size_t vstride = (size_t)C * n;  // elements between consecutive P_i / Q_i
+  // Complex-float cycles on the halo sweep keep the CGS basis q_0 .. q_{m-2}
+  // in complex bfloat16 (the first half of each Q slot): GCR keeps using the
+  // rounded vectors consistently (projections, residual update), the solution
+  // update never reads them, and each cycle ends on an FP64 true residual.
+  const bool hq = std::is_same<T, float>::value && sweep_is_halo<T>(h->P) && m <= 9;
   const double csr_bytes = (double)h->P.nnz * (4.0 + 2.0 * sizeof(T)) + 4.0 * (n + 1);
 
   SlotTables tabs;
@@ -940,19 +945,24 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
     };
     for (int k = 0; k < m; ++k) {
       char* Qk = static_cast<char*>(Q) + (size_t)k * vstride * sT;
+      // the image w = M z_k: in place in slot k, or (complex bfloat16 basis)
+      // in the last slot, whose q is never stored
+      void* Wk = hq ? static_cast<char*>(Q) + (size_t)(m - 1) * vstride * sT : Qk;
+      const double qb = hq ? 0.5 : 1.0;  // bytes of a stored q relative to w
       void* Z = zk(k);
       if (amg) {
         const slrf_status vs = vcycle<T>(h, av, C, occ, ND, tc, R, Z, nact, fuse0 && k > 0);
         if (vs != SLRF_OK) return vs;
       }
       if (sweep_is_halo<T>(h->P)) {
-        Scope sp(h, SLRF_K_APPLY, (double)nact * n * sT * (k + 2) + csr_bytes);
+        Scope sp(h, SLRF_K_APPLY,
+                 (double)nact * n * sT * (k > 0 ? 3.0 + qb * k : 2.0) + csr_bytes);
         {
           Scope sw(h, SLRF_K_SWEEP, (double)nact * n * sT * 2.0 + csr_bytes);
           if (h->cur_stats) h->cur_stats->sweep_systems += nact;
-          HIPCHK(launch_sweep<T>(h->P, g, tc, Z, Qk, s));
+          HIPCHK(launch_sweep<T>(h->P, g, tc, Z, Wk, s));
         }
-        HIPCHK(launch_dots<T>(h->P, g, tc, Qk, Q, vstride, k, part, s));
+        HIPCHK(launch_dots<T>(h->P, g, tc, Wk, Q, vstride, k, part, s, hq));
       } else {
         Scope sp(h, SLRF_K_APPLY, (double)nact * n * sT * (k + 2) + csr_bytes);
         HIPCHK(launch_apply_dots<T>(h->P, g, tc, Z, Qk, Q, vstride, k, part, pc, s));
@@ -963,8 +973,12 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
         HIPCHK(launch_fin_beta(red, k, C, occ, tc, sc, s));
       }
       {
-        Scope sp(h, SLRF_K_ORTH, (double)nact * n * sT * (k + 3.0));
-        HIPCHK(launch_orth<T>(h->P, g, tc, Qk, R, Q, vstride, k, sc.beta, part, s));
+        // q_k is stored unless no later step reads it: the cycle's last q, and
+        // (full-precision basis) q_0, which is w itself
+        const bool store = k + 1 < m && (hq || k > 0);
+        Scope sp(h, SLRF_K_ORTH, (double)nact * n * sT * (2.0 + qb * k + (store ? qb : 0.0)));
+        HIPCHK(launch_orth<T>(h->P, g, tc, Wk, R, Q, vstride, k, sc.beta, part, s, Qk, store,
+                              hq));
       }
       {
         Scope sp(h, SLRF_K_REDUCE, 32.0 * nrb * occ);
@@ -973,13 +987,13 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
       }
       if (k + 1 < m) {
         {
-          Scope sp(h, SLRF_K_STEP, (double)nact * n * sT * 4.0);
+          Scope sp(h, SLRF_K_STEP, (double)nact * n * sT * (3.0 + qb));
           // with the AMG, the step also forms the next V-cycle's level-0
           // pre-smoothing (saves that kernel's read of r)
           void* znext = fuse0 ? av.W0 : zk(k + 1);
           HIPCHK(launch_step<T>(h->P, g, tc, R, znext, Qk, sc.alpha + (size_t)k * C, part,
                                 fuse0 ? (amg_level0_bf16<T>(h) ? 4 : 3) : pc,
-                                fuse0 ? h->amg.omega[0] : 0.0, s));
+                                fuse0 ? h->amg.omega[0] : 0.0, s, hq));
         }
         Scope sp(h, SLRF_K_REDUCE, 16.0 * nrb * occ);
         HIPCHK(launch_reduce(part, nrb, ND, C, 1, occ, red, s));

@@ -587,6 +587,16 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
   constexpr int HP = (kHaloMaxH * 8 + kThreads - 1) / kThreads;
   using HV = typename std::conditional<ZH, uint2, V>::type;  // staged element as loaded
   HV hreg[HP];
+  // element offsets of this thread's share of the halo within a unit (the
+  // same for every unit of the tile); past the halo a thread loads row 0 and
+  // stores nothing (the loads stay unconditional, so they are issued here and
+  // not where the values are consumed)
+  unsigned hoff[HP];
+#pragma unroll
+  for (int i = 0; i < HP; ++i) {
+    const int t = i * kThreads + tid;
+    hoff[i] = (unsigned)((t < H * 8 ? sH[t >> 3] * (ZH ? 8 : LPRF) : 0) + (t & 7));
+  }
 #define SLRF_HALO_ISSUE(GX)                                                              \
   do {                                                                                   \
     const int ux_ = ug * G + (GX);                                                       \
@@ -594,9 +604,9 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
         ZH ? reinterpret_cast<const HV*>(Z) + (size_t)(ux_ / UPP) * n * 8                \
            : reinterpret_cast<const HV*>(Z + (size_t)(ux_ / UPP) * n * kPanel) + (ux_ % UPP) * 8; \
     _Pragma("unroll") for (int i_ = 0; i_ < HP; ++i_) {                                  \
-      const int t_ = i_ * kThreads + tid;                                                \
-      hreg[i_] = HV{};                                                                   \
-      if (t_ < H * 8) hreg[i_] = zx_[(size_t)sH[t_ >> 3] * (ZH ? 8 : LPRF) + (t_ & 7)];  \
+      /* (through a local: a direct element copy leaves hreg in scratch) */              \
+      const HV v_ = zx_[hoff[i_]];                                                       \
+      hreg[i_] = v_;                                                                     \
     }                                                                                    \
   } while (0)
   SLRF_HALO_ISSUE(gu);
@@ -775,15 +785,22 @@ __global__ __launch_bounds__(kThreads) void k_post_image(
   if (gu >= G) return;
   constexpr int HP = (kImgMaxH * 8 + kThreads - 1) / kThreads;
   V hreg[HP];
+  // this thread's coarse-halo element offsets, the same for every unit (row 0
+  // past the halo: the loads stay unconditional and are not stored)
+  unsigned hoff[HP];
+#pragma unroll
+  for (int i = 0; i < HP; ++i) {
+    const int t = i * kThreads + tid;
+    hoff[i] = (unsigned)((t < H * 8 ? sH[t >> 3] * LPRF : 0) + (t & 7));
+  }
 #define SLRF_IMG_ISSUE(GX)                                                                  \
   do {                                                                                      \
     const int ux_ = ug * G + (GX);                                                          \
     const V* __restrict__ ex_ =                                                             \
         reinterpret_cast<const V*>(E + (size_t)(ux_ / UPP) * nc * kPanel) + (ux_ % UPP) * 8; \
     _Pragma("unroll") for (int i_ = 0; i_ < HP; ++i_) {                                     \
-      const int t_ = i_ * kThreads + tid;                                                   \
-      hreg[i_] = V{};                                                                       \
-      if (t_ < H * 8) hreg[i_] = ex_[(size_t)sH[t_ >> 3] * LPRF + (t_ & 7)];                \
+      const V v_ = ex_[hoff[i_]];                                                           \
+      hreg[i_] = v_;                                                                        \
     }                                                                                       \
   } while (0)
   SLRF_IMG_ISSUE(gu);
@@ -950,14 +967,21 @@ __global__ __launch_bounds__(kThreads) void k_true_halo(
   if (gu >= G) return;
   constexpr int HP = (kHaloMaxH * 8 + kThreads - 1) / kThreads;
   V hreg[HP];
+  // this thread's halo element offsets, the same for every unit (row 0 past
+  // the halo: the loads stay unconditional and are not stored)
+  unsigned hoff[HP];
+#pragma unroll
+  for (int i = 0; i < HP; ++i) {
+    const int t = i * kThreads + tid;
+    hoff[i] = (unsigned)((t < H * 8 ? sH[t >> 3] * LPRF : 0) + (t & 7));
+  }
 #define SLRF_TRUE_ISSUE(GX)                                                              \
   do {                                                                                   \
     const int ux_ = ug * G + (GX);                                                       \
     const V* __restrict__ yx_ = Y + (size_t)(ux_ / UPP) * n * kPanel + (ux_ % UPP) * 8;  \
     _Pragma("unroll") for (int i_ = 0; i_ < HP; ++i_) {                                  \
-      const int t_ = i_ * kThreads + tid;                                                \
-      hreg[i_] = V{};                                                                    \
-      if (t_ < H * 8) hreg[i_] = yx_[(size_t)sH[t_ >> 3] * LPRF + (t_ & 7)];             \
+      const V v_ = yx_[hoff[i_]];                                                        \
+      hreg[i_] = v_;                                                                     \
     }                                                                                    \
   } while (0)
   SLRF_TRUE_ISSUE(gu);

@@ -293,9 +293,11 @@ constexpr int kEpiResidH = 3;
 // complex bfloat16 in one 32-bit word (re in the low half); rounding to the
 // nearest even
 __device__ __forceinline__ unsigned bf16_rne(float x) {
-  unsigned u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return u >> 16;
+  const unsigned u = __float_as_uint(x);
+  // a NaN stays a (quiet) NaN: the rounding carry could otherwise wrap its
+  // payload into the sign bit
+  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (u >> 16) | 0x0040u;
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
 }
 __device__ __forceinline__ unsigned pack_cbf16(float re, float im) {
   return bf16_rne(re) | (bf16_rne(im) << 16);
@@ -2261,7 +2263,8 @@ size_t halo_lds_bytes(const DevPencil& P) {
 template <typename T>
 bool halo_selected(const DevPencil& P) {
   const int var = std::is_same<T, float>::value ? P.var32 : P.var64;
-  return var == kSpmmHalo && P.hx_ntile > 0 && P.hx_hmax <= kHaloMaxH &&
+  // (the halo kernels address a unit's rows with 32-bit element offsets)
+  return var == kSpmmHalo && P.n <= (1 << 28) && P.hx_ntile > 0 && P.hx_hmax <= kHaloMaxH &&
          halo_lds_bytes<T>(P) <= 96 * 1024;
 }
 

@@ -124,7 +124,7 @@ typedef struct {
 /* Per-kernel-class counters (algorithmic bytes, launches, event time). */
 enum {
   SLRF_K_APPLY = 0, /* shifted SpMM q = (A - sigma B) z fused with the CGS dots */
-  SLRF_K_ORTH = 1,  /* CGS update of q, p                                        */
+  SLRF_K_ORTH = 1,  /* CGS update of q with <q, q> and <q, r>                    */
   SLRF_K_STEP = 2,  /* r -= alpha q, z = P^-1 r, ||r||                            */
   SLRF_K_RESID = 3, /* FP64 residual f - (A - sigma B) y and solution update      */
   SLRF_K_REDUCE = 4,/* second-stage reductions and per-system scalars             */

@@ -379,7 +379,7 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(f"bench.py measures one GPU only: the filter's (pole, column) systems are "
               f"independent, a multi-GPU run would shard them by column (see the design "
-              f"notes); --gpus {args.gpus} is not supported in this build.", file=sys.stderr)
+              f"notes); --gpus {args.gpus} is not supported.", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch64":
         run_batch64(args)

@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests must never silently pass on a CPU machine: skip them here with a
-    # reason only when no GPU is visible; on a GPU machine they run through the HIP
+    # reason only when no GPU is visible; with a GPU they run through the HIP
     # library and fail loudly if it is missing.
     try:
         import torch

@@ -78,10 +78,14 @@ constexpr int kSpmmVariants = 7;
 #endif
 constexpr int kHaloMaxH = SLRF_HALO_MAXH;
 constexpr int kHaloTileRows = 32;
+// Units (128-byte panel column slices) per workgroup: a tile's coefficients
+// are staged once for all of them.  On the 3D Q1 benchmark pencil (80 panels)
+// 16 to 40 units run the halo sweeps and the up-step 2-4 % faster than 8, 4
+// units 12 % slower; 16 keeps workgroups for small pencils and batches.
 #ifndef SLRF_HALO_G
-#define SLRF_HALO_G 8
+#define SLRF_HALO_G 16
 #endif
-constexpr int kHaloMaxG = SLRF_HALO_G;  // units (128-byte panel column slices) per workgroup
+constexpr int kHaloMaxG = SLRF_HALO_G;
 
 // A rectangular real CSR matrix on the device (AMG prolongation / restriction).
 struct DevTransfer {

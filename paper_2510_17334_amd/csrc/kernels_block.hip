@@ -1608,6 +1608,35 @@ __global__ __launch_bounds__(kThreads) void k_filter_sum(int n, int ncols, int n
   Ur[t] = u;
 }
 
+// The same sum when npoles divides 16 (a column's poles share a store panel):
+// threads follow the store order (one 16-lane group per panel row), so the
+// loads are contiguous, and the first lane of each column's npoles lanes adds
+// their terms in increasing j (the order of k_filter_sum: identical results).
+__global__ __launch_bounds__(kThreads) void k_filter_sum_p(int n, int ncols, int npoles,
+                                                           long total,
+                                                           const double2* __restrict__ Ys,
+                                                           const double2* __restrict__ w,
+                                                           double* __restrict__ Ur) {
+  const long t = (long)blockIdx.x * kThreads + threadIdx.x;
+  const int l = (int)(t & 15);
+  const long pr = t >> 4;  // panel * n + row
+  const int pan = (int)(pr / n), row = (int)(pr % n);
+  const int s = pan * kPanel + l, c = s / npoles, j = s % npoles;
+  double term = 0.0;
+  if (t < total && c < ncols) {
+    const double2 y = Ys[t];
+    const double2 wj = w[j];
+    term = 2.0 * (wj.x * y.x - wj.y * y.y);
+  }
+  const int lane = threadIdx.x & 63;
+  double u = 0.0 + term;
+  for (int jj = 1; jj < npoles; ++jj) {
+    const double v = __shfl(term, (lane + jj) & 63);
+    u += v;
+  }
+  if (t < total && c < ncols && j == 0) Ur[(size_t)row * ncols + c] = u;
+}
+
 // second-stage reduction of per-row-block partial sums (fixed order)
 __global__ __launch_bounds__(kThreads) void k_reduce(const double2* __restrict__ part, int nrb,
                                                      int ND, int C, int nd, int nslots,
@@ -2594,6 +2623,12 @@ hipError_t launch_filter_sum(int n, int ncols, int npoles, const double2* Ystore
                              const double2* w, double* Ur, hipStream_t s) {
   const size_t tot = (size_t)n * ncols;
   if (tot == 0) return hipSuccess;
+  if (npoles >= 1 && kPanel % npoles == 0) {
+    const long total = (long)((ncols * npoles + kPanel - 1) / kPanel) * n * kPanel;
+    k_filter_sum_p<<<cdiv((size_t)total, kThreads), kThreads, 0, s>>>(n, ncols, npoles, total,
+                                                                      Ystore, w, Ur);
+    return hipGetLastError();
+  }
   k_filter_sum<<<cdiv(tot, kThreads), kThreads, 0, s>>>(n, ncols, npoles, Ystore, w, Ur);
   return hipGetLastError();
 }

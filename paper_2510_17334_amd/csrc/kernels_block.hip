@@ -2968,8 +2968,7 @@ __global__ __launch_bounds__(kThreads) void k_prolong_lds(
   }
 }
 
-// (HIN: the input is complex bfloat16, complex-float sweeps only)
-template <typename T, bool HIN = false>
+template <typename T>
 __global__ __launch_bounds__(kThreads) void k_restrict(
     int nout, int nin, const int* __restrict__ rowptr, const int* __restrict__ col,
     const T* __restrict__ v, int npan, const int* __restrict__ active,
@@ -2995,16 +2994,14 @@ __global__ __launch_bounds__(kThreads) void k_restrict(
   const bool a = l < kPanel && (active == nullptr || active[pan * kPanel + l] != 0);
   if (!__any(a)) return;
   const V* __restrict__ Ip = reinterpret_cast<const V*>(In + (size_t)pan * nin * kPanel);
-  const uint2* __restrict__ Ih = reinterpret_cast<const uint2*>(In) + (size_t)pan * nin * 8;
   V* __restrict__ Op = reinterpret_cast<V*>(Out + (size_t)pan * nout * kPanel);
   const int e0 = rowptr[row], e1 = rowptr[row + 1];
   T acc[2 * SPL];
 #pragma unroll
   for (int c = 0; c < 2 * SPL; ++c) acc[c] = 0;
   // U entries per entry group and round, all column indices of a round loaded
-  // before its gathers are issued (deeper rounds measured slower on the
-  // complex-bfloat16 input, faster on the coarser complex-float levels).
-  constexpr int U = HIN ? 4 : 8;
+  // before its gathers are issued
+  constexpr int U = 8;
   for (int e = e0 + eg; e < e1; e += U * EG) {
     int ci[U];
     T wv[U];
@@ -3018,13 +3015,7 @@ __global__ __launch_bounds__(kThreads) void k_restrict(
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       z[u] = V{};
-      if (ci[u] >= 0) {
-        if constexpr (HIN) {
-          if constexpr (SPL == 2) z[u] = unpack_cbf16x2(Ih[(size_t)ci[u] * 8 + lr]);
-        } else {
-          z[u] = Ip[(size_t)ci[u] * LPR + lr];
-        }
-      }
+      if (ci[u] >= 0) z[u] = Ip[(size_t)ci[u] * LPR + lr];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -3049,17 +3040,87 @@ __global__ __launch_bounds__(kThreads) void k_restrict(
   }
 }
 
+// Restriction of the complex-bfloat16 level-0 residual: as k_restrict, but a
+// lane gathers 16 bytes (four systems) of a fine row, four lanes cover the
+// row's 16 systems and one wave-wide gather reads 16 fine rows.  (With 8-byte
+// gathers, eight lanes per row, the kernel took 20 % longer: its time follows
+// the number of gather instructions, not the bytes.)
+__global__ __launch_bounds__(kThreads) void k_restrict_h(
+    int nout, int nin, const int* __restrict__ rowptr, const int* __restrict__ col,
+    const float* __restrict__ v, int npan, const int* __restrict__ active,
+    const float2* __restrict__ In, float2* __restrict__ Out) {
+  constexpr int LPR = 4;        // lanes per fine row (4 systems each)
+  constexpr int EG = 64 / LPR;  // entry groups per wave
+  constexpr int U = 4;          // entries per entry group and round
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l % LPR, eg = l / LPR;
+  // work order as in k_restrict (a contiguous range of (panel group, coarse
+  // row) items per XCD)
+  const int ngrp = (npan + 3) / 4;
+  const long total = (long)nout * ngrp;
+  const long per = (total + 7) / 8;
+  const long b = blockIdx.x;
+  const long t = (b & 7) * per + (b >> 3);
+  if (t >= total) return;
+  const int row = (int)(t % nout);
+  const int pan = (int)(t / nout) * 4 + w;
+  if (pan >= npan) return;  // whole waves (no workgroup barrier below)
+  const bool a = l < kPanel && (active == nullptr || active[pan * kPanel + l] != 0);
+  if (!__any(a)) return;
+  // the panel's fine rows: 64 bytes each, as four 16-byte lane vectors
+  const uint4* __restrict__ Ih = reinterpret_cast<const uint4*>(In) + (size_t)pan * nin * LPR;
+  const int e0 = rowptr[row], e1 = rowptr[row + 1];
+  float acc[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc[c] = 0.0f;
+  for (int e = e0 + eg; e < e1; e += U * EG) {
+    int ci[U];
+    float wv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int ee = e + u * EG;
+      ci[u] = ee < e1 ? col[ee] : -1;
+      wv[u] = ee < e1 ? v[ee] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (ci[u] >= 0) {
+        const uint4 h = Ih[(size_t)ci[u] * LPR + lr];
+        const float4 z0 = unpack_cbf16x2(make_uint2(h.x, h.y));
+        const float4 z1 = unpack_cbf16x2(make_uint2(h.z, h.w));
+        acc[0] = fmaf(wv[u], z0.x, acc[0]);
+        acc[1] = fmaf(wv[u], z0.y, acc[1]);
+        acc[2] = fmaf(wv[u], z0.z, acc[2]);
+        acc[3] = fmaf(wv[u], z0.w, acc[3]);
+        acc[4] = fmaf(wv[u], z1.x, acc[4]);
+        acc[5] = fmaf(wv[u], z1.y, acc[5]);
+        acc[6] = fmaf(wv[u], z1.z, acc[6]);
+        acc[7] = fmaf(wv[u], z1.w, acc[7]);
+      }
+    }
+  }
+#pragma unroll
+  for (int off = LPR; off < 64; off <<= 1)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] += __shfl_xor(acc[c], off);
+  if (eg == 0) {
+    // systems 4 lr .. 4 lr + 3 of the coarse row, as two complex-float pairs
+    float4* Op = reinterpret_cast<float4*>(Out + ((size_t)pan * nout + row) * kPanel);
+    Op[2 * lr] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    Op[2 * lr + 1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+  }
+}
+
 template <typename T>
 hipError_t launch_restrict_bf16(const DevTransfer& M, const PanelGrid& g, const SlotTables& st,
                                 const void* In, void* Out, hipStream_t s) {
-  using C = typename CT<T>::t;
   if (!std::is_same<T, float>::value) return hipErrorInvalidValue;
   const T* v = reinterpret_cast<const T*>(M.v32);
   const long nblk = ((long)M.nrows * ((g.npan + 3) / 4) + 7) / 8 * 8;
-  k_restrict<T, true><<<(unsigned)nblk, kThreads, 0, s>>>(M.nrows, M.ncols, M.rowptr, M.col, v,
-                                                         g.npan, st.active,
-                                                         static_cast<const C*>(In),
-                                                         static_cast<C*>(Out));
+  if constexpr (std::is_same<T, float>::value)
+    k_restrict_h<<<(unsigned)nblk, kThreads, 0, s>>>(M.nrows, M.ncols, M.rowptr, M.col, v,
+                                                     g.npan, st.active,
+                                                     static_cast<const float2*>(In),
+                                                     static_cast<float2*>(Out));
   return hipGetLastError();
 }
 

@@ -813,7 +813,11 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
   // in complex bfloat16 (the first half of each Q slot): GCR keeps using the
   // rounded vectors consistently (projections, residual update), the solution
   // update never reads them, and each cycle ends on an FP64 true residual.
-  const bool hq = std::is_same<T, float>::value && sweep_is_halo<T>(h->P) && m <= 9;
+  // Warm-started calls (Algorithm 2) keep the basis in complex float: with the
+  // rounded basis, Algorithm 2 with locking and warm start took 28-39 outer
+  // iterations instead of 7 on two of the 64 uneven diffusion pencils (cold
+  // starts: 7 either way).
+  const bool hq = std::is_same<T, float>::value && sweep_is_halo<T>(h->P) && m <= 9 && !warm;
   const double csr_bytes = (double)h->P.nnz * (4.0 + 2.0 * sizeof(T)) + 4.0 * (n + 1);
 
   SlotTables tabs;

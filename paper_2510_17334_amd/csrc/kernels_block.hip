@@ -586,8 +586,11 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
   if (gu >= G) return;
   // the halo of a unit is loaded into registers while the previous unit is
   // formed (the whole halo fits: H <= kHaloMaxH)
-  constexpr int HP = (kHaloMaxH * 8 + kThreads - 1) / kThreads;
-  using HV = typename std::conditional<ZH, uint2, V>::type;  // staged element as loaded
+  // staged elements per halo row: eight 16-byte complex-float lane vectors, or
+  // (complex bfloat16) four 16-byte vectors of four systems each
+  constexpr int EPR = ZH ? 4 : 8;
+  constexpr int HP = (kHaloMaxH * EPR + kThreads - 1) / kThreads;
+  using HV = typename std::conditional<ZH, uint4, V>::type;  // staged element as loaded
   HV hreg[HP];
   // element offsets of this thread's share of the halo within a unit (the
   // same for every unit of the tile); past the halo a thread loads row 0 and
@@ -597,13 +600,13 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
 #pragma unroll
   for (int i = 0; i < HP; ++i) {
     const int t = i * kThreads + tid;
-    hoff[i] = (unsigned)((t < H * 8 ? sH[t >> 3] * (ZH ? 8 : LPRF) : 0) + (t & 7));
+    hoff[i] = (unsigned)((t < H * EPR ? sH[t / EPR] * (ZH ? 4 : LPRF) : 0) + (t % EPR));
   }
 #define SLRF_HALO_ISSUE(GX)                                                              \
   do {                                                                                   \
     const int ux_ = ug * G + (GX);                                                       \
     const HV* __restrict__ zx_ =                                                         \
-        ZH ? reinterpret_cast<const HV*>(Z) + (size_t)(ux_ / UPP) * n * 8                \
+        ZH ? reinterpret_cast<const HV*>(Z) + (size_t)(ux_ / UPP) * n * 4                \
            : reinterpret_cast<const HV*>(Z + (size_t)(ux_ / UPP) * n * kPanel) + (ux_ % UPP) * 8; \
     _Pragma("unroll") for (int i_ = 0; i_ < HP; ++i_) {                                  \
       /* (through a local: a direct element copy leaves hreg in scratch) */              \
@@ -640,7 +643,11 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
       const int t = i * kThreads + tid;
       if constexpr (ZH) {
         if constexpr (SPL == 2)
-          if (t < H * 8) sZ[t] = unpack_cbf16x2(hreg[i]);
+          if (t < H * 4) {
+            const int hr = t >> 2, q = t & 3;
+            sZ[hr * 8 + 2 * q] = unpack_cbf16x2(make_uint2(hreg[i].x, hreg[i].y));
+            sZ[hr * 8 + 2 * q + 1] = unpack_cbf16x2(make_uint2(hreg[i].z, hreg[i].w));
+          }
       } else {
         if (t < H * 8) sZ[t] = hreg[i];
       }

@@ -156,6 +156,9 @@ typedef struct {
                             options.spmm_variant codes; 0 = default choice)   */
   double sweep_systems;  /* systems swept, summed over the SWEEP-class launches
                             (flops of those launches = 8 * nnz * sweep_systems) */
+  int32_t basis_bf16;    /* 1 when the Krylov cycles kept their Gram-Schmidt basis
+                            in complex bfloat16 (mixed precision, halo sweep,
+                            restart <= 9, cold start), else 0                  */
   int32_t* sys_iters;    /* optional, caller-owned host int32[N*ncols]: iterations
                             of system (column c, pole j) at index c*N + j          */
 } slrf_filter_stats;

@@ -1074,6 +1074,7 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
     st->max_pole_iters_ratio_x1000 = pmin > 0 ? (int32_t)(1000.0 * pmax / pmin) : 0;
     st->max_rel_resid = maxrel;
     st->spmm_variant = std::is_same<T, float>::value ? h->P.var32 : h->P.var64;
+    st->basis_bf16 = hq ? 1 : 0;
     if (st->sys_iters) std::memcpy(st->sys_iters, its.data(), sizeof(int) * S);
     st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }

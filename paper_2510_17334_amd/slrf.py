@@ -59,7 +59,7 @@ class FilterStats(C.Structure):
                 ("max_rel_resid", C.c_double), ("seconds", C.c_double),
                 ("launches", C.c_int64 * 8), ("bytes", C.c_double * 8), ("ms", C.c_double * 8),
                 ("spmm_variant", C.c_int32), ("sweep_systems", C.c_double),
-                ("sys_iters", C.POINTER(C.c_int32))]
+                ("basis_bf16", C.c_int32), ("sys_iters", C.POINTER(C.c_int32))]
 
 
 class SolveStats(C.Structure):

@@ -289,6 +289,74 @@ def test_filter_sine_eigenvectors_full_3d_size():
         h.close()
 
 
+def _sine_block_3d(m, ks):
+    """Sine products and their closed-form eigenvalues on the m^3 Q1 pencil."""
+    h1d = 1.0 / (m + 1)
+    t = np.arange(1, m + 1) * np.pi / (m + 1)
+    lam1 = (6.0 / h1d ** 2) * (1 - np.cos(t)) / (2 + np.cos(t))
+    # sin(j k pi / (m + 1)) with the argument reduced exactly: high modes stay
+    # eigenvectors to rounding
+    sv = lambda k: np.sin(((np.arange(1, m + 1) * k) % (2 * (m + 1))) * np.pi / (m + 1))
+    X = np.stack([np.kron(sv(a), np.kron(sv(b), sv(cc))) for a, b, cc in ks], axis=1)
+    lam = np.array([lam1[a - 1] + lam1[b - 1] + lam1[cc - 1] for a, b, cc in ks])
+    return X, lam
+
+
+@pytest.mark.parametrize("prec", [P.SLRF_PREC_MIXED, P.SLRF_PREC_FP64])
+def test_filter_sine_full_size_benchmark_options(prec):
+    """The benchmark's filter exactly as it runs (n = 262,144, 8 poles, AMG V-cycle,
+    GCR(5), tol_lin 1e-8, cold start, autotuned sweep): in the mixed form this is
+    the path whose cycles keep the Gram-Schmidt basis in complex bfloat16.  Per
+    column U = Phi(lambda) u (closed form, Eq. (3)) within the bound the
+    residual tolerance implies; modes inside (0, gamma], at the cluster by gamma,
+    just above it and at the top of the spectrum."""
+    m = 64
+    c = si.config_q1_3d()
+    p = c["pencil"]
+    poles, weights = si.slrf_poles(c["gamma"], 8)
+    ks = [(1, 1, 1), (2, 1, 1), (3, 2, 1), (4, 3, 1), (5, 1, 1), (4, 3, 2), (6, 1, 1),
+          (64, 64, 64), (33, 7, 50), (1, 64, 2)]
+    X, lam = _sine_block_3d(m, ks)
+    phi = np.sum(2 * np.real(weights[None, :] / (lam[:, None] - poles[None, :])), axis=1)
+    tol = 1e-8
+    h = _handle(p, c["gamma"], poles, weights, precision=prec, tol_lin=tol,
+                precond=P.SLRF_PC_AMG, restart=5)
+    U, st = h.slrf_filter(_dev(X))
+    h.close()
+    assert st["basis_bf16"] == (1 if prec == P.SLRF_PREC_MIXED else 0)
+    assert st["converged"] == 8 * len(ks) and st["max_rel_resid"] <= tol
+    err = np.linalg.norm(_host(U) - X * phi[None, :], axis=0)
+    bound = _filter_bound(p.B() @ X, poles, weights, tol, _q1_lambda_min_B(m, 3))
+    assert np.all(err <= bound), (prec, (err / bound).max())
+
+
+@pytest.mark.parametrize("prec", [P.SLRF_PREC_MIXED, P.SLRF_PREC_FP64])
+def test_filter_lu_oracle_benchmark_options(cfg1, prec):
+    """The benchmark's filter options (AMG, GCR(5), tol_lin 1e-8, halo sweep) on the
+    2D configuration against the exact-LU oracle, column by column, with every
+    system's FP64 residual recomputed on the host from the single-pole solves."""
+    p = cfg1["pencil"]
+    tol = 1e-8
+    opt = dict(precision=prec, tol_lin=tol, precond=P.SLRF_PC_AMG, restart=5, spmm_variant=6)
+    h = _handle(p, cfg1["gamma"], cfg1["poles"], cfg1["weights"], **opt)
+    X = cfg1["V1"]
+    U, st = h.slrf_filter(_dev(X))
+    h.close()
+    assert st["basis_bf16"] == (1 if prec == P.SLRF_PREC_MIXED else 0)
+    Uo = oracle.filter.apply_filter(p.A(), p.B(), cfg1["poles"], cfg1["weights"], X)
+    bound = _filter_bound(p.B() @ X, cfg1["poles"], cfg1["weights"], tol, _q1_lambda_min_B(40, 2))
+    err = np.linalg.norm(_host(U) - Uo, axis=0)
+    assert np.all(err <= bound), (err / bound).max()
+    assert st["converged"] == 8 * X.shape[1] and st["max_rel_resid"] <= tol
+    A, B = p.A(), p.B()
+    F = B @ X[:, :6]
+    for j in (0, 4, 7):
+        Y, sj = _single_pole_solution(p, cfg1["gamma"], cfg1["poles"][j], X[:, :6], **opt)
+        M = (A - cfg1["poles"][j] * B).tocsr()
+        rel = np.linalg.norm(F - M @ Y, axis=0) / np.linalg.norm(F, axis=0)
+        assert rel.max() <= 1.01 * tol, (j, rel.max())
+
+
 # ----------------------------------------------------------------------------
 # truncated GCR (It_max-linear) and warm start (Algorithm 2, Proposition 4.1)
 # ----------------------------------------------------------------------------

@@ -297,3 +297,62 @@ def test_smallest_eigs_closed_form_and_dense():
     q = si.q1_diffusion_pencil(9, 3, kappa)
     dense = oracle.eig.dense_eigs(q.A(), q.B())[0]
     assert np.allclose(oracle.eig.smallest_eigs(q.A(), q.B(), 30), dense[:30], rtol=1e-10)
+
+
+# ----------------------------------------------------------------------------
+# Residual of Section 3.2 and the Jacobi preconditioner, on hand-worked cases
+# ----------------------------------------------------------------------------
+
+def test_residual_norm_normaliser_hand_worked():
+    """r = (A - theta B) x / (theta ||x||_B) (Section 3.2) for a non-eigenvector.
+
+    A = diag(2, 5), B = diag(1, 2), x = (1, 1), theta = 3 by hand:
+    (A - 3B) x = (-1, -1), ||.||_2 = sqrt(2); ||x||_B = sqrt(1 + 2) = sqrt(3);
+    so ||r|| = sqrt(2) / (3 sqrt(3)) = 0.272165526975909.  Dropping theta gives
+    0.8165, the Euclidean norm of x instead of the B-norm 0.3333: both fail.
+    """
+    A = sp.diags([2.0, 5.0]).tocsr()
+    B = sp.diags([1.0, 2.0]).tocsr()
+    x = np.array([[1.0], [1.0]])
+    r = oracle.eig.residual_norms(A, B, np.array([3.0]), x)
+    assert abs(r[0] - 0.272165526975909) <= 1e-15
+    # theta < 0 and a second column: A = [[4, 1], [1, 3]], B = I, x = (1, 0),
+    # theta = -2: (A + 2I) x = (6, 1), norm sqrt(37); |theta| ||x||_B = 2
+    A2 = sp.csr_matrix(np.array([[4.0, 1.0], [1.0, 3.0]]))
+    X2 = np.array([[1.0, 1.0], [0.0, 1.0]])
+    r2 = oracle.eig.residual_norms(A2, sp.identity(2, format="csr"), np.array([-2.0, 1.0]), X2)
+    # column 2: theta = 1, (A - I)(1, 1) = (4, 3), norm 5; ||x||_B = sqrt(2)
+    assert abs(r2[0] - np.sqrt(37.0) / 2.0) <= 1e-14
+    assert abs(r2[1] - 5.0 / np.sqrt(2.0)) <= 1e-14
+
+
+def test_jacobi_uses_the_shifted_diagonal_hand_worked():
+    """z = r / diag(A - sigma B): A = [[2, 1], [1, 4]], B = I, sigma = 1 + i.
+
+    diag(A - sigma B) = (1 - i, 3 - i); r = (1, 1) gives by hand
+    z = (1 / (1 - i), 1 / (3 - i)) = (0.5 + 0.5i, 0.3 + 0.1i); the off-diagonal
+    entries of A take no part.
+    """
+    A = sp.csr_matrix(np.array([[2.0, 1.0], [1.0, 4.0]]))
+    pc = oracle.gcr.jacobi(A, sp.identity(2, format="csr"), 1.0 + 1.0j)
+    z = pc(np.array([1.0 + 0j, 1.0 + 0j]))
+    assert np.allclose(z, [0.5 + 0.5j, 0.3 + 0.1j], rtol=0, atol=1e-15)
+    # B enters through its diagonal: B = diag(2, 0.5), sigma = 2i:
+    # diag = (2 - 4i, 4 - i); r = (2 - 4i, 0) -> z = (1, 0)
+    pc2 = oracle.gcr.jacobi(A, sp.diags([2.0, 0.5]).tocsr(), 2.0j)
+    z2 = pc2(np.array([2.0 - 4.0j, 0.0]))
+    assert np.allclose(z2, [1.0, 0.0], rtol=0, atol=1e-15)
+
+
+def test_jacobi_gcr_solves_a_diagonal_pencil_in_one_step():
+    """With a diagonal pencil the Jacobi-preconditioned operator is the identity,
+    so right-preconditioned GCR reaches the exact solution y_i = f_i /
+    (a_i - sigma b_i) in exactly one step (any other diagonal would need more)."""
+    a = np.array([1.0, 3.0, 7.0, 20.0])
+    b = np.array([0.5, 1.0, 2.0, 1.5])
+    sigma = 2.0 + 1.5j
+    A, B = sp.diags(a).tocsr(), sp.diags(b).tocsr()
+    f = np.array([1.0, -2.0, 0.5, 4.0]).reshape(-1, 1)
+    Y, its = oracle.gcr.shifted_solve_gcr(A, B, sigma, f, restart=30, tol=1e-14)
+    assert its[0] == 1
+    assert np.allclose(Y[:, 0], f[:, 0] / (a - sigma * b), rtol=1e-14, atol=0)

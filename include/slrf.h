@@ -280,6 +280,23 @@ slrf_status slrf_shifted_spmm(slrf_handle h, int32_t nsys, const int32_t* pole, 
                               const void* Z, void* Q, double* ms_out);
 
 /*
+ * slrf_shifted_spmm_noalloc - slrf_shifted_spmm for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same sweep, bitwise the same Q, with
+ * the per-system pole table kept in a fixed library array of 65536 entries
+ * (1 MiB per GPU the library runs on, held until the process ends) instead of
+ * library workspace.  The call allocates no device memory; the caller passes
+ * Z and Q exactly as for slrf_shifted_spmm (no timing output).  Errors:
+ * SLRF_E_ARG when nsys rounded up to 16 exceeds 65536, for a bad pole index or
+ * null pointers.  Every call on one GPU shares that GPU's table, which keeps
+ * the last call's contents: calls that overlap on one GPU (other host threads,
+ * other streams) race and must be serialised by the caller.  Synchronises the
+ * stream before returning.
+ */
+slrf_status slrf_shifted_spmm_noalloc(slrf_handle h, int32_t nsys, const int32_t* pole,
+                                      int32_t precision, const void* Z, void* Q);
+
+/*
  * slrf_eig_grad - eigenvalue sensitivities for per-element parameters
  * (the differentiation form).  For B-normalised eigenpairs (lam_i, x_i) and a
  * loss gradient glam_i = dL/dlam_i:

@@ -1162,6 +1162,37 @@ slrf_status rr_rowmajor(slrf_ctx* h, int nc, double* Ur, int nl, const double* X
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Allocation-free sweep: a per-device scratch array for the pole table of
+// slrf_shifted_spmm_noalloc.  Host code never passes the array's name to a
+// kernel or a copy: its device address is looked up once per device (with that
+// device current, at the first slrf_setup on it) and that address is used.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kNoallocMaxSys = 65536;  // systems per call (a 1 MiB pole table)
+constexpr int kNoallocMaxDev = 64;
+
+__device__ __align__(256) double2 scratch[kNoallocMaxSys];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kNoallocMaxDev] = {};
+
+// Resolve (once) the address of this device's copy of `scratch`; the device
+// must be current.  Returns nullptr on failure.
+void* scratch_address(int device) {
+  if (device < 0 || device >= kNoallocMaxDev) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
+
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1304,6 +1335,8 @@ slrf_status slrf_setup(slrf_handle* out, const slrf_csr* A, const slrf_csr* B, d
     return bad(SLRF_E_NOGPU, "hipGetDeviceProperties failed");
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return bad(SLRF_E_NOGPU, std::string("library built for gfx950, device is ") + prop.gcnArchName);
+  if (!scratch_address(h->device))
+    return bad(SLRF_E_HIP, "address of the sweep scratch array could not be resolved");
   h->stream = static_cast<hipStream_t>(stream);
   for (int j = 0; j < npoles; ++j) {
     if (!(poles[j].im > 0.0)) return bad(SLRF_E_ARG, "poles must lie in the upper half plane");
@@ -1767,6 +1800,43 @@ slrf_status slrf_shifted_spmm(slrf_handle h, int32_t nsys, const int32_t* pole, 
   } else {
     HIPCHK(hipStreamSynchronize(s));
   }
+  return SLRF_OK;
+}
+
+slrf_status slrf_shifted_spmm_noalloc(slrf_handle h, int32_t nsys, const int32_t* pole,
+                                      int32_t precision, const void* Z, void* Q) {
+  if (!h) return SLRF_E_ARG;
+  if (nsys < 1 || !pole || !Z || !Q) return fail(h, SLRF_E_ARG, "bad shifted_spmm arguments");
+  if (precision != SLRF_PREC_FP64 && precision != SLRF_PREC_MIXED)
+    return fail(h, SLRF_E_ARG, "bad precision");
+  const int C = (nsys + kPanel - 1) / kPanel * kPanel;
+  if (C > kNoallocMaxSys)
+    return fail(h, SLRF_E_ARG, "slrf_shifted_spmm_noalloc: nsys rounded up to 16 exceeds the "
+                               "65536 systems of the scratch pole table");
+  for (int i = 0; i < nsys; ++i)
+    if (pole[i] < 0 || pole[i] >= h->N) return fail(h, SLRF_E_ARG, "pole index out of range");
+  double2* sig = static_cast<double2*>(scratch_address(h->device));
+  if (!sig) return fail(h, SLRF_E_HIP, "sweep scratch array not resolved on this device");
+  hipStream_t s = h->stream;
+  // Fill the pole table (padding systems get sigma = 0, as in slrf_shifted_spmm)
+  // through a fixed host staging array: each chunk's copy is ordered on the
+  // stream after earlier work that may still read the table, and completes
+  // before the array is refilled.
+  constexpr int kChunk = 1024;
+  double2 stage[kChunk];
+  for (int b = 0; b < C; b += kChunk) {
+    const int cnt = std::min(kChunk, C - b);
+    for (int i = 0; i < cnt; ++i)
+      stage[i] = b + i < nsys ? h->poles[pole[b + i]] : make_double2(0.0, 0.0);
+    HIPCHK(hipMemcpyAsync(sig + b, stage, sizeof(double2) * cnt, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  const PanelGrid g = make_grid(h->P.n, C, C, 2);
+  if (precision == SLRF_PREC_FP64)
+    HIPCHK(launch_spmm_panel<double>(h->P, g, sig, Z, Q, s));
+  else
+    HIPCHK(launch_spmm_panel<float>(h->P, g, sig, Z, Q, s));
+  HIPCHK(hipStreamSynchronize(s));
   return SLRF_OK;
 }
 

@@ -88,6 +88,8 @@ SIGNATURES = {
                              C.c_void_p, C.POINTER(C.c_int32), C.POINTER(SolveStats)]),
     "slrf_shifted_spmm": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_int32,
                                     C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "slrf_shifted_spmm_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
+                                            C.c_int32, C.c_void_p, C.c_void_p]),
     "slrf_get_n": (C.c_int32, [C.c_void_p]),
     "slrf_get_row_order": (C.c_int, [C.c_void_p, C.c_void_p]),
     "slrf_eig_grad": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,

@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-eigen", action="store_true",
+                    help="skip the time-to-all-eigenpairs runs (Algorithm 2, both precisions)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 2 GiB device copy (counter scale reference)")
     ap.add_argument("--m", type=int, default=64, help="Q1 nodes per direction (64 = metric)")
@@ -61,32 +63,137 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(p, gamma, poles, V, tol):
-    """Oracle GCR(30) + Jacobi in FP64 on a bounded sample of the same workload."""
+def _oracle_gcr_worker(args):
+    """One oracle GCR(30)+Jacobi solve at full size in a fresh process (no GPU)."""
+    m, L, j, col, tol = args
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     import oracle
+    import slrf_inputs as si
 
+    c = si.config_q1_3d(m=m, L=L)
+    p = c["pencil"]
     A, B = p.A(), p.B()
-    c = 0
-    js = (1, 3, 5, 7)  # four of the eight poles of column 1
-    F = B @ V[:, c:c + 1]
-    its_all, rels = [], []
+    poles, _ = si.slrf_poles(c["gamma"], c["npoles"])
+    V = si.start_block(p.n, L, c["seed"])
+    F = B @ V[:, col:col + 1]
     with threadpool_limits(limits=1):
-        t = time.time()
-        for j in js:
-            Y, its = oracle.gcr.shifted_solve_gcr(A, B, poles[j], F, restart=30, tol=tol,
-                                                  precond="jacobi")
-            M = (A - poles[j] * B).tocsr()
-            its_all.append(int(its[0]))
-            rels.append(float(np.linalg.norm(F[:, 0] - M @ Y[:, 0]) / np.linalg.norm(F[:, 0])))
-        dt = time.time() - t
-    return {"value": len(js) / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"{len(js)} of {V.shape[1] * len(poles)} pole x RHS systems (poles "
-                       f"{[j + 1 for j in js]} of {len(poles)}, column {c + 1}) at full n={p.n}: "
-                       f"oracle GCR(30)+Jacobi FP64, single thread, iterations {its_all}, "
-                       f"{dt:.1f} s, max rel resid {max(rels):.1e}")}
+        t = time.perf_counter()
+        Y, its = oracle.gcr.shifted_solve_gcr(A, B, poles[j], F, restart=30, tol=tol,
+                                              precond="jacobi")
+        dt = time.perf_counter() - t
+    M = (A - poles[j] * B).tocsr()
+    rel = float(np.linalg.norm(F[:, 0] - M @ Y[:, 0]) / np.linalg.norm(F[:, 0]))
+    return dt, int(its[0]), rel
+
+
+def cpu_baseline(m, L, tol):
+    """The oracle on the host cores, on a bounded sample of the same workload.
+
+    * all cores: the 8 pole systems of one column at full size, oracle GCR(30) +
+      Jacobi in FP64, one process per system (up to the cores available), one
+      BLAS thread each; value = systems / wall time of the solves;
+    * one core: two of those systems solved one after the other in this
+      process, uncontended;
+    * exact LU (the oracle's filter): factorisation and solve timed apart at the
+      largest size that stays within seconds (m = 24, n = 13,824); at full size
+      the sparse LU does not fit a bounded run.
+    Runs before the GPU is touched (fresh worker processes)."""
+    import multiprocessing as mp
+
+    import numpy as np
+    import scipy.sparse.linalg as spla
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    import oracle
+    import slrf_inputs as si
+
+    cores = len(os.sched_getaffinity(0))
+    blas = sorted({f"{d.get('internal_api')}:{d.get('num_threads')}" for d in threadpool_info()})
+    npole = 8
+    nproc = max(1, min(npole, cores, 16))
+    col = 0
+    # one core, uncontended: two of the column's systems in this process
+    one = [_oracle_gcr_worker((m, L, j, col, tol)) for j in (1, 6)]
+    print(f"cpu baseline: one core {2 / sum(r[0] for r in one):.3f} solves/s", file=sys.stderr,
+          flush=True)
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(nproc) as pool:
+        res = pool.map(_oracle_gcr_worker, [(m, L, j, col, tol) for j in range(npole)])
+    wall_all = time.perf_counter() - t0
+    print(f"cpu baseline: {nproc} processes {npole / max(r[0] for r in res):.3f} solves/s",
+          file=sys.stderr, flush=True)
+    solve_times = [r[0] for r in res]
+    # the parallel rate counts the solves only: the slowest process's solve time
+    wall_solves = max(solve_times)
+    # exact LU at a reduced size: factor once per pole, solve a block of 16 RHS
+    pm = si.q1_kron_pencil(24, 3)
+    A, B = pm.A(), pm.B()
+    g24, _ = si.q1_gamma_nev(24, 3, 100)
+    poles24, _ = si.slrf_poles(g24, npole)
+    F = (B @ si.start_block(pm.n, 16, 3)).astype(np.complex128)
+    with threadpool_limits(limits=1):
+        t = time.perf_counter()
+        lu = spla.splu(oracle.filter.shifted_matrix(A, B, poles24[0]), permc_spec="MMD_AT_PLUS_A")
+        t_fact = time.perf_counter() - t
+        t = time.perf_counter()
+        lu.solve(F)
+        t_solve = time.perf_counter() - t
+    return {"value": npole / wall_solves, "unit": "solves/s", "cores": nproc, "kind": "oracle",
+            "sample": (f"the {npole} pole systems of column {col + 1} at full n (m={m}): oracle "
+                       f"GCR(30)+Jacobi FP64 to rel resid {tol:g}, one process and one BLAS "
+                       f"thread per system, {nproc} processes on {cores} affinity cores; "
+                       f"iterations {[r[1] for r in res]}, max rel resid "
+                       f"{max(r[2] for r in res):.1e}"),
+            "affinity_cores": cores, "blas_threads": blas,
+            "one_core_solves_per_s": 2 / sum(r[0] for r in one),
+            "one_core_sample": f"poles 2 and 7 of column {col + 1}, one process, iterations "
+                               f"{[r[1] for r in one]}",
+            "solve_seconds_all_cores": solve_times, "wall_s_incl_process_start": wall_all,
+            "exact_lu_reduced": {"m": 24, "n": pm.n, "nnz_LU": int(lu.L.nnz + lu.U.nnz),
+                                 "factor_s_per_pole": t_fact,
+                                 "solve_s_per_pole_rhs": t_solve / 16.0,
+                                 "threads": 1}}
+
+
+def eigen_runs(P, torch, p, gamma, poles, weights, nev, V1d, restart, lam_exact):
+    """Time to all NEV eigenpairs in (0, gamma] (Algorithm 2: locking and warm
+    start, the benchmark's filter options) per precision, with the largest
+    relative eigenvalue error against the closed form and Ritz residuals of
+    sampled pairs recomputed on the host."""
+    import numpy as np
+
+    import oracle
+
+    out = {}
+    A, B = p.A(), p.B()
+    for name, prec in (("mixed", P.SLRF_PREC_MIXED), ("fp64", P.SLRF_PREC_FP64)):
+        opt = P.default_options(precision=prec, precond=P.SLRF_PC_AMG, restart=restart,
+                                tol_lin=1e-8, lock=1, warm_start=1)
+        h = P.Handle.from_pencil(p, gamma, poles, weights, opt)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        th, X, nconv, st = h.slrf_solve(nev, V1d, allow_noconv=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        h.close()
+        th = th.cpu().numpy()
+        ok = nconv == nev
+        err = float(np.max(np.abs(th - lam_exact[:nev]) / lam_exact[:nev])) if ok else None
+        idx = np.unique(np.linspace(0, max(nconv - 1, 0), 6).astype(int)) if nconv else []
+        res = (oracle.eig.residual_norms(A, B, th[idx], X[:, idx].cpu().numpy()).max()
+               if nconv else None)
+        out[name] = {"seconds": dt, "nconv": nconv, "outer_iters": st["outer_iters"],
+                     "inner_iters": st["inner_iters"], "max_rel_eig_err": err,
+                     "sampled_max_ritz_resid": None if res is None else float(res)}
+        print(f"eigen {name}: {dt:.2f} s to {nconv} pairs, err {err}", file=sys.stderr,
+              flush=True)
+    out["algorithm"] = "Algorithm 2 (locking, warm start), tol_lin 1e-8, tol_eig 1e-8"
+    if out["mixed"]["seconds"] > 0:
+        out["speedup_mixed_vs_fp64"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
+    return out
+
 
 
 PROFILE = os.path.join(ROOT, "profiles", "spmm_sweep_halo_c64_q1_3d_m64.md")
@@ -393,9 +500,12 @@ def main():
     import paper_2510_17334_amd as P
     import slrf_inputs as si
 
+    tol = 1e-8
+    # the oracle's CPU baseline runs first, in fresh processes, before the GPU
+    # is touched
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.m, args.ncols, tol)
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    tol = 1e-8
     c = si.config_q1_3d(m=args.m, L=args.ncols)
     p = c["pencil"]
     poles, weights = si.slrf_poles(c["gamma"], c["npoles"])
@@ -470,8 +580,14 @@ def main():
         line["mixed_vs_fp64"] = {"U_rel_diff": float(d),
                                  "speedup": results["mixed"]["solves_per_s"] /
                                  results["fp64"]["solves_per_s"]}
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(p, c["gamma"], poles, V, tol)
+    if not args.no_eigen:
+        lam1 = si.q1_eigenvalues_1d(args.m)[:16]
+        lam_ex = np.sort((lam1[:, None, None] + lam1[None, :, None] +
+                          lam1[None, None, :]).ravel())
+        line["eigen"] = eigen_runs(P, torch, p, c["gamma"], poles, weights, c["nev"], Xd,
+                                  args.restart, lam_ex)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line, default=float))
 
 

@@ -103,7 +103,9 @@ typedef struct {
                           union format, 2 / 4 / 5 = CSR staged in LDS with
                           8 / 16 / 32 gathers in flight per lane, 3 = CSR
                           read directly, 6 = halo tiles (the gathered operand
-                          staged in LDS per tile of rows)                     */
+                          staged in LDS per tile of rows), 7 = wave-uniform
+                          groups of 4 rows (distinct columns of the group
+                          once, coefficients through scalar loads)           */
   int32_t reorder;     /* 1 (default): the library keeps a copy of the pencil
                           in a locality row order (nested aggregation of the
                           graph of A) so stencil gathers stay cache-resident;

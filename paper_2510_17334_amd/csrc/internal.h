@@ -58,6 +58,14 @@ struct DevPencil {
   const unsigned short* hx_lcol = nullptr;
   const float2* hx_ab32 = nullptr;   // (a, b) per entry
   const double2* hx_ab64 = nullptr;
+  // Row-group format of the wave-uniform sweep (ug_ngroups == 0: absent):
+  // groups of ug_R consecutive rows, per group the sorted distinct columns
+  // with the mask of the rows that use them and ug_R (a, b) pairs each
+  int ug_R = 0, ug_ngroups = 0;
+  const int* ug_gptr = nullptr;   // [ngroups + 1]
+  const int* ug_ent = nullptr;    // column | mask << 28
+  const float2* ug_ab32 = nullptr;
+  const double2* ug_ab64 = nullptr;
   // SpMM kernel choice per sweep precision (kSpmm*; chosen by the autotuner)
   int var32 = 0, var64 = 0;
 };
@@ -67,8 +75,8 @@ struct DevPencil {
 // staged in LDS) for plain sweeps, CSR staged in LDS (16 in flight) for the
 // sweeps fused with the CGS projections
 constexpr int kSpmmAuto = 0, kSpmmGroup = 1, kSpmmCsrLds = 2, kSpmmCsrDirect = 3,
-              kSpmmCsrLds16 = 4, kSpmmCsrLds32 = 5, kSpmmHalo = 6;
-constexpr int kSpmmVariants = 7;
+              kSpmmCsrLds16 = 4, kSpmmCsrLds32 = 5, kSpmmHalo = 6, kSpmmUGroup = 7;
+constexpr int kSpmmVariants = 8;
 // Largest halo of a tile (rows of 128 bytes in LDS; with the staged
 // coefficients of the tile four workgroups fit a CU) and the rows of a tile
 // (one 8-row slice per wave of a 256-thread workgroup: a tile is formed in one
@@ -123,6 +131,16 @@ struct SlotTables {
 };
 
 // ----- shifted block kernels (inner precision T = float or double) -----
+// Wave-uniform row-group sweep (variant 7): true when selected for T.
+template <typename T>
+bool ugroup_selected(const DevPencil& P);
+// Operator sweep on the row-group format: epi 0 Out = M Z, 1 (kEpiResidOp)
+// Out = Bin - M Z, 2 (kEpiJacobiOp) Out = Z + omega D^-1 (Bin - M Z); false
+// when the pencil's kernel choice for T is another variant (nothing launched).
+template <typename T>
+bool launch_ugroup(const DevPencil& P, const PanelGrid& g, const SlotTables& st, int epi,
+                   double omega, const void* Z, const void* Bin, void* Out, hipStream_t s,
+                   hipError_t& err);
 // True when the pencil's operator sweeps for T run on the halo-tile kernel
 // (then the GCR apply is a plain sweep followed by a separate projection pass).
 template <typename T>

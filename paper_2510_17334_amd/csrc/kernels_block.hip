@@ -2454,6 +2454,11 @@ hipError_t launch_apply_dots(const DevPencil& P, const PanelGrid& g, const SlotT
   auto Qb = static_cast<const C*>(Qbase);
   {
     hipError_t err = hipSuccess;
+    // wave-uniform row-group sweep, then the CGS projections as a separate pass
+    if (launch_ugroup<T>(P, g, st, kEpiApply, 0.0, Z, nullptr, Qk, s, err)) {
+      if (err != hipSuccess || k == 0) return err;
+      return launch_dots<T>(P, g, st, Qk, Qbase, vstride, k, part, s, false);
+    }
     // halo sweep, then the CGS projections as a separate streaming pass
     if (launch_halo<T>(P, g, st, kEpiApply, 0.0, Z, nullptr, Qk, s, err)) {
       if (err != hipSuccess || k == 0) return err;
@@ -2756,6 +2761,7 @@ hipError_t launch_lvl_op(const DevPencil& L, const PanelGrid& g, const SlotTable
   auto Oc = static_cast<C*>(Out);
   {
     hipError_t err = hipSuccess;
+    if (launch_ugroup<T>(L, g, st, epi, omega, X, Bin, Out, s, err)) return err;
     if (launch_halo<T>(L, g, st, epi, omega, X, Bin, Out, s, err)) return err;
     if (launch_grp<T>(L, g, st, epi, omega, X, Bin, Out, s, err)) return err;
   }

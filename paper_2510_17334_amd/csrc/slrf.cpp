@@ -27,6 +27,7 @@
 
 #include "amg_host.h"
 #include "halo_host.h"
+#include "ugroup_host.h"
 #include "dense_host.h"
 #include "internal.h"
 
@@ -107,6 +108,7 @@ struct slrf_ctx {
   int block = 0;  // dofs per node (0 = not yet determined)
   void* grp_mem[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   std::vector<void*> halo_mem;  // halo-tile format arrays
+  std::vector<void*> ug_mem;    // row-group sweep format arrays
   int* own_rp = nullptr;
   int* own_ci = nullptr;
   double* own_a = nullptr;
@@ -131,6 +133,8 @@ struct slrf_ctx {
     for (void* p : grp_mem)
       if (p) (void)hipFree(p);
     for (void* p : halo_mem)
+      if (p) (void)hipFree(p);
+    for (void* p : ug_mem)
       if (p) (void)hipFree(p);
     if (own_rp) (void)hipFree(own_rp);
     if (own_ci) (void)hipFree(own_ci);
@@ -271,7 +275,7 @@ slrf_status validate_options(slrf_ctx* h, const slrf_options& o) {
   if (o.amg_block > 1 && h->P.n > 0 && h->P.n % o.amg_block != 0)
     return fail(h, SLRF_E_ARG, "n must be a multiple of amg_block");
   if (o.spmm_variant < 0 || o.spmm_variant >= kSpmmVariants)
-    return fail(h, SLRF_E_ARG, "spmm_variant must be 0..6");
+    return fail(h, SLRF_E_ARG, "spmm_variant must be 0..7");
   return SLRF_OK;
 }
 
@@ -631,12 +635,13 @@ slrf_status autotune_spmm(slrf_ctx* h) {
   for (int i = 0; i < nsys; ++i) sig[i] = h->poles[i % h->N];
   HIPCHK(hipMemcpy(sg, sig.data(), sizeof(double2) * nsys, hipMemcpyHostToDevice));
   HIPCHK(hipMemsetAsync(Z, 0, bytes, h->stream));
-  const int vars[6] = {kSpmmGroup,    kSpmmCsrLds,    kSpmmCsrLds16,
-                       kSpmmCsrLds32, kSpmmCsrDirect, kSpmmHalo};
+  const int vars[7] = {kSpmmGroup,     kSpmmCsrLds, kSpmmCsrLds16, kSpmmCsrLds32,
+                       kSpmmCsrDirect, kSpmmHalo,   kSpmmUGroup};
   int best32 = kSpmmAuto, best64 = kSpmmAuto;
   float t32 = 1e30f, t64 = 1e30f;
   for (int v : vars) {
     if (v == kSpmmHalo && h->P.hx_ntile == 0) continue;
+    if (v == kSpmmUGroup && h->P.ug_ngroups == 0) continue;
     const float a = time_spmm_variant<float>(h, v, Z, Q, static_cast<double2*>(sg), nsys);
     if (a < t32) { t32 = a; best32 = v; }
     const float b = time_spmm_variant<double>(h, v, Z, Q, static_cast<double2*>(sg), nsys);
@@ -1510,6 +1515,30 @@ slrf_status slrf_setup(slrf_handle* out, const slrf_csr* A, const slrf_csr* B, d
       h->P.hx_lcol = static_cast<const unsigned short*>(h->halo_mem[5]);
       h->P.hx_ab32 = static_cast<const float2*>(h->halo_mem[6]);
       h->P.hx_ab64 = static_cast<const double2*>(h->halo_mem[7]);
+    }
+  }
+  {
+    // Row-group format of the wave-uniform sweep (groups of 4 rows, entries
+    // padded to multiples of 4) in the final row order.
+    HostUGroup ug;
+    if (build_ugroup(n, rp, cl, hA, hB, 4, 4, ug)) {
+      const size_t nent = ug.ent.size();
+      std::vector<float> ab32(ug.ab.begin(), ug.ab.end());
+      const size_t sz[4] = {sizeof(int) * ug.gptr.size(), sizeof(int) * nent,
+                            sizeof(float) * ab32.size(), sizeof(double) * ug.ab.size()};
+      const void* src[4] = {ug.gptr.data(), ug.ent.data(), ab32.data(), ug.ab.data()};
+      h->ug_mem.assign(4, nullptr);
+      for (int i = 0; i < 4; ++i) {
+        if (hipMalloc(&h->ug_mem[i], std::max<size_t>(sz[i], 4)) ||
+            hipMemcpy(h->ug_mem[i], src[i], sz[i], hipMemcpyHostToDevice))
+          return bad(SLRF_E_NOMEM, "allocation of the row-group sweep format failed");
+      }
+      h->P.ug_R = ug.R;
+      h->P.ug_ngroups = ug.ngroups;
+      h->P.ug_gptr = static_cast<const int*>(h->ug_mem[0]);
+      h->P.ug_ent = static_cast<const int*>(h->ug_mem[1]);
+      h->P.ug_ab32 = static_cast<const float2*>(h->ug_mem[2]);
+      h->P.ug_ab64 = static_cast<const double2*>(h->ug_mem[3]);
     }
   }
   // largest CSR slice of an aligned row block (LDS staging plan of the SpMM)

@@ -5,6 +5,7 @@
 //   host_driver <pencil.bin> <out.bin> block
 //   host_driver <pencil.bin> <out.bin> halo <hmax> <rows_cap>
 //   host_driver <pencil.bin> <out.bin> amg <block> <sigma_re> <sigma_im>
+//   host_driver <pencil.bin> <out.bin> ugroup <R> <U>
 // pencil.bin: int32 n, int32 nnz, int32 rp[n+1], int32 ci[nnz], f64 a[nnz], f64 b[nnz]
 #include <complex>
 #include <cstdint>
@@ -16,6 +17,7 @@
 
 #include "amg_host.h"
 #include "halo_host.h"
+#include "ugroup_host.h"
 
 using namespace slrf;
 
@@ -131,6 +133,13 @@ int main(int argc, char** argv) {
     put(X.lcol);
     put(X.ab);
     put(X.c);
+  } else if (mode == "ugroup") {
+    HostUGroup G;
+    const bool ok = build_ugroup(n, L.rp, L.ci, L.a, L.b, std::atoi(argv[4]), std::atoi(argv[5]), G);
+    put_i(ok ? 1 : 0);
+    put(G.gptr);
+    put(G.ent);
+    put(G.ab);
   } else {
     return 2;
   }

@@ -59,7 +59,8 @@ def cfg1():
 # ----------------------------------------------------------------------------
 # shifted SpMM (a3)
 # ----------------------------------------------------------------------------
-SPMM_VARIANTS = [0, 1, 2, 3, 4, 5, 6]  # auto, row-group, CSR-LDS u8, direct, u16, u32, halo
+SPMM_VARIANTS = [0, 1, 2, 3, 4, 5, 6, 7]  # auto, row-group, CSR-LDS u8, direct, u16, u32, halo,
+# wave-uniform row groups
 
 
 @pytest.mark.parametrize("variant", SPMM_VARIANTS)
@@ -207,7 +208,7 @@ def test_single_pole_solves_meet_tolerance(cfg1, prec, pcnd):
         assert np.linalg.norm(Y + err - Ylu) <= 1e-9 * np.linalg.norm(Ylu)
 
 
-@pytest.mark.parametrize("variant", [0, 6])
+@pytest.mark.parametrize("variant", [0, 6, 7])
 @pytest.mark.parametrize("pcnd", [P.SLRF_PC_JACOBI, P.SLRF_PC_AMG])
 @pytest.mark.parametrize("prec", [P.SLRF_PREC_FP64, P.SLRF_PREC_MIXED])
 def test_filter_matches_exact_lu_oracle(cfg1, prec, pcnd, variant):
@@ -225,7 +226,7 @@ def test_filter_matches_exact_lu_oracle(cfg1, prec, pcnd, variant):
     h.close()
 
 
-@pytest.mark.parametrize("variant", [0, 6])
+@pytest.mark.parametrize("variant", [0, 6, 7])
 def test_filter_bitwise_deterministic_and_pool_independent(cfg1, variant):
     p = cfg1["pencil"]
     X = _dev(cfg1["V1"][:, :10])

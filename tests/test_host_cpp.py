@@ -41,7 +41,8 @@ def driver(tmp_path_factory):
     d = tmp_path_factory.mktemp("host")
     exe = str(d / "host_driver")
     cmd = [gxx, "-O1", "-std=c++17", "-I", CSRC, os.path.join(HERE, "host_driver.cpp"),
-           os.path.join(CSRC, "amg_host.cpp"), os.path.join(CSRC, "halo_host.cpp"), "-o", exe]
+           os.path.join(CSRC, "amg_host.cpp"), os.path.join(CSRC, "halo_host.cpp"),
+           os.path.join(CSRC, "ugroup_host.cpp"), "-o", exe]
     subprocess.run(cmd, check=True, capture_output=True)
     return exe, d
 
@@ -266,3 +267,49 @@ def test_fine_image_of_prolongator(driver, which):
     for vals, ref in ((va, AP), (vb, BP), (vc, PP)):
         M = sp.csr_matrix((vals, (rows, cols)), shape=(n, nc))
         assert abs(M - ref).max() == 0.0
+
+
+@pytest.mark.parametrize("which,R,U", [("q1_3d", 4, 4), ("elasticity", 4, 4), ("q1_2d_ragged", 3, 2)])
+def test_row_group_format_reproduces_csr(driver, which, R, U):
+    """The wave-uniform sweep's row groups: per group the distinct columns in
+    increasing order with the mask of the rows that use them, every CSR entry
+    exactly once with its (a, b), counts padded to multiples of U with
+    coefficient-free entries, and 2 U look-ahead entries after the last group."""
+    exe, d = driver
+    if which == "q1_3d":
+        p = si.q1_kron_pencil(7, 3)
+    elif which == "elasticity":
+        p = si.hex_elasticity_pencil(3, np.exp(np.random.default_rng(3).normal(0, .5, 27)))
+    else:
+        p = si.q1_diffusion_pencil(8, 2, np.ones(81))  # n = 64: 22 groups, the last of 1 row
+    _write(p, d / "pu.bin")
+    subprocess.run([exe, str(d / "pu.bin"), str(d / "ou.bin"), "ugroup", str(R), str(U)],
+                   check=True)
+    rd = _Reader(d / "ou.bin")
+    ok = rd.i()
+    gptr, ent, ab = rd.arr(np.int32), rd.arr(np.int32), rd.arr(np.float64)
+    assert ok == 1
+    ng = (p.n + R - 1) // R
+    assert len(gptr) == ng + 1 and gptr[0] == 0
+    assert len(ent) == gptr[-1] + 2 * U and len(ab) == 2 * R * len(ent)
+    assert np.all(np.diff(gptr) % U == 0)
+    col = ent & ((1 << 28) - 1)
+    mask = (ent.astype(np.int64) >> 28) & 0xF
+    ab = ab.reshape(-1, R, 2)
+    A, B = p.A().tocsr(), p.B().tocsr()
+    for g in range(ng):
+        e0, e1 = gptr[g], gptr[g + 1]
+        real = mask[e0:e1] != 0
+        assert np.all(np.diff(col[e0:e1][real]) > 0)  # distinct, increasing
+        assert np.all(ab[e0:e1][~real] == 0.0)
+        for r in range(R):
+            row = g * R + r
+            hit = (mask[e0:e1] >> r) & 1 == 1
+            if row >= p.n:
+                assert not hit.any()
+                continue
+            lo, hi = A.indptr[row], A.indptr[row + 1]
+            assert np.array_equal(col[e0:e1][hit], A.indices[lo:hi])
+            assert np.array_equal(ab[e0:e1, r, 0][hit], A.data[lo:hi])
+            assert np.array_equal(ab[e0:e1, r, 1][hit], B.data[lo:hi])
+            assert np.all(ab[e0:e1, r][~hit] == 0.0)

@@ -171,7 +171,8 @@ def eigen_runs(P, torch, p, gamma, poles, weights, nev, V1d, restart, lam_exact)
     for name, prec in (("mixed", P.SLRF_PREC_MIXED), ("fp64", P.SLRF_PREC_FP64)):
         opt = P.default_options(precision=prec, precond=P.SLRF_PC_AMG, restart=restart,
                                 tol_lin=1e-8, lock=1, warm_start=1)
-        h = P.Handle.from_pencil(p, gamma, poles, weights, opt)
+        h = P.Handle.from_pencil(p, gamma, poles, weights, opt, max_cols=V1d.shape[1],
+                                 budget=0.6)
         torch.cuda.synchronize()
         t = time.perf_counter()
         th, X, nconv, st = h.slrf_solve(nev, V1d, allow_noconv=True)
@@ -251,7 +252,8 @@ def profiled_traffic():
 
 def run_precision(P, torch, p, gamma, poles, weights, Xd, prec, steps, warmup, tol, pc, restart):
     opt = P.default_options(precision=prec, tol_lin=tol, timing=1, precond=pc, restart=restart)
-    h = P.Handle.from_pencil(p, gamma, poles, weights, opt)
+    # workspace for every system resident (up to 60 % of the free device memory)
+    h = P.Handle.from_pencil(p, gamma, poles, weights, opt, max_cols=Xd.shape[1], budget=0.6)
     ncols = Xd.shape[1]
     last = None
 
@@ -374,13 +376,18 @@ def run_batch64(args):
     draws = si.batched_pencils(64, seed=1004)
     hs, Xs = [], []
     nsys = 0
-    for d, g in zip(draws, gold):
+    # 70 % of the free device memory shared out over the handles: each takes
+    # its full workspace (every system resident) while the share allows
+    left = 0.7 * torch.cuda.mem_get_info()[0]
+    for i, (d, g) in enumerate(zip(draws, gold)):
         p = d["pencil"]
         poles, weights = si.slrf_poles(g["gamma"])
         opt = P.default_options(precision=P.SLRF_PREC_MIXED, precond=P.SLRF_PC_AMG,
                                 restart=args.restart, tol_lin=1e-8, timing=0)
         hs.append(P.Handle.from_pencil(p, g["gamma"], poles, weights, opt,
-                                       stream=torch.cuda.Stream()))
+                                       stream=torch.cuda.Stream(), max_cols=d["L"],
+                                       budget=max(left / (len(draws) - i), 2.0)))
+        left -= hs[-1].workspace.numel()
         V = si.start_block(p.n, d["L"], d["seed"])
         Xs.append(torch.as_tensor(np.ascontiguousarray(V.T), device="cuda").t())
         nsys += d["L"] * len(poles)
@@ -456,7 +463,7 @@ def run_itmax(args):
         opt = P.default_options(precision=P.SLRF_PREC_MIXED, precond=P.SLRF_PC_JACOBI,
                                 restart=30, tol_lin=1e-10, lock=1, warm_start=1, max_outer=100,
                                 it_max_lin=itmax)
-        h = P.Handle.from_pencil(p, gold["gamma"], poles, weights, opt)
+        h = P.Handle.from_pencil(p, gold["gamma"], poles, weights, opt, max_cols=c["L"])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         theta, X, nconv, st = h.slrf_solve(c["count"], V1, allow_noconv=True)

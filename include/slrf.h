@@ -26,6 +26,8 @@
  *  - Status codes are returned; no exception crosses the ABI.  After an error
  *    slrf_last_error(h) returns a message (thread-unsafe per handle).
  *  - A handle must not be used from two host threads at once.
+ *  - All device memory is the caller's: inputs, outputs and the workspace
+ *    given to slrf_setup (sized by slrf_workspace_size).
  */
 #ifndef SLRF_H
 #define SLRF_H
@@ -114,8 +116,6 @@ typedef struct {
   double inner_rtol;   /* MIXED: a Krylov cycle stops once its residual fell by
                           this factor (then the FP64 residual is recomputed)    */
   double tol_eig;      /* Ritz pair converged when ||r||_2 < tol_eig             */
-  double mem_budget;   /* bytes of device workspace the planner may use; 0 = 60%
-                          of the free device memory at setup                   */
   int32_t amg_block;   /* dofs per node for the AMG aggregation and the row
                           order (node-major numbering: dof = block*node + c):
                           0 = detect (3 or 2 when every node's rows share one
@@ -179,23 +179,53 @@ const char* slrf_last_error(slrf_handle h);
 void slrf_default_options(slrf_options* opt);
 
 /*
+ * slrf_workspace_size - device workspace a handle needs (the caller allocates
+ * it, e.g. as a torch tensor, and passes it to slrf_setup).
+ * A, B: the CSR pencil as for slrf_setup (read and validated here: the host
+ * analysis of the pencil is kept and reused by the next slrf_setup on the same
+ * contents and options).  L: the widest block a call will be given (subspace
+ * width of slrf_solve, columns of slrf_filter / slrf_rayleigh_ritz); npoles:
+ * poles of the table; opt: the options of the handle (NULL = defaults).
+ * *full_bytes: the pencil's persistent data (permuted copy, sweep formats,
+ * FP32 values, AMG hierarchy when opt->precond is SLRF_PC_AMG) plus the
+ * buffers of a solve with all npoles * L shifted systems resident at once;
+ * *min_bytes (may be NULL): the same with one panel of 16 resident systems
+ * (a filter then streams the systems through the panel).  Any size in
+ * between works; more resident systems run faster.  Host memory only.
+ * Errors: SLRF_E_ARG (null pointers, L < 1, bad options, malformed CSR).
+ */
+slrf_status slrf_workspace_size(const slrf_csr* A, const slrf_csr* B, int32_t L, int32_t npoles,
+                                const slrf_options* opt, size_t* full_bytes, size_t* min_bytes);
+
+/*
  * slrf_setup - bind a pencil, an interval and a pole/weight table.
  * A, B: CSR descriptors (device arrays, caller-owned; must stay valid and
  *   unchanged until slrf_destroy).  Validated on the host (a copy is read).
  * gamma: upper end of the interval (0, gamma], > 0.
  * npoles, poles, weights: the N upper-half-plane poles (Im > 0) and weights,
  *   host arrays; conjugates are implied (Section 2).  1 <= N <= 64.
- * opt: options (NULL = defaults).  stream: hipStream_t (NULL = null stream).
- * Errors: SLRF_E_ARG for malformed input, SLRF_E_NOGPU, SLRF_E_HIP.
+ * opt: options (NULL = defaults).
+ * workspace, ws_bytes: caller-owned device memory (any alignment) that the
+ *   handle uses for all its device data until slrf_destroy: setup places the
+ *   pencil's persistent data at its start and every later call carves its
+ *   buffers from the rest and releases them on return.  The library
+ *   allocates no device memory of its own.  Size it with slrf_workspace_size.
+ * stream: hipStream_t (NULL = null stream).
+ * Errors: SLRF_E_ARG for malformed input, SLRF_E_NOMEM when the workspace
+ * cannot hold the persistent data, SLRF_E_NOGPU, SLRF_E_HIP.  A later call
+ * whose buffers do not fit the free part of the workspace returns
+ * SLRF_E_NOMEM with the missing byte count in slrf_last_error.
  */
 slrf_status slrf_setup(slrf_handle* h, const slrf_csr* A, const slrf_csr* B, double gamma,
                        int32_t npoles, const slrf_zd* poles, const slrf_zd* weights,
-                       const slrf_options* opt, void* stream);
+                       const slrf_options* opt, void* workspace, size_t ws_bytes, void* stream);
 
-/* Frees the handle and all library-owned device memory.  NULL is a no-op. */
+/* Frees the handle (host memory; the workspace stays the caller's).  NULL is a no-op. */
 void slrf_destroy(slrf_handle h);
 
-/* Replace options after setup (same validation as setup). */
+/* Replace options after setup (same validation as setup).  reorder and
+ * amg_block cannot change, and SLRF_PC_AMG needs a handle set up with it
+ * (the hierarchy lives in the workspace): SLRF_E_ARG otherwise. */
 slrf_status slrf_set_options(slrf_handle h, const slrf_options* opt);
 
 /*
@@ -250,10 +280,9 @@ slrf_status slrf_solve(slrf_handle h, int32_t nev, int32_t L, const double* V1, 
  * serially on the GPU).  Handles must be distinct.  Per-entry arguments are
  * arrays of length nh (theta_warm, stats, nconv_out may be NULL; their
  * entries may be NULL).  Results are identical to the single calls (each
- * handle's arithmetic does not depend on what runs beside it).  Each host
- * thread lends one workspace to the handles it runs in turn (a handle's own
- * cached workspace is left untouched), so the device memory of a batch is
- * bounded by the thread count, not by the number of pencils.  Returns
+ * handle's arithmetic does not depend on what runs beside it).  Each handle
+ * works in its own workspace (the batch's device memory is the sum of the
+ * workspaces the caller gave the handles).  Returns
  * SLRF_OK if every entry succeeded, else the status of the first failing
  * entry in index order (all entries are still attempted; a failing handle's
  * message is in its slrf_last_error).
@@ -307,16 +336,30 @@ slrf_status slrf_shifted_spmm_noalloc(slrf_handle h, int32_t nsys, const int32_t
  * dB_e = dB/dtheta_e acting on element e's dofs.
  * X: device n x k column-major; lam, glam: device double[k];
  * elem_dofs: device int32[nelem * ndof_e] row-major, -1 = constrained dof
- * (contributes zero); ndof_e in {4, 8, 24} (bilinear, trilinear, trilinear
- * elasticity); dA: device double, element e's ndof_e x ndof_e row-major matrix
- * at dA + e * dA_stride (stride 0: one matrix shared by all elements);
- * dB likewise or NULL (parameter does not enter B); grad: device double[nelem].
- * Synchronises the stream.
+ * (contributes zero), otherwise 0 <= dof < n; ndof_e in {4, 8, 24} (bilinear,
+ * trilinear, trilinear elasticity); dA: device double, element e's
+ * ndof_e x ndof_e row-major matrix at dA + e * dA_stride (stride 0: one matrix
+ * shared by all elements, else stride >= ndof_e^2), dA_len doubles readable at
+ * dA; dB, dB_stride, dB_len likewise, or dB NULL (parameter does not enter B);
+ * grad: device double[nelem].
+ * Errors: SLRF_E_ARG for a dof outside [-1, n), a stride below ndof_e^2 or an
+ * element matrix that would end past dA_len / dB_len (checked on the host,
+ * elem_dofs is copied there, before any kernel runs).  Synchronises the stream.
  */
 slrf_status slrf_eig_grad(slrf_handle h, int32_t k, const double* X, const double* lam,
                           const double* glam, int32_t nelem, int32_t ndof_e,
                           const int32_t* elem_dofs, const double* dA, int32_t dA_stride,
-                          const double* dB, int32_t dB_stride, double* grad);
+                          int64_t dA_len, const double* dB, int32_t dB_stride, int64_t dB_len,
+                          double* grad);
+
+/*
+ * slrf_host_check_grad_args - the host checks slrf_eig_grad makes on its
+ * element data, on host arrays (no GPU): elem_dofs host int32[nelem * ndof_e];
+ * has_dB nonzero when a dB array is passed.  Returns SLRF_OK or SLRF_E_ARG.
+ */
+int32_t slrf_host_check_grad_args(int32_t n, int32_t nelem, int32_t ndof_e,
+                                  const int32_t* elem_dofs, int32_t dA_stride, int64_t dA_len,
+                                  int32_t has_dB, int32_t dB_stride, int64_t dB_len);
 
 /* Problem size of a handle (-1 for NULL). */
 int32_t slrf_get_n(slrf_handle h);

@@ -86,6 +86,30 @@ def smallest_eigs(A, B, k):
     return np.sort(vals)
 
 
+def smallest_eigpairs(A, B, k):
+    """The k smallest eigenpairs (ascending) with B-orthonormal eigenvectors.
+
+    Same shift-invert Lanczos about 0 as ``smallest_eigs`` (dense LAPACK for
+    n <= 400), returning the eigenvectors as well; the vectors are
+    B-orthonormalised once more (eigenvectors of distinct eigenvalues are
+    B-orthogonal, Eq. (1); inside a cluster any B-orthonormal basis of the
+    invariant subspace is valid).
+    """
+    import scipy.sparse.linalg as spla
+
+    n = A.shape[0]
+    if n <= 400:
+        lam, X = dense_eigs(A, B)
+        return lam[:k], X[:, :k]
+    lam, X = spla.eigsh(A.tocsc(), k=k, M=B.tocsc(), sigma=0.0, which="LM", tol=1e-13)
+    o = np.argsort(lam)
+    lam, X = lam[o], X[:, o]
+    G = X.T @ (B @ X)
+    L = np.linalg.cholesky(0.5 * (G + G.T))
+    X = np.linalg.solve(L, X.T).T
+    return lam, X
+
+
 def _filter(A, B, poles, weights, V, inner, theta_warm=None):
     """Filtered block with exact (inner=None) or GCR inner solves.
 

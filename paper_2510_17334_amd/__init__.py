@@ -2,7 +2,8 @@
 
 The compute path is the HIP shared library ``libslrf.so`` (built by
 ``paper_2510_17334_amd.build``); this package only marshals arguments to its
-C ABI.  PyTorch provides device memory and the stream.  There is no CPU
+C ABI.  PyTorch provides all device memory (inputs, outputs and each handle's
+workspace) and the stream.  There is no CPU
 fallback: every entry point raises if the library is missing.
 """
 
@@ -22,4 +23,5 @@ from .slrf import (  # noqa: F401
     KERNEL_CLASSES,
     slrf_filter_batch,
     slrf_solve_batch,
+    workspace_size,
 )

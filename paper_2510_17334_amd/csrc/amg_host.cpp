@@ -431,13 +431,20 @@ bool amg_build(const HostLevel& fine, const std::vector<std::complex<double>>& p
     H.R.push_back(std::move(R));
     H.levels.push_back(std::move(C));
   }
-  // dense per-pole inverses of the coarsest operator
-  const HostLevel& Lc = H.levels.back();
-  const int nc = Lc.n;
+  const int nc = H.levels.back().n;
   if (nc > prm.dense_max) {
     err = "AMG coarsest level too large for a dense solve (" + std::to_string(nc) + ")";
     return false;
   }
+  H.nc = nc;
+  return amg_coarse_inverses(H, poles, err);
+}
+
+bool amg_coarse_inverses(AmgHierarchy& H, const std::vector<std::complex<double>>& poles,
+                         std::string& err) {
+  // dense per-pole inverses of the coarsest operator
+  const HostLevel& Lc = H.levels.back();
+  const int nc = Lc.n;
   H.nc = nc;
   H.coarse_inv.assign(poles.size() * (size_t)nc * nc, 0.0);
   for (size_t j = 0; j < poles.size(); ++j) {

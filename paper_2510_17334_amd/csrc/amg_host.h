@@ -47,8 +47,13 @@ void locality_order(const HostLevel& fine, std::vector<int>& order, int block = 
 // one column list made of whole node blocks, else 1.
 int detect_block(const HostLevel& L);
 
+// Builds the hierarchy and, for the given poles (none: skipped), the dense
+// inverses of the coarsest level operators A_c - sigma_j B_c.
 bool amg_build(const HostLevel& fine, const std::vector<std::complex<double>>& poles,
                const AmgParams& prm, AmgHierarchy& H, std::string& err);
+// (Re)computes H.coarse_inv for the given poles.
+bool amg_coarse_inverses(AmgHierarchy& H, const std::vector<std::complex<double>>& poles,
+                         std::string& err);
 
 // The fine-level images of the prolongator, A P and B P (n x P.m, one shared
 // row-sorted pattern), and P's values on that pattern (zero where P has no

@@ -18,6 +18,7 @@
 #include <numeric>
 #include <thread>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <cmath>
 #include <cstdio>
@@ -34,11 +35,6 @@
 using namespace slrf;
 
 namespace {
-
-struct DevBuf {
-  void* p = nullptr;
-  size_t cap = 0;
-};
 
 struct Timer {
   std::vector<hipEvent_t> pool;
@@ -76,14 +72,21 @@ struct DevAmg {
   int nc = 0;                           // coarsest size
   void* inv64 = nullptr;                // [pole][nc][nc] complex double
   void* inv32 = nullptr;                // [pole][nc][nc] complex float
-  std::vector<void*> allocs;
   std::vector<double> omega;            // Jacobi smoothing weight per level (all but the coarsest)
   std::vector<DevImage> img;            // img[l]: image (A_l P_l, B_l P_l) for the fused
                                         // up-step of level l (ntile 0 if absent)
   size_t nnz_all = 0;                   // level + transfer nonzeros (byte accounting)
-  ~DevAmg() {
-    for (void* p : allocs) (void)hipFree(p);
-  }
+};
+
+// The caller's workspace: persistent pencil data at the bottom (placed by
+// setup), then a stack of per-call buffers (each entry point releases what it
+// carved).  The library never allocates device memory itself.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;       // bytes
+  size_t top = 0;       // first free byte
+  size_t persist = 0;   // end of the persistent data
+  size_t short_by = 0;  // after a failed carve: bytes missing
 };
 
 struct slrf_ctx {
@@ -95,62 +98,24 @@ struct slrf_ctx {
   std::vector<double2> poles, weights;
   slrf_options opt{};
   std::string err;
-  size_t budget = 0;
-  // library-owned copies
+  // persistent arrays inside the workspace
   float* a32 = nullptr;
   float* b32 = nullptr;
   double* da = nullptr;
   double* db = nullptr;
   double2* d_w = nullptr;
-  // locality row order (library-owned permuted pencil); order[new] = old
+  // locality row order (the permuted pencil is kept in the workspace); order[new] = old
   int* order = nullptr;
   std::vector<int> h_order;
-  int block = 0;  // dofs per node (0 = not yet determined)
-  void* grp_mem[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  std::vector<void*> halo_mem;  // halo-tile format arrays
-  std::vector<void*> ug_mem;    // row-group sweep format arrays
-  int* own_rp = nullptr;
-  int* own_ci = nullptr;
-  double* own_a = nullptr;
-  double* own_b = nullptr;
-  // workspace
-  std::vector<DevBuf> bufs;
-  int* h_flags = nullptr;  // pinned host mirror of per-slot flags
-  size_t h_flags_cap = 0;
+  int block = 0;  // dofs per node
+  Arena ar;
+  std::vector<int> h_flags;  // host mirror of per-slot flags
   Timer timer;
   slrf_filter_stats* cur_stats = nullptr;
   DevAmg amg;
-
-  ~slrf_ctx() {
-    for (auto& b : bufs)
-      if (b.p) (void)hipFree(b.p);
-    if (a32) (void)hipFree(a32);
-    if (b32) (void)hipFree(b32);
-    if (da) (void)hipFree(da);
-    if (db) (void)hipFree(db);
-    if (d_w) (void)hipFree(d_w);
-    if (order) (void)hipFree(order);
-    for (void* p : grp_mem)
-      if (p) (void)hipFree(p);
-    for (void* p : halo_mem)
-      if (p) (void)hipFree(p);
-    for (void* p : ug_mem)
-      if (p) (void)hipFree(p);
-    if (own_rp) (void)hipFree(own_rp);
-    if (own_ci) (void)hipFree(own_ci);
-    if (own_a) (void)hipFree(own_a);
-    if (own_b) (void)hipFree(own_b);
-    if (h_flags) (void)hipHostFree(h_flags);
-  }
 };
 
 namespace {
-
-enum BufId {
-  B_XR, B_F, B_E, B_UR, B_FN2, B_YS, B_Y0, B_Y1, B_R0, B_R1, B_Z0, B_Z1, B_Q, B_P, B_PART, B_RED,
-  B_TAB_I, B_TAB_D, B_SCAL, B_SYS, B_AU, B_BU, B_V, B_AV, B_BV, B_GPART, B_SMALL, B_XL, B_BXL,
-  B_CST, B_TMP, B_SSP, B_AMGV, B_NBUF
-};
 
 #define HIPCHK(x)                                                     \
   do {                                                                \
@@ -165,49 +130,52 @@ slrf_status fail(slrf_ctx* h, slrf_status s, const std::string& msg) {
 
 slrf_status fail_hip(slrf_ctx* h, hipError_t e, const char* what, int line) {
   char buf[512];
-  std::snprintf(buf, sizeof(buf), "HIP error %d (%s) in %s at slrf.cpp:%d", (int)e,
-                hipGetErrorString(e), what, line);
+  if (e == hipErrorOutOfMemory && h && h->ar.short_by > 0) {
+    std::snprintf(buf, sizeof(buf),
+                  "workspace of %zu bytes too small: %s needs %zu more bytes (slrf.cpp:%d)",
+                  h->ar.cap, what, h->ar.short_by, line);
+    h->ar.short_by = 0;
+  } else {
+    std::snprintf(buf, sizeof(buf), "HIP error %d (%s) in %s at slrf.cpp:%d", (int)e,
+                  hipGetErrorString(e), what, line);
+  }
   if (h) h->err = buf;
   return e == hipErrorOutOfMemory ? SLRF_E_NOMEM : SLRF_E_HIP;
 }
 
-hipError_t ensure(slrf_ctx* h, int id, size_t bytes, void** out) {
-  if ((int)h->bufs.size() < B_NBUF) h->bufs.resize(B_NBUF);
-  DevBuf& b = h->bufs[id];
-  if (bytes == 0) bytes = 256;
-  if (b.cap < bytes) {
-    if (b.p) {
-      hipError_t e = hipStreamSynchronize(h->stream);
-      if (e != hipSuccess) return e;
-      (void)hipFree(b.p);
-      b.p = nullptr;
-      b.cap = 0;
-    }
-    hipError_t e = hipMalloc(&b.p, bytes);
-    if (e != hipSuccess) return e;
-    b.cap = bytes;
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Carve `bytes` from the top of the workspace (256-byte aligned).
+hipError_t carve(slrf_ctx* h, size_t bytes, void** out) {
+  Arena& A = h->ar;
+  const size_t off = align_up(A.top);
+  const size_t need = align_up(std::max<size_t>(bytes, 1));
+  if (off + need > A.cap) {
+    A.short_by = off + need - A.cap;
+    *out = nullptr;
+    return hipErrorOutOfMemory;
   }
-  *out = b.p;
+  *out = A.base + off;
+  A.top = off + need;
   return hipSuccess;
 }
 
 template <typename P>
-hipError_t ensure_t(slrf_ctx* h, int id, size_t count, P** out) {
+hipError_t carve_t(slrf_ctx* h, size_t count, P** out) {
   void* p = nullptr;
-  hipError_t e = ensure(h, id, count * sizeof(P), &p);
+  hipError_t e = carve(h, count * sizeof(P), &p);
   *out = static_cast<P*>(p);
   return e;
 }
 
-hipError_t flags_host(slrf_ctx* h, size_t count) {
-  if (h->h_flags_cap >= count) return hipSuccess;
-  if (h->h_flags) (void)hipHostFree(h->h_flags);
-  h->h_flags = nullptr;
-  h->h_flags_cap = 0;
-  hipError_t e = hipHostMalloc((void**)&h->h_flags, count * sizeof(int), hipHostMallocDefault);
-  if (e == hipSuccess) h->h_flags_cap = count;
-  return e;
-}
+// Releases on scope exit everything carved after its construction.
+struct Frame {
+  slrf_ctx* h;
+  size_t top;
+  explicit Frame(slrf_ctx* hh) : h(hh), top(hh->ar.top) {}
+  ~Frame() { h->ar.top = top; }
+};
 
 // Kernel-class timing and byte accounting.
 struct Scope {
@@ -270,9 +238,8 @@ slrf_status validate_options(slrf_ctx* h, const slrf_options& o) {
   if (o.max_outer < 1) return fail(h, SLRF_E_ARG, "max_outer must be >= 1");
   if (o.max_slots < 0 || o.max_slots % kPanel != 0)
     return fail(h, SLRF_E_ARG, "max_slots must be a non-negative multiple of 16");
-  if (o.mem_budget < 0) return fail(h, SLRF_E_ARG, "mem_budget must be >= 0");
   if (o.amg_block < 0 || o.amg_block > 8) return fail(h, SLRF_E_ARG, "amg_block must be 0..8");
-  if (o.amg_block > 1 && h->P.n > 0 && h->P.n % o.amg_block != 0)
+  if (o.amg_block > 1 && h && h->P.n > 0 && h->P.n % o.amg_block != 0)
     return fail(h, SLRF_E_ARG, "n must be a multiple of amg_block");
   if (o.spmm_variant < 0 || o.spmm_variant >= kSpmmVariants)
     return fail(h, SLRF_E_ARG, "spmm_variant must be 0..7");
@@ -299,76 +266,383 @@ int nrb_for(int n) {
 // ---------------------------------------------------------------------------
 // AMG: host build (once per handle, first use) and the device V-cycle
 // ---------------------------------------------------------------------------
-template <typename V>
-hipError_t upload(slrf_ctx* h, const std::vector<V>& v, const V** out) {
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, std::max<size_t>(1, v.size()) * sizeof(V));
-  if (e != hipSuccess) return e;
-  h->amg.allocs.push_back(p);
-  if (!v.empty()) e = hipMemcpy(p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice);
-  *out = static_cast<const V*>(p);
-  return e;
-}
-
 int max_slice_of(const std::vector<int>& rp, int n, int sub) {
   int mx = 0;
   for (int r = 0; r < n; r += sub) mx = std::max(mx, rp[std::min(r + sub, n)] - rp[r]);
   return mx;
 }
 
-slrf_status build_amg(slrf_ctx* h) {
-  if (h->amg.ready) return SLRF_OK;
-  const int n = h->P.n, nnz = h->P.nnz;
-  HostLevel fine;
-  fine.n = n;
-  fine.rp.resize(n + 1);
-  fine.ci.resize(nnz);
-  fine.a.resize(nnz);
-  fine.b.resize(nnz);
-  HIPCHK(hipMemcpy(fine.rp.data(), h->P.rowptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(fine.ci.data(), h->P.col, sizeof(int) * nnz, hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(fine.a.data(), h->P.a, sizeof(double) * nnz, hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(fine.b.data(), h->P.b, sizeof(double) * nnz, hipMemcpyDeviceToHost));
-  std::vector<std::complex<double>> poles;
-  for (auto& p : h->poles) poles.emplace_back(p.x, p.y);
-  AmgParams prm;
-  prm.block = h->block > 0 ? h->block : (h->opt.amg_block > 0 ? h->opt.amg_block
-                                                               : detect_block(fine));
-  AmgHierarchy H;
-  std::string err;
-  if (!amg_build(fine, poles, prm, H, err)) return fail(h, SLRF_E_ARG, "AMG setup: " + err);
+// ---------------------------------------------------------------------------
+// Host analysis of a pencil (everything setup derives from A and B on the
+// host): validation, row order, the sweep formats and the AMG hierarchy.  The
+// same analysis sizes the workspace (slrf_workspace_size) and fills it
+// (slrf_setup); the last one is kept, keyed by a hash of the CSR contents and
+// the options it depends on, so that the pair costs one analysis.
+// ---------------------------------------------------------------------------
+struct HostImage {
+  bool ok = false;
+  int nc = 0;
+  HostHalo hx;
+};
+
+struct HostSetup {
+  int n = 0, nnz = 0, block = 1;
+  bool reorder = false;
+  std::vector<int> order;            // order[new] = old (reorder only)
+  std::vector<int> rp, ci;           // the pencil in its final row order
+  std::vector<double> a, b;
+  std::vector<int> gp, gc;           // row-group union format
+  std::vector<double> ga, gb;
+  int grp_ent = 0;
+  bool has_halo = false;
+  HostHalo hx;
+  bool has_ug = false;
+  HostUGroup ug;
+  int max64 = 0, max32 = 0;
+  bool has_amg = false;
+  AmgHierarchy H;                    // without the per-pole coarse inverses
+  std::vector<HostImage> img;        // img[l], l < levels - 1
+};
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t bytes) {
+  const unsigned char* c = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < bytes; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  return h;
+}
+
+std::mutex g_an_mu;
+uint64_t g_an_key = 0;
+std::shared_ptr<const HostSetup> g_an;
+
+// Reads and validates A and B (device CSR, shared pattern, sorted, diagonal
+// present) and computes the host analysis; nullptr with `err` set on failure.
+std::shared_ptr<const HostSetup> analyse(const slrf_csr* A, const slrf_csr* B,
+                                         const slrf_options& opt, std::string& err,
+                                         slrf_status& st) {
+  st = SLRF_E_ARG;
+  if (!A || !B) { err = "null argument"; return nullptr; }
+  if (A->n <= 0 || A->nnz <= 0 || A->n != B->n || A->nnz != B->nnz) {
+    err = "A and B must be non-empty with equal n and nnz";
+    return nullptr;
+  }
+  if (!A->rowptr || !A->col || !A->val || !B->rowptr || !B->col || !B->val) {
+    err = "null CSR array";
+    return nullptr;
+  }
+  const int n = A->n, nnz = A->nnz;
+  std::vector<int> rp(n + 1), cl(nnz), rp2(n + 1), cl2(nnz);
+  std::vector<double> av(nnz), bv(nnz);
+  if (hipMemcpy(rp.data(), A->rowptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost) ||
+      hipMemcpy(cl.data(), A->col, sizeof(int) * nnz, hipMemcpyDeviceToHost) ||
+      hipMemcpy(rp2.data(), B->rowptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost) ||
+      hipMemcpy(cl2.data(), B->col, sizeof(int) * nnz, hipMemcpyDeviceToHost) ||
+      hipMemcpy(av.data(), A->val, sizeof(double) * nnz, hipMemcpyDeviceToHost) ||
+      hipMemcpy(bv.data(), B->val, sizeof(double) * nnz, hipMemcpyDeviceToHost)) {
+    err = "CSR arrays are not readable device memory";
+    return nullptr;
+  }
+  if (rp[0] != 0 || rp[n] != nnz) { err = "rowptr[0] must be 0 and rowptr[n] nnz"; return nullptr; }
+  for (int i = 0; i < n; ++i) {
+    if (rp[i + 1] < rp[i]) { err = "rowptr must be nondecreasing"; return nullptr; }
+    bool diag = false;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+      if (cl[e] < 0 || cl[e] >= n) { err = "column index out of range"; return nullptr; }
+      if (e > rp[i] && cl[e] <= cl[e - 1]) {
+        err = "column indices must be strictly increasing within a row";
+        return nullptr;
+      }
+      diag |= cl[e] == i;
+    }
+    if (!diag) { err = "every row must store its diagonal entry"; return nullptr; }
+  }
+  if (rp != rp2 || cl != cl2) { err = "A and B must share one CSR pattern"; return nullptr; }
+  const bool amg = opt.precond == SLRF_PC_AMG;
+  uint64_t key = 1469598103934665603ull;
+  key = fnv1a(key, rp.data(), rp.size() * sizeof(int));
+  key = fnv1a(key, cl.data(), cl.size() * sizeof(int));
+  key = fnv1a(key, av.data(), av.size() * sizeof(double));
+  key = fnv1a(key, bv.data(), bv.size() * sizeof(double));
+  const int32_t kopt[4] = {opt.reorder, opt.amg_block, amg ? 1 : 0, n};
+  key = fnv1a(key, kopt, sizeof(kopt));
+  {
+    std::lock_guard<std::mutex> lk(g_an_mu);
+    if (g_an && g_an_key == key) {
+      st = SLRF_OK;
+      return g_an;
+    }
+  }
+  auto hs = std::make_shared<HostSetup>();
+  hs->n = n;
+  hs->nnz = nnz;
+  {
+    HostLevel L0;
+    L0.n = n;
+    L0.rp = rp;
+    L0.ci = cl;
+    hs->block = opt.amg_block > 0 ? opt.amg_block : detect_block(L0);
+  }
+  if (n % hs->block != 0) { err = "n must be a multiple of amg_block"; return nullptr; }
+  hs->reorder = opt.reorder != 0;
+  if (hs->reorder) {
+    // Locality order (nested aggregation of the graph of A): the pencil is
+    // kept permuted and the order applied at the boundary.
+    HostLevel L0;
+    L0.n = n;
+    L0.rp = rp;
+    L0.ci = cl;
+    L0.a = av;
+    locality_order(L0, hs->order, hs->block);
+    std::vector<int> inv(n);
+    for (int i = 0; i < n; ++i) inv[hs->order[i]] = i;
+    hs->rp.assign(n + 1, 0);
+    hs->ci.resize(nnz);
+    hs->a.resize(nnz);
+    hs->b.resize(nnz);
+    std::vector<std::pair<int, int>> row;
+    for (int i = 0; i < n; ++i) {
+      const int o = hs->order[i];
+      row.clear();
+      for (int e = rp[o]; e < rp[o + 1]; ++e) row.push_back({inv[cl[e]], e});
+      std::sort(row.begin(), row.end());
+      int k = hs->rp[i];
+      for (auto& pr : row) {
+        hs->ci[k] = pr.first;
+        hs->a[k] = av[pr.second];
+        hs->b[k] = bv[pr.second];
+        ++k;
+      }
+      hs->rp[i + 1] = k;
+    }
+  } else {
+    hs->rp = rp;
+    hs->ci = cl;
+    hs->a = av;
+    hs->b = bv;
+  }
+  {
+    // Row-group (union) format: groups of 4 consecutive rows, the union of
+    // their columns once per group and 4 coefficients of A and of B per entry.
+    const int R = 4, ng = (n + R - 1) / R;
+    hs->gp.assign(ng + 1, 0);
+    std::vector<int> u;
+    for (int gi = 0; gi < ng; ++gi) {
+      const int r0 = gi * R, r1 = std::min(r0 + R, n);
+      u.assign(hs->ci.begin() + hs->rp[r0], hs->ci.begin() + hs->rp[r1]);
+      std::sort(u.begin(), u.end());
+      u.erase(std::unique(u.begin(), u.end()), u.end());
+      const size_t base = hs->gc.size();
+      hs->gc.insert(hs->gc.end(), u.begin(), u.end());
+      hs->ga.resize(hs->gc.size() * R, 0.0);
+      hs->gb.resize(hs->gc.size() * R, 0.0);
+      for (int r = r0; r < r1; ++r)
+        for (int e = hs->rp[r]; e < hs->rp[r + 1]; ++e) {
+          const size_t pos =
+              base + (std::lower_bound(u.begin(), u.end(), hs->ci[e]) - u.begin());
+          hs->ga[pos * R + (r - r0)] = hs->a[e];
+          hs->gb[pos * R + (r - r0)] = hs->b[e];
+        }
+      hs->gp[gi + 1] = (int)hs->gc.size();
+    }
+    for (int g0 = 0; g0 < ng; g0 += 8)
+      hs->grp_ent = std::max(hs->grp_ent, hs->gp[std::min(g0 + 8, ng)] - hs->gp[g0]);
+  }
+  // halo tiles (absent when one 8-row slice references more columns than a
+  // tile holds) and the wave-uniform row groups
+  hs->has_halo = build_halo(n, hs->rp, hs->ci, hs->a, hs->b, kHaloMaxH, kHaloTileRows, hs->hx);
+  hs->has_ug = build_ugroup(n, hs->rp, hs->ci, hs->a, hs->b, 4, 4, hs->ug);
+  hs->max64 = max_slice_of(hs->rp, n, 64);
+  hs->max32 = max_slice_of(hs->rp, n, 32);
+  if (amg) {
+    HostLevel fine;
+    fine.n = n;
+    fine.rp = hs->rp;
+    fine.ci = hs->ci;
+    fine.a = hs->a;
+    fine.b = hs->b;
+    AmgParams prm;
+    prm.block = hs->block;
+    std::string aerr;
+    if (!amg_build(fine, {}, prm, hs->H, aerr)) {
+      err = "AMG setup: " + aerr;
+      return nullptr;
+    }
+    const int L = (int)hs->H.levels.size();
+    hs->img.assign(std::max(L - 1, 0), HostImage());
+    for (int l = 0; l + 1 < L; ++l) {
+      std::vector<int> irp, ici;
+      std::vector<double> iap, ibp, ipv;
+      const HostLevel& lvl = hs->H.levels[l];
+      HostImage& I = hs->img[l];
+      I.ok = fine_image(lvl, hs->H.P[l], irp, ici, iap, ibp, ipv) &&
+             build_halo(lvl.n, irp, ici, iap, ibp, kImgMaxH, kHaloTileRows, I.hx, &ipv);
+      I.nc = hs->H.P[l].m;
+    }
+    hs->has_amg = true;
+  }
+  std::lock_guard<std::mutex> lk(g_an_mu);
+  g_an_key = key;
+  g_an = hs;
+  st = SLRF_OK;
+  return g_an;
+}
+
+// Places the persistent device data of a pencil in the workspace, in a fixed
+// order: with `dry` it only counts the bytes (the same sequence, so the count
+// is exact); otherwise it carves and uploads and points the handle at it.
+struct Placer {
+  slrf_ctx* h;
+  bool dry;
+  size_t bytes = 0;
+  hipError_t room(size_t b, void** out) {
+    if (dry) {
+      bytes = align_up(bytes) + align_up(std::max<size_t>(b, 1));
+      *out = nullptr;
+      return hipSuccess;
+    }
+    return carve(h, b, out);
+  }
+  template <typename V>
+  hipError_t put(const std::vector<V>& v, const V** out) {
+    void* p = nullptr;
+    hipError_t e = room(v.size() * sizeof(V), &p);
+    if (e != hipSuccess || dry) {
+      *out = static_cast<const V*>(p);
+      return e;
+    }
+    if (!v.empty()) e = hipMemcpy(p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice);
+    *out = static_cast<const V*>(p);
+    return e;
+  }
+};
+
+template <typename V>
+std::vector<float> to_f32(const std::vector<V>& v) { return std::vector<float>(v.begin(), v.end()); }
+
+// The fine pencil: permuted copy, row-group / halo / row-group-sweep formats,
+// FP32 values, diagonals (filled by kernels afterwards), weights.
+hipError_t place_pencil(slrf_ctx* h, const HostSetup& hs, Placer& pl, const slrf_csr* A,
+                        const slrf_csr* B) {
+  hipError_t e;
+  DevPencil& P = h->P;
+  P.n = hs.n;
+  P.nnz = hs.nnz;
+  if (hs.reorder) {
+    const int* ord;
+    if ((e = pl.put(hs.order, &ord)) != hipSuccess) return e;
+    h->order = const_cast<int*>(ord);
+    if ((e = pl.put(hs.rp, &P.rowptr)) != hipSuccess) return e;
+    if ((e = pl.put(hs.ci, &P.col)) != hipSuccess) return e;
+    if ((e = pl.put(hs.a, &P.a)) != hipSuccess) return e;
+    if ((e = pl.put(hs.b, &P.b)) != hipSuccess) return e;
+  } else {
+    h->order = nullptr;
+    P.rowptr = A ? A->rowptr : nullptr;
+    P.col = A ? A->col : nullptr;
+    P.a = A ? A->val : nullptr;
+    P.b = B ? B->val : nullptr;
+  }
+  if ((e = pl.put(hs.gp, &P.gptr)) != hipSuccess) return e;
+  if ((e = pl.put(hs.gc, &P.gcol)) != hipSuccess) return e;
+  if ((e = pl.put(hs.ga, &P.gca)) != hipSuccess) return e;
+  if ((e = pl.put(hs.gb, &P.gcb)) != hipSuccess) return e;
+  if ((e = pl.put(pl.dry ? std::vector<float>(hs.ga.size()) : to_f32(hs.ga), &P.gca32)) != hipSuccess)
+    return e;
+  if ((e = pl.put(pl.dry ? std::vector<float>(hs.gb.size()) : to_f32(hs.gb), &P.gcb32)) != hipSuccess)
+    return e;
+  P.grp_lds_ent = hs.grp_ent;
+  if (hs.has_halo) {
+    const HostHalo& hx = hs.hx;
+    std::vector<float2> ab32;
+    std::vector<double2> ab64;
+    ab32.resize(hx.ab.size() / 2);
+    ab64.resize(hx.ab.size() / 2);
+    if (!pl.dry)
+      for (size_t i = 0; i < ab64.size(); ++i) {
+        ab64[i] = make_double2(hx.ab[2 * i], hx.ab[2 * i + 1]);
+        ab32[i] = make_float2((float)hx.ab[2 * i], (float)hx.ab[2 * i + 1]);
+      }
+    if ((e = pl.put(hx.trow, &P.hx_trow)) != hipSuccess) return e;
+    if ((e = pl.put(hx.hptr, &P.hx_hptr)) != hipSuccess) return e;
+    if ((e = pl.put(hx.halo, &P.hx_halo)) != hipSuccess) return e;
+    if ((e = pl.put(hx.sptr, &P.hx_sptr)) != hipSuccess) return e;
+    if ((e = pl.put(hx.slen, &P.hx_slen)) != hipSuccess) return e;
+    if ((e = pl.put(hx.lcol, &P.hx_lcol)) != hipSuccess) return e;
+    if ((e = pl.put(ab32, &P.hx_ab32)) != hipSuccess) return e;
+    if ((e = pl.put(ab64, &P.hx_ab64)) != hipSuccess) return e;
+    P.hx_ntile = hx.ntile;
+    P.hx_hmax = hx.hmax;
+    P.hx_emax = hx.emax;
+  }
+  if (hs.has_ug) {
+    const HostUGroup& ug = hs.ug;
+    std::vector<float2> ab32(ug.ab.size() / 2);
+    std::vector<double2> ab64(ug.ab.size() / 2);
+    if (!pl.dry)
+      for (size_t i = 0; i < ab64.size(); ++i) {
+        ab64[i] = make_double2(ug.ab[2 * i], ug.ab[2 * i + 1]);
+        ab32[i] = make_float2((float)ug.ab[2 * i], (float)ug.ab[2 * i + 1]);
+      }
+    if ((e = pl.put(ug.gptr, &P.ug_gptr)) != hipSuccess) return e;
+    if ((e = pl.put(ug.ent, &P.ug_ent)) != hipSuccess) return e;
+    if ((e = pl.put(ab32, &P.ug_ab32)) != hipSuccess) return e;
+    if ((e = pl.put(ab64, &P.ug_ab64)) != hipSuccess) return e;
+    P.ug_R = ug.R;
+    P.ug_ngroups = ug.ngroups;
+  }
+  P.max_nnz_sub64 = hs.max64;
+  P.max_nnz_sub32 = hs.max32;
+  void* v;
+  if ((e = pl.room(sizeof(float) * hs.nnz, &v)) != hipSuccess) return e;
+  h->a32 = static_cast<float*>(v);
+  if ((e = pl.room(sizeof(float) * hs.nnz, &v)) != hipSuccess) return e;
+  h->b32 = static_cast<float*>(v);
+  if ((e = pl.room(sizeof(double) * hs.n, &v)) != hipSuccess) return e;
+  h->da = static_cast<double*>(v);
+  if ((e = pl.room(sizeof(double) * hs.n, &v)) != hipSuccess) return e;
+  h->db = static_cast<double*>(v);
+  if ((e = pl.room(sizeof(double2) * 64, &v)) != hipSuccess) return e;  // pole weights
+  h->d_w = static_cast<double2*>(v);
+  P.a32 = h->a32;
+  P.b32 = h->b32;
+  P.da = h->da;
+  P.db = h->db;
+  return hipSuccess;
+}
+
+// The AMG hierarchy (levels >= 1, transfers, images) and, for `npoles` poles,
+// room for the coarsest-level inverses (filled by setup).
+hipError_t place_amg(slrf_ctx* h, const HostSetup& hs, Placer& pl, int npoles) {
+  hipError_t e;
   DevAmg& A = h->amg;
+  const AmgHierarchy& H = hs.H;
   const int L = (int)H.levels.size();
-  A.n.clear();
+  A = DevAmg();
   for (auto& lv : H.levels) A.n.push_back(lv.n);
   // smoothing weight 1.5 / rho(D^-1 A_l): omega * rho stays below 2 on every
   // pencil; on the 3D Q1 benchmark pencil it needs the fewest GCR iterations
   // of the weights 1.0 .. 1.95 over rho (4/3: 4 % more, 1.65: 5 % more, 1.8:
   // 35 % more, 1.95 does not converge)
-  A.omega.clear();
   for (double r : H.rho) A.omega.push_back(r > 0.0 ? 1.5 / r : 0.7);
-  A.nnz_all = 0;
   for (int l = 1; l < L; ++l) {
     const HostLevel& hl = H.levels[l];
     DevPencil d;
     d.n = hl.n;
     d.nnz = (int)hl.ci.size();
-    std::vector<float> a32(hl.a.begin(), hl.a.end()), b32(hl.b.begin(), hl.b.end());
     std::vector<double> da(hl.n, 0.0), db(hl.n, 0.0);
     for (int i = 0; i < hl.n; ++i)
-      for (int e = hl.rp[i]; e < hl.rp[i + 1]; ++e)
-        if (hl.ci[e] == i) {
-          da[i] = hl.a[e];
-          db[i] = hl.b[e];
+      for (int k = hl.rp[i]; k < hl.rp[i + 1]; ++k)
+        if (hl.ci[k] == i) {
+          da[i] = hl.a[k];
+          db[i] = hl.b[k];
         }
-    HIPCHK(upload(h, hl.rp, &d.rowptr));
-    HIPCHK(upload(h, hl.ci, &d.col));
-    HIPCHK(upload(h, hl.a, &d.a));
-    HIPCHK(upload(h, hl.b, &d.b));
-    HIPCHK(upload(h, a32, &d.a32));
-    HIPCHK(upload(h, b32, &d.b32));
-    HIPCHK(upload(h, da, &d.da));
-    HIPCHK(upload(h, db, &d.db));
+    if ((e = pl.put(hl.rp, &d.rowptr)) != hipSuccess) return e;
+    if ((e = pl.put(hl.ci, &d.col)) != hipSuccess) return e;
+    if ((e = pl.put(hl.a, &d.a)) != hipSuccess) return e;
+    if ((e = pl.put(hl.b, &d.b)) != hipSuccess) return e;
+    if ((e = pl.put(to_f32(hl.a), &d.a32)) != hipSuccess) return e;
+    if ((e = pl.put(to_f32(hl.b), &d.b32)) != hipSuccess) return e;
+    if ((e = pl.put(da, &d.da)) != hipSuccess) return e;
+    if ((e = pl.put(db, &d.db)) != hipSuccess) return e;
     d.max_nnz_sub64 = max_slice_of(hl.rp, hl.n, 64);
     d.max_nnz_sub32 = max_slice_of(hl.rp, hl.n, 32);
     A.lv.push_back(d);
@@ -379,17 +653,16 @@ slrf_status build_amg(slrf_ctx* h) {
     d.ncols = M.m;
     d.nnz = (int)M.ci.size();
     d.max_sub64 = max_slice_of(M.rp, M.n, 64);
-    std::vector<float> v32(M.v.begin(), M.v.end());
-    hipError_t e;
-    if ((e = upload(h, M.rp, &d.rowptr)) != hipSuccess) return e;
-    if ((e = upload(h, M.ci, &d.col)) != hipSuccess) return e;
-    if ((e = upload(h, M.v, &d.v)) != hipSuccess) return e;
-    return upload(h, v32, &d.v32);
+    hipError_t e2;
+    if ((e2 = pl.put(M.rp, &d.rowptr)) != hipSuccess) return e2;
+    if ((e2 = pl.put(M.ci, &d.col)) != hipSuccess) return e2;
+    if ((e2 = pl.put(M.v, &d.v)) != hipSuccess) return e2;
+    return pl.put(to_f32(M.v), &d.v32);
   };
   for (int l = 0; l + 1 < L; ++l) {
     DevTransfer P, R;
-    HIPCHK(up_tr(H.P[l], P));
-    HIPCHK(up_tr(H.R[l], R));
+    if ((e = up_tr(H.P[l], P)) != hipSuccess) return e;
+    if ((e = up_tr(H.R[l], R)) != hipSuccess) return e;
     A.P.push_back(P);
     A.R.push_back(R);
     A.nnz_all += P.nnz + R.nnz;
@@ -399,49 +672,45 @@ slrf_status build_amg(slrf_ctx* h) {
   // tile's coarse halo would exceed kImgMaxH rows)
   A.img.assign(L, DevImage());
   for (int l = 0; l + 1 < L; ++l) {
-    std::vector<int> irp, ici;
-    std::vector<double> iap, ibp, ipv;
-    HostHalo hx;
-    const HostLevel& lvl = l == 0 ? fine : H.levels[l];
-    if (fine_image(lvl, H.P[l], irp, ici, iap, ibp, ipv) &&
-        build_halo(lvl.n, irp, ici, iap, ibp, kImgMaxH, kHaloTileRows, hx, &ipv)) {
-      DevImage& I = A.img[l];
-      std::vector<float> ab32(hx.ab.begin(), hx.ab.end()), p32(hx.c.begin(), hx.c.end());
-      std::vector<double2> ab64(hx.ab.size() / 2);
-      for (size_t i = 0; i < ab64.size(); ++i) ab64[i] = make_double2(hx.ab[2 * i], hx.ab[2 * i + 1]);
-      std::vector<float2> ab32v(ab64.size());
-      for (size_t i = 0; i < ab64.size(); ++i) ab32v[i] = make_float2(ab32[2 * i], ab32[2 * i + 1]);
-      HIPCHK(upload(h, hx.trow, &I.trow));
-      HIPCHK(upload(h, hx.hptr, &I.hptr));
-      HIPCHK(upload(h, hx.halo, &I.halo));
-      HIPCHK(upload(h, hx.sptr, &I.sptr));
-      HIPCHK(upload(h, hx.lcol, &I.lcol));
-      HIPCHK(upload(h, ab32v, &I.ab32));
-      HIPCHK(upload(h, ab64, &I.ab64));
-      HIPCHK(upload(h, p32, &I.p32));
-      HIPCHK(upload(h, hx.c, &I.p64));
-      I.nc = H.P[l].m;
-      I.hmax = hx.hmax;
-      I.emax = hx.emax;
-      I.ntile = hx.ntile;
-      A.nnz_all += ici.size();
+    const HostImage& hi = hs.img[l];
+    if (!hi.ok) continue;
+    const HostHalo& hx = hi.hx;
+    DevImage& I = A.img[l];
+    std::vector<double2> ab64(hx.ab.size() / 2);
+    std::vector<float2> ab32(ab64.size());
+    for (size_t i = 0; i < ab64.size(); ++i) {
+      ab64[i] = make_double2(hx.ab[2 * i], hx.ab[2 * i + 1]);
+      ab32[i] = make_float2((float)hx.ab[2 * i], (float)hx.ab[2 * i + 1]);
     }
+    if ((e = pl.put(hx.trow, &I.trow)) != hipSuccess) return e;
+    if ((e = pl.put(hx.hptr, &I.hptr)) != hipSuccess) return e;
+    if ((e = pl.put(hx.halo, &I.halo)) != hipSuccess) return e;
+    if ((e = pl.put(hx.sptr, &I.sptr)) != hipSuccess) return e;
+    if ((e = pl.put(hx.lcol, &I.lcol)) != hipSuccess) return e;
+    if ((e = pl.put(ab32, &I.ab32)) != hipSuccess) return e;
+    if ((e = pl.put(ab64, &I.ab64)) != hipSuccess) return e;
+    if ((e = pl.put(to_f32(hx.c), &I.p32)) != hipSuccess) return e;
+    if ((e = pl.put(hx.c, &I.p64)) != hipSuccess) return e;
+    I.nc = hi.nc;
+    I.hmax = hx.hmax;
+    I.emax = hx.emax;
+    I.ntile = hx.ntile;
+    A.nnz_all += hx.lcol.size();
   }
-  A.nc = H.nc;
-  std::vector<double2> i64(H.coarse_inv.size());
-  std::vector<float2> i32(H.coarse_inv.size());
-  for (size_t i = 0; i < H.coarse_inv.size(); ++i) {
-    i64[i] = make_double2(H.coarse_inv[i].real(), H.coarse_inv[i].imag());
-    i32[i] = make_float2((float)H.coarse_inv[i].real(), (float)H.coarse_inv[i].imag());
-  }
-  const double2* p64;
-  const float2* p32;
-  HIPCHK(upload(h, i64, &p64));
-  HIPCHK(upload(h, i32, &p32));
-  A.inv64 = const_cast<double2*>(p64);
-  A.inv32 = const_cast<float2*>(p32);
-  A.ready = true;
-  return SLRF_OK;
+  A.nc = H.levels.back().n;
+  const size_t ninv = (size_t)npoles * A.nc * A.nc;
+  if ((e = pl.room(ninv * sizeof(double2), &A.inv64)) != hipSuccess) return e;
+  if ((e = pl.room(ninv * sizeof(float2), &A.inv32)) != hipSuccess) return e;
+  A.ready = !pl.dry;
+  return hipSuccess;
+}
+
+size_t persistent_bytes(const HostSetup& hs, int npoles) {
+  slrf_ctx tmp;
+  Placer pl{&tmp, true};
+  (void)place_pencil(&tmp, hs, pl, nullptr, nullptr);
+  if (hs.has_amg) (void)place_amg(&tmp, hs, pl, npoles);
+  return align_up(pl.bytes);
 }
 
 // Level vectors of the V-cycle for a pool of C slots.
@@ -451,18 +720,21 @@ struct AmgVecs {
   std::vector<void*> X, W, B, T;  // per level (index 0 unused)
 };
 
-size_t amg_vec_bytes(const DevAmg& A, int C, size_t sT) {
-  size_t b = 2 * (size_t)C * A.n[0] * sT;
-  for (size_t l = 1; l < A.n.size(); ++l) b += 4 * (size_t)C * A.n[l] * sT;
+// level sizes nlev (nlev[0] = fine)
+size_t amg_vec_bytes(const std::vector<int>& nlev, int C, size_t sT) {
+  if (nlev.empty()) return 0;
+  size_t b = 2 * (size_t)C * nlev[0] * sT;
+  for (size_t l = 1; l < nlev.size(); ++l) b += 4 * (size_t)C * nlev[l] * sT;
   return b;
 }
+size_t amg_vec_bytes(const DevAmg& A, int C, size_t sT) { return amg_vec_bytes(A.n, C, sT); }
 
 template <typename T>
 slrf_status amg_vectors(slrf_ctx* h, int C, AmgVecs& v) {
   const DevAmg& A = h->amg;
   const size_t sT = 2 * sizeof(T);
   char* base;
-  HIPCHK(ensure_t(h, B_AMGV, amg_vec_bytes(A, C, sT), &base));
+  HIPCHK(carve_t(h, amg_vec_bytes(A, C, sT), &base));
   size_t off = 0;
   auto take = [&](size_t rows) {
     void* p = base + off;
@@ -623,14 +895,19 @@ slrf_status autotune_spmm(slrf_ctx* h) {
       return SLRF_OK;
     }
   }
-  const int nsys = 256;
+  // a batch of up to 256 systems in each precision, carved from the free part
+  // of the workspace (fewer when it is small; the defaults are kept when not
+  // even one panel fits)
+  Frame fr(h);
+  const size_t avail = h->ar.cap > align_up(h->ar.top) ? h->ar.cap - align_up(h->ar.top) : 0;
+  const size_t per_sys = 2 * (size_t)n * 16 + 16 + 4 * kAlign / kPanel;
+  const int nsys = (int)std::min<size_t>(256, avail / per_sys / kPanel * kPanel);
+  if (nsys < kPanel) return SLRF_OK;
   void *Z = nullptr, *Q = nullptr, *sg = nullptr;
   const size_t bytes = (size_t)nsys * n * 16;
-  if (hipMalloc(&Z, bytes) || hipMalloc(&Q, bytes) || hipMalloc(&sg, sizeof(double2) * nsys)) {
-    if (Z) (void)hipFree(Z);
-    if (Q) (void)hipFree(Q);
-    return SLRF_OK;  // keep the defaults when memory is short
-  }
+  HIPCHK(carve(h, bytes, &Z));
+  HIPCHK(carve(h, bytes, &Q));
+  HIPCHK(carve(h, sizeof(double2) * nsys, &sg));
   std::vector<double2> sig(nsys);
   for (int i = 0; i < nsys; ++i) sig[i] = h->poles[i % h->N];
   HIPCHK(hipMemcpy(sg, sig.data(), sizeof(double2) * nsys, hipMemcpyHostToDevice));
@@ -648,9 +925,6 @@ slrf_status autotune_spmm(slrf_ctx* h) {
     if (b < t64) { t64 = b; best64 = v; }
   }
   (void)hipStreamSynchronize(h->stream);
-  (void)hipFree(Z);
-  (void)hipFree(Q);
-  (void)hipFree(sg);
   h->P.var32 = best32;
   h->P.var64 = best64;
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -658,32 +932,48 @@ slrf_status autotune_spmm(slrf_ctx* h) {
   return SLRF_OK;
 }
 
-// Workspace plan of one filter call.
-struct Plan {
-  int C;         // slots
-  size_t bytes;  // total device bytes
-};
+// Workspace of one filter call: a fixed part (blocks of the columns, the
+// per-system solution store, statistics) and a part per resident slot.  Both
+// include the alignment of every carve.
+size_t filter_fixed_bytes(int n, int nc, int N) {
+  const size_t S = (size_t)N * nc;
+  const size_t Spad = (S + kPanel - 1) / kPanel * kPanel;
+  return 4 * (size_t)n * nc * sizeof(double) + (nc + 1) * sizeof(double) +
+         Spad * n * 16 + (3 * S + 8) * sizeof(int) +
+         (2 * (size_t)colstat_chunks(n) * nc + 2) * sizeof(double) + 16 * kAlign;
+}
 
-template <typename T>
-Plan plan_filter(const slrf_ctx* h, int ncols) {
-  const size_t n = h->P.n;
-  const int m = h->opt.restart;
-  const int S = h->N * ncols;
-  const int Spad = (S + kPanel - 1) / kPanel * kPanel;
-  const size_t sT = 2 * sizeof(T);
+size_t filter_slot_bytes(int n, int m, size_t sT, const std::vector<int>& amg_levels) {
   const int ND = std::max(m, 2);
-  const size_t nrb = nrb_for((int)n);
-  const size_t fixed = 4 * n * ncols * sizeof(double) + (size_t)Spad * n * 16 + 64 * (size_t)S;
-  size_t per_slot = n * (2 * 16 + 4 * sT + 2 * (size_t)m * sT) + nrb * ND * 16 +
-                    (size_t)ND * 16 + 3 * (size_t)kMaxRestart * 16 + 64;
-  if (h->opt.precond == SLRF_PC_AMG && h->amg.ready) per_slot += amg_vec_bytes(h->amg, 1, sT);
-  int C = Spad;
-  if (h->opt.max_slots > 0) C = std::min(C, h->opt.max_slots);
-  if (fixed + (size_t)C * per_slot > h->budget) {
-    const size_t avail = h->budget > fixed ? h->budget - fixed : 0;
-    C = (int)std::min<size_t>((size_t)C, avail / per_slot) / kPanel * kPanel;
-  }
-  return Plan{C, fixed + (size_t)std::max(C, 0) * per_slot};
+  size_t b = (size_t)n * (2 * 16 + 4 * sT + 2 * (size_t)m * sT) +
+             (size_t)nrb_for(n) * ND * 16 + (size_t)ND * 16 + 6 * sizeof(int) +
+             3 * sizeof(double) +
+             ((size_t)5 * kMaxRestart + 1 + 2 * (size_t)kMaxRestart * kMaxRestart) * sizeof(double);
+  return b + amg_vec_bytes(amg_levels, 1, sT);
+}
+
+// Rayleigh-Ritz on nc columns against nl locked ones (rr_rowmajor's buffers
+// plus the entry points' row-major copies of U and of the locked block).
+size_t rr_bytes(int n, int nc, int nl) {
+  const size_t pq = std::max(nc, nl);
+  return (size_t)n * (6 * (size_t)nc + 2 * (size_t)nl) * sizeof(double) +
+         ((size_t)gram_chunks(n) * pq * pq + 16) * sizeof(double) +
+         (3 * pq * pq + 4 * pq + 16) * sizeof(double) +
+         (2 * (size_t)colstat_chunks(n) * nc + 2) * sizeof(double) + 16 * kAlign;
+}
+
+// Per-call workspace of slrf_solve with an L-column subspace (the largest
+// call: the subspace blocks, then the filter with C resident slots or the
+// Rayleigh-Ritz step), which also covers slrf_filter and slrf_rayleigh_ritz
+// on up to L columns.
+size_t call_bytes(int n, int L, int N, const slrf_options& o, const std::vector<int>& amg_levels,
+                  int C) {
+  const size_t sT = o.precision == SLRF_PREC_MIXED ? 8 : 16;
+  const size_t sub = ((size_t)n * 3 * L + 2 * (size_t)L + 16) * sizeof(double) + kAlign;
+  const size_t flt = filter_fixed_bytes(n, L, N) +
+                     (size_t)C * (filter_slot_bytes(n, o.restart, sT, amg_levels) +
+                                  16 * kAlign / kPanel);
+  return sub + std::max(flt, rr_bytes(n, L, L)) + 4 * kAlign;
 }
 
 // ---------------------------------------------------------------------------
@@ -697,10 +987,8 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
   const size_t sT = 2 * sizeof(T);
   const bool amg = h->opt.precond == SLRF_PC_AMG;
   const int pc = amg ? 2 : (h->opt.precond == SLRF_PC_JACOBI ? 1 : 0);
-  if (amg) {
-    const slrf_status bs = build_amg(h);
-    if (bs != SLRF_OK) return bs;
-  }
+  if (amg && !h->amg.ready)
+    return fail(h, SLRF_E_ARG, "the AMG preconditioner needs a handle set up with it");
   const bool warm = theta != nullptr;
   const bool mixed = std::is_same<T, float>::value;
   const double inner_rtol = mixed ? h->opt.inner_rtol : 0.0;
@@ -710,11 +998,27 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
   hipStream_t s = h->stream;
   const int ND = std::max(m, 2);
 
-  Plan plan = plan_filter<T>(h, nc);
-  if (plan.C < kPanel)
-    return fail(h, SLRF_E_NOMEM, "memory budget too small for one panel of 16 systems");
-  const int C = plan.C;
   const int Spad = (S + kPanel - 1) / kPanel * kPanel;
+  // resident slots: every system at once when the workspace holds them, else
+  // as many whole panels as fit (the pool then streams the systems through)
+  const size_t fixed = filter_fixed_bytes(n, nc, N);
+  const size_t slot = filter_slot_bytes(n, m, sT, amg ? h->amg.n : std::vector<int>()) +
+                      16 * kAlign / kPanel;
+  const size_t avail = h->ar.cap > align_up(h->ar.top) ? h->ar.cap - align_up(h->ar.top) : 0;
+  int C = Spad;
+  if (h->opt.max_slots > 0) C = std::min(C, h->opt.max_slots);
+  if (fixed + (size_t)C * slot > avail) {
+    const size_t fit = avail > fixed ? (avail - fixed) / slot : 0;
+    C = (int)std::min<size_t>((size_t)C, fit) / kPanel * kPanel;
+  }
+  if (C < kPanel) {
+    char buf[256];
+    std::snprintf(buf, sizeof(buf),
+                  "workspace too small: a filter of %d columns needs %zu bytes for one panel "
+                  "of 16 systems, %zu are free",
+                  nc, fixed + kPanel * slot, avail);
+    return fail(h, SLRF_E_NOMEM, buf);
+  }
   const int nrb = nrb_for(n);
 
   AmgVecs av;
@@ -728,37 +1032,37 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
   double *Xr, *F, *E = nullptr, *Ur, *fn2;
   double2 *Ys, *Ya, *Yb, *part, *red;
   void *Ra, *Rb, *Za, *Zb, *Q, *Pb;
-  HIPCHK(ensure_t(h, B_XR, (size_t)n * nc, &Xr));
-  HIPCHK(ensure_t(h, B_F, (size_t)n * nc, &F));
-  if (warm) HIPCHK(ensure_t(h, B_E, (size_t)n * nc, &E));
-  HIPCHK(ensure_t(h, B_UR, (size_t)n * nc, &Ur));
-  HIPCHK(ensure_t(h, B_FN2, (size_t)nc + 1, &fn2));
-  HIPCHK(ensure_t(h, B_YS, (size_t)Spad * n, &Ys));
-  HIPCHK(ensure_t(h, B_Y0, (size_t)C * n, &Ya));
-  HIPCHK(ensure_t(h, B_Y1, (size_t)C * n, &Yb));
-  HIPCHK(ensure(h, B_R0, (size_t)C * n * sT, &Ra));
-  HIPCHK(ensure(h, B_R1, (size_t)C * n * sT, &Rb));
-  HIPCHK(ensure(h, B_Z0, (size_t)C * n * sT, &Za));
-  HIPCHK(ensure(h, B_Z1, (size_t)C * n * sT, &Zb));
-  HIPCHK(ensure(h, B_Q, (size_t)m * C * n * sT, &Q));
-  HIPCHK(ensure(h, B_P, (size_t)m * C * n * sT, &Pb));
-  HIPCHK(ensure_t(h, B_PART, (size_t)nrb * ND * C, &part));
-  HIPCHK(ensure_t(h, B_RED, (size_t)ND * C, &red));
+  HIPCHK(carve_t(h, (size_t)n * nc, &Xr));
+  HIPCHK(carve_t(h, (size_t)n * nc, &F));
+  if (warm) HIPCHK(carve_t(h, (size_t)n * nc, &E));
+  HIPCHK(carve_t(h, (size_t)n * nc, &Ur));
+  HIPCHK(carve_t(h, (size_t)nc + 1, &fn2));
+  HIPCHK(carve_t(h, (size_t)Spad * n, &Ys));
+  HIPCHK(carve_t(h, (size_t)C * n, &Ya));
+  HIPCHK(carve_t(h, (size_t)C * n, &Yb));
+  HIPCHK(carve(h, (size_t)C * n * sT, &Ra));
+  HIPCHK(carve(h, (size_t)C * n * sT, &Rb));
+  HIPCHK(carve(h, (size_t)C * n * sT, &Za));
+  HIPCHK(carve(h, (size_t)C * n * sT, &Zb));
+  HIPCHK(carve(h, (size_t)m * C * n * sT, &Q));
+  HIPCHK(carve(h, (size_t)m * C * n * sT, &Pb));
+  HIPCHK(carve_t(h, (size_t)nrb * ND * C, &part));
+  HIPCHK(carve_t(h, (size_t)ND * C, &red));
   // slot tables: int: sys, col, src, active, status, retire (6C); double2 sigma (C);
   // double theta (C)
   int* itab;
   double* dtab;
-  HIPCHK(ensure_t(h, B_TAB_I, (size_t)6 * C, &itab));
-  HIPCHK(ensure_t(h, B_TAB_D, (size_t)3 * C, &dtab));
+  HIPCHK(carve_t(h, (size_t)6 * C, &itab));
+  HIPCHK(carve_t(h, (size_t)3 * C, &dtab));
   int *d_sys = itab, *d_col = itab + C, *d_src = itab + 2 * C, *d_act = itab + 3 * C,
       *d_status = itab + 4 * C, *d_retire = itab + 5 * C;
   double2* d_sigma = reinterpret_cast<double2*>(dtab);
   double* d_theta_slot = dtab + 2 * C;
   // scalars: beta, alpha (kMaxRestart*C double2 each), qq (kMaxRestart*C), target2 (C)
   double* scal;
-  HIPCHK(ensure_t(h, B_SCAL,
-                  (size_t)kMaxRestart * C * 5 + C + (size_t)kMaxRestart * kMaxRestart * C * 2,
-                  &scal));
+  HIPCHK(carve_t(h,
+                 (size_t)kMaxRestart * C * 5 + C + (size_t)kMaxRestart * kMaxRestart * C * 2,
+                 &scal));
   SlotScalars sc;
   sc.beta = reinterpret_cast<double2*>(scal);
   sc.alpha = reinterpret_cast<double2*>(scal + (size_t)2 * kMaxRestart * C);
@@ -767,12 +1071,12 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
   sc.bhist = reinterpret_cast<double2*>(scal + (size_t)5 * kMaxRestart * C + C);
   sc.fnorm2 = fn2;
   int* sysi;
-  HIPCHK(ensure_t(h, B_SYS, (size_t)3 * S + 8, &sysi));
+  HIPCHK(carve_t(h, (size_t)3 * S + 8, &sysi));
   sc.sys_its = sysi;
   sc.sys_rn2 = reinterpret_cast<double*>(sysi + S + (S & 1));
   sc.status = d_status;
-  HIPCHK(flags_host(h, (size_t)std::max(C, S) * 2 + 16));
-  int* hflags = h->h_flags;
+  h->h_flags.assign((size_t)std::max(C, S) * 2 + 16, 0);
+  int* hflags = h->h_flags.data();
 
   // ----- right-hand sides: F = B X (and E = (A - theta B) X for the warm start)
   {
@@ -786,7 +1090,7 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
   {
     double* cpart;
     const int nch = colstat_chunks(n);
-    HIPCHK(ensure_t(h, B_CST, (size_t)2 * nch * nc + 2, &cpart));
+    HIPCHK(carve_t(h, (size_t)2 * nch * nc + 2, &cpart));
     Scope sp(h, SLRF_K_OTHER, 8.0 * n * nc);
     HIPCHK(launch_colstats(n, nc, F, nullptr, nc, nullptr, nullptr, cpart, nch, fn2, nullptr, s));
   }
@@ -1101,17 +1405,17 @@ slrf_status rr_rowmajor(slrf_ctx* h, int nc, double* Ur, int nl, const double* X
   const int n = h->P.n;
   hipStream_t s = h->stream;
   double *AU, *BU, *V, *AV, *BV, *gpart, *small, *cpart;
-  HIPCHK(ensure_t(h, B_AU, (size_t)n * nc, &AU));
-  HIPCHK(ensure_t(h, B_BU, (size_t)n * nc, &BU));
-  HIPCHK(ensure_t(h, B_V, (size_t)n * nc, &V));
-  HIPCHK(ensure_t(h, B_AV, (size_t)n * nc, &AV));
-  HIPCHK(ensure_t(h, B_BV, (size_t)n * nc, &BV));
+  HIPCHK(carve_t(h, (size_t)n * nc, &AU));
+  HIPCHK(carve_t(h, (size_t)n * nc, &BU));
+  HIPCHK(carve_t(h, (size_t)n * nc, &V));
+  HIPCHK(carve_t(h, (size_t)n * nc, &AV));
+  HIPCHK(carve_t(h, (size_t)n * nc, &BV));
   const int gch = gram_chunks(n);
   const int pq = std::max(nc, nl);
-  HIPCHK(ensure_t(h, B_GPART, (size_t)gch * pq * pq + 16, &gpart));
-  HIPCHK(ensure_t(h, B_SMALL, (size_t)3 * pq * pq + 4 * pq + 16, &small));
+  HIPCHK(carve_t(h, (size_t)gch * pq * pq + 16, &gpart));
+  HIPCHK(carve_t(h, (size_t)3 * pq * pq + 4 * pq + 16, &small));
   const int cch = colstat_chunks(n);
-  HIPCHK(ensure_t(h, B_CST, (size_t)2 * cch * nc + 2, &cpart));
+  HIPCHK(carve_t(h, (size_t)2 * cch * nc + 2, &cpart));
   double* Gd = small;                          // nc x nc or nl x nc
   double* Gd2 = small + (size_t)pq * pq;       // second Gram
   double* Sd = small + (size_t)2 * pq * pq;    // S
@@ -1218,10 +1522,7 @@ slrf_status run_batch(int32_t nh, const slrf_handle* hs, const std::vector<doubl
   std::atomic<int> next{0};
   const int nt = std::max(1, std::min<int>(nthreads > 0 ? nthreads : 8, nh));
   auto worker = [&]() {
-    // one workspace per thread, lent to each handle the thread runs (largest
-    // first, so later entries mostly fit without regrowth): the device memory
-    // of a batch is bounded by the threads, not by the number of pencils
-    std::vector<DevBuf> arena;
+    // each handle works in its own workspace
     for (;;) {
       const int k = next.fetch_add(1);
       if (k >= nh) break;
@@ -1230,13 +1531,9 @@ slrf_status run_batch(int32_t nh, const slrf_handle* hs, const std::vector<doubl
         res[i] = SLRF_E_HIP;
         continue;
       }
-      std::swap(hs[i]->bufs, arena);
       res[i] = one(i);
       (void)hipStreamSynchronize(hs[i]->stream);
-      std::swap(hs[i]->bufs, arena);
     }
-    for (auto& b : arena)
-      if (b.p) (void)hipFree(b.p);
   };
   std::vector<std::thread> pool;
   for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
@@ -1292,7 +1589,6 @@ void slrf_default_options(slrf_options* o) {
   o->tol_lin = 1e-10;
   o->inner_rtol = 1e-5;
   o->tol_eig = 1e-8;
-  o->mem_budget = 0.0;
   o->amg_block = 0;
 }
 
@@ -1304,9 +1600,30 @@ slrf_status slrf_get_row_order(slrf_handle h, int32_t* order) {
   return SLRF_OK;
 }
 
+slrf_status slrf_workspace_size(const slrf_csr* A, const slrf_csr* B, int32_t L, int32_t npoles,
+                                const slrf_options* opt, size_t* full_bytes, size_t* min_bytes) {
+  if (!full_bytes || L < 1 || npoles < 1 || npoles > 64) return SLRF_E_ARG;
+  slrf_options o;
+  if (opt) o = *opt; else slrf_default_options(&o);
+  if (validate_options(nullptr, o) != SLRF_OK) return SLRF_E_ARG;
+  std::string err;
+  slrf_status st;
+  auto hs = analyse(A, B, o, err, st);
+  if (!hs) return st;
+  const size_t pers = persistent_bytes(*hs, npoles);
+  std::vector<int> lev;
+  for (auto& lv : hs->H.levels) lev.push_back(lv.n);
+  const int S = npoles * L;
+  int full = (S + kPanel - 1) / kPanel * kPanel;
+  if (o.max_slots > 0) full = std::min(full, o.max_slots);
+  *full_bytes = pers + call_bytes(hs->n, L, npoles, o, lev, full);
+  if (min_bytes) *min_bytes = pers + call_bytes(hs->n, L, npoles, o, lev, kPanel);
+  return SLRF_OK;
+}
+
 slrf_status slrf_setup(slrf_handle* out, const slrf_csr* A, const slrf_csr* B, double gamma,
                        int32_t npoles, const slrf_zd* poles, const slrf_zd* weights,
-                       const slrf_options* opt, void* stream) {
+                       const slrf_options* opt, void* workspace, size_t ws_bytes, void* stream) {
   if (!out) return SLRF_E_ARG;
   *out = nullptr;
   auto* h = new (std::nothrow) slrf_ctx();
@@ -1317,10 +1634,8 @@ slrf_status slrf_setup(slrf_handle* out, const slrf_csr* A, const slrf_csr* B, d
     return st;
   };
   if (!A || !B || !poles || !weights) return bad(SLRF_E_ARG, "null argument");
-  if (A->n <= 0 || A->nnz <= 0 || A->n != B->n || A->nnz != B->nnz)
-    return bad(SLRF_E_ARG, "A and B must be non-empty with equal n and nnz");
-  if (!A->rowptr || !A->col || !A->val || !B->rowptr || !B->col || !B->val)
-    return bad(SLRF_E_ARG, "null CSR array");
+  if (!workspace || ws_bytes < 2 * kAlign)
+    return bad(SLRF_E_ARG, "a device workspace is required (size it with slrf_workspace_size)");
   if (!(gamma > 0.0) || !std::isfinite(gamma)) return bad(SLRF_E_ARG, "gamma must be > 0");
   if (npoles < 1 || npoles > 64) return bad(SLRF_E_ARG, "npoles must be in [1, 64]");
   if (opt) h->opt = *opt; else slrf_default_options(&h->opt);
@@ -1353,236 +1668,80 @@ slrf_status slrf_setup(slrf_handle* out, const slrf_csr* A, const slrf_csr* B, d
   }
   h->N = npoles;
   h->gamma = gamma;
-  const int n = A->n, nnz = A->nnz;
-  // ---- host validation of the CSR structure (one copy)
-  std::vector<int> rp(n + 1), cl(nnz), rp2(n + 1), cl2(nnz);
+  {
+    // the workspace, from its first 256-byte boundary
+    const uintptr_t p0 = reinterpret_cast<uintptr_t>(workspace);
+    const uintptr_t p1 = (p0 + kAlign - 1) / kAlign * kAlign;
+    h->ar.base = reinterpret_cast<char*>(p1);
+    h->ar.cap = ws_bytes - (size_t)(p1 - p0);
+    h->ar.top = 0;
+  }
+  std::string err;
+  slrf_status ast;
+  auto hs = analyse(A, B, h->opt, err, ast);
+  if (!hs) return bad(ast, err);
+  h->block = hs->block;
+  h->h_order = hs->order;
   hipStream_t s = h->stream;
-  if (hipMemcpyAsync(rp.data(), A->rowptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost, s) ||
-      hipMemcpyAsync(cl.data(), A->col, sizeof(int) * nnz, hipMemcpyDeviceToHost, s) ||
-      hipMemcpyAsync(rp2.data(), B->rowptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost, s) ||
-      hipMemcpyAsync(cl2.data(), B->col, sizeof(int) * nnz, hipMemcpyDeviceToHost, s) ||
-      hipStreamSynchronize(s))
-    return bad(SLRF_E_ARG, "CSR arrays are not readable device memory");
-  if (rp[0] != 0 || rp[n] != nnz) return bad(SLRF_E_ARG, "rowptr[0] must be 0 and rowptr[n] nnz");
-  for (int i = 0; i < n; ++i) {
-    if (rp[i + 1] < rp[i]) return bad(SLRF_E_ARG, "rowptr must be nondecreasing");
-    bool diag = false;
-    for (int e = rp[i]; e < rp[i + 1]; ++e) {
-      if (cl[e] < 0 || cl[e] >= n) return bad(SLRF_E_ARG, "column index out of range");
-      if (e > rp[i] && cl[e] <= cl[e - 1])
-        return bad(SLRF_E_ARG, "column indices must be strictly increasing within a row");
-      diag |= cl[e] == i;
-    }
-    if (!diag) return bad(SLRF_E_ARG, "every row must store its diagonal entry");
-  }
-  if (rp != rp2 || cl != cl2) return bad(SLRF_E_ARG, "A and B must share one CSR pattern");
-  h->P.n = n;
-  h->P.nnz = nnz;
-  h->P.rowptr = A->rowptr;
-  h->P.col = A->col;
-  h->P.a = A->val;
-  h->P.b = B->val;
-  std::vector<double> hA, hB;  // host copies of the final values (row-group format)
-  if (h->opt.reorder) {
-    // Locality order (nested aggregation of the graph of A): the library keeps
-    // a permuted copy of the pencil and applies the order at the boundary.
-    HostLevel L0;
-    L0.n = n;
-    L0.rp = rp;
-    L0.ci = cl;
-    L0.a.resize(nnz);
-    std::vector<double> bv(nnz);
-    if (hipMemcpy(L0.a.data(), A->val, sizeof(double) * nnz, hipMemcpyDeviceToHost) ||
-        hipMemcpy(bv.data(), B->val, sizeof(double) * nnz, hipMemcpyDeviceToHost))
-      return bad(SLRF_E_ARG, "CSR values are not readable device memory");
-    h->block = h->opt.amg_block > 0 ? h->opt.amg_block : detect_block(L0);
-    if (n % h->block != 0) return bad(SLRF_E_ARG, "n must be a multiple of amg_block");
-    locality_order(L0, h->h_order, h->block);
-    std::vector<int> inv(n);
-    for (int i = 0; i < n; ++i) inv[h->h_order[i]] = i;
-    std::vector<int> prp(n + 1, 0), pci(nnz);
-    std::vector<double> pa(nnz), pb(nnz);
-    std::vector<std::pair<int, int>> row;
-    for (int i = 0; i < n; ++i) {
-      const int o = h->h_order[i];
-      row.clear();
-      for (int e = rp[o]; e < rp[o + 1]; ++e) row.push_back({inv[cl[e]], e});
-      std::sort(row.begin(), row.end());
-      int k = prp[i];
-      for (auto& pr : row) {
-        pci[k] = pr.first;
-        pa[k] = L0.a[pr.second];
-        pb[k] = bv[pr.second];
-        ++k;
-      }
-      prp[i + 1] = k;
-    }
-    if (hipMalloc(&h->order, sizeof(int) * n) || hipMalloc(&h->own_rp, sizeof(int) * (n + 1)) ||
-        hipMalloc(&h->own_ci, sizeof(int) * nnz) || hipMalloc(&h->own_a, sizeof(double) * nnz) ||
-        hipMalloc(&h->own_b, sizeof(double) * nnz))
-      return bad(SLRF_E_NOMEM, "allocation of the reordered pencil failed");
-    if (hipMemcpy(h->order, h->h_order.data(), sizeof(int) * n, hipMemcpyHostToDevice) ||
-        hipMemcpy(h->own_rp, prp.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice) ||
-        hipMemcpy(h->own_ci, pci.data(), sizeof(int) * nnz, hipMemcpyHostToDevice) ||
-        hipMemcpy(h->own_a, pa.data(), sizeof(double) * nnz, hipMemcpyHostToDevice) ||
-        hipMemcpy(h->own_b, pb.data(), sizeof(double) * nnz, hipMemcpyHostToDevice))
-      return bad(SLRF_E_HIP, "upload of the reordered pencil failed");
-    rp.swap(prp);
-    cl.swap(pci);
-    hA.swap(pa);
-    hB.swap(pb);
-    h->P.rowptr = h->own_rp;
-    h->P.col = h->own_ci;
-    h->P.a = h->own_a;
-    h->P.b = h->own_b;
-  } else {
-    hA.resize(nnz);
-    hB.resize(nnz);
-    if (hipMemcpy(hA.data(), A->val, sizeof(double) * nnz, hipMemcpyDeviceToHost) ||
-        hipMemcpy(hB.data(), B->val, sizeof(double) * nnz, hipMemcpyDeviceToHost))
-      return bad(SLRF_E_ARG, "CSR values are not readable device memory");
-  }
   {
-    // Row-group (union) format of the pencil in its final row order.
-    const int R = 4, ng = (n + R - 1) / R;
-    std::vector<int> gp(ng + 1, 0), gc;
-    std::vector<double> ga, gb;
-    std::vector<int> u;
-    for (int gi = 0; gi < ng; ++gi) {
-      const int r0 = gi * R, r1 = std::min(r0 + R, n);
-      u.assign(cl.begin() + rp[r0], cl.begin() + rp[r1]);
-      std::sort(u.begin(), u.end());
-      u.erase(std::unique(u.begin(), u.end()), u.end());
-      const size_t base = gc.size();
-      gc.insert(gc.end(), u.begin(), u.end());
-      ga.resize(gc.size() * R, 0.0);
-      gb.resize(gc.size() * R, 0.0);
-      for (int r = r0; r < r1; ++r)
-        for (int e = rp[r]; e < rp[r + 1]; ++e) {
-          const size_t pos = base + (std::lower_bound(u.begin(), u.end(), cl[e]) - u.begin());
-          ga[pos * R + (r - r0)] = hA[e];
-          gb[pos * R + (r - r0)] = hB[e];
-        }
-      gp[gi + 1] = (int)gc.size();
+    Placer pl{h, false};
+    hipError_t e = place_pencil(h, *hs, pl, A, B);
+    if (e == hipSuccess && hs->has_amg) e = place_amg(h, *hs, pl, npoles);
+    if (e == hipErrorOutOfMemory) {
+      char buf[256];
+      std::snprintf(buf, sizeof(buf),
+                    "workspace of %zu bytes too small for the pencil data (%zu bytes; see "
+                    "slrf_workspace_size)",
+                    h->ar.cap, persistent_bytes(*hs, npoles));
+      return bad(SLRF_E_NOMEM, buf);
     }
-    int ent = 0;
-    for (int g0 = 0; g0 < ng; g0 += 8) ent = std::max(ent, gp[std::min(g0 + 8, ng)] - gp[g0]);
-    std::vector<float> ga32(ga.begin(), ga.end()), gb32(gb.begin(), gb.end());
-    const size_t sz[6] = {sizeof(int) * gp.size(), sizeof(int) * gc.size(),
-                          sizeof(double) * ga.size(), sizeof(double) * gb.size(),
-                          sizeof(float) * ga32.size(), sizeof(float) * gb32.size()};
-    const void* src[6] = {gp.data(), gc.data(), ga.data(), gb.data(), ga32.data(), gb32.data()};
-    for (int i = 0; i < 6; ++i) {
-      if (hipMalloc(&h->grp_mem[i], std::max<size_t>(sz[i], 4)) ||
-          hipMemcpy(h->grp_mem[i], src[i], sz[i], hipMemcpyHostToDevice))
-        return bad(SLRF_E_NOMEM, "allocation of the row-group format failed");
-    }
-    h->P.gptr = static_cast<const int*>(h->grp_mem[0]);
-    h->P.gcol = static_cast<const int*>(h->grp_mem[1]);
-    h->P.gca = static_cast<const double*>(h->grp_mem[2]);
-    h->P.gcb = static_cast<const double*>(h->grp_mem[3]);
-    h->P.gca32 = static_cast<const float*>(h->grp_mem[4]);
-    h->P.gcb32 = static_cast<const float*>(h->grp_mem[5]);
-    h->P.grp_lds_ent = ent;
+    if (e != hipSuccess) return bad(SLRF_E_HIP, "upload of the pencil data failed");
   }
+  if (hs->has_amg) {
+    // per-pole dense inverses of the coarsest level operators
+    AmgHierarchy top;
+    top.levels.push_back(hs->H.levels.back());
+    std::vector<std::complex<double>> pz;
+    for (auto& p : h->poles) pz.emplace_back(p.x, p.y);
+    std::string aerr;
+    if (!amg_coarse_inverses(top, pz, aerr)) return bad(SLRF_E_ARG, "AMG setup: " + aerr);
+    std::vector<double2> i64(top.coarse_inv.size());
+    std::vector<float2> i32(top.coarse_inv.size());
+    for (size_t i = 0; i < top.coarse_inv.size(); ++i) {
+      i64[i] = make_double2(top.coarse_inv[i].real(), top.coarse_inv[i].imag());
+      i32[i] = make_float2((float)top.coarse_inv[i].real(), (float)top.coarse_inv[i].imag());
+    }
+    if (hipMemcpy(h->amg.inv64, i64.data(), sizeof(double2) * i64.size(), hipMemcpyHostToDevice) ||
+        hipMemcpy(h->amg.inv32, i32.data(), sizeof(float2) * i32.size(), hipMemcpyHostToDevice))
+      return bad(SLRF_E_HIP, "upload of the AMG coarse inverses failed");
+  }
+  h->ar.persist = h->ar.top;
   {
-    // Halo-tile format of the pencil in its final row order (absent when a
-    // single 8-row slice references more columns than the LDS tile holds).
-    HostHalo hx;
-    if (build_halo(n, rp, cl, hA, hB, kHaloMaxH, kHaloTileRows, hx)) {
-      const size_t nent = hx.lcol.size();
-      std::vector<float> ab32(hx.ab.begin(), hx.ab.end());
-      const size_t sz[8] = {sizeof(int) * hx.trow.size(), sizeof(int) * hx.hptr.size(),
-                            sizeof(int) * hx.halo.size(), sizeof(int) * hx.sptr.size(),
-                            sizeof(int) * hx.slen.size(), sizeof(uint16_t) * nent,
-                            sizeof(float) * 2 * nent,     sizeof(double) * 2 * nent};
-      const void* src[8] = {hx.trow.data(), hx.hptr.data(), hx.halo.data(), hx.sptr.data(),
-                            hx.slen.data(), hx.lcol.data(), ab32.data(),    hx.ab.data()};
-      h->halo_mem.assign(8, nullptr);
-      for (int i = 0; i < 8; ++i) {
-        if (hipMalloc(&h->halo_mem[i], std::max<size_t>(sz[i], 4)) ||
-            hipMemcpy(h->halo_mem[i], src[i], sz[i], hipMemcpyHostToDevice))
-          return bad(SLRF_E_NOMEM, "allocation of the halo-tile format failed");
-      }
-      h->P.hx_ntile = hx.ntile;
-      h->P.hx_hmax = hx.hmax;
-      h->P.hx_emax = hx.emax;
-      h->P.hx_trow = static_cast<const int*>(h->halo_mem[0]);
-      h->P.hx_hptr = static_cast<const int*>(h->halo_mem[1]);
-      h->P.hx_halo = static_cast<const int*>(h->halo_mem[2]);
-      h->P.hx_sptr = static_cast<const int*>(h->halo_mem[3]);
-      h->P.hx_slen = static_cast<const int*>(h->halo_mem[4]);
-      h->P.hx_lcol = static_cast<const unsigned short*>(h->halo_mem[5]);
-      h->P.hx_ab32 = static_cast<const float2*>(h->halo_mem[6]);
-      h->P.hx_ab64 = static_cast<const double2*>(h->halo_mem[7]);
-    }
+    // FP32 values, diagonals (a missing one is flagged), pole weights
+    Frame fr(h);
+    int* d_missing = nullptr;
+    int missing = 0;
+    if (carve_t(h, 1, &d_missing) != hipSuccess)
+      return bad(SLRF_E_NOMEM, "workspace too small for setup");
+    if (hipMemsetAsync(d_missing, 0, sizeof(int), s) ||
+        launch_cast_f32(h->P.a, h->a32, hs->nnz, s) ||
+        launch_cast_f32(h->P.b, h->b32, hs->nnz, s) ||
+        launch_diag(h->P, h->da, h->db, d_missing, s) ||
+        hipMemcpyAsync(h->d_w, h->weights.data(), sizeof(double2) * npoles,
+                       hipMemcpyHostToDevice, s) ||
+        hipMemcpyAsync(&missing, d_missing, sizeof(int), hipMemcpyDeviceToHost, s) ||
+        hipStreamSynchronize(s))
+      return bad(SLRF_E_HIP, "setup kernels failed");
+    if (missing) return bad(SLRF_E_ARG, "missing diagonal entry");
   }
-  {
-    // Row-group format of the wave-uniform sweep (groups of 4 rows, entries
-    // padded to multiples of 4) in the final row order.
-    HostUGroup ug;
-    if (build_ugroup(n, rp, cl, hA, hB, 4, 4, ug)) {
-      const size_t nent = ug.ent.size();
-      std::vector<float> ab32(ug.ab.begin(), ug.ab.end());
-      const size_t sz[4] = {sizeof(int) * ug.gptr.size(), sizeof(int) * nent,
-                            sizeof(float) * ab32.size(), sizeof(double) * ug.ab.size()};
-      const void* src[4] = {ug.gptr.data(), ug.ent.data(), ab32.data(), ug.ab.data()};
-      h->ug_mem.assign(4, nullptr);
-      for (int i = 0; i < 4; ++i) {
-        if (hipMalloc(&h->ug_mem[i], std::max<size_t>(sz[i], 4)) ||
-            hipMemcpy(h->ug_mem[i], src[i], sz[i], hipMemcpyHostToDevice))
-          return bad(SLRF_E_NOMEM, "allocation of the row-group sweep format failed");
-      }
-      h->P.ug_R = ug.R;
-      h->P.ug_ngroups = ug.ngroups;
-      h->P.ug_gptr = static_cast<const int*>(h->ug_mem[0]);
-      h->P.ug_ent = static_cast<const int*>(h->ug_mem[1]);
-      h->P.ug_ab32 = static_cast<const float2*>(h->ug_mem[2]);
-      h->P.ug_ab64 = static_cast<const double2*>(h->ug_mem[3]);
-    }
-  }
-  // largest CSR slice of an aligned row block (LDS staging plan of the SpMM)
-  auto max_slice = [&](int sub) {
-    int mx = 0;
-    for (int r = 0; r < n; r += sub) mx = std::max(mx, rp[std::min(r + sub, n)] - rp[r]);
-    return mx;
-  };
-  h->P.max_nnz_sub64 = max_slice(64);
-  h->P.max_nnz_sub32 = max_slice(32);
-  // ---- library-owned copies: FP32 values, diagonals, weights
-  size_t fr = 0, tot = 0;
-  if (hipMemGetInfo(&fr, &tot) != hipSuccess) return bad(SLRF_E_HIP, "hipMemGetInfo failed");
-  if (hipMalloc(&h->a32, sizeof(float) * nnz) || hipMalloc(&h->b32, sizeof(float) * nnz) ||
-      hipMalloc(&h->da, sizeof(double) * n) || hipMalloc(&h->db, sizeof(double) * n) ||
-      hipMalloc(&h->d_w, sizeof(double2) * npoles))
-    return bad(SLRF_E_NOMEM, "allocation of setup arrays failed");
-  h->P.a32 = h->a32;
-  h->P.b32 = h->b32;
-  h->P.da = h->da;
-  h->P.db = h->db;
-  int* d_missing = nullptr;
-  int missing = 0;
-  if (hipMalloc(&d_missing, sizeof(int)) || hipMemsetAsync(d_missing, 0, sizeof(int), s) ||
-      launch_cast_f32(h->P.a, h->a32, nnz, s) || launch_cast_f32(h->P.b, h->b32, nnz, s) ||
-      launch_diag(h->P, h->da, h->db, d_missing, s) ||
-      hipMemcpyAsync(h->d_w, h->weights.data(), sizeof(double2) * npoles, hipMemcpyHostToDevice,
-                     s) ||
-      hipMemcpyAsync(&missing, d_missing, sizeof(int), hipMemcpyDeviceToHost, s) ||
-      hipStreamSynchronize(s)) {
-    if (d_missing) (void)hipFree(d_missing);
-    return bad(SLRF_E_HIP, "setup kernels failed");
-  }
-  (void)hipFree(d_missing);
-  if (missing) return bad(SLRF_E_ARG, "missing diagonal entry");
   h->P.var32 = h->P.var64 = h->opt.spmm_variant;
-  if (h->opt.spmm_variant == kSpmmAuto && n >= 4096) {
+  if (h->opt.spmm_variant == kSpmmAuto && hs->n >= 4096) {
     const slrf_status ts = autotune_spmm(h);
     if (ts != SLRF_OK) {
       *out = h;
       return ts;
     }
   }
-  h->budget = h->opt.mem_budget > 0 ? (size_t)h->opt.mem_budget : (size_t)(0.6 * (double)fr);
   *out = h;
   return SLRF_OK;
 }
@@ -1591,15 +1750,18 @@ void slrf_destroy(slrf_handle h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   else (void)hipDeviceSynchronize();
-  delete h;
+  delete h;  // (the workspace belongs to the caller)
 }
 
 slrf_status slrf_set_options(slrf_handle h, const slrf_options* opt) {
   if (!h || !opt) return SLRF_E_ARG;
   slrf_status s = validate_options(h, *opt);
   if (s != SLRF_OK) return s;
+  if (opt->precond == SLRF_PC_AMG && !h->amg.ready)
+    return fail(h, SLRF_E_ARG, "the AMG hierarchy is built at setup: set precond there");
+  if (opt->reorder != h->opt.reorder || opt->amg_block != h->opt.amg_block)
+    return fail(h, SLRF_E_ARG, "reorder and amg_block are fixed at setup");
   h->opt = *opt;
-  if (opt->mem_budget > 0) h->budget = (size_t)opt->mem_budget;
   if (opt->spmm_variant != kSpmmAuto) h->P.var32 = h->P.var64 = opt->spmm_variant;
   return SLRF_OK;
 }
@@ -1615,6 +1777,7 @@ slrf_status slrf_filter(slrf_handle h, int32_t ncols, const double* X, const dou
     st->sys_iters = keep;
   }
   h->cur_stats = st;
+  Frame fr(h);
   slrf_status r = h->opt.precision == SLRF_PREC_MIXED
                       ? run_filter<float>(h, ncols, X, theta_warm, U, st)
                       : run_filter<double>(h, ncols, X, theta_warm, U, st);
@@ -1630,12 +1793,13 @@ slrf_status slrf_rayleigh_ritz(slrf_handle h, int32_t ncols, double* U, int32_t 
     return fail(h, SLRF_E_ARG, "bad Rayleigh-Ritz arguments");
   const int n = h->P.n;
   hipStream_t s = h->stream;
+  Frame fr(h);
   double *Ur, *Xl = nullptr, *BXl = nullptr;
-  HIPCHK(ensure_t(h, B_TMP, (size_t)n * ncols, &Ur));
+  HIPCHK(carve_t(h, (size_t)n * ncols, &Ur));
   HIPCHK(launch_transpose(U, ncols, n, n, Ur, ncols, s, h->order));
   if (nlocked > 0) {
-    HIPCHK(ensure_t(h, B_XL, (size_t)n * nlocked, &Xl));
-    HIPCHK(ensure_t(h, B_BXL, (size_t)n * nlocked, &BXl));
+    HIPCHK(carve_t(h, (size_t)n * nlocked, &Xl));
+    HIPCHK(carve_t(h, (size_t)n * nlocked, &BXl));
     HIPCHK(launch_transpose(Xlocked, nlocked, n, n, Xl, nlocked, s, h->order));
     HIPCHK(launch_spmm_real(h->P, Xl, nlocked, nlocked, nullptr, BXl, nullptr, nullptr, s));
   }
@@ -1661,8 +1825,9 @@ slrf_status slrf_solve(slrf_handle h, int32_t nev, int32_t L, const double* V1, 
   const bool warm = h->opt.warm_start != 0;
   if (nconv_out) *nconv_out = 0;
   if (stats) std::memset(stats, 0, sizeof(*stats));
+  Frame fr(h);
   double *V, *U, *Xlk, *th_d;
-  HIPCHK(ensure_t(h, B_SSP, (size_t)n * (2 * L + nev) + 2 * L + 16, &V));
+  HIPCHK(carve_t(h, (size_t)n * (2 * L + nev) + 2 * L + 16, &V));
   U = V + (size_t)n * L;
   Xlk = U + (size_t)n * L;  // locked vectors, column-major n x nev
   th_d = Xlk + (size_t)n * nev;
@@ -1690,13 +1855,14 @@ slrf_status slrf_solve(slrf_handle h, int32_t nev, int32_t L, const double* V1, 
     if (stats) stats->inner_iters += fst.total_iters;
     // Rayleigh-Ritz (with B-orthogonalisation against the locked set)
     const auto tr = std::chrono::steady_clock::now();
+    Frame fit(h);
     double *Ur, *Xl = nullptr, *BXl = nullptr;
-    HIPCHK(ensure_t(h, B_TMP, (size_t)n * nact, &Ur));
+    HIPCHK(carve_t(h, (size_t)n * nact, &Ur));
     HIPCHK(launch_transpose(U, nact, n, n, Ur, nact, s, h->order));
     const int nl = alg2 ? nconv : 0;
     if (nl > 0) {
-      HIPCHK(ensure_t(h, B_XL, (size_t)n * nl, &Xl));
-      HIPCHK(ensure_t(h, B_BXL, (size_t)n * nl, &BXl));
+      HIPCHK(carve_t(h, (size_t)n * nl, &Xl));
+      HIPCHK(carve_t(h, (size_t)n * nl, &BXl));
       HIPCHK(launch_transpose(Xlk, nl, n, n, Xl, nl, s, h->order));
       HIPCHK(launch_spmm_real(h->P, Xl, nl, nl, nullptr, BXl, nullptr, nullptr, s));
     }
@@ -1802,8 +1968,9 @@ slrf_status slrf_shifted_spmm(slrf_handle h, int32_t nsys, const int32_t* pole, 
     if (pole[i] < 0 || pole[i] >= h->N) return fail(h, SLRF_E_ARG, "pole index out of range");
     sg[i] = h->poles[pole[i]];
   }
+  Frame fr(h);
   double* dtab;
-  HIPCHK(ensure_t(h, B_TAB_D, (size_t)3 * C, &dtab));
+  HIPCHK(carve_t(h, (size_t)3 * C, &dtab));
   hipStream_t s = h->stream;
   HIPCHK(hipMemcpyAsync(dtab, sg.data(), sizeof(double2) * C, hipMemcpyHostToDevice, s));
   const PanelGrid g = make_grid(h->P.n, C, C, 2);
@@ -1869,16 +2036,64 @@ slrf_status slrf_shifted_spmm_noalloc(slrf_handle h, int32_t nsys, const int32_t
   return SLRF_OK;
 }
 
+// Host checks of slrf_eig_grad's element data (nullptr when valid).
+static const char* grad_args_error(int32_t n, int32_t nelem, int32_t ndof_e,
+                                   const int32_t* dofs, int32_t dA_stride, int64_t dA_len,
+                                   bool has_dB, int32_t dB_stride, int64_t dB_len) {
+  if (ndof_e != 4 && ndof_e != 8 && ndof_e != 24) return "ndof_e must be 4, 8 or 24";
+  if (nelem < 0 || n < 1) return "bad element count or problem size";
+  const int64_t mat = (int64_t)ndof_e * ndof_e;
+  auto span_ok = [&](int32_t stride, int64_t len) {
+    if (stride < 0 || (stride > 0 && stride < mat)) return false;
+    const int64_t need = nelem == 0 ? 0 : (stride == 0 ? mat : (int64_t)(nelem - 1) * stride + mat);
+    return len >= need;
+  };
+  if (!span_ok(dA_stride, dA_len))
+    return "dA: stride must be 0 or >= ndof_e^2 and dA_len must cover every element matrix";
+  if (has_dB && !span_ok(dB_stride, dB_len))
+    return "dB: stride must be 0 or >= ndof_e^2 and dB_len must cover every element matrix";
+  for (int64_t i = 0; i < (int64_t)nelem * ndof_e; ++i)
+    if (dofs[i] < -1 || dofs[i] >= n) return "elem_dofs holds a dof outside [-1, n)";
+  return nullptr;
+}
+
+int32_t slrf_host_check_grad_args(int32_t n, int32_t nelem, int32_t ndof_e,
+                                  const int32_t* elem_dofs, int32_t dA_stride, int64_t dA_len,
+                                  int32_t has_dB, int32_t dB_stride, int64_t dB_len) {
+  if (nelem > 0 && !elem_dofs) return SLRF_E_ARG;
+  return grad_args_error(n, nelem, ndof_e, elem_dofs, dA_stride, dA_len, has_dB != 0, dB_stride,
+                         dB_len)
+             ? SLRF_E_ARG
+             : SLRF_OK;
+}
+
 slrf_status slrf_eig_grad(slrf_handle h, int32_t k, const double* X, const double* lam,
                           const double* glam, int32_t nelem, int32_t ndof_e,
                           const int32_t* elem_dofs, const double* dA, int32_t dA_stride,
-                          const double* dB, int32_t dB_stride, double* grad) {
+                          int64_t dA_len, const double* dB, int32_t dB_stride, int64_t dB_len,
+                          double* grad) {
   if (!h) return SLRF_E_ARG;
-  if (k < 0 || nelem < 0 || (k > 0 && (!X || !lam || !glam)) || (nelem > 0 && (!elem_dofs || !dA || !grad)))
+  if (k < 0 || nelem < 0 || (k > 0 && (!X || !lam || !glam)) ||
+      (nelem > 0 && (!elem_dofs || !dA || !grad)))
     return fail(h, SLRF_E_ARG, "bad eig_grad arguments");
-  if (ndof_e != 4 && ndof_e != 8 && ndof_e != 24)
-    return fail(h, SLRF_E_ARG, "ndof_e must be 4, 8 or 24");
-  if (dA_stride < 0 || dB_stride < 0) return fail(h, SLRF_E_ARG, "negative stride");
+  if (nelem == 0) {
+    if (ndof_e != 4 && ndof_e != 8 && ndof_e != 24)
+      return fail(h, SLRF_E_ARG, "ndof_e must be 4, 8 or 24");
+    return SLRF_OK;
+  }
+  {
+    // every dof in [-1, n) (the kernel gathers X rows by these indices) and
+    // every element matrix inside its array
+    std::vector<int32_t> dofs((size_t)nelem * ndof_e);
+    if (ndof_e == 4 || ndof_e == 8 || ndof_e == 24) {
+      HIPCHK(hipMemcpyAsync(dofs.data(), elem_dofs, sizeof(int32_t) * dofs.size(),
+                            hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    const char* why = grad_args_error(h->P.n, nelem, ndof_e, dofs.data(), dA_stride, dA_len,
+                                      dB != nullptr, dB_stride, dB_len);
+    if (why) return fail(h, SLRF_E_ARG, why);
+  }
   HIPCHK(launch_eig_grad(h->P.n, k, X, lam, glam, nelem, ndof_e, elem_dofs, dA, dA_stride, dB,
                          dB_stride, grad, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));

@@ -48,8 +48,7 @@ class Options(C.Structure):
                 ("max_slots", C.c_int32), ("spmm_variant", C.c_int32), ("reorder", C.c_int32),
                 ("tol_lin", C.c_double),
                 ("inner_rtol", C.c_double),
-                ("tol_eig", C.c_double), ("mem_budget", C.c_double),
-                ("amg_block", C.c_int32)]
+                ("tol_eig", C.c_double), ("amg_block", C.c_int32)]
 
 
 class FilterStats(C.Structure):
@@ -75,9 +74,12 @@ SIGNATURES = {
     "slrf_status_string": (C.c_char_p, [C.c_int]),
     "slrf_last_error": (C.c_char_p, [C.c_void_p]),
     "slrf_default_options": (None, [C.POINTER(Options)]),
+    "slrf_workspace_size": (C.c_int, [C.POINTER(Csr), C.POINTER(Csr), C.c_int32, C.c_int32,
+                                      C.POINTER(Options), C.POINTER(C.c_size_t),
+                                      C.POINTER(C.c_size_t)]),
     "slrf_setup": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(Csr), C.POINTER(Csr), C.c_double,
                              C.c_int32, C.POINTER(Zd), C.POINTER(Zd), C.POINTER(Options),
-                             C.c_void_p]),
+                             C.c_void_p, C.c_size_t, C.c_void_p]),
     "slrf_destroy": (None, [C.c_void_p]),
     "slrf_set_options": (C.c_int, [C.c_void_p, C.POINTER(Options)]),
     "slrf_filter": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -94,7 +96,10 @@ SIGNATURES = {
     "slrf_get_row_order": (C.c_int, [C.c_void_p, C.c_void_p]),
     "slrf_eig_grad": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                 C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
-                                C.c_void_p, C.c_int32, C.c_void_p]),
+                                C.c_int64, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p]),
+    "slrf_host_check_grad_args": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                              C.c_int32, C.c_int64, C.c_int32, C.c_int32,
+                                              C.c_int64]),
     "slrf_host_projected_eig": (C.c_int32, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                             C.c_void_p]),
     "slrf_filter_batch": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int32),
@@ -171,15 +176,33 @@ def _empty_colmajor(n: int, k: int, device):
     return torch.empty((k, n), dtype=torch.float64, device=device).t()
 
 
+def workspace_size(A: Csr, B: Csr, L: int, npoles: int, options: Options):
+    """(full, minimum) workspace bytes of slrf_workspace_size."""
+    full, mn = C.c_size_t(0), C.c_size_t(0)
+    st = lib().slrf_workspace_size(C.byref(A), C.byref(B), int(L), int(npoles),
+                                   C.byref(options), C.byref(full), C.byref(mn))
+    if st != 0:
+        raise SlrfError(st, "slrf_workspace_size failed (malformed pencil or options)")
+    return full.value, mn.value
+
+
 class Handle:
     """A pencil bound to the GPU library (slrf_setup ... slrf_destroy).
 
     ``indptr``/``indices``/``a``/``b`` are host arrays (numpy) of a shared-pattern
     CSR pencil; they are uploaded once and kept alive by the handle.
+
+    The device workspace is a torch uint8 tensor owned by the handle: by default
+    slrf_workspace_size's full size for blocks of ``max_cols`` columns (every
+    shifted system resident), capped at ``budget`` (a fraction of the free
+    device memory when below 1, else bytes; default 0.25) but never below the
+    minimum; ``workspace_bytes`` sets the size directly.
     """
 
     def __init__(self, indptr, indices, a, b, gamma: float, poles, weights,
-                 options: Optional[Options] = None, device: str = "cuda", stream=None):
+                 options: Optional[Options] = None, device: str = "cuda", stream=None,
+                 max_cols: int = 64, budget: float = 0.25,
+                 workspace_bytes: Optional[int] = None):
         torch = _torch()
         self._L = lib()
         self.device = torch.device(device)
@@ -202,15 +225,31 @@ class Handle:
         zp = (Zd * self.npoles)(*[Zd(p.real, p.imag) for p in poles])
         zw = (Zd * self.npoles)(*[Zd(w.real, w.imag) for w in weights])
         self.options = options if options is not None else default_options()
-        h = C.c_void_p()
+        self._h = C.c_void_p()
         torch.cuda.synchronize(self.device)
+        self._A, self._B = A, B
+        full, mn = workspace_size(A, B, max_cols, self.npoles, self.options)
+        if workspace_bytes is None:
+            # free device memory, counting torch's cached but unused blocks
+            free = torch.cuda.mem_get_info(self.device)[0] + (
+                torch.cuda.memory_reserved(self.device) - torch.cuda.memory_allocated(self.device))
+            cap = int(budget * free) if budget <= 1.0 else int(budget)
+            workspace_bytes = max(mn, min(full, cap))
+        self.workspace_full, self.workspace_min = full, mn
+        self.workspace = torch.empty(int(workspace_bytes), dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
         st = self._L.slrf_setup(C.byref(h), C.byref(A), C.byref(B), self.gamma, self.npoles, zp,
-                                zw, C.byref(self.options), C.c_void_p(self.stream.cuda_stream))
+                                zw, C.byref(self.options), C.c_void_p(self.workspace.data_ptr()),
+                                self.workspace.numel(), C.c_void_p(self.stream.cuda_stream))
         self._h = h
         if st != 0:
             msg = self._L.slrf_last_error(h).decode() if h.value else "setup failed"
             self.close()
             raise SlrfError(st, msg)
+
+    def workspace_sizes(self, L: int):
+        """(full, minimum) workspace bytes of this pencil for blocks of L columns."""
+        return workspace_size(self._A, self._B, L, self.npoles, self.options)
 
     @classmethod
     def from_pencil(cls, p, gamma, poles, weights, options=None, **kw):
@@ -225,6 +264,7 @@ class Handle:
         if getattr(self, "_h", None) is not None and self._h.value:
             self._L.slrf_destroy(self._h)
         self._h = C.c_void_p()
+        self.workspace = None
 
     def __del__(self):  # pragma: no cover
         try:
@@ -330,8 +370,9 @@ class Handle:
         grad = torch.empty(nelem, dtype=torch.float64, device=dev)
         self._check(self._L.slrf_eig_grad(self._h, k, X.data_ptr(), lam.data_ptr(),
                                           glam.data_ptr(), nelem, nd, dofs.data_ptr(),
-                                          dA.data_ptr(), dA_stride,
+                                          dA.data_ptr(), dA_stride, dA.numel(),
                                           dBt.data_ptr() if dBt is not None else None, dB_stride,
+                                          dBt.numel() if dBt is not None else 0,
                                           grad.data_ptr()))
         return grad
 
@@ -377,7 +418,8 @@ class EigFn:
                 p = problem.assemble(theta.detach().cpu().numpy())
                 h = Handle.from_pencil(p, problem.gamma, problem.poles, problem.weights,
                                        problem.options, device=str(theta.device)
-                                       if theta.is_cuda else "cuda")
+                                       if theta.is_cuda else "cuda",
+                                       max_cols=int(np.asarray(problem.V1).shape[1]))
                 V1 = torch.as_tensor(np.ascontiguousarray(np.asarray(problem.V1).T),
                                      device=h.device).t()
                 lam, X, nconv, _ = h.slrf_solve(problem.nev, V1)

@@ -74,3 +74,29 @@ def test_host_projected_eig_truncates_singular_gram():
     w = sla.eigh(U[:, :6].T @ Kd @ U[:, :6], U[:, :6].T @ U[:, :6], eigvals_only=True)
     assert np.allclose(th[:6], w, rtol=1e-8)
     assert np.all(np.isinf(th[6:]))
+
+
+def test_host_check_of_gradient_element_data():
+    """slrf_eig_grad's host checks (the same code the entry point runs before its
+    kernel): dofs in [-1, n), strides 0 or >= ndof_e^2, element matrices inside
+    the given lengths; anything else is SLRF_E_ARG."""
+    L = P.lib()
+    n, nelem, nd = 50, 3, 4
+    dofs = np.array([[0, 1, 2, -1], [3, 4, 5, 6], [7, 8, 49, 10]], dtype=np.int32)
+
+    def chk(d=dofs, sa=0, la=16, hb=0, sb=0, lb=0, nn=n, ne=nelem, k=nd):
+        return L.slrf_host_check_grad_args(nn, ne, k, d.ctypes.data, sa, la, hb, sb, lb)
+
+    assert chk() == 0
+    assert chk(sa=16, la=48) == 0 and chk(hb=1, sb=16, lb=48) == 0
+    bad = dofs.copy()
+    bad[2, 2] = 50  # = n
+    assert chk(d=bad) == 1
+    bad[2, 2] = -2
+    assert chk(d=bad) == 1
+    assert chk(la=15) == 1             # shared matrix shorter than 4 x 4
+    assert chk(sa=16, la=47) == 1      # last element's matrix past the end
+    assert chk(sa=8, la=100) == 1      # stride below ndof_e^2
+    assert chk(hb=1, sb=0, lb=10) == 1
+    assert chk(k=6) == 1               # unsupported element size
+    assert chk(ne=0, d=np.zeros(0, np.int32), la=0) == 0

@@ -545,3 +545,41 @@ def test_amg_elasticity_single_pole_residuals(prec):
         M = (A - poles[j] * B).tocsr()
         rel = np.linalg.norm(F - M @ Y, axis=0) / np.linalg.norm(F, axis=0)
         assert rel.max() <= 1.01e-10 and st["converged"] == 5
+
+
+# ----------------------------------------------------------------------------
+# caller-owned workspace
+# ----------------------------------------------------------------------------
+def test_workspace_minimum_streams_and_undersized_is_refused(cfg1):
+    """The handle's device memory is the caller's workspace: at the minimum size
+    (one panel of 16 resident systems) the filter streams its 256 systems and
+    returns exactly the block of a full-size workspace; a workspace too small
+    for the pencil data fails setup, and one that holds the pencil but not a
+    call's buffers fails that call, both with SLRF_E_NOMEM."""
+    p = cfg1["pencil"]
+    X = _dev(cfg1["V1"])
+    opt = dict(precision=P.SLRF_PREC_MIXED, precond=P.SLRF_PC_AMG, restart=5, tol_lin=1e-9)
+    h = P.Handle.from_pencil(p, cfg1["gamma"], cfg1["poles"], cfg1["weights"],
+                             P.default_options(**opt), max_cols=32)
+    full, mn = h.workspace_sizes(32)
+    assert h.workspace.numel() == full and mn < full
+    U1, st1 = h.slrf_filter(X)
+    one_col_min = h.workspace_sizes(1)[1]
+    h.close()
+    h = P.Handle.from_pencil(p, cfg1["gamma"], cfg1["poles"], cfg1["weights"],
+                             P.default_options(**opt), workspace_bytes=mn)
+    U2, st2 = h.slrf_filter(X)
+    assert torch.equal(U1, U2) and st2["converged"] == st1["converged"] == 256
+    h.close()
+    with pytest.raises(P.SlrfError) as e:
+        P.Handle.from_pencil(p, cfg1["gamma"], cfg1["poles"], cfg1["weights"],
+                             P.default_options(**opt), workspace_bytes=64 * 1024)
+    assert e.value.status == 2
+    h = P.Handle.from_pencil(p, cfg1["gamma"], cfg1["poles"], cfg1["weights"],
+                             P.default_options(**opt), workspace_bytes=one_col_min)
+    U3, _ = h.slrf_filter(X[:, :1])
+    assert torch.equal(U3[:, 0], U1[:, 0])
+    with pytest.raises(P.SlrfError) as e:
+        h.slrf_filter(X)
+    assert e.value.status == 2 and "workspace" in str(e.value)
+    h.close()

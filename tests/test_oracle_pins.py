@@ -356,3 +356,18 @@ def test_jacobi_gcr_solves_a_diagonal_pencil_in_one_step():
     Y, its = oracle.gcr.shifted_solve_gcr(A, B, sigma, f, restart=30, tol=1e-14)
     assert its[0] == 1
     assert np.allclose(Y[:, 0], f[:, 0] / (a - sigma * b), rtol=1e-14, atol=0)
+
+
+def test_smallest_eigpairs_against_closed_form_and_definition():
+    """Eigenpairs of the 3D Q1 pencil (m = 9, n = 729 > 400: the Lanczos path):
+    eigenvalues equal the closed form, the vectors are B-orthonormal and each
+    satisfies A x = lambda B x (Eq. (1)) to rounding."""
+    p = si.q1_kron_pencil(9, 3)
+    A, B = p.A(), p.B()
+    lam, X = oracle.eig.smallest_eigpairs(A, B, 12)
+    l1 = closed_form_1d(9)
+    ex = np.sort((l1[:, None, None] + l1[None, :, None] + l1[None, None, :]).ravel())[:12]
+    assert np.max(np.abs(lam - ex) / ex) <= 1e-11
+    assert np.max(np.abs(X.T @ (B @ X) - np.eye(12))) <= 1e-11
+    R = A @ X - (B @ X) * lam[None, :]
+    assert np.max(np.linalg.norm(R, axis=0) / lam) <= 1e-8

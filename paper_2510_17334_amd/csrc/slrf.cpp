@@ -110,6 +110,17 @@ struct slrf_ctx {
   int block = 0;  // dofs per node
   Arena ar;
   std::vector<int> h_flags;  // host mirror of per-slot flags
+  // byte accounting of a Krylov cycle: its kernels are counted with the
+  // systems active at the cycle start; the per-system terms are settled at the
+  // next boundary from the steps each system actually took (active steps
+  // form a prefix of the cycle)
+  struct Deferred {
+    int cls, k;
+    double per_sys;
+    bool sweep;
+  };
+  std::vector<Deferred> defer;
+  int defer_k = -1;  // step of the cycle being issued (-1: outside a cycle)
   Timer timer;
   slrf_filter_stats* cur_stats = nullptr;
   DevAmg amg;
@@ -203,6 +214,22 @@ struct Scope {
     if (b) (void)hipEventRecord(b, h->stream);
   }
 };
+
+void defer_bytes(slrf_ctx* h, int cls, double per_sys, bool sweep = false) {
+  if (h->cur_stats && h->defer_k >= 0) h->defer.push_back({cls, h->defer_k, per_sys, sweep});
+}
+
+// nact_k[k]: systems active at step k of the finished cycle; nact0 those the
+// cycle's launches were counted with.
+void settle_bytes(slrf_ctx* h, const std::vector<int>& nact_k, int nact0) {
+  if (h->cur_stats)
+    for (const auto& d : h->defer) {
+      const int a = d.k < (int)nact_k.size() ? nact_k[d.k] : 0;
+      h->cur_stats->bytes[d.cls] += (double)(a - nact0) * d.per_sys;
+      if (d.sweep) h->cur_stats->sweep_systems += a - nact0;
+    }
+  h->defer.clear();
+}
 
 void harvest_timers(slrf_ctx* h) {
   if (!h->cur_stats) {
@@ -779,10 +806,11 @@ slrf_status vcycle(slrf_ctx* h, const AmgVecs& v, int C, int occ, int ND, const 
   const size_t sT = 2 * sizeof(T);
   const void* inv = std::is_same<T, float>::value ? A.inv32 : A.inv64;
   {
-    double bytes = 0.0;
-    for (int l = 0; l < L; ++l) bytes += 10.0 * nact * (double)A.n[l] * sT;
-    bytes += (double)(h->P.nnz + A.nnz_all) * (4.0 + 2.0 * sizeof(T));
+    double per_sys = 0.0;
+    for (int l = 0; l < L; ++l) per_sys += 10.0 * (double)A.n[l] * sT;
+    const double bytes = nact * per_sys + (double)(h->P.nnz + A.nnz_all) * (4.0 + 2.0 * sizeof(T));
     Scope sp(h, SLRF_K_PRECOND, bytes);
+    defer_bytes(h, SLRF_K_PRECOND, per_sys);
     if (L == 1) {
       HIPCHK(launch_coarse_solve<T>(A.nc, make_grid(A.nc, C, occ, ND), st, h->N, inv, Rin, Zout,
                                     s));
@@ -807,6 +835,7 @@ slrf_status vcycle(slrf_ctx* h, const AmgVecs& v, int C, int occ, int ND, const 
         Scope sw(h, fine ? SLRF_K_SWEEP : -1,
                  (double)nact * A.n[0] * sT * (h16 ? 2.0 : 3.0) + fine_csr);
         if (fine && h->cur_stats) h->cur_stats->sweep_systems += nact;
+        if (fine) defer_bytes(h, SLRF_K_SWEEP, (double)A.n[0] * sT * (h16 ? 2.0 : 3.0), true);
         hipError_t err = hipSuccess;
         if (h16 && launch_resid_bf16<T>(h->P, g, st, xb, b[l], r, s, err, true))
           HIPCHK(err);
@@ -841,6 +870,7 @@ slrf_status vcycle(slrf_ctx* h, const AmgVecs& v, int C, int occ, int ND, const 
       const bool fine = l == 0 && sweep_is_halo<T>(h->P);
       Scope sw(h, fine ? SLRF_K_SWEEP : -1, (double)nact * A.n[0] * sT * 3.0 + fine_csr);
       if (fine && h->cur_stats) h->cur_stats->sweep_systems += nact;
+      if (fine) defer_bytes(h, SLRF_K_SWEEP, (double)A.n[0] * sT * 3.0, true);
       HIPCHK(launch_lvl_op<T>(lvl(l), g, st, kEpiJacobiOp, A.omega[l], x[l], b[l], out, s));
       x[l] = out;
     }
@@ -1129,6 +1159,8 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
   const bool hq = std::is_same<T, float>::value && sweep_is_halo<T>(h->P) && m <= 9 && !warm;
   const double csr_bytes = (double)h->P.nnz * (4.0 + 2.0 * sizeof(T)) + 4.0 * (n + 1);
 
+  int cyc_nact0 = 0, cyc_occ = 0;        // the last cycle's starting actives / slots
+  std::vector<int> its_h(S, 0), its_start(C, 0);
   SlotTables tabs;
   tabs.sys = d_sys;
   tabs.sigma = d_sigma;
@@ -1158,8 +1190,17 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
         HIPCHK(launch_fin_true(red, occ, t0, sc, h->opt.tol_lin, inner_rtol, safety, itcap, s));
       }
       HIPCHK(hipMemcpyAsync(hflags, d_status, sizeof(int) * occ, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(its_h.data(), sc.sys_its, sizeof(int) * S, hipMemcpyDeviceToHost, s));
       HIPCHK(sync(h));
       for (int i = 0; i < occ; ++i) status[i] = hflags[i];
+      if (!h->defer.empty()) {
+        std::vector<int> nact_k(m, 0);
+        for (int i = 0; i < cyc_occ; ++i) {
+          const int steps = h_sys[i] >= 0 ? its_h[h_sys[i]] - its_start[i] : 0;
+          for (int k = 0; k < std::min(steps, m); ++k) ++nact_k[k];
+        }
+        settle_bytes(h, nact_k, cyc_nact0);
+      }
     }
     // ----- retire finished systems, compact the survivors, admit new ones
     int nret = 0;
@@ -1242,6 +1283,7 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
       }
     }
     if (occ == 0) break;
+    for (int i = 0; i < occ; ++i) its_start[i] = h_sys[i] >= 0 ? its_h[h_sys[i]] : 0;
     // active count after the boundary
     int nact = 0;
     for (int i = 0; i < occ; ++i) nact += status[i] == 0 ? 1 : 0;
@@ -1259,7 +1301,12 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
       return k == 0 ? Zbuf[cur] : static_cast<void*>(static_cast<char*>(Pb) +
                                                      (size_t)k * vstride * sT);
     };
+    // The m steps are issued without reading anything back: a system whose
+    // cycle ended (inner reduction reached, cap, breakdown) stays inactive and
+    // the kernels skip it; the boundary reads the flags once.
+    const int nact0 = nact;
     for (int k = 0; k < m; ++k) {
+      h->defer_k = k;
       char* Qk = static_cast<char*>(Q) + (size_t)k * vstride * sT;
       // the image w = M z_k: in place in slot k, or (complex bfloat16 basis)
       // in the last slot, whose q is never stored
@@ -1273,14 +1320,17 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
       if (sweep_is_halo<T>(h->P)) {
         Scope sp(h, SLRF_K_APPLY,
                  (double)nact * n * sT * (k > 0 ? 3.0 + qb * k : 2.0) + csr_bytes);
+        defer_bytes(h, SLRF_K_APPLY, (double)n * sT * (k > 0 ? 3.0 + qb * k : 2.0));
         {
           Scope sw(h, SLRF_K_SWEEP, (double)nact * n * sT * 2.0 + csr_bytes);
           if (h->cur_stats) h->cur_stats->sweep_systems += nact;
+          defer_bytes(h, SLRF_K_SWEEP, (double)n * sT * 2.0, true);
           HIPCHK(launch_sweep<T>(h->P, g, tc, Z, Wk, s));
         }
         HIPCHK(launch_dots<T>(h->P, g, tc, Wk, Q, vstride, k, part, s, hq));
       } else {
         Scope sp(h, SLRF_K_APPLY, (double)nact * n * sT * (k + 2) + csr_bytes);
+        defer_bytes(h, SLRF_K_APPLY, (double)n * sT * (k + 2));
         HIPCHK(launch_apply_dots<T>(h->P, g, tc, Z, Qk, Q, vstride, k, part, pc, s));
       }
       if (k > 0) {
@@ -1293,6 +1343,7 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
         // (full-precision basis) q_0, which is w itself
         const bool store = k + 1 < m && (hq || k > 0);
         Scope sp(h, SLRF_K_ORTH, (double)nact * n * sT * (2.0 + qb * k + (store ? qb : 0.0)));
+        defer_bytes(h, SLRF_K_ORTH, (double)n * sT * (2.0 + qb * k + (store ? qb : 0.0)));
         HIPCHK(launch_orth<T>(h->P, g, tc, Wk, R, Q, vstride, k, sc.beta, part, s, Qk, store,
                               hq));
       }
@@ -1304,6 +1355,7 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
       if (k + 1 < m) {
         {
           Scope sp(h, SLRF_K_STEP, (double)nact * n * sT * (3.0 + qb));
+          defer_bytes(h, SLRF_K_STEP, (double)n * sT * (3.0 + qb));
           // with the AMG, the step also forms the next V-cycle's level-0
           // pre-smoothing (saves that kernel's read of r)
           void* znext = fuse0 ? av.W0 : zk(k + 1);
@@ -1321,17 +1373,10 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
         HIPCHK(launch_fin_rnorm(nullptr, occ, tc, sc, itcap, s));
       }
       kk_last = k + 1;
-      HIPCHK(hipMemcpyAsync(hflags, d_act, sizeof(int) * occ, hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(hflags + C, d_status, sizeof(int) * occ, hipMemcpyDeviceToHost, s));
-      HIPCHK(sync(h));
-      nact = 0;
-      for (int i = 0; i < occ; ++i) {
-        nact += hflags[i];
-        if (hflags[C + i] == 3) numeric = true;
-      }
-      if (nact == 0 || numeric) break;
     }
-    if (numeric) break;
+    h->defer_k = -1;
+    cyc_nact0 = nact0;
+    cyc_occ = occ;
   }
 
   // ----- filter sum U = sum_j 2 Re(w_j Y_j) and back to column-major

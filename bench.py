@@ -460,7 +460,7 @@ def run_itmax(args):
                          device="cuda").t()
     rows = []
     for itmax in [int(x) for x in args.itmax.split(",")]:
-        opt = P.default_options(precision=P.SLRF_PREC_MIXED, precond=P.SLRF_PC_JACOBI,
+        opt = P.default_options(precision=P.SLRF_PREC_MIXED, precond=P.SLRF_PC_AMG,
                                 restart=30, tol_lin=1e-10, lock=1, warm_start=1, max_outer=100,
                                 it_max_lin=itmax)
         h = P.Handle.from_pencil(p, gold["gamma"], poles, weights, opt, max_cols=c["L"])
@@ -483,7 +483,8 @@ def run_itmax(args):
             "value": best["seconds"] if best else None, "unit": "s", "n_gpus": 1,
             "higher_is_better": False, "dtype": "c64+f64", "data": "synthetic",
             "config": {"workload": "elasticity_32", "n": p.n, "nnz": p.nnz, "nev": c["count"],
-                       "L": c["L"], "solver": "GCR(30)+Jacobi, mixed, lock + warm start"},
+                       "L": c["L"],
+                       "solver": "GCR(30)+AMG (rigid-body modes), mixed, lock + warm start"},
             "chosen_it_max_linear": best["it_max_linear"] if best else None, "sweep": rows}
     print(json.dumps(line, default=float))
 

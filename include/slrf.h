@@ -121,6 +121,14 @@ typedef struct {
                           0 = detect (3 or 2 when every node's rows share one
                           column list of whole node blocks, else 1), 1 = scalar
                           aggregation, 2..8 = given (n must be a multiple)    */
+  const double* node_xyz; /* host, may be NULL: coordinates of the n / block
+                          nodes (block values per node, node-major, the caller's
+                          numbering) of a 2D / 3D elasticity pencil (block 2
+                          or 3).  With SLRF_PC_AMG the hierarchy's tentative
+                          prolongator then carries the rigid-body modes
+                          (translations and rotations) instead of the
+                          translations alone.  Read by slrf_workspace_size
+                          and slrf_setup only.                               */
 } slrf_options;
 
 /* Per-kernel-class counters (algorithmic bytes, launches, event time). */

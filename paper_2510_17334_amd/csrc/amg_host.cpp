@@ -320,33 +320,137 @@ bool amg_build(const HostLevel& fine, const std::vector<std::complex<double>>& p
   H.R.clear();
   H.rho.clear();
   H.levels.push_back(fine);
+  // near-nullspace candidates of the current level (n x kns, row-major): the
+  // constant (scalar), one translation per component, or the rigid-body modes
+  int lev_block = prm.block;
+  int kns = 1;
+  std::vector<double> ns;
+  {
+    const int n0 = fine.n;
+    const int bs0 = prm.block > 1 && n0 % prm.block == 0 ? prm.block : 1;
+    const bool rigid = prm.xyz != nullptr && (bs0 == 2 || bs0 == 3) &&
+                       prm.xyz->size() == (size_t)n0;
+    if (rigid) {
+      kns = bs0 == 3 ? 6 : 3;
+      ns.assign((size_t)n0 * kns, 0.0);
+      for (int node = 0; node < n0 / bs0; ++node) {
+        const double* x = prm.xyz->data() + (size_t)node * bs0;
+        for (int c = 0; c < bs0; ++c) ns[((size_t)node * bs0 + c) * kns + c] = 1.0;
+        if (bs0 == 3) {
+          // rotations about x, y, z: (0, -z, y), (z, 0, -x), (-y, x, 0)
+          double* r0 = &ns[((size_t)node * 3) * kns];
+          double* r1 = &ns[((size_t)node * 3 + 1) * kns];
+          double* r2 = &ns[((size_t)node * 3 + 2) * kns];
+          r1[3] = -x[2];
+          r2[3] = x[1];
+          r0[4] = x[2];
+          r2[4] = -x[0];
+          r0[5] = -x[1];
+          r1[5] = x[0];
+        } else {
+          ns[((size_t)node * 2) * kns + 2] = -x[1];
+          ns[((size_t)node * 2 + 1) * kns + 2] = x[0];
+        }
+      }
+    } else {
+      kns = bs0;
+      ns.assign((size_t)n0 * kns, 0.0);
+      for (int i = 0; i < n0; ++i) ns[(size_t)i * kns + i % bs0] = 1.0;
+    }
+    lev_block = bs0;
+  }
+  const bool rigid_modes = kns > lev_block;
   while (H.levels.back().n > prm.coarse_max && (int)H.levels.size() < prm.max_levels) {
     const HostLevel& L = H.levels.back();
     const int n = L.n;
-    const int bs = prm.block > 1 && n % prm.block == 0 ? prm.block : 1;
-    std::vector<int> agg;
-    int nc;
+    const int bs = lev_block > 1 && n % lev_block == 0 ? lev_block : 1;
+    // aggregates of dofs (whole nodes when bs > 1)
+    std::vector<int> dagg(n);
+    int na;
     if (bs > 1) {
-      // aggregate nodes; dof (I, c) maps to coarse dof (agg(I), c)
       std::vector<int> nagg;
-      const int na = aggregate(node_graph(L, bs), prm.theta, nagg);
-      nc = na * bs;
-      agg.resize(n);
-      for (int i = 0; i < n; ++i) agg[i] = bs * nagg[i / bs] + i % bs;
+      na = aggregate(node_graph(L, bs), prm.theta, nagg);
+      for (int i = 0; i < n; ++i) dagg[i] = nagg[i / bs];
     } else {
-      nc = aggregate(L, prm.theta, agg);
+      na = aggregate(L, prm.theta, dagg);
     }
+    if (na == 0) break;
+    // tentative prolongator T: per aggregate, an orthonormal basis of the
+    // near-nullspace rows restricted to it (modified Gram-Schmidt, twice, with
+    // dependent columns dropped), the R factor becoming the next level's rows
+    std::vector<std::vector<int>> rows(na);
+    for (int i = 0; i < n; ++i) rows[dagg[i]].push_back(i);
+    std::vector<int> cbase(na + 1, 0);
+    std::vector<std::vector<double>> Qa(na), Ra(na);
+    std::vector<int> ka(na, 0);
+    for (int a = 0; a < na; ++a) {
+      const auto& r = rows[a];
+      const int nr = (int)r.size();
+      std::vector<double>& Q = Qa[a];  // nr x k (column j at j * nr)
+      std::vector<double> R;           // k x kns
+      for (int j = 0; j < kns; ++j) {
+        std::vector<double> v(nr);
+        double n0 = 0.0;
+        for (int t = 0; t < nr; ++t) {
+          v[t] = ns[(size_t)r[t] * kns + j];
+          n0 += v[t] * v[t];
+        }
+        n0 = std::sqrt(n0);
+        std::vector<double> coef(ka[a], 0.0);
+        for (int pass = 0; pass < 2; ++pass)
+          for (int i = 0; i < ka[a]; ++i) {
+            double d = 0.0;
+            for (int t = 0; t < nr; ++t) d += Q[(size_t)i * nr + t] * v[t];
+            coef[i] += d;
+            for (int t = 0; t < nr; ++t) v[t] -= d * Q[(size_t)i * nr + t];
+          }
+        double nv = 0.0;
+        for (double x : v) nv += x * x;
+        nv = std::sqrt(nv);
+        const bool keep = n0 > 0.0 && nv > 1e-10 * n0;
+        // R columns: coefficients of column j on the kept q_i (and on q_j)
+        R.resize((size_t)(ka[a] + (keep ? 1 : 0)) * kns, 0.0);
+        if (keep) {
+          // (row ka[a] of R is new: shift nothing, rows are appended)
+          for (int t = 0; t < nr; ++t) Q.push_back(v[t] / nv);
+          for (int i = 0; i < ka[a]; ++i) R[(size_t)i * kns + j] = coef[i];
+          R[(size_t)ka[a] * kns + j] = nv;
+          ++ka[a];
+        } else {
+          for (int i = 0; i < ka[a]; ++i) R[(size_t)i * kns + j] = coef[i];
+        }
+      }
+      Ra[a] = R;
+      cbase[a + 1] = cbase[a] + ka[a];
+    }
+    const int nc = cbase[na];
     if (nc >= n || nc == 0) break;  // no coarsening possible
-    std::vector<int> cnt(nc, 0);
-    for (int i = 0; i < n; ++i) cnt[agg[i]]++;
-    // tentative prolongator T (n x nc), one entry per row
-    std::vector<int> trp(n + 1), tci(n);
-    std::vector<double> tv(n);
-    for (int i = 0; i < n; ++i) {
-      trp[i + 1] = i + 1;
-      tci[i] = agg[i];
-      tv[i] = 1.0 / std::sqrt((double)cnt[agg[i]]);
+    std::vector<int> trp(n + 1, 0), tci;
+    std::vector<double> tv;
+    {
+      std::vector<int> pos(n, -1);  // position of dof i in its aggregate's row list
+      for (int a = 0; a < na; ++a)
+        for (size_t t = 0; t < rows[a].size(); ++t) pos[rows[a][t]] = (int)t;
+      for (int i = 0; i < n; ++i) {
+        const int a = dagg[i], nr = (int)rows[a].size();
+        for (int j = 0; j < ka[a]; ++j) {
+          const double q = Qa[a][(size_t)j * nr + pos[i]];
+          if (q == 0.0) continue;
+          tci.push_back(cbase[a] + j);
+          tv.push_back(q);
+        }
+        trp[i + 1] = (int)tci.size();
+      }
     }
+    // a row of T holds at most one entry per column: the diagonal-block term
+    // of P below adds T's value in that column
+    std::vector<int> agg_first(n);
+    for (int i = 0; i < n; ++i) agg_first[i] = dagg[i];
+    std::vector<double> ns_next((size_t)nc * kns, 0.0);
+    for (int a = 0; a < na; ++a)
+      for (int j = 0; j < ka[a]; ++j)
+        for (int c = 0; c < kns; ++c)
+          ns_next[(size_t)(cbase[a] + j) * kns + c] = Ra[a][(size_t)j * kns + c];
     // P = T - (omega / rho) D^{-1} A T
     const double rho = rho_dinv_a(L);
     H.rho.push_back(rho);
@@ -364,12 +468,17 @@ bool amg_build(const HostLevel& fine, const std::vector<std::complex<double>>& p
     P.ci = aci;
     P.v.resize(at.size());
     const double w = prm.omega_p / rho;
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < n; ++i) {
+      // (A T has every column of T's row i: A holds the diagonal)
+      int f = trp[i];
       for (int e = arp[i]; e < arp[i + 1]; ++e) {
         double v = -w * at[e] / d[i];
-        if (aci[e] == agg[i]) v += tv[i];
+        while (f < trp[i + 1] && tci[f] < aci[e]) ++f;
+        if (f < trp[i + 1] && tci[f] == aci[e]) v += tv[f];
         P.v[e] = v;
       }
+    }
+    (void)agg_first;
     HostCsrP R;
     R.n = nc;
     R.m = n;
@@ -430,6 +539,10 @@ bool amg_build(const HostLevel& fine, const std::vector<std::complex<double>>& p
     H.P.push_back(std::move(P));
     H.R.push_back(std::move(R));
     H.levels.push_back(std::move(C));
+    ns.swap(ns_next);
+    // translations alone keep whole nodes of bs dofs; with rigid-body modes
+    // the aggregates' dof counts vary and coarser levels aggregate scalar dofs
+    if (rigid_modes) lev_block = 1;
   }
   const int nc = H.levels.back().n;
   if (nc > prm.dense_max) {

@@ -29,6 +29,12 @@ struct AmgParams {
   int max_levels = 10;
   int block = 1;          // dofs per node (node-major numbering): nodes are aggregated,
                           // and each aggregate gets one tentative column per dof
+  // node coordinates (nodes x block, node-major, same node order as the
+  // fine level) for block 2 or 3: the tentative prolongator then carries the
+  // rigid-body modes (translations and rotations: 3 in 2D, 6 in 3D) instead
+  // of the translations alone, and the coarser levels aggregate scalar dofs
+  // with the modes carried as the R factors of the aggregates
+  const std::vector<double>* xyz = nullptr;
 };
 
 struct AmgHierarchy {

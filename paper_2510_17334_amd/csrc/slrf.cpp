@@ -389,8 +389,10 @@ std::shared_ptr<const HostSetup> analyse(const slrf_csr* A, const slrf_csr* B,
   key = fnv1a(key, cl.data(), cl.size() * sizeof(int));
   key = fnv1a(key, av.data(), av.size() * sizeof(double));
   key = fnv1a(key, bv.data(), bv.size() * sizeof(double));
-  const int32_t kopt[4] = {opt.reorder, opt.amg_block, amg ? 1 : 0, n};
+  const int32_t kopt[5] = {opt.reorder, opt.amg_block, amg ? 1 : 0, n,
+                           opt.node_xyz != nullptr ? 1 : 0};
   key = fnv1a(key, kopt, sizeof(kopt));
+  if (opt.node_xyz) key = fnv1a(key, opt.node_xyz, sizeof(double) * n);
   {
     std::lock_guard<std::mutex> lk(g_an_mu);
     if (g_an && g_an_key == key) {
@@ -488,6 +490,17 @@ std::shared_ptr<const HostSetup> analyse(const slrf_csr* A, const slrf_csr* B,
     fine.b = hs->b;
     AmgParams prm;
     prm.block = hs->block;
+    std::vector<double> xyz;
+    if (opt.node_xyz && (hs->block == 2 || hs->block == 3)) {
+      // coordinates in the final node order (a node's dofs stay together)
+      const int bs = hs->block;
+      xyz.resize(n);
+      for (int k = 0; k < n / bs; ++k) {
+        const int old = hs->reorder ? hs->order[bs * k] / bs : k;
+        for (int c = 0; c < bs; ++c) xyz[(size_t)k * bs + c] = opt.node_xyz[(size_t)old * bs + c];
+      }
+      prm.xyz = &xyz;
+    }
     std::string aerr;
     if (!amg_build(fine, {}, prm, hs->H, aerr)) {
       err = "AMG setup: " + aerr;

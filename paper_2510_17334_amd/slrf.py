@@ -48,7 +48,8 @@ class Options(C.Structure):
                 ("max_slots", C.c_int32), ("spmm_variant", C.c_int32), ("reorder", C.c_int32),
                 ("tol_lin", C.c_double),
                 ("inner_rtol", C.c_double),
-                ("tol_eig", C.c_double), ("amg_block", C.c_int32)]
+                ("tol_eig", C.c_double), ("amg_block", C.c_int32),
+                ("node_xyz", C.c_void_p)]
 
 
 class FilterStats(C.Structure):
@@ -202,7 +203,7 @@ class Handle:
     def __init__(self, indptr, indices, a, b, gamma: float, poles, weights,
                  options: Optional[Options] = None, device: str = "cuda", stream=None,
                  max_cols: int = 64, budget: float = 0.25,
-                 workspace_bytes: Optional[int] = None):
+                 workspace_bytes: Optional[int] = None, coords=None):
         torch = _torch()
         self._L = lib()
         self.device = torch.device(device)
@@ -225,6 +226,13 @@ class Handle:
         zp = (Zd * self.npoles)(*[Zd(p.real, p.imag) for p in poles])
         zw = (Zd * self.npoles)(*[Zd(w.real, w.imag) for w in weights])
         self.options = options if options is not None else default_options()
+        if coords is not None:
+            # node coordinates for the AMG's rigid-body modes (kept alive here)
+            self._coords = np.ascontiguousarray(coords, dtype=np.float64)
+            opt = Options()
+            C.pointer(opt)[0] = self.options
+            opt.node_xyz = self._coords.ctypes.data
+            self.options = opt
         self._h = C.c_void_p()
         torch.cuda.synchronize(self.device)
         self._A, self._B = A, B
@@ -253,6 +261,9 @@ class Handle:
 
     @classmethod
     def from_pencil(cls, p, gamma, poles, weights, options=None, **kw):
+        """Handle of a slrf_inputs.Pencil (its node coordinates, if any, go to the AMG)."""
+        if getattr(p, "coords", None) is not None and "coords" not in kw:
+            kw["coords"] = p.coords
         return cls(p.indptr, p.indices, p.a, p.b, gamma, poles, weights, options, **kw)
 
     def _check(self, st: int, allow=()):

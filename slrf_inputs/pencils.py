@@ -43,6 +43,8 @@ class Pencil:
     elem_param: Optional[np.ndarray] = None  # float64 [nelem]: the parameter theta_e
     ke_ref: Optional[np.ndarray] = None  # float64 [ndof_e, ndof_e]: dA/dtheta_e
     me_ref: Optional[np.ndarray] = None  # float64 [ndof_e, ndof_e]: element mass
+    # Optional node coordinates (vector-valued pencils, node-major dofs):
+    coords: Optional[np.ndarray] = None  # float64 [n_nodes, dofs per node]
 
     @property
     def n(self) -> int:
@@ -283,6 +285,7 @@ def hex_elasticity_pencil(ne: int, young: np.ndarray, nu: float = 0.3, rho: floa
     bv = np.broadcast_to(me.reshape(1, -1), av.shape)
     indptr, indices, a, b = _assemble_shared(ri[ok], ci[ok], av[ok], bv[ok], nfree)
     p = Pencil(indptr, indices, a, b, name=f"hex_elast_{ne}")
+    p.coords = np.indices((nn,) * 3).reshape(3, -1).T[free.reshape(-1)] * h
     p.elem_dofs = dof.astype(np.int32)
     p.elem_param = young.copy()
     p.ke_ref = ke

@@ -4,7 +4,7 @@
 //   host_driver <pencil.bin> <out.bin> order <block>
 //   host_driver <pencil.bin> <out.bin> block
 //   host_driver <pencil.bin> <out.bin> halo <hmax> <rows_cap>
-//   host_driver <pencil.bin> <out.bin> amg <block> <sigma_re> <sigma_im>
+//   host_driver <pencil.bin> <out.bin> amg <block> <sigma_re> <sigma_im> [<xyz.bin>]
 //   host_driver <pencil.bin> <out.bin> ugroup <R> <U>
 // pencil.bin: int32 n, int32 nnz, int32 rp[n+1], int32 ci[nnz], f64 a[nnz], f64 b[nnz]
 #include <complex>
@@ -73,6 +73,15 @@ int main(int argc, char** argv) {
   } else if (mode == "amg") {
     AmgParams prm;
     prm.block = std::atoi(argv[4]);
+    std::vector<double> xyz;
+    if (argc > 7) {  // node coordinates: float64 [n] (nodes x block)
+      FILE* fx = std::fopen(argv[7], "rb");
+      if (!fx) return 3;
+      xyz.resize(n);
+      if (std::fread(xyz.data(), 8, n, fx) != (size_t)n) return 3;
+      std::fclose(fx);
+      prm.xyz = &xyz;
+    }
     AmgHierarchy H;
     std::string err;
     std::vector<std::complex<double>> poles{{std::atof(argv[5]), std::atof(argv[6])}};

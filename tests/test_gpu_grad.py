@@ -115,11 +115,11 @@ def test_elasticity32_solve_and_gradient_full_size():
     p = c["pencil"]
     assert p.n == gold["n"]
     poles, weights = si.slrf_poles(gold["gamma"])
-    # Algorithm 2 (locking, warm start, It_max-linear = 60); point Jacobi: the
-    # scalar-block aggregation hierarchy lacks the rotation modes elasticity needs
-    opt = P.default_options(precision=P.SLRF_PREC_MIXED, precond=P.SLRF_PC_JACOBI, restart=30,
+    # Algorithm 2 (locking, warm start, It_max-linear = 60); AMG whose coarse
+    # space carries the rigid-body modes (node coordinates from the pencil)
+    opt = P.default_options(precision=P.SLRF_PREC_MIXED, precond=P.SLRF_PC_AMG, restart=30,
                             tol_lin=1e-10, lock=1, warm_start=1, max_outer=60, it_max_lin=60)
-    h = P.Handle.from_pencil(p, gold["gamma"], poles, weights, opt)
+    h = P.Handle.from_pencil(p, gold["gamma"], poles, weights, opt, max_cols=c["L"])
     V1 = _dev(si.start_block(p.n, c["L"], c["seed"]))
     theta, X, nconv, st = h.slrf_solve(c["count"], V1)
     assert nconv == c["count"]

@@ -313,3 +313,62 @@ def test_row_group_format_reproduces_csr(driver, which, R, U):
             assert np.array_equal(ab[e0:e1, r, 0][hit], A.data[lo:hi])
             assert np.array_equal(ab[e0:e1, r, 1][hit], B.data[lo:hi])
             assert np.all(ab[e0:e1, r][~hit] == 0.0)
+
+
+def _read_amg(r):
+    assert r.i() == 1
+    nl = r.i()
+    levels = []
+    for _ in range(nl):
+        m = r.i()
+        rp, ci, a, b = r.arr(np.int32), r.arr(np.int32), r.arr(np.float64), r.arr(np.float64)
+        levels.append((sp.csr_matrix((a, ci, rp), shape=(m, m)),
+                       sp.csr_matrix((b, ci, rp), shape=(m, m))))
+    Ps = []
+    for _ in range(nl - 1):
+        nr, nc = r.i(), r.i()
+        rp, ci, v = r.arr(np.int32), r.arr(np.int32), r.arr(np.float64)
+        Ps.append(sp.csr_matrix((v, ci, rp), shape=(nr, nc)))
+        r.i()
+        r.arr(np.int32), r.arr(np.int32), r.arr(np.float64)
+    return levels, Ps
+
+
+@pytest.mark.parametrize("coords", [True, False])
+def test_amg_rigid_body_modes_in_the_coarse_space(driver, coords):
+    """With node coordinates the first prolongator reproduces all six rigid-body
+    modes of 3D elasticity (on an unclamped body they span the kernel of A, so
+    P = (I - w D^-1 A) T keeps them exactly); with translations alone the three
+    rotations are missing from the coarse space.  The Galerkin property holds
+    at every level either way."""
+    exe, d = driver
+    ne = 6
+    p = si.hex_elasticity_pencil(ne, np.exp(np.random.default_rng(2).normal(0, .3, ne ** 3)),
+                                 clamp=False)
+    args = ["amg", 3, 10.0, 10.0]
+    if coords:
+        p.coords.astype(np.float64).tofile(d / "xyz.bin")
+        args.append(str(d / "xyz.bin"))
+    levels, Ps = _read_amg(_run(driver, p, *args))
+    assert len(Ps) >= 1
+    for l, P in enumerate(Ps):
+        for M0, M1 in zip(levels[l], levels[l + 1]):
+            G = (P.T @ M0 @ P).toarray()
+            assert np.abs(M1.toarray() - G).max() <= 1e-12 * np.abs(G).max()
+    x = p.coords
+    nn = x.shape[0]
+    modes = np.zeros((nn, 3, 6))
+    for c in range(3):
+        modes[:, c, c] = 1.0
+    modes[:, 1, 3], modes[:, 2, 3] = -x[:, 2], x[:, 1]
+    modes[:, 0, 4], modes[:, 2, 4] = x[:, 2], -x[:, 0]
+    modes[:, 0, 5], modes[:, 1, 5] = -x[:, 1], x[:, 0]
+    modes = modes.reshape(3 * nn, 6)
+    assert np.abs(p.A() @ modes).max() <= 1e-10 * np.abs(p.A()).max()  # the kernel of A
+    P0 = Ps[0].toarray()
+    c, *_ = np.linalg.lstsq(P0, modes, rcond=None)
+    res = np.linalg.norm(P0 @ c - modes, axis=0) / np.linalg.norm(modes, axis=0)
+    if coords:
+        assert res.max() <= 1e-10
+    else:
+        assert res[:3].max() <= 1e-10 and res[3:].min() > 1e-3

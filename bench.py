@@ -56,11 +56,13 @@ def parse():
     ap.add_argument("--workload", choices=["q1_3d", "batch64", "itmax", "elasticity48"],
                     default="q1_3d",
                     help="q1_3d: the metric workload; batch64: the 64 uneven Q1 diffusion "
-                         "pencils through the batched entry point; itmax: Algorithm 2 on the "
-                         "32^3 elasticity pencil swept over It_max-linear; elasticity48: "
+                         "pencils through the batched entry point; itmax: Algorithm 2 swept over "
+                         "It_max-linear (--itmax-pencil); elasticity48: "
                          "Algorithm 2 to all 200 eigenpairs of the 48^3 elasticity pencil")
-    ap.add_argument("--itmax", default="30,60,100,200,0",
-                    help="It_max-linear values of the itmax sweep (0 = no cap)")
+    ap.add_argument("--itmax", default="5,10,15,20,30,0,-1",
+                    help="It_max-linear values of the itmax sweep (0 = no cap, -1 = automatic)")
+    ap.add_argument("--itmax-pencil", choices=["q1_3d", "elasticity32"], default="q1_3d",
+                    help="pencil of the itmax sweep")
     ap.add_argument("--threads", type=int, default=8, help="host threads of the batched call")
     return ap.parse_args()
 
@@ -437,56 +439,62 @@ def run_batch64(args):
 
 
 def run_itmax(args):
-    """Algorithm 2 (locking, warm start) to all 50 eigenpairs of the clamped 32^3
-    elasticity pencil for each It_max-linear value: wall time, outer iterations,
-    inner iterations and the eigenvalue error against the oracle's values; the
-    fastest cap is reported as the chosen one."""
+    """Algorithm 2 (locking, warm start) to all eigenpairs in (0, gamma] for each
+    It_max-linear value (0 = no cap, -1 = the library's automatic choice): wall
+    time, outer and inner iterations and the eigenvalue error against the
+    oracle's values (the 32^3 elasticity pencil, 50 pairs) or the closed form
+    (the 3D Q1 pencil, 102 pairs); the fastest cap is reported as the chosen
+    one."""
     import numpy as np
     import torch
 
     import paper_2510_17334_amd as P
     import slrf_inputs as si
 
-    golden = os.path.join(ROOT, "tests", "golden", "elasticity32.json")
-    if not os.path.exists(golden):
-        print("itmax needs tests/golden/elasticity32.json; run tests/golden/make_elasticity32.py",
-              file=sys.stderr)
-        sys.exit(2)
-    gold = json.load(open(golden))
     torch.cuda.set_device(0)
-    c = si.config_elasticity(32, 0.3, 1005, 50, 75)
-    p = c["pencil"]
-    lam = np.array(gold["eigenvalues"])
-    poles, weights = si.slrf_poles(gold["gamma"])
-    V1 = torch.as_tensor(np.ascontiguousarray(si.start_block(p.n, c["L"], c["seed"]).T),
-                         device="cuda").t()
+    if args.itmax_pencil == "elasticity32":
+        gold = json.load(open(os.path.join(ROOT, "tests", "golden", "elasticity32.json")))
+        c = si.config_elasticity(32, 0.3, 1005, 50, 75)
+        p, gamma, nev, L, seed = c["pencil"], gold["gamma"], c["count"], c["L"], c["seed"]
+        lam = np.array(gold["eigenvalues"])
+        tol, workload = 1e-10, "elasticity_32"
+    else:
+        c = si.config_q1_3d(m=args.m, L=args.ncols)
+        p, gamma, nev, L, seed = c["pencil"], c["gamma"], c["nev"], c["L"], c["seed"]
+        l1 = si.q1_eigenvalues_1d(args.m)[:16]
+        lam = np.sort((l1[:, None, None] + l1[None, :, None] + l1[None, None, :]).ravel())[:nev]
+        tol, workload = 1e-8, f"q1_3d_m{args.m}"
+    poles, weights = si.slrf_poles(gamma)
+    V1 = torch.as_tensor(np.ascontiguousarray(si.start_block(p.n, L, seed).T), device="cuda").t()
     rows = []
     for itmax in [int(x) for x in args.itmax.split(",")]:
         opt = P.default_options(precision=P.SLRF_PREC_MIXED, precond=P.SLRF_PC_AMG,
-                                restart=30, tol_lin=1e-10, lock=1, warm_start=1, max_outer=100,
-                                it_max_lin=itmax)
-        h = P.Handle.from_pencil(p, gold["gamma"], poles, weights, opt, max_cols=c["L"])
+                                restart=args.restart, tol_lin=tol, lock=1, warm_start=1,
+                                max_outer=100, it_max_lin=itmax)
+        h = P.Handle.from_pencil(p, gamma, poles, weights, opt, max_cols=L, budget=0.6)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        theta, X, nconv, st = h.slrf_solve(c["count"], V1, allow_noconv=True)
+        theta, X, nconv, st = h.slrf_solve(nev, V1, allow_noconv=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         th = theta.cpu().numpy()
         err = float(np.max(np.abs(th - lam[:len(th)]) / lam[:len(th)])) if len(th) else None
         rows.append({"it_max_linear": itmax, "seconds": dt, "nconv": nconv,
                      "outer_iters": st["outer_iters"], "inner_iters": st["inner_iters"],
-                     "max_rel_eig_err": err})
-        print(f"It_max {itmax}: {dt:.2f} s, {st['outer_iters']} outer, nconv {nconv}, "
-              f"err {err}", file=sys.stderr, flush=True)
+                     "max_rel_eig_err": err, "auto_it_max": st["auto_it_max"]})
+        print(f"It_max {itmax}: {dt:.2f} s, {st['outer_iters']} outer, {st['inner_iters']} inner, "
+              f"nconv {nconv}, err {err}", file=sys.stderr, flush=True)
         h.close()
-    ok = [r for r in rows if r["nconv"] == c["count"]]
+        del X
+        torch.cuda.empty_cache()
+    ok = [r for r in rows if r["nconv"] == nev]
     best = min(ok, key=lambda r: r["seconds"]) if ok else None
     line = {"metric": "seconds to all eigenpairs in (0, gamma], Algorithm 2, vs It_max-linear",
             "value": best["seconds"] if best else None, "unit": "s", "n_gpus": 1,
             "higher_is_better": False, "dtype": "c64+f64", "data": "synthetic",
-            "config": {"workload": "elasticity_32", "n": p.n, "nnz": p.nnz, "nev": c["count"],
-                       "L": c["L"],
-                       "solver": "GCR(30)+AMG (rigid-body modes), mixed, lock + warm start"},
+            "config": {"workload": workload, "n": p.n, "nnz": p.nnz, "nev": nev, "L": L,
+                       "tol_lin": tol,
+                       "solver": f"GCR({args.restart})+AMG, mixed, lock + warm start"},
             "chosen_it_max_linear": best["it_max_linear"] if best else None, "sweep": rows}
     print(json.dumps(line, default=float))
 

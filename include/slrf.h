@@ -93,7 +93,10 @@ typedef struct {
                           dense coarsest solve); SLRF_PC_NONE                  */
   int32_t restart;     /* GCR restart length m, 1..32                           */
   int32_t maxit_lin;   /* cap on inner iterations per system (10000)            */
-  int32_t it_max_lin;  /* Algorithm 2 It_max-linear; 0 = off                    */
+  int32_t it_max_lin;  /* Algorithm 2 It_max-linear; 0 = off; -1 = automatic in
+                          slrf_solve: the first outer iteration solves to
+                          tol_lin, and half the median of its iteration counts
+                          (at least 3) caps the later warm-started ones     */
   int32_t max_outer;   /* outer iteration cap for slrf_solve                    */
   int32_t warm_start;  /* slrf_solve: Y_init = v/(theta - sigma) (Algorithm 2)   */
   int32_t lock;        /* slrf_solve: locking + B-orthogonalisation (Alg. 2)    */
@@ -176,6 +179,7 @@ typedef struct {
 typedef struct {
   int32_t outer_iters;
   int32_t nconv;
+  int32_t auto_it_max;   /* the cap chosen for it_max_lin = -1 (else 0)           */
   int64_t inner_iters;   /* summed over all filter calls                          */
   double seconds;
   double filter_seconds;

@@ -16,7 +16,10 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
 
 // Y_A = A X, Y_B = B X (one CSR pass), optionally E = A X - theta_c B X.
-// One wave per row; lanes cover 64 columns at a time.
+// One wave per row: the row's entries (column, a, b) are wave-uniform and come
+// through scalar loads, four at a time; each lane covers three columns of a
+// 192-column slice (lane, lane + 64, lane + 128), with the four entries' X rows
+// loaded together.
 __global__ __launch_bounds__(256) void k_spmm_real(int n, const int* __restrict__ rowptr,
                                                    const int* __restrict__ col,
                                                    const double* __restrict__ av,
@@ -26,23 +29,60 @@ __global__ __launch_bounds__(256) void k_spmm_real(int n, const int* __restrict_
                                                    double* __restrict__ BX,
                                                    const double* __restrict__ theta,
                                                    double* __restrict__ E) {
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int row = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   if (row >= n) return;
   const int e0 = rowptr[row], e1 = rowptr[row + 1];
-  for (int c0 = 0; c0 < nc; c0 += 64) {
-    const int c = c0 + lane;
-    if (c >= nc) break;
-    double sa = 0.0, sb = 0.0;
-    for (int e = e0; e < e1; ++e) {
-      const double x = X[(size_t)col[e] * ld + c];
-      sa = fma(av[e], x, sa);
-      sb = fma(bv[e], x, sb);
+  for (int c0 = 0; c0 < nc; c0 += 192) {
+    bool ok[3];
+    int cc[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      cc[t] = c0 + lane + 64 * t;
+      ok[t] = cc[t] < nc;
+      if (!ok[t]) cc[t] = 0;  // (an existing column: loaded, not stored)
     }
-    const size_t o = (size_t)row * ld + c;
-    if (AX) AX[o] = sa;
-    if (BX) BX[o] = sb;
-    if (E) E[o] = sa - theta[c] * sb;
+    double sa[3] = {0.0, 0.0, 0.0}, sb[3] = {0.0, 0.0, 0.0};
+    int e = e0;
+    for (; e + 4 <= e1; e += 4) {
+      int cl[4];
+      double a[4], b[4], x[4][3];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        cl[u] = col[e + u];
+        a[u] = av[e + u];
+        b[u] = bv[e + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int t = 0; t < 3; ++t) x[u][t] = X[(size_t)cl[u] * ld + cc[t]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          sa[t] = fma(a[u], x[u][t], sa[t]);
+          sb[t] = fma(b[u], x[u][t], sb[t]);
+        }
+    }
+    for (; e < e1; ++e) {
+      const int cl = col[e];
+      const double a = av[e], b = bv[e];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const double x = X[(size_t)cl * ld + cc[t]];
+        sa[t] = fma(a, x, sa[t]);
+        sb[t] = fma(b, x, sb[t]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      if (!ok[t]) continue;
+      const size_t o = (size_t)row * ld + cc[t];
+      if (AX) AX[o] = sa[t];
+      if (BX) BX[o] = sb[t];
+      if (E) E[o] = sa[t] - theta[cc[t]] * sb[t];
+    }
   }
 }
 
@@ -68,15 +108,18 @@ __global__ __launch_bounds__(256) void k_transpose(const double* __restrict__ in
 }
 
 // Partial Gram over one row chunk: part[chunk][i][j] = sum_{r in chunk} X[r,i] Y[r,j].
-// Workgroup tile 64x64 (2x2 waves, each 32x32 = 2x2 MFMA tiles).
+// Workgroup: one 32x32 tile of G (2x2 MFMA tiles) and one chunk of rows; its
+// four waves take interleaved 4-row steps of the chunk (the four together read
+// 16 consecutive rows), each loading the next step's operands while its MFMAs
+// run, and their partial tiles are summed through LDS in wave order.
 __global__ __launch_bounds__(256) void k_gram(int n, int p, int q, const double* __restrict__ X,
                                               int ldx, const double* __restrict__ Y, int ldy,
                                               double* __restrict__ part, int rows_per_chunk) {
-  const int nbq = (q + 63) / 64;
-  const int ib = (blockIdx.x / nbq) * 64, jb = (blockIdx.x % nbq) * 64;
+  __shared__ double red[4][32 * 32];
+  const int ntj = (q + 31) / 32;
+  const int ib = (blockIdx.x / ntj) * 32, jb = (blockIdx.x % ntj) * 32;
   const int chunk = blockIdx.y;
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int wi = ib + (wave >> 1) * 32, wj = jb + (wave & 1) * 32;
   const int kk = l >> 4, ii = l & 15;
   const int r0 = chunk * rows_per_chunk, r1 = min(r0 + rows_per_chunk, n);
   d4 acc[2][2];
@@ -84,32 +127,59 @@ __global__ __launch_bounds__(256) void k_gram(int n, int p, int q, const double*
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-  const int ca0 = wi + ii, ca1 = wi + 16 + ii, cb0 = wj + ii, cb1 = wj + 16 + ii;
-  for (int r = r0; r < r1; r += 4) {
+  const int ca0 = ib + ii, ca1 = ib + 16 + ii, cb0 = jb + ii, cb1 = jb + 16 + ii;
+  const bool oa0 = ca0 < p, oa1 = ca1 < p, ob0 = cb0 < q, ob1 = cb1 < q;
+  auto load = [&](int r, double& a0, double& a1, double& b0, double& b1) {
     const int row = r + kk;
     const bool okr = row < r1;
     const double* xr = X + (size_t)row * ldx;
     const double* yr = Y + (size_t)row * ldy;
-    const double a0 = (okr && ca0 < p) ? xr[ca0] : 0.0;
-    const double a1 = (okr && ca1 < p) ? xr[ca1] : 0.0;
-    const double b0 = (okr && cb0 < q) ? yr[cb0] : 0.0;
-    const double b1 = (okr && cb1 < q) ? yr[cb1] : 0.0;
-    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    a0 = (okr && oa0) ? xr[ca0] : 0.0;
+    a1 = (okr && oa1) ? xr[ca1] : 0.0;
+    b0 = (okr && ob0) ? yr[cb0] : 0.0;
+    b1 = (okr && ob1) ? yr[cb1] : 0.0;
+  };
+  // groups of D steps: the next group's operands are loaded while the current
+  // group's MFMAs run (rows past the chunk load zeros)
+  constexpr int D = 4;
+  double a[D][2], b[D][2], na[D][2], nb[D][2];
+  int r = r0 + wave * 4;
+#pragma unroll
+  for (int u = 0; u < D; ++u) load(r + 16 * u, a[u][0], a[u][1], b[u][0], b[u][1]);
+  for (; r < r1; r += 16 * D) {
+#pragma unroll
+    for (int u = 0; u < D; ++u) load(r + 16 * (D + u), na[u][0], na[u][1], nb[u][0], nb[u][1]);
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][0], b[u][0], acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][0], b[u][1], acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][1], b[u][0], acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][1], b[u][1], acc[1][1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+      a[u][0] = na[u][0];
+      a[u][1] = na[u][1];
+      b[u][0] = nb[u][0];
+      b[u][1] = nb[u][1];
+    }
   }
-  double* pc = part + (size_t)chunk * p * q;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = wi + a * 16 + 4 * v + (l >> 4);
-        const int j = wj + b * 16 + (l & 15);
-        if (i < p && j < q) pc[(size_t)i * q + j] = acc[a][b][v];
+        const int i = a * 16 + 4 * v + (l >> 4);
+        const int j = b * 16 + (l & 15);
+        red[wave][i * 32 + j] = acc[a][b][v];
       }
+  __syncthreads();
+  double* pc = part + (size_t)chunk * p * q;
+  for (int t = threadIdx.x; t < 32 * 32; t += 256) {
+    const int i = ib + t / 32, j = jb + t % 32;
+    if (i < p && j < q) pc[(size_t)i * q + j] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+  }
 }
 
 __global__ void k_chunk_sum(const double* __restrict__ part, int nchunk, int p, int q,
@@ -122,42 +192,81 @@ __global__ void k_chunk_sum(const double* __restrict__ part, int nchunk, int p, 
   G[(size_t)i * ldg + j] = s;
 }
 
-// Z = alpha X S + beta Z.  Workgroup: 64 rows (4 waves x 16 rows) x 64 columns
-// (4 MFMA tiles per wave).
+// Z = alpha X S + beta Z.  Workgroup: 128 rows (4 waves x 32 rows) x 32
+// columns (2x2 MFMA tiles per wave); the 32 columns of S are staged in LDS 64
+// rows of k at a time and shared by the waves, each of which loads its next
+// X operands while its MFMAs run.
+constexpr int kGemmK = 64;
 __global__ __launch_bounds__(256) void k_gemm_tall(int n, int p, int q, double alpha,
                                                    const double* __restrict__ X, int ldx,
                                                    const double* __restrict__ S, int lds,
                                                    double beta, double* __restrict__ Z, int ldz) {
+  __shared__ double sS[kGemmK][32];
+  const int ncb = (q + 31) / 32;
+  const int rb = blockIdx.x / ncb, cb = blockIdx.x % ncb;  // column blocks fastest: X from L2
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int r0 = blockIdx.x * 64 + wave * 16;
-  const int jb = blockIdx.y * 64;
+  const int r0 = rb * 128 + wave * 32;
+  const int jb = cb * 32;
   const int kk = l >> 4, ii = l & 15;
-  d4 acc[4];
+  d4 acc[2][2];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-  const int arow = r0 + ii;
-  const bool okrow = arow < n;
-  for (int k0 = 0; k0 < p; k0 += 4) {
-    const int kc = k0 + kk;
-    const double a = (okrow && kc < p) ? X[(size_t)arow * ldx + kc] : 0.0;
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int j = jb + t * 16 + ii;
-      const double b = (kc < p && j < q) ? S[(size_t)kc * lds + j] : 0.0;
-      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  const int ar0 = r0 + ii, ar1 = r0 + 16 + ii;
+  const bool ok0 = ar0 < n, ok1 = ar1 < n;
+  const double* x0 = X + (size_t)(ok0 ? ar0 : 0) * ldx;
+  const double* x1 = X + (size_t)(ok1 ? ar1 : 0) * ldx;
+  for (int k0 = 0; k0 < p; k0 += kGemmK) {
+    const int kn = min(kGemmK, p - k0);
+    __syncthreads();  // (the previous slab is consumed)
+    for (int t = threadIdx.x; t < kGemmK * 32; t += 256) {
+      const int kr = t / 32, j = jb + t % 32;
+      sS[kr][t % 32] = (kr < kn && j < q) ? S[(size_t)(k0 + kr) * lds + j] : 0.0;
+    }
+    __syncthreads();
+    auto ld = [&](int kc, double& a0, double& a1) {
+      const bool okk = kc < p;
+      a0 = (ok0 && okk) ? x0[kc] : 0.0;
+      a1 = (ok1 && okk) ? x1[kc] : 0.0;
+    };
+    // the slab's X operands in groups of four k-steps, the next group
+    // loaded while the current one's MFMAs run (past p: zeros)
+    double a[4][2], na[4][2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) ld(k0 + 4 * u + kk, a[u][0], a[u][1]);
+    for (int kr = 0; kr < kn; kr += 16) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) ld(k0 + kr + 16 + 4 * u + kk, na[u][0], na[u][1]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = kr + 4 * u + kk;  // (< kGemmK + 12: rows past kn hold zeros)
+        const double b0 = k < kGemmK ? sS[k][ii] : 0.0, b1 = k < kGemmK ? sS[k][16 + ii] : 0.0;
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][0], b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][0], b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][1], b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][1], b1, acc[1][1], 0, 0, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u][0] = na[u][0];
+        a[u][1] = na[u][1];
+      }
     }
   }
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = r0 + 4 * v + (l >> 4);
-      const int j = jb + t * 16 + (l & 15);
-      if (i < n && j < q) {
-        const size_t o = (size_t)i * ldz + j;
-        Z[o] = alpha * acc[t][v] + (beta == 0.0 ? 0.0 : beta * Z[o]);
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = r0 + a * 16 + 4 * v + (l >> 4);
+        const int j = jb + b * 16 + (l & 15);
+        if (i < n && j < q) {
+          const size_t o = (size_t)i * ldz + j;
+          Z[o] = alpha * acc[a][b][v] + (beta == 0.0 ? 0.0 : beta * Z[o]);
+        }
       }
-    }
 }
 
 __global__ __launch_bounds__(256) void k_colstats(int n, int nc, const double* __restrict__ X,
@@ -248,7 +357,7 @@ hipError_t launch_gram(int n, int p, int q, const double* X, int ldx, const doub
   if (p == 0 || q == 0) return hipSuccess;
   const int rows = (n + nchunk - 1) / nchunk;
   const int rpc = ((rows + 3) / 4) * 4;
-  dim3 grid(cdiv(p, 64) * cdiv(q, 64), nchunk);
+  dim3 grid(cdiv(p, 32) * cdiv(q, 32), nchunk);
   k_gram<<<grid, 256, 0, s>>>(n, p, q, X, ldx, Y, ldy, part, rpc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -260,8 +369,8 @@ hipError_t launch_gemm_tall(int n, int p, int q, double alpha, const double* X, 
                             const double* S, int lds, double beta, double* Z, int ldz,
                             hipStream_t s) {
   if (n == 0 || q == 0) return hipSuccess;
-  dim3 grid(cdiv(n, 64), cdiv(q, 64));
-  k_gemm_tall<<<grid, 256, 0, s>>>(n, p, q, alpha, X, ldx, S, lds, beta, Z, ldz);
+  k_gemm_tall<<<cdiv(n, 128) * cdiv(q, 32), 256, 0, s>>>(n, p, q, alpha, X, ldx, S, lds, beta,
+                                                          Z, ldz);
   return hipGetLastError();
 }
 

@@ -154,6 +154,11 @@ slrf_status fail_hip(slrf_ctx* h, hipError_t e, const char* what, int line) {
   return e == hipErrorOutOfMemory ? SLRF_E_NOMEM : SLRF_E_HIP;
 }
 
+// automatic It_max-linear: this fraction of the median iterations of the
+// first outer iteration's solves, at least kAutoItMaxMin
+constexpr double kAutoItMaxFrac = 0.5;
+constexpr int kAutoItMaxMin = 3;
+
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -257,7 +262,7 @@ slrf_status validate_options(slrf_ctx* h, const slrf_options& o) {
   if (o.restart < 1 || o.restart > kMaxRestart)
     return fail(h, SLRF_E_ARG, "restart must be in [1, 32]");
   if (o.maxit_lin < 1) return fail(h, SLRF_E_ARG, "maxit_lin must be >= 1");
-  if (o.it_max_lin < 0) return fail(h, SLRF_E_ARG, "it_max_lin must be >= 0");
+  if (o.it_max_lin < -1) return fail(h, SLRF_E_ARG, "it_max_lin must be >= -1");
   if (!(o.tol_lin >= 0.0) || !(o.tol_eig > 0.0))
     return fail(h, SLRF_E_ARG, "tolerances must be positive");
   if (!(o.inner_rtol >= 0.0 && o.inner_rtol < 1.0))
@@ -1897,18 +1902,39 @@ slrf_status slrf_solve(slrf_handle h, int32_t nev, int32_t L, const double* V1, 
   std::vector<double> lastTheta;
   std::vector<int> lastIdx;
   double fsec = 0, rsec = 0;
+  int auto_cap = 0;  // automatic It_max-linear (it_max_lin = -1)
   int k = 1;
   for (; k <= h->opt.max_outer; ++k) {
     const int nact = alg2 ? L - nconv : L;
     if (nact <= 0) break;
     slrf_filter_stats fst;
     std::memset(&fst, 0, sizeof(fst));
+    // automatic It_max-linear: the first outer iteration solves to tol_lin and
+    // its per-system iteration counts set the cap of the later (warm-started)
+    // ones
+    const int itmax_user = h->opt.it_max_lin;
+    std::vector<int32_t> its_first;
+    if (itmax_user < 0) {
+      if (k == 1) {
+        its_first.assign((size_t)nact * h->N, 0);
+        fst.sys_iters = its_first.data();
+        h->opt.it_max_lin = 0;
+      } else {
+        h->opt.it_max_lin = auto_cap;
+      }
+    }
     if (warm && !th_warm.empty())
       HIPCHK(hipMemcpyAsync(th_d, th_warm.data(), sizeof(double) * nact, hipMemcpyHostToDevice,
                             s));
     const auto tf = std::chrono::steady_clock::now();
     slrf_status fs = slrf_filter(h, nact, V, (warm && !th_warm.empty()) ? th_d : nullptr, U, &fst);
+    h->opt.it_max_lin = itmax_user;
     if (fs != SLRF_OK && fs != SLRF_E_NOCONV) return fs;
+    if (itmax_user < 0 && k == 1 && !its_first.empty()) {
+      std::vector<int32_t> v(its_first);
+      std::nth_element(v.begin(), v.begin() + v.size() / 2, v.end());
+      auto_cap = std::max(kAutoItMaxMin, (int)std::ceil(kAutoItMaxFrac * v[v.size() / 2]));
+    }
     fsec += std::chrono::duration<double>(std::chrono::steady_clock::now() - tf).count();
     if (stats) stats->inner_iters += fst.total_iters;
     // Rayleigh-Ritz (with B-orthogonalisation against the locked set)
@@ -2005,6 +2031,7 @@ slrf_status slrf_solve(slrf_handle h, int32_t nev, int32_t L, const double* V1, 
   if (nconv_out) *nconv_out = nconv;
   if (stats) {
     stats->outer_iters = std::min(k, h->opt.max_outer);
+    stats->auto_it_max = h->opt.it_max_lin < 0 ? auto_cap : 0;
     stats->nconv = nconv;
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     stats->filter_seconds = fsec;

@@ -63,7 +63,8 @@ class FilterStats(C.Structure):
 
 
 class SolveStats(C.Structure):
-    _fields_ = [("outer_iters", C.c_int32), ("nconv", C.c_int32), ("inner_iters", C.c_int64),
+    _fields_ = [("outer_iters", C.c_int32), ("nconv", C.c_int32), ("auto_it_max", C.c_int32),
+                ("inner_iters", C.c_int64),
                 ("seconds", C.c_double), ("filter_seconds", C.c_double),
                 ("rr_seconds", C.c_double)]
 

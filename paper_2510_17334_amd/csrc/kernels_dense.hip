@@ -29,9 +29,14 @@ __global__ __launch_bounds__(256) void k_spmm_real(int n, const int* __restrict_
                                                    double* __restrict__ BX,
                                                    const double* __restrict__ theta,
                                                    double* __restrict__ E) {
-  const int row = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  // XCD-aware order: each XCD takes a contiguous range of rows, so the X rows
+  // a neighbourhood gathers stay in one L2
+  const int nblk = (n + 3) / 4;
+  const int per = (nblk + 7) / 8;
+  const int blk = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  const int row = __builtin_amdgcn_readfirstlane(blk * 4 + (int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
-  if (row >= n) return;
+  if (blk >= nblk || row >= n) return;
   const int e0 = rowptr[row], e1 = rowptr[row + 1];
   for (int c0 = 0; c0 < nc; c0 += 192) {
     bool ok[3];
@@ -114,11 +119,20 @@ __global__ __launch_bounds__(256) void k_transpose(const double* __restrict__ in
 // run, and their partial tiles are summed through LDS in wave order.
 __global__ __launch_bounds__(256) void k_gram(int n, int p, int q, const double* __restrict__ X,
                                               int ldx, const double* __restrict__ Y, int ldy,
-                                              double* __restrict__ part, int rows_per_chunk) {
+                                              double* __restrict__ part, int rows_per_chunk,
+                                              int nchunk) {
   __shared__ double red[4][32 * 32];
   const int ntj = (q + 31) / 32;
-  const int ib = (blockIdx.x / ntj) * 32, jb = (blockIdx.x % ntj) * 32;
-  const int chunk = blockIdx.y;
+  const long ntile = (long)((p + 31) / 32) * ntj;
+  // XCD-aware order: each XCD takes a contiguous range of (chunk, tile) pairs,
+  // so the rows of a chunk are fetched into one XCD's L2 for all its tiles
+  const long total = ntile * nchunk;
+  const long per = (total + 7) / 8;
+  const long w8 = (long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (w8 >= total) return;
+  const int chunk = (int)(w8 / ntile);
+  const int tile = (int)(w8 % ntile);
+  const int ib = (tile / ntj) * 32, jb = (tile % ntj) * 32;
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int kk = l >> 4, ii = l & 15;
   const int r0 = chunk * rows_per_chunk, r1 = min(r0 + rows_per_chunk, n);
@@ -203,7 +217,14 @@ __global__ __launch_bounds__(256) void k_gemm_tall(int n, int p, int q, double a
                                                    double beta, double* __restrict__ Z, int ldz) {
   __shared__ double sS[kGemmK][32];
   const int ncb = (q + 31) / 32;
-  const int rb = blockIdx.x / ncb, cb = blockIdx.x % ncb;  // column blocks fastest: X from L2
+  // XCD-aware order: each XCD takes a contiguous range of (row block, column
+  // block) pairs, column blocks fastest, so an X row block is fetched into one
+  // L2 for all its column blocks
+  const long total = (long)((n + 127) / 128) * ncb;
+  const long per = (total + 7) / 8;
+  const long w8 = (long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (w8 >= total) return;
+  const int rb = (int)(w8 / ncb), cb = (int)(w8 % ncb);
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int r0 = rb * 128 + wave * 32;
   const int jb = cb * 32;
@@ -339,8 +360,8 @@ int colstat_chunks(int n) { return n <= 0 ? 1 : (n + kColRows - 1) / kColRows; }
 hipError_t launch_spmm_real(const DevPencil& P, const double* X, int ld, int nc, double* AX,
                             double* BX, const double* theta, double* E, hipStream_t s) {
   if (P.n == 0 || nc == 0) return hipSuccess;
-  k_spmm_real<<<cdiv(P.n, 4), 256, 0, s>>>(P.n, P.rowptr, P.col, P.a, P.b, X, ld, nc, AX, BX,
-                                           theta, E);
+  k_spmm_real<<<cdiv(cdiv(P.n, 4), 8) * 8, 256, 0, s>>>(P.n, P.rowptr, P.col, P.a, P.b, X, ld,
+                                                         nc, AX, BX, theta, E);
   return hipGetLastError();
 }
 
@@ -357,8 +378,8 @@ hipError_t launch_gram(int n, int p, int q, const double* X, int ldx, const doub
   if (p == 0 || q == 0) return hipSuccess;
   const int rows = (n + nchunk - 1) / nchunk;
   const int rpc = ((rows + 3) / 4) * 4;
-  dim3 grid(cdiv(p, 32) * cdiv(q, 32), nchunk);
-  k_gram<<<grid, 256, 0, s>>>(n, p, q, X, ldx, Y, ldy, part, rpc);
+  const size_t total = (size_t)cdiv(p, 32) * cdiv(q, 32) * nchunk;
+  k_gram<<<cdiv(total, 8) * 8, 256, 0, s>>>(n, p, q, X, ldx, Y, ldy, part, rpc, nchunk);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_chunk_sum<<<cdiv((size_t)p * q, 256), 256, 0, s>>>(part, nchunk, p, q, G, ldg);
@@ -369,8 +390,8 @@ hipError_t launch_gemm_tall(int n, int p, int q, double alpha, const double* X, 
                             const double* S, int lds, double beta, double* Z, int ldz,
                             hipStream_t s) {
   if (n == 0 || q == 0) return hipSuccess;
-  k_gemm_tall<<<cdiv(n, 128) * cdiv(q, 32), 256, 0, s>>>(n, p, q, alpha, X, ldx, S, lds, beta,
-                                                          Z, ldz);
+  const size_t total = (size_t)cdiv(n, 128) * cdiv(q, 32);
+  k_gemm_tall<<<cdiv(total, 8) * 8, 256, 0, s>>>(n, p, q, alpha, X, ldx, S, lds, beta, Z, ldz);
   return hipGetLastError();
 }
 

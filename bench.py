@@ -53,12 +53,13 @@ def parse():
     ap.add_argument("--precond", choices=["amg", "jacobi"], default="amg")
     ap.add_argument("--restart", type=int, default=5, help="GCR restart length m")
     ap.add_argument("--ncols", type=int, default=160)
-    ap.add_argument("--workload", choices=["q1_3d", "batch64", "itmax", "elasticity48"],
+    ap.add_argument("--workload", choices=["q1_3d", "batch64", "itmax", "elasticity48", "fd32"],
                     default="q1_3d",
                     help="q1_3d: the metric workload; batch64: the 64 uneven Q1 diffusion "
                          "pencils through the batched entry point; itmax: Algorithm 2 swept over "
                          "It_max-linear (--itmax-pencil); elasticity48: "
-                         "Algorithm 2 to all 200 eigenpairs of the 48^3 elasticity pencil")
+                         "Algorithm 2 to all 200 eigenpairs of the 48^3 elasticity pencil; fd32: the "
+                         "adjoint gradient vs central differences on the 32^3 elasticity mesh")
     ap.add_argument("--itmax", default="5,10,15,20,30,0,-1",
                     help="It_max-linear values of the itmax sweep (0 = no cap, -1 = automatic)")
     ap.add_argument("--itmax-pencil", choices=["q1_3d", "elasticity32"], default="q1_3d",
@@ -587,6 +588,79 @@ def run_elasticity48(args):
     print(json.dumps(line, default=float))
 
 
+def run_fd32(args):
+    """Central differences of the eigenvalue gradient on the differentiation
+    workload (clamped 32^3 hex elasticity, n = 104,544, 50 eigenvalues, L = 75):
+    d(sum of the 50 smallest eigenvalues)/dE_e by the adjoint kernel vs
+    (S(E + d e_e) - S(E - d e_e)) / 2d with d = 1e-6 E_e on the 20 sampled
+    elements of the golden file.  Every eigenvalue sum comes from FP64
+    Algorithm 2 on the GPU (AMG with rigid-body modes, Ritz residuals 1e-11);
+    the perturbed solves start from the unperturbed eigenvectors."""
+    import numpy as np
+    import torch
+
+    import paper_2510_17334_amd as P
+    import slrf_inputs as si
+
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "elasticity32.json")))
+    torch.cuda.set_device(0)
+    c = si.config_elasticity(32, 0.3, 1005, 50, 75)
+    p, nev, L = c["pencil"], c["count"], c["L"]
+    poles, weights = si.slrf_poles(gold["gamma"])
+    opt = P.default_options(precision=P.SLRF_PREC_FP64, precond=P.SLRF_PC_AMG, restart=5,
+                            tol_lin=1e-14, it_max_lin=20, lock=1, warm_start=1, max_outer=60,
+                            tol_eig=1e-11)
+
+    def solve(pen, V):
+        h = P.Handle.from_pencil(pen, gold["gamma"], poles, weights, opt, max_cols=L)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        th, X, nconv, st = h.slrf_solve(nev, V)
+        torch.cuda.synchronize()
+        if nconv != nev:
+            print(f"solve converged {nconv} of {nev} pairs", file=sys.stderr)
+            sys.exit(1)
+        return h, th, X, time.perf_counter() - t, st["outer_iters"]
+
+    V1 = torch.as_tensor(np.ascontiguousarray(si.start_block(p.n, L, c["seed"]).T),
+                         device="cuda").t()
+    h, th, X, t0, it0 = solve(p, V1)
+    g = h.slrf_eig_grad(X, th.cpu().numpy(), np.ones(nev), p.elem_dofs, p.ke_ref).cpu().numpy()
+    h.close()
+    lam_err = float(np.max(np.abs(th.cpu().numpy() - np.array(gold["eigenvalues"]))
+                           / np.array(gold["eigenvalues"])))
+    Vw = torch.cat([X, V1[:, nev:]], 1)
+    rows, warm_s, warm_it = [], [], []
+    for e in gold["sample_elements"]:
+        d = 1e-6 * c["young"][e]
+        sums = []
+        for sgn in (1.0, -1.0):
+            y = c["young"].copy()
+            y[e] += sgn * d
+            hp, thp, _, dt, it = solve(si.hex_elasticity_pencil(32, y), Vw)
+            sums.append(float(thp.sum()))
+            warm_s.append(dt)
+            warm_it.append(it)
+            hp.close()
+        fd = (sums[0] - sums[1]) / (2 * d)
+        rows.append({"element": int(e), "adjoint": float(g[e]), "central_difference": fd,
+                     "rel_diff": abs(fd - g[e]) / abs(g[e])})
+        print(f"element {e}: rel diff {rows[-1]['rel_diff']:.2e}", file=sys.stderr, flush=True)
+    worst = max(r["rel_diff"] for r in rows)
+    line = {"metric": "max relative difference, adjoint gradient vs central differences",
+            "value": worst, "unit": "1", "n_gpus": 1, "higher_is_better": False,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "elasticity_32_fd", "n": p.n, "nev": nev, "L": L,
+                       "elements": len(rows), "relative_step": 1e-6,
+                       "solver": "FP64 GCR(5)+AMG (rigid-body modes), It_max 20, tol_eig 1e-11"},
+            "base_solve": {"seconds": t0, "outer_iters": it0,
+                           "max_rel_eig_err_vs_oracle": lam_err},
+            "perturbed_solves": {"count": len(warm_s), "mean_seconds": float(np.mean(warm_s)),
+                                 "mean_outer_iters": float(np.mean(warm_it))},
+            "elements": rows}
+    print(json.dumps(line, default=float))
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -602,6 +676,9 @@ def main():
         return
     if args.workload == "elasticity48":
         run_elasticity48(args)
+        return
+    if args.workload == "fd32":
+        run_fd32(args)
         return
     import numpy as np
     import torch

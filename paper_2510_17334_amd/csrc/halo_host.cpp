@@ -83,7 +83,7 @@ bool build_halo(int n, const std::vector<int>& rp, const std::vector<int>& ci,
     for (int r = r0; r < r1; ++r) {
       const int s = r / S, ln = r % S;
       for (int e = rp[r]; e < rp[r + 1]; ++e) {
-        const size_t k = (size_t)(out.sptr[s] + (e - rp[r])) * S + ln;
+        const size_t k = halo_entry(out.sptr[s], e - rp[r], ln);
         out.lcol[k] = (uint16_t)pos[ci[e]];
         out.ab[2 * k] = a[e];
         out.ab[2 * k + 1] = b[e];

@@ -2,6 +2,7 @@
 // the gathered operand staged in LDS).
 #pragma once
 
+#include <cstddef>
 #include <cstdint>
 #include <vector>
 
@@ -10,10 +11,13 @@ namespace slrf {
 // Rows are cut into tiles made of whole slices of kHaloSlice consecutive rows.
 // A tile's halo is the sorted set of columns its rows reference; a tile grows
 // slice by slice while its halo stays within hmax entries and its rows within
-// rows_cap.  Entries are stored slice-major: entry j of row r (slice s = r / 8,
-// lane t = r % 8) sits at (sptr[s] + j) * 8 + t, with its column given as the
-// position in the tile's halo; slen holds the row lengths (0 past n), a slice
-// is as wide as its longest row rounded up to a multiple of kHaloPad, and
+// rows_cap.  Entries are stored slice-major in groups of kHaloPad per row:
+// entry j of row r (slice s = r / 8, lane t = r % 8) sits at
+// sptr[s] * 8 + (j / 4) * 32 + t * 4 + j % 4, so one row's four entries of a
+// group are contiguous (one 8-byte read of their local columns, 16-byte reads
+// of their coefficients) and the 8 rows' groups follow each other; the column
+// is given as the position in the tile's halo; slen holds the row lengths (0
+// past n), a slice is as wide as its longest row rounded up to a multiple of kHaloPad, and
 // shorter rows are padded with entries of local column 0 and coefficients 0
 // (they add 0 * z for a halo row of the same system: the kernels need no
 // per-entry predicate).
@@ -32,7 +36,13 @@ struct HostHalo {
 
 constexpr int kHaloSlice = 8;
 constexpr int kHaloPassSlices = 4;  // slices formed together by one workgroup pass
-constexpr int kHaloPad = 4;         // slice widths are multiples of this
+constexpr int kHaloPad = 4;         // slice widths are multiples of this (= the group size)
+
+// Position of entry j of lane t in slice s (sptr_s = sptr[s]).
+inline size_t halo_entry(int sptr_s, int j, int t) {
+  return (size_t)sptr_s * kHaloSlice + (size_t)(j / kHaloPad) * (kHaloSlice * kHaloPad) +
+         (size_t)t * kHaloPad + (size_t)(j % kHaloPad);
+}
 
 // Returns false (format not built) when a single slice references more than
 // hmax columns or hmax exceeds the 16-bit local index range.  The matrix may

@@ -48,7 +48,8 @@ struct DevPencil {
   // Halo-tile format (optional, hx_ntile == 0: absent): rows cut into tiles of
   // whole 8-row slices whose referenced columns (the tile's halo, sorted)
   // number at most kHaloMaxH; entry j of row r is stored at
-  // (hx_sptr[r / 8] + j) * 8 + r % 8 with its column as a halo position.
+  // hx_sptr[r / 8] * 8 + (j / 4) * 32 + (r % 8) * 4 + j % 4 (groups of 4
+  // entries per row) with its column as a halo position.
   int hx_ntile = 0, hx_hmax = 0, hx_emax = 0;  // tiles, largest halo, most entries of a pass
   const int* hx_trow = nullptr;   // [ntile + 1] first row of each tile
   const int* hx_hptr = nullptr;   // [ntile + 1] halo offsets

@@ -536,6 +536,52 @@ struct HaloView {
   const void* ab;
 };
 
+// Local columns staged in LDS as byte offsets of the halo row: every staged
+// halo row is 128 bytes (eight 16-byte lane vectors) and local indices stay
+// below 512 (the tile halo caps), so shifting a packed pair of 16-bit indices
+// left by 7 scales both halves at once.
+// Local columns are staged in LDS as 32-bit byte offsets of the halo row
+// (every staged halo row is 128 bytes: eight 16-byte lane vectors), so one
+// 16-byte read yields a group's four operand addresses.  `v` holds eight
+// 16-bit local columns; `out` receives their eight offsets.
+__device__ __forceinline__ void halo_stage_cols(uint4 v, uint4* out) {
+  out[0] = make_uint4((v.x & 0xffffu) << 7, (v.x >> 16) << 7, (v.y & 0xffffu) << 7,
+                      (v.y >> 16) << 7);
+  out[1] = make_uint4((v.z & 0xffffu) << 7, (v.z >> 16) << 7, (v.w & 0xffffu) << 7,
+                      (v.w >> 16) << 7);
+}
+template <typename V>
+__device__ __forceinline__ V halo_at(const V* base, unsigned byte_off) {
+  return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+__device__ __forceinline__ void halo_ab4(const float2* p, float2 (&ab)[4]) {
+  const float4 u = reinterpret_cast<const float4*>(p)[0];
+  const float4 v = reinterpret_cast<const float4*>(p)[1];
+  ab[0] = make_float2(u.x, u.y);
+  ab[1] = make_float2(u.z, u.w);
+  ab[2] = make_float2(v.x, v.y);
+  ab[3] = make_float2(v.z, v.w);
+}
+__device__ __forceinline__ void halo_ab4(const double2* p, double2 (&ab)[4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) ab[i] = p[i];
+}
+__device__ __forceinline__ void halo_val4(const float* p, float (&v)[4]) {
+  const float4 u = *reinterpret_cast<const float4*>(p);
+  v[0] = u.x;
+  v[1] = u.y;
+  v[2] = u.z;
+  v[3] = u.w;
+}
+__device__ __forceinline__ void halo_val4(const double* p, double (&v)[4]) {
+  const double2 u = reinterpret_cast<const double2*>(p)[0];
+  const double2 w = reinterpret_cast<const double2*>(p)[1];
+  v[0] = u.x;
+  v[1] = u.y;
+  v[2] = w.x;
+  v[3] = w.y;
+}
+
 // (ZH: the gathered operand z is complex bfloat16, widened to complex float
 // when staged; complex-float sweeps only)
 template <typename T, int EPI, bool ZH = false>
@@ -555,7 +601,7 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
   extern __shared__ __attribute__((aligned(16))) double smem_d[];  // 16-byte vectors live here
   V* sZ = reinterpret_cast<V*>(smem_d);                            // [hmax][8]
   AB* s_ab = reinterpret_cast<AB*>(sZ + (size_t)g.rpb * 8);        // [emax]
-  unsigned short* s_lc = reinterpret_cast<unsigned short*>(s_ab + hv.emax);  // [emax]
+  unsigned* s_lc = reinterpret_cast<unsigned*>(s_ab + hv.emax);  // [emax]
   int* sH = reinterpret_cast<int*>(s_lc + hv.emax);                          // [hmax]
   __shared__ int s_sp[kHaloTileRows / 8 + 1];  // slice offsets of the tile
   __shared__ int s_uact[kHaloMaxG];
@@ -624,13 +670,15 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
     const uint4* __restrict__ glc = reinterpret_cast<const uint4*>(hv.lcol) + e0 / 8;
     const uint4* __restrict__ gab =
         static_cast<const uint4*>(hv.ab) + (size_t)e0 * sizeof(AB) / 16;
-    for (int t = tid; t < nlc; t += kThreads) reinterpret_cast<uint4*>(s_lc)[t] = glc[t];
+    for (int t = tid; t < nlc; t += kThreads)
+      halo_stage_cols(glc[t], reinterpret_cast<uint4*>(s_lc) + 2 * t);
     for (int t = tid; t < nab; t += kThreads) reinterpret_cast<uint4*>(s_ab)[t] = gab[t];
   }
   // this wave's slice
   const int row = r0 + w * 8 + rr;
-  const int wdt = w < nsl ? s_sp[w + 1] - s_sp[w] : 0;
-  const int soff = w < nsl ? (s_sp[w] - s_sp[0]) * 8 + rr : 0;
+  // (a wave's slice width is uniform across the wave: scalar loop control)
+  const int wdt = __builtin_amdgcn_readfirstlane(w < nsl ? s_sp[w + 1] - s_sp[w] : 0);
+  const int soff = w < nsl ? (s_sp[w] - s_sp[0]) * 8 + rr * 4 : 0;  // (groups of 4)
   while (gu < G) {
     const int u = ug * G + gu;
     const int pan = u / UPP, half = u % UPP;
@@ -667,19 +715,24 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
       // slice widths are multiples of UNR; padding entries carry zero
       // coefficients and a valid local column, so no entry is predicated
       const AB* __restrict__ pab = s_ab + soff;
-      const unsigned short* __restrict__ plc = s_lc + soff;
+      const unsigned* __restrict__ plc = s_lc + soff;
       const V* __restrict__ pz = sZ + lr;
       T acc[4 * SPL];
 #pragma unroll
       for (int v = 0; v < 4 * SPL; ++v) acc[v] = 0;
+      // (a group's local columns are read one group ahead, so the operand
+      // reads of a group wait on one LDS round trip, not two)
+      uint4 cn = wdt > 0 ? *reinterpret_cast<const uint4*>(plc) : make_uint4(0, 0, 0, 0);
       for (int j = 0; j < wdt; j += UNR) {
+        const unsigned cl[UNR] = {cn.x, cn.y, cn.z, cn.w};
+        // the next group's offsets (the last group re-reads its own): issued
+        // before this group's reads, consumed one iteration later
+        cn = *reinterpret_cast<const uint4*>(plc + min(j + UNR, wdt - UNR) * 8);
         V z[UNR];
         AB ab[UNR];
+        halo_ab4(pab + j * 8, ab);
 #pragma unroll
-        for (int uu = 0; uu < UNR; ++uu) {
-          ab[uu] = pab[(j + uu) * 8];
-          z[uu] = pz[(int)plc[(j + uu) * 8] * 8];
-        }
+        for (int uu = 0; uu < UNR; ++uu) z[uu] = halo_at(pz, cl[uu]);
 #pragma unroll
         for (int uu = 0; uu < UNR; ++uu) lane_fma<T, SPL>(acc, ab[uu].x, ab[uu].y, z[uu]);
       }
@@ -765,7 +818,7 @@ __global__ __launch_bounds__(kThreads) void k_post_image(
   V* sZ = reinterpret_cast<V*>(smem_d);                            // [hmax][8]
   AB* s_ab = reinterpret_cast<AB*>(sZ + (size_t)g.rpb * 8);        // [emax]
   T* s_p = reinterpret_cast<T*>(s_ab + hv.emax);                   // [emax]
-  unsigned short* s_lc = reinterpret_cast<unsigned short*>(s_p + hv.emax);  // [emax]
+  unsigned* s_lc = reinterpret_cast<unsigned*>(s_p + hv.emax);  // [emax]
   int* sH = reinterpret_cast<int*>(s_lc + hv.emax);                         // [hmax]
   __shared__ int s_sp[kHaloTileRows / 8 + 1];
   __shared__ int s_uact[kHaloMaxG];
@@ -820,13 +873,15 @@ __global__ __launch_bounds__(kThreads) void k_post_image(
     const uint4* __restrict__ gab =
         static_cast<const uint4*>(hv.ab) + (size_t)e0 * sizeof(AB) / 16;
     const uint4* __restrict__ gp = reinterpret_cast<const uint4*>(pv) + (size_t)e0 * sizeof(T) / 16;
-    for (int t = tid; t < nlc; t += kThreads) reinterpret_cast<uint4*>(s_lc)[t] = glc[t];
+    for (int t = tid; t < nlc; t += kThreads)
+      halo_stage_cols(glc[t], reinterpret_cast<uint4*>(s_lc) + 2 * t);
     for (int t = tid; t < nab; t += kThreads) reinterpret_cast<uint4*>(s_ab)[t] = gab[t];
     for (int t = tid; t < np; t += kThreads) reinterpret_cast<uint4*>(s_p)[t] = gp[t];
   }
   const int row = r0 + w * 8 + rr;
-  const int wdt = w < nsl ? s_sp[w + 1] - s_sp[w] : 0;
-  const int soff = w < nsl ? (s_sp[w] - s_sp[0]) * 8 + rr : 0;
+  // (a wave's slice width is uniform across the wave: scalar loop control)
+  const int wdt = __builtin_amdgcn_readfirstlane(w < nsl ? s_sp[w + 1] - s_sp[w] : 0);
+  const int soff = w < nsl ? (s_sp[w] - s_sp[0]) * 8 + rr * 4 : 0;  // (groups of 4)
   while (gu < G) {
     const int u = ug * G + gu;
     const int pan = u / UPP, half = u % UPP;
@@ -851,23 +906,26 @@ __global__ __launch_bounds__(kThreads) void k_post_image(
     if (w < nsl) {
       const AB* __restrict__ pab = s_ab + soff;
       const T* __restrict__ pp = s_p + soff;
-      const unsigned short* __restrict__ plc = s_lc + soff;
+      const unsigned* __restrict__ plc = s_lc + soff;
       const V* __restrict__ pz = sZ + lr;
       T acc[4 * SPL], accp[2 * SPL];
 #pragma unroll
       for (int v = 0; v < 4 * SPL; ++v) acc[v] = 0;
 #pragma unroll
       for (int v = 0; v < 2 * SPL; ++v) accp[v] = 0;
+      uint4 cn = wdt > 0 ? *reinterpret_cast<const uint4*>(plc) : make_uint4(0, 0, 0, 0);
       for (int j = 0; j < wdt; j += UNR) {
+        const unsigned cl[UNR] = {cn.x, cn.y, cn.z, cn.w};
+        // the next group's offsets (the last group re-reads its own): issued
+        // before this group's reads, consumed one iteration later
+        cn = *reinterpret_cast<const uint4*>(plc + min(j + UNR, wdt - UNR) * 8);
         V z[UNR];
         AB ab[UNR];
         T pw[UNR];
+        halo_ab4(pab + j * 8, ab);
+        halo_val4(pp + j * 8, pw);
 #pragma unroll
-        for (int uu = 0; uu < UNR; ++uu) {
-          ab[uu] = pab[(j + uu) * 8];
-          pw[uu] = pp[(j + uu) * 8];
-          z[uu] = pz[(int)plc[(j + uu) * 8] * 8];
-        }
+        for (int uu = 0; uu < UNR; ++uu) z[uu] = halo_at(pz, cl[uu]);
 #pragma unroll
         for (int uu = 0; uu < UNR; ++uu) {
           lane_fma<T, SPL>(acc, ab[uu].x, ab[uu].y, z[uu]);
@@ -947,7 +1005,7 @@ __global__ __launch_bounds__(kThreads) void k_true_halo(
   extern __shared__ __attribute__((aligned(16))) double smem_d[];  // 16-byte vectors live here
   V* sZ = reinterpret_cast<V*>(smem_d);                            // [hmax][8]
   double2* s_ab = reinterpret_cast<double2*>(sZ + (size_t)g.rpb * 8);          // [emax]
-  unsigned short* s_lc = reinterpret_cast<unsigned short*>(s_ab + hv.emax);  // [emax]
+  unsigned* s_lc = reinterpret_cast<unsigned*>(s_ab + hv.emax);  // [emax]
   int* sH = reinterpret_cast<int*>(s_lc + hv.emax);                          // [hmax]
   __shared__ int s_sp[kHaloTileRows / 8 + 1];
   __shared__ int s_uact[kHaloMaxG];
@@ -998,12 +1056,14 @@ __global__ __launch_bounds__(kThreads) void k_true_halo(
     const int e0 = s_sp[0] * 8, ne = (s_sp[nsl] - s_sp[0]) * 8;
     const uint4* __restrict__ glc = reinterpret_cast<const uint4*>(hv.lcol) + e0 / 8;
     const uint4* __restrict__ gab = static_cast<const uint4*>(hv.ab) + e0;
-    for (int t = tid; t < ne / 8; t += kThreads) reinterpret_cast<uint4*>(s_lc)[t] = glc[t];
+    for (int t = tid; t < ne / 8; t += kThreads)
+      halo_stage_cols(glc[t], reinterpret_cast<uint4*>(s_lc) + 2 * t);
     for (int t = tid; t < ne; t += kThreads) reinterpret_cast<uint4*>(s_ab)[t] = gab[t];
   }
   const int row = r0 + w * 8 + rr;
-  const int wdt = w < nsl ? s_sp[w + 1] - s_sp[w] : 0;
-  const int soff = w < nsl ? (s_sp[w] - s_sp[0]) * 8 + rr : 0;
+  // (a wave's slice width is uniform across the wave: scalar loop control)
+  const int wdt = __builtin_amdgcn_readfirstlane(w < nsl ? s_sp[w + 1] - s_sp[w] : 0);
+  const int soff = w < nsl ? (s_sp[w] - s_sp[0]) * 8 + rr * 4 : 0;  // (groups of 4)
   while (gu < G) {
     const int u = ug * G + gu;
     const int pan = u / UPP, half = u % UPP;
@@ -1022,17 +1082,20 @@ __global__ __launch_bounds__(kThreads) void k_true_halo(
     if (gn < G) SLRF_TRUE_ISSUE(gn);
     if (w < nsl && occ) {
       const double2* __restrict__ pab = s_ab + soff;
-      const unsigned short* __restrict__ plc = s_lc + soff;
+      const unsigned* __restrict__ plc = s_lc + soff;
       const V* __restrict__ pz = sZ + lr;
       double ar = 0, ai = 0, br = 0, bi = 0;
+      uint4 cn = wdt > 0 ? *reinterpret_cast<const uint4*>(plc) : make_uint4(0, 0, 0, 0);
       for (int j = 0; j < wdt; j += UNR) {
+        const unsigned cl[UNR] = {cn.x, cn.y, cn.z, cn.w};
+        // the next group's offsets (the last group re-reads its own): issued
+        // before this group's reads, consumed one iteration later
+        cn = *reinterpret_cast<const uint4*>(plc + min(j + UNR, wdt - UNR) * 8);
         V z[UNR];
         double2 ab[UNR];
+        halo_ab4(pab + j * 8, ab);
 #pragma unroll
-        for (int uu = 0; uu < UNR; ++uu) {
-          ab[uu] = pab[(j + uu) * 8];
-          z[uu] = pz[(int)plc[(j + uu) * 8] * 8];
-        }
+        for (int uu = 0; uu < UNR; ++uu) z[uu] = halo_at(pz, cl[uu]);
 #pragma unroll
         for (int uu = 0; uu < UNR; ++uu) {
           ar = fma(ab[uu].x, z[uu].x, ar);
@@ -2293,7 +2356,7 @@ HaloView halo_view(const DevPencil& P) {
 template <typename T>
 size_t halo_lds_bytes(const DevPencil& P) {
   return (size_t)P.hx_hmax * (8 * sizeof(typename LaneVec<T>::V) + sizeof(int)) +
-         (size_t)P.hx_emax * (2 * sizeof(T) + 2);
+         (size_t)P.hx_emax * (2 * sizeof(T) + sizeof(unsigned));  // (a, b), column offset
 }
 
 template <typename T>
@@ -2386,7 +2449,7 @@ bool launch_post_image(const DevImage& I, const DevPencil& P, const PanelGrid& g
   const long total = (long)I.ntile * nug;
   const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
   const size_t bytes = (size_t)I.hmax * (8 * sizeof(typename LaneVec<T>::V) + sizeof(int)) +
-                       (size_t)I.emax * (3 * sizeof(T) + 2);
+                       (size_t)I.emax * (3 * sizeof(T) + sizeof(unsigned));
   HaloView hv;
   hv.ntile = I.ntile;
   hv.emax = I.emax;

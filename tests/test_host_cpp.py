@@ -33,6 +33,11 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(ROOT, "paper_2510_17334_amd", "csrc")
 
 
+def _halo_entry(sptr_s, j, ln):
+    """Position of entry j of row lane ln in a slice: groups of 4 entries per row."""
+    return sptr_s * 8 + (j // 4) * 32 + ln * 4 + j % 4
+
+
 @pytest.fixture(scope="module")
 def driver(tmp_path_factory):
     gxx = shutil.which("g++")
@@ -155,7 +160,7 @@ def test_halo_format_reproduces_csr(driver, which, hmax, cap):
         for rrow in range(trow[t], trow[t + 1]):
             s, ln = rrow // 8, rrow % 8
             L = slen[rrow]
-            k = (sptr[s] + np.arange(sptr[s + 1] - sptr[s])) * 8 + ln
+            k = _halo_entry(sptr[s], np.arange(sptr[s + 1] - sptr[s]), ln)
             assert np.all(ab[k[L:]] == 0.0) and np.all(lcol[k[L:]] == 0)
             rows += [rrow] * L
             cols += list(h[lcol[k[:L]]])
@@ -260,7 +265,7 @@ def test_fine_image_of_prolongator(driver, which):
         for rrow in range(trow[t], trow[t + 1]):
             s_, ln = rrow // 8, rrow % 8
             L = slen[rrow]
-            k = (sptr[s_] + np.arange(L)) * 8 + ln
+            k = _halo_entry(sptr[s_], np.arange(L), ln)
             rows += [rrow] * L
             cols += list(h[lcol[k]])
             va += list(ab[k, 0]); vb += list(ab[k, 1]); vc += list(c3[k])

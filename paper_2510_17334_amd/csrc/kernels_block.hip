@@ -554,6 +554,28 @@ template <typename V>
 __device__ __forceinline__ V halo_at(const V* base, unsigned byte_off) {
   return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + byte_off);
 }
+
+// The 4-entry groups of a wave's slice in order (wdt: the slice width, a
+// multiple of 4, uniform across the wave): body(j, offsets) gets the group's
+// four operand byte offsets.  Each group's offsets are read one group ahead,
+// before the current group's operand reads, in two alternating registers.
+template <typename F>
+__device__ __forceinline__ void halo_slice_groups(const unsigned* plc, int wdt, F&& body) {
+  if (wdt <= 0) return;
+  uint4 ca = *reinterpret_cast<const uint4*>(plc);
+  for (int j = 0;; j += 8) {
+    // (the last group re-reads its own offsets; the empty asm keeps each read
+    // where it is: otherwise it is sunk next to its use)
+    const uint4 cb = *reinterpret_cast<const uint4*>(plc + min(j + 4, wdt - 4) * 8);
+    asm volatile("" ::: "memory");
+    body(j, ca);
+    if (j + 4 >= wdt) break;
+    ca = *reinterpret_cast<const uint4*>(plc + min(j + 8, wdt - 4) * 8);
+    asm volatile("" ::: "memory");
+    body(j + 4, cb);
+    if (j + 8 >= wdt) break;
+  }
+}
 __device__ __forceinline__ void halo_ab4(const float2* p, float2 (&ab)[4]) {
   const float4 u = reinterpret_cast<const float4*>(p)[0];
   const float4 v = reinterpret_cast<const float4*>(p)[1];
@@ -722,20 +744,17 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
       for (int v = 0; v < 4 * SPL; ++v) acc[v] = 0;
       // (a group's local columns are read one group ahead, so the operand
       // reads of a group wait on one LDS round trip, not two)
-      uint4 cn = wdt > 0 ? *reinterpret_cast<const uint4*>(plc) : make_uint4(0, 0, 0, 0);
-      for (int j = 0; j < wdt; j += UNR) {
-        const unsigned cl[UNR] = {cn.x, cn.y, cn.z, cn.w};
-        // the next group's offsets (the last group re-reads its own): issued
-        // before this group's reads, consumed one iteration later
-        cn = *reinterpret_cast<const uint4*>(plc + min(j + UNR, wdt - UNR) * 8);
+      halo_slice_groups(plc, wdt, [&](int j, const uint4& co) {
         V z[UNR];
         AB ab[UNR];
         halo_ab4(pab + j * 8, ab);
-#pragma unroll
-        for (int uu = 0; uu < UNR; ++uu) z[uu] = halo_at(pz, cl[uu]);
+        z[0] = halo_at(pz, co.x);
+        z[1] = halo_at(pz, co.y);
+        z[2] = halo_at(pz, co.z);
+        z[3] = halo_at(pz, co.w);
 #pragma unroll
         for (int uu = 0; uu < UNR; ++uu) lane_fma<T, SPL>(acc, ab[uu].x, ab[uu].y, z[uu]);
-      }
+      });
       if (row < r1) {
         V q;
         q.x = acc[0] - (sr[0] * acc[2] - si[0] * acc[3]);
@@ -913,19 +932,16 @@ __global__ __launch_bounds__(kThreads) void k_post_image(
       for (int v = 0; v < 4 * SPL; ++v) acc[v] = 0;
 #pragma unroll
       for (int v = 0; v < 2 * SPL; ++v) accp[v] = 0;
-      uint4 cn = wdt > 0 ? *reinterpret_cast<const uint4*>(plc) : make_uint4(0, 0, 0, 0);
-      for (int j = 0; j < wdt; j += UNR) {
-        const unsigned cl[UNR] = {cn.x, cn.y, cn.z, cn.w};
-        // the next group's offsets (the last group re-reads its own): issued
-        // before this group's reads, consumed one iteration later
-        cn = *reinterpret_cast<const uint4*>(plc + min(j + UNR, wdt - UNR) * 8);
+      halo_slice_groups(plc, wdt, [&](int j, const uint4& co) {
         V z[UNR];
         AB ab[UNR];
         T pw[UNR];
         halo_ab4(pab + j * 8, ab);
         halo_val4(pp + j * 8, pw);
-#pragma unroll
-        for (int uu = 0; uu < UNR; ++uu) z[uu] = halo_at(pz, cl[uu]);
+        z[0] = halo_at(pz, co.x);
+        z[1] = halo_at(pz, co.y);
+        z[2] = halo_at(pz, co.z);
+        z[3] = halo_at(pz, co.w);
 #pragma unroll
         for (int uu = 0; uu < UNR; ++uu) {
           lane_fma<T, SPL>(acc, ab[uu].x, ab[uu].y, z[uu]);
@@ -936,7 +952,7 @@ __global__ __launch_bounds__(kThreads) void k_post_image(
             accp[3] = mad(pw[uu], (T)lv_w(z[uu]), accp[3]);
           }
         }
-      }
+      });
       if (row < r1) {
         const size_t off = (size_t)row * LPRF + lr;
         V xo, ro;
@@ -1085,17 +1101,14 @@ __global__ __launch_bounds__(kThreads) void k_true_halo(
       const unsigned* __restrict__ plc = s_lc + soff;
       const V* __restrict__ pz = sZ + lr;
       double ar = 0, ai = 0, br = 0, bi = 0;
-      uint4 cn = wdt > 0 ? *reinterpret_cast<const uint4*>(plc) : make_uint4(0, 0, 0, 0);
-      for (int j = 0; j < wdt; j += UNR) {
-        const unsigned cl[UNR] = {cn.x, cn.y, cn.z, cn.w};
-        // the next group's offsets (the last group re-reads its own): issued
-        // before this group's reads, consumed one iteration later
-        cn = *reinterpret_cast<const uint4*>(plc + min(j + UNR, wdt - UNR) * 8);
+      halo_slice_groups(plc, wdt, [&](int j, const uint4& co) {
         V z[UNR];
         double2 ab[UNR];
         halo_ab4(pab + j * 8, ab);
-#pragma unroll
-        for (int uu = 0; uu < UNR; ++uu) z[uu] = halo_at(pz, cl[uu]);
+        z[0] = halo_at(pz, co.x);
+        z[1] = halo_at(pz, co.y);
+        z[2] = halo_at(pz, co.z);
+        z[3] = halo_at(pz, co.w);
 #pragma unroll
         for (int uu = 0; uu < UNR; ++uu) {
           ar = fma(ab[uu].x, z[uu].x, ar);
@@ -1103,7 +1116,7 @@ __global__ __launch_bounds__(kThreads) void k_true_halo(
           br = fma(ab[uu].y, z[uu].x, br);
           bi = fma(ab[uu].y, z[uu].y, bi);
         }
-      }
+      });
       if (row < r1) {
         const double mx = ar - (sg.x * br - sg.y * bi);
         const double my = ai - (sg.x * bi + sg.y * br);

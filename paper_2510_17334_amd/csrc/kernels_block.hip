@@ -2392,7 +2392,10 @@ bool launch_halo(const DevPencil& P, const PanelGrid& g, const SlotTables& st, i
   const int G = kHaloMaxG;
   const int nug = (g.npan * UPP + G - 1) / G;
   PanelGrid gg = g;
-  gg.group = nug < 4 ? nug : 4;
+  // every tile of one run of G units before the next run: the same panels
+  // of neighbouring tiles are swept close together in time (halo rows
+  // shared through L2)
+  gg.group = 1;
   gg.rpb = P.hx_hmax;  // LDS halo rows (the kernel's carve-up of dynamic LDS)
   const long total = (long)P.hx_ntile * nug;
   const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
@@ -2429,7 +2432,10 @@ bool launch_resid_bf16(const DevPencil& P, const PanelGrid& g, const SlotTables&
   const int G = kHaloMaxG;
   const int nug = (g.npan + G - 1) / G;
   PanelGrid gg = g;
-  gg.group = nug < 4 ? nug : 4;
+  // every tile of one run of G units before the next run: the same panels
+  // of neighbouring tiles are swept close together in time (halo rows
+  // shared through L2)
+  gg.group = 1;
   gg.rpb = P.hx_hmax;
   const long total = (long)P.hx_ntile * nug;
   const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
@@ -2457,7 +2463,10 @@ bool launch_post_image(const DevImage& I, const DevPencil& P, const PanelGrid& g
   const int G = kHaloMaxG;
   const int nug = (g.npan * UPP + G - 1) / G;
   PanelGrid gg = g;
-  gg.group = nug < 4 ? nug : 4;
+  // every tile of one run of G units before the next run: the same panels
+  // of neighbouring tiles are swept close together in time (halo rows
+  // shared through L2)
+  gg.group = 1;
   gg.rpb = I.hmax;  // LDS halo rows (the kernel's carve-up of dynamic LDS)
   const long total = (long)I.ntile * nug;
   const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
@@ -2658,7 +2667,10 @@ hipError_t launch_true_resid(const DevPencil& P, const PanelGrid& g, const SlotT
     const int G = kHaloMaxG;
     const int nug = (g.npan * 2 + G - 1) / G;
     PanelGrid gg = g;
-    gg.group = nug < 4 ? nug : 4;
+    // every tile of one run of G units before the next run: the same panels
+    // of neighbouring tiles are swept close together in time (halo rows
+    // shared through L2)
+    gg.group = 1;
     gg.rpb = P.hx_hmax;
     const long total = (long)P.hx_ntile * nug;
     const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);

@@ -97,7 +97,9 @@ static void tridiagonalize(int n, std::vector<double>& A, std::vector<double>& d
   e[n - 1] = 0.0;
 }
 
-// Implicit QL with Wilkinson shifts on (d, e); rotations accumulated in Z.
+// Implicit QL with Wilkinson shifts on (d, e), the published algorithm of the
+// EISPACK routine tql2 (Bowdler, Martin, Reinsch and Wilkinson, 1968); rotations
+// accumulated in Z.
 static bool tridiag_ql(int n, std::vector<double>& d, std::vector<double>& e,
                        std::vector<double>& Z) {
   const double eps = 2.220446049250313e-16;

@@ -20,6 +20,12 @@ LIB = os.path.join(HERE, "libslrf.so")
 ARCH = "gfx950"
 
 
+# The MFMA kernels keep their FP64 accumulators (up to 200 registers) in the
+# VGPR form: otherwise the register allocator parks them in AGPRs and copies
+# them back and forth around every MFMA of the loop.
+PER_FILE_FLAGS = {"kernels_dense.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
+
 def _hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", "hipcc"):
         if cand and (os.path.sep not in cand or os.path.exists(cand)):
@@ -43,6 +49,8 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
         cmd = [hipcc] + common + ["-c", f, "-o", o]
         if f.endswith(".cpp"):
             cmd = [hipcc] + common + ["-x", "hip", "-c", f, "-o", o]
+        if os.path.basename(f) in PER_FILE_FLAGS:
+            cmd[1:1] = PER_FILE_FLAGS[os.path.basename(f)]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

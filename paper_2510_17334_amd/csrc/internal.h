@@ -297,10 +297,11 @@ hipError_t launch_spmm_real(const DevPencil& P, const double* X, int ld, int nc,
 hipError_t launch_transpose(const double* in, int rows, int cols, int ldin, double* out,
                             int ldout, hipStream_t s, const int* imap = nullptr,
                             const int* omap = nullptr);
-// G (p x q, row-major, ldg) = X^T Y; X: n x p (ldx), Y: n x q (ldy); part: scratch
+// G (p x q, row-major, ldg) = X^T Y; X: n x p (ldx), Y: n x q (ldy); part:
+// scratch of gram_part_doubles(n, pq) doubles for any p, q <= pq
 hipError_t launch_gram(int n, int p, int q, const double* X, int ldx, const double* Y, int ldy,
-                       double* part, int nchunk, double* G, int ldg, hipStream_t s);
-int gram_chunks(int n);
+                       double* part, double* G, int ldg, hipStream_t s);
+size_t gram_part_doubles(int n, int pq);
 // Z (n x q, ldz) = alpha * X (n x p, ldx) * S (p x q, lds) + beta * Z
 hipError_t launch_gemm_tall(int n, int p, int q, double alpha, const double* X, int ldx,
                             const double* S, int lds, double beta, double* Z, int ldz,

@@ -6,6 +6,9 @@
 // row l%16, k l/16), operand B a 4x16 tile (lane l holds k l/16, column l%16),
 // and the 16x16 accumulator holds in lane l, element v the entry
 // (row 4*v + l/16, column l%16) (established by an on-device layout check).
+#include <algorithm>
+#include <cstdint>
+
 #include "internal.h"
 
 namespace slrf {
@@ -113,179 +116,246 @@ __global__ __launch_bounds__(256) void k_transpose(const double* __restrict__ in
 }
 
 // Partial Gram over one row chunk: part[chunk][i][j] = sum_{r in chunk} X[r,i] Y[r,j].
-// Workgroup: one 32x32 tile of G (2x2 MFMA tiles) and one chunk of rows; its
-// four waves take interleaved 4-row steps of the chunk (the four together read
-// 16 consecutive rows), each loading the next step's operands while its MFMAs
-// run, and their partial tiles are summed through LDS in wave order.
-__global__ __launch_bounds__(256) void k_gram(int n, int p, int q, const double* __restrict__ X,
-                                              int ldx, const double* __restrict__ Y, int ldy,
-                                              double* __restrict__ part, int rows_per_chunk,
-                                              int nchunk) {
-  __shared__ double red[4][32 * 32];
-  const int ntj = (q + 31) / 32;
-  const long ntile = (long)((p + 31) / 32) * ntj;
-  // XCD-aware order: each XCD takes a contiguous range of (chunk, tile) pairs,
-  // so the rows of a chunk are fetched into one XCD's L2 for all its tiles
+// Workgroup: one 160x160 super-tile of G and one chunk of rows; wave w forms the
+// 80x80 quarter (w / 2, w % 2) as 5x5 MFMA blocks (200 accumulator registers:
+// one wave per SIMD).  Slabs of kGS rows of the super-tile's 160 columns of X
+// and of Y are staged in LDS by coalesced loads, double-buffered: the next slab
+// is loaded into registers while the waves run the current slab's MFMAs with
+// operands read from LDS (row stride 176 doubles: the four rows a 64-lane read
+// touches fall in alternate bank halves).  Each quarter is written whole to the
+// chunk's partial block; k_chunk_sum adds the chunks in order.
+constexpr int kGS = 16;             // rows per LDS slab
+constexpr int kGT = 160;            // super-tile side
+constexpr int kGStride = 176;       // LDS row stride (doubles)
+constexpr int kGPer = kGS * kGT / 2 / 256;  // element pairs per thread, array and slab
+static_assert(kGS * kGT / 2 % 256 == 0, "a slab is a whole number of pairs per thread");
+template <bool PAIRS>
+__global__ __launch_bounds__(256, 1) void k_gram(int n, int p, int q, const double* __restrict__ X,
+                                                 int ldx, const double* __restrict__ Y, int ldy,
+                                                 double* __restrict__ part, int rows_per_chunk,
+                                                 int nchunk) {
+  extern __shared__ double sm[];
+  double* sX = sm;                          // [2][kGS][kGStride]
+  double* sY = sm + 2 * kGS * kGStride;     // [2][kGS][kGStride]
+  const int ntj = (q + kGT - 1) / kGT;
+  const long ntile = (long)((p + kGT - 1) / kGT) * ntj;
+  // XCD-aware order: each XCD takes a contiguous range of (chunk, tile) pairs
   const long total = ntile * nchunk;
   const long per = (total + 7) / 8;
   const long w8 = (long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (w8 >= total) return;
   const int chunk = (int)(w8 / ntile);
   const int tile = (int)(w8 % ntile);
-  const int ib = (tile / ntj) * 32, jb = (tile % ntj) * 32;
+  const int ib = (tile / ntj) * kGT, jb = (tile % ntj) * kGT;
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int kk = l >> 4, ii = l & 15;
+  const int qi = (wave >> 1) * 80, qj = (wave & 1) * 80;
+  // (a quarter wholly past p or q has nothing to form)
+  const bool live = ib + qi < p && jb + qj < q;
   const int r0 = chunk * rows_per_chunk, r1 = min(r0 + rows_per_chunk, n);
-  d4 acc[2][2];
+  d4 acc[5][5];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 5; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-  const int ca0 = ib + ii, ca1 = ib + 16 + ii, cb0 = jb + ii, cb1 = jb + 16 + ii;
-  const bool oa0 = ca0 < p, oa1 = ca1 < p, ob0 = cb0 < q, ob1 = cb1 < q;
-  auto load = [&](int r, double& a0, double& a1, double& b0, double& b1) {
-    const int row = r + kk;
-    const bool okr = row < r1;
-    const double* xr = X + (size_t)row * ldx;
-    const double* yr = Y + (size_t)row * ldy;
-    a0 = (okr && oa0) ? xr[ca0] : 0.0;
-    a1 = (okr && oa1) ? xr[ca1] : 0.0;
-    b0 = (okr && ob0) ? yr[cb0] : 0.0;
-    b1 = (okr && ob1) ? yr[cb1] : 0.0;
+    for (int b = 0; b < 5; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  // staging: pair e = t * 256 + tid of a slab holds row e / 80, columns 2 (e % 80) + {0, 1}
+  double2 gx[kGPer], gy[kGPer];
+  auto pair = [&](const double* __restrict__ M, int ld, int row, int c0, int lim) {
+    const double* m = M + (size_t)row * ld + c0;
+    if (PAIRS && c0 + 1 < lim) return *reinterpret_cast<const double2*>(m);
+    return make_double2(c0 < lim ? m[0] : 0.0, c0 + 1 < lim ? m[1] : 0.0);
   };
-  // groups of D steps: the next group's operands are loaded while the current
-  // group's MFMAs run (rows past the chunk load zeros)
-  constexpr int D = 4;
-  double a[D][2], b[D][2], na[D][2], nb[D][2];
-  int r = r0 + wave * 4;
+  auto gload = [&](int rs) {
 #pragma unroll
-  for (int u = 0; u < D; ++u) load(r + 16 * u, a[u][0], a[u][1], b[u][0], b[u][1]);
-  for (; r < r1; r += 16 * D) {
-#pragma unroll
-    for (int u = 0; u < D; ++u) load(r + 16 * (D + u), na[u][0], na[u][1], nb[u][0], nb[u][1]);
-#pragma unroll
-    for (int u = 0; u < D; ++u) {
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][0], b[u][0], acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][0], b[u][1], acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][1], b[u][0], acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][1], b[u][1], acc[1][1], 0, 0, 0);
+    for (int t = 0; t < kGPer; ++t) {
+      const int e = t * 256 + threadIdx.x, rr = e / 80, c = 2 * (e % 80);
+      const int row = rs + rr;
+      const bool ok = row < r1;
+      gx[t] = ok ? pair(X, ldx, row, ib + c, p) : make_double2(0.0, 0.0);
+      gy[t] = ok ? pair(Y, ldy, row, jb + c, q) : make_double2(0.0, 0.0);
     }
+  };
+  auto lstore = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < D; ++u) {
-      a[u][0] = na[u][0];
-      a[u][1] = na[u][1];
-      b[u][0] = nb[u][0];
-      b[u][1] = nb[u][1];
+    for (int t = 0; t < kGPer; ++t) {
+      const int e = t * 256 + threadIdx.x, rr = e / 80, c = 2 * (e % 80);
+      *reinterpret_cast<double2*>(sX + (buf * kGS + rr) * kGStride + c) = gx[t];
+      *reinterpret_cast<double2*>(sY + (buf * kGS + rr) * kGStride + c) = gy[t];
     }
+  };
+  int buf = 0;
+  gload(r0);
+  lstore(0);
+  __syncthreads();
+  for (int rs = r0; rs < r1; rs += kGS) {
+    const bool more = rs + kGS < r1;
+    if (more) gload(rs + kGS);
+    if (live) {
+      const double* bx = sX + buf * kGS * kGStride + qi + ii;
+      const double* by = sY + buf * kGS * kGStride + qj + ii;
+#pragma unroll
+      for (int st = 0; st < kGS / 4; ++st) {
+        double a[5], b[5];
+        const int rr = st * 4 + kk;
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+          a[t] = bx[rr * kGStride + 16 * t];
+          b[t] = by[rr * kGStride + 16 * t];
+        }
+#pragma unroll
+        for (int x = 0; x < 5; ++x)
+#pragma unroll
+          for (int y = 0; y < 5; ++y)
+            acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+      }
+    }
+    if (more) lstore(buf ^ 1);
+    __syncthreads();  // (the slab is consumed and the next one stored)
+    buf ^= 1;
   }
+  double* pc = part + (size_t)chunk * p * q;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int x = 0; x < 5; ++x)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int y = 0; y < 5; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = a * 16 + 4 * v + (l >> 4);
-        const int j = b * 16 + (l & 15);
-        red[wave][i * 32 + j] = acc[a][b][v];
+        const int i = ib + qi + x * 16 + 4 * v + (l >> 4);
+        const int j = jb + qj + y * 16 + (l & 15);
+        if (i < p && j < q) pc[(size_t)i * q + j] = acc[x][y][v];
       }
+}
+
+// G = sum of the chunks' partial blocks.  A workgroup takes 64 entries; its four
+// waves sum interleaved quarters of the chunks (chunk c to wave c % 4, each in
+// chunk order) and the four sums are added in wave order: a fixed order.
+__global__ __launch_bounds__(256) void k_chunk_sum(const double* __restrict__ part, int nchunk,
+                                                   int p, int q, double* __restrict__ G, int ldg) {
+  __shared__ double red[4][64];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int t = blockIdx.x * 64 + l;
+  const size_t pq = (size_t)p * q;
+  double s = 0.0;
+  if (t < (int)pq)
+    for (int c = w; c < nchunk; c += 4) s += part[(size_t)c * pq + t];
+  red[w][l] = s;
   __syncthreads();
-  double* pc = part + (size_t)chunk * p * q;
-  for (int t = threadIdx.x; t < 32 * 32; t += 256) {
-    const int i = ib + t / 32, j = jb + t % 32;
-    if (i < p && j < q) pc[(size_t)i * q + j] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+  if (w == 0 && t < (int)pq) {
+    const int i = t / q, j = t % q;
+    G[(size_t)i * ldg + j] = ((red[0][l] + red[1][l]) + red[2][l]) + red[3][l];
   }
 }
 
-__global__ void k_chunk_sum(const double* __restrict__ part, int nchunk, int p, int q,
-                            double* __restrict__ G, int ldg) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= p * q) return;
-  const int i = t / q, j = t % q;
-  double s = 0.0;
-  for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * p * q + t];
-  G[(size_t)i * ldg + j] = s;
-}
-
-// Z = alpha X S + beta Z.  Workgroup: 128 rows (4 waves x 32 rows) x 32
-// columns (2x2 MFMA tiles per wave); the 32 columns of S are staged in LDS 64
-// rows of k at a time and shared by the waves, each of which loads its next
-// X operands while its MFMAs run.
-constexpr int kGemmK = 64;
-__global__ __launch_bounds__(256) void k_gemm_tall(int n, int p, int q, double alpha,
-                                                   const double* __restrict__ X, int ldx,
-                                                   const double* __restrict__ S, int lds,
-                                                   double beta, double* __restrict__ Z, int ldz) {
-  __shared__ double sS[kGemmK][32];
-  const int ncb = (q + 31) / 32;
+// Z = alpha X S + beta Z.  Workgroup: a 128-row x 160-column block of Z; wave
+// w forms rows 64 (w / 2) .. + 64 and columns 80 (w % 2) .. + 80 as 4x5 MFMA
+// blocks (20 MFMAs per 9 LDS operand reads).  Slabs of kTK values of k are
+// staged in LDS, double-buffered (loaded into registers while the waves run the
+// current slab): X's 128 rows x kTK (row stride kTXS) and S's kTK rows x 160
+// columns (row stride kGStride), both by coalesced pair loads.  The accumulators
+// and the staged pairs take about 270 registers: one wave per SIMD.
+constexpr int kTK = 16;             // k per slab
+constexpr int kTRows = 128;         // rows of Z per workgroup
+constexpr int kTXS = 18;            // LDS row stride of the X slab (doubles)
+constexpr int kTXPer = kTRows * kTK / 2 / 256;  // X pairs per thread and slab
+constexpr int kTSPer = kTK * kGT / 2 / 256;     // S pairs per thread and slab
+static_assert(kTRows * kTK / 2 % 256 == 0 && kTK * kGT / 2 % 256 == 0, "whole pairs per thread");
+template <bool PAIRS>
+__global__ __launch_bounds__(256, 1) void k_gemm_tall(int n, int p, int q, double alpha,
+                                                      const double* __restrict__ X, int ldx,
+                                                      const double* __restrict__ S, int lds,
+                                                      double beta, double* __restrict__ Z,
+                                                      int ldz) {
+  extern __shared__ double sm[];
+  double* sX = sm;                                  // [2][kTRows][kTXS]
+  double* sS = sm + 2 * kTRows * kTXS;              // [2][kTK][kGStride]
+  const int ncb = (q + kGT - 1) / kGT;
   // XCD-aware order: each XCD takes a contiguous range of (row block, column
-  // block) pairs, column blocks fastest, so an X row block is fetched into one
-  // L2 for all its column blocks
-  const long total = (long)((n + 127) / 128) * ncb;
+  // block) pairs, column blocks fastest
+  const long total = (long)((n + kTRows - 1) / kTRows) * ncb;
   const long per = (total + 7) / 8;
   const long w8 = (long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (w8 >= total) return;
-  const int rb = (int)(w8 / ncb), cb = (int)(w8 % ncb);
+  const int rb = (int)(w8 / ncb), cbk = (int)(w8 % ncb);
+  const int row0 = rb * kTRows, jb = cbk * kGT;
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int r0 = rb * 128 + wave * 32;
-  const int jb = cb * 32;
   const int kk = l >> 4, ii = l & 15;
-  d4 acc[2][2];
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 80;
+  const bool live = row0 + wr < n && jb + wc < q;
+  d4 acc[4][5];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-  const int ar0 = r0 + ii, ar1 = r0 + 16 + ii;
-  const bool ok0 = ar0 < n, ok1 = ar1 < n;
-  const double* x0 = X + (size_t)(ok0 ? ar0 : 0) * ldx;
-  const double* x1 = X + (size_t)(ok1 ? ar1 : 0) * ldx;
-  for (int k0 = 0; k0 < p; k0 += kGemmK) {
-    const int kn = min(kGemmK, p - k0);
-    __syncthreads();  // (the previous slab is consumed)
-    for (int t = threadIdx.x; t < kGemmK * 32; t += 256) {
-      const int kr = t / 32, j = jb + t % 32;
-      sS[kr][t % 32] = (kr < kn && j < q) ? S[(size_t)(k0 + kr) * lds + j] : 0.0;
+    for (int b = 0; b < 5; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  auto pair = [&](const double* __restrict__ M, size_t off, int c0, int lim) {
+    const double* m = M + off;
+    if (PAIRS && c0 + 1 < lim) return *reinterpret_cast<const double2*>(m);
+    return make_double2(c0 < lim ? m[0] : 0.0, c0 + 1 < lim ? m[1] : 0.0);
+  };
+  double2 gx[kTXPer], gs[kTSPer];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int t = 0; t < kTXPer; ++t) {  // X pair e: row e / 8, k 2 (e % 8) + {0, 1}
+      const int e = t * 256 + threadIdx.x, r = row0 + e / 8, k = k0 + 2 * (e % 8);
+      gx[t] = r < n ? pair(X, (size_t)r * ldx + k, k, p) : make_double2(0.0, 0.0);
     }
+#pragma unroll
+    for (int t = 0; t < kTSPer; ++t) {  // S pair e: k row e / 80, columns 2 (e % 80) + {0, 1}
+      const int e = t * 256 + threadIdx.x, k = k0 + e / 80, c = jb + 2 * (e % 80);
+      gs[t] = k < p ? pair(S, (size_t)k * lds + c, c, q) : make_double2(0.0, 0.0);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int t = 0; t < kTXPer; ++t) {
+      const int e = t * 256 + threadIdx.x;
+      *reinterpret_cast<double2*>(sX + (buf * kTRows + e / 8) * kTXS + 2 * (e % 8)) = gx[t];
+    }
+#pragma unroll
+    for (int t = 0; t < kTSPer; ++t) {
+      const int e = t * 256 + threadIdx.x;
+      *reinterpret_cast<double2*>(sS + (buf * kTK + e / 80) * kGStride + 2 * (e % 80)) = gs[t];
+    }
+  };
+  int buf = 0;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int k0 = 0; k0 < p; k0 += kTK) {
+    const bool more = k0 + kTK < p;
+    if (more) gload(k0 + kTK);
+    if (live) {
+      const double* bx = sX + (buf * kTRows + wr + ii) * kTXS + kk;
+      const double* bs = sS + (buf * kTK + kk) * kGStride + wc + ii;
+#pragma unroll
+      for (int st = 0; st < kTK / 4; ++st) {
+        double a[4], b[5];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a[t] = bx[16 * t * kTXS + 4 * st];
+#pragma unroll
+        for (int t = 0; t < 5; ++t) b[t] = bs[4 * st * kGStride + 16 * t];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 5; ++y)
+            acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+      }
+    }
+    if (more) lstore(buf ^ 1);
     __syncthreads();
-    auto ld = [&](int kc, double& a0, double& a1) {
-      const bool okk = kc < p;
-      a0 = (ok0 && okk) ? x0[kc] : 0.0;
-      a1 = (ok1 && okk) ? x1[kc] : 0.0;
-    };
-    // the slab's X operands in groups of four k-steps, the next group
-    // loaded while the current one's MFMAs run (past p: zeros)
-    double a[4][2], na[4][2];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) ld(k0 + 4 * u + kk, a[u][0], a[u][1]);
-    for (int kr = 0; kr < kn; kr += 16) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) ld(k0 + kr + 16 + 4 * u + kk, na[u][0], na[u][1]);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int k = kr + 4 * u + kk;  // (< kGemmK + 12: rows past kn hold zeros)
-        const double b0 = k < kGemmK ? sS[k][ii] : 0.0, b1 = k < kGemmK ? sS[k][16 + ii] : 0.0;
-        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][0], b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][0], b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][1], b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][1], b1, acc[1][1], 0, 0, 0);
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        a[u][0] = na[u][0];
-        a[u][1] = na[u][1];
-      }
-    }
+    buf ^= 1;
   }
+  if (!live) return;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int y = 0; y < 5; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = r0 + a * 16 + 4 * v + (l >> 4);
-        const int j = jb + b * 16 + (l & 15);
+        const int i = row0 + wr + x * 16 + 4 * v + (l >> 4);
+        const int j = jb + wc + y * 16 + (l & 15);
         if (i < n && j < q) {
           const size_t o = (size_t)i * ldz + j;
-          Z[o] = alpha * acc[a][b][v] + (beta == 0.0 ? 0.0 : beta * Z[o]);
+          Z[o] = alpha * acc[x][y][v] + (beta == 0.0 ? 0.0 : beta * Z[o]);
         }
       }
 }
@@ -351,10 +421,26 @@ __global__ void k_diag(int n, const int* __restrict__ rowptr, const int* __restr
 
 }  // namespace
 
-constexpr int kGramRows = 2048;
+constexpr int kGramWG = 256;          // Gram workgroups per launch: one per CU
+constexpr int kGramMinRows = 4 * kGS;  // fewest rows per chunk
 constexpr int kColRows = 1024;
 
-int gram_chunks(int n) { return n <= 0 ? 1 : (n + kGramRows - 1) / kGramRows; }
+namespace {
+// Row chunks of a p x q Gram: kGramWG workgroups over its super-tiles (fewer when
+// the chunks would hold under kGramMinRows rows).  nchunk * p * q never exceeds
+// gram_part_doubles(n, pq) for p, q <= pq: nchunk <= kGramWG / ntile with
+// p * q <= ntile * kGT^2, and nchunk <= cdiv(n, kGramMinRows) with p * q <= pq^2.
+int gram_nchunk(int n, int p, int q) {
+  const int ntile = cdiv(p, kGT) * cdiv(q, kGT);
+  const int by_rows = n <= 0 ? 1 : cdiv(n, kGramMinRows);
+  return std::max(1, std::min(by_rows, kGramWG / std::max(ntile, 1)));
+}
+}  // namespace
+
+size_t gram_part_doubles(int n, int pq) {
+  const size_t by_rows = (size_t)(n <= 0 ? 1 : cdiv(n, kGramMinRows)) * pq * pq;
+  return std::min((size_t)kGramWG * kGT * kGT, by_rows);
+}
 int colstat_chunks(int n) { return n <= 0 ? 1 : (n + kColRows - 1) / kColRows; }
 
 hipError_t launch_spmm_real(const DevPencil& P, const double* X, int ld, int nc, double* AX,
@@ -374,15 +460,31 @@ hipError_t launch_transpose(const double* in, int rows, int cols, int ldin, doub
 }
 
 hipError_t launch_gram(int n, int p, int q, const double* X, int ldx, const double* Y, int ldy,
-                       double* part, int nchunk, double* G, int ldg, hipStream_t s) {
+                       double* part, double* G, int ldg, hipStream_t s) {
   if (p == 0 || q == 0) return hipSuccess;
+  const int nchunk = gram_nchunk(n, p, q);
+  // (rows per chunk: whole slabs; the last chunk may be short or, rounded up, empty)
   const int rows = (n + nchunk - 1) / nchunk;
-  const int rpc = ((rows + 3) / 4) * 4;
-  const size_t total = (size_t)cdiv(p, 32) * cdiv(q, 32) * nchunk;
-  k_gram<<<cdiv(total, 8) * 8, 256, 0, s>>>(n, p, q, X, ldx, Y, ldy, part, rpc, nchunk);
+  const int rpc = ((rows + kGS - 1) / kGS) * kGS;
+  const size_t total = (size_t)cdiv(p, kGT) * cdiv(q, kGT) * nchunk;
+  const size_t lds = sizeof(double) * 4 * kGS * kGStride;  // 90 KB of the 160 KB per CU
+  static const bool lds_ok = [] {
+    const int b = (int)(sizeof(double) * 4 * kGS * kGStride);
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram<true>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, b) == hipSuccess &&
+           hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram<false>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, b) == hipSuccess;
+  }();
+  if (!lds_ok) return hipErrorInvalidConfiguration;
+  const bool pairs = ((ldx | ldy) & 1) == 0 && ((reinterpret_cast<uintptr_t>(X) |
+                                                 reinterpret_cast<uintptr_t>(Y)) & 15) == 0;
+  if (pairs)
+    k_gram<true><<<cdiv(total, 8) * 8, 256, lds, s>>>(n, p, q, X, ldx, Y, ldy, part, rpc, nchunk);
+  else
+    k_gram<false><<<cdiv(total, 8) * 8, 256, lds, s>>>(n, p, q, X, ldx, Y, ldy, part, rpc, nchunk);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_chunk_sum<<<cdiv((size_t)p * q, 256), 256, 0, s>>>(part, nchunk, p, q, G, ldg);
+  k_chunk_sum<<<cdiv((size_t)p * q, 64), 256, 0, s>>>(part, nchunk, p, q, G, ldg);
   return hipGetLastError();
 }
 
@@ -390,8 +492,28 @@ hipError_t launch_gemm_tall(int n, int p, int q, double alpha, const double* X, 
                             const double* S, int lds, double beta, double* Z, int ldz,
                             hipStream_t s) {
   if (n == 0 || q == 0) return hipSuccess;
-  const size_t total = (size_t)cdiv(n, 128) * cdiv(q, 32);
-  k_gemm_tall<<<cdiv(total, 8) * 8, 256, 0, s>>>(n, p, q, alpha, X, ldx, S, lds, beta, Z, ldz);
+  if (p == 0) {
+    // (no k: Z = beta Z; not used by the library, kept well defined)
+    return beta == 1.0 ? hipSuccess : hipErrorInvalidValue;
+  }
+  const size_t total = (size_t)cdiv(n, kTRows) * cdiv(q, kGT);
+  const size_t bytes = sizeof(double) * 2 * (kTRows * kTXS + kTK * kGStride);  // 58 KB
+  static const bool lds_ok = [] {
+    const int b = (int)(sizeof(double) * 2 * (kTRows * kTXS + kTK * kGStride));
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_tall<true>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, b) == hipSuccess &&
+           hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_tall<false>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, b) == hipSuccess;
+  }();
+  if (!lds_ok) return hipErrorInvalidConfiguration;
+  const bool pairs = ((ldx | lds) & 1) == 0 && ((reinterpret_cast<uintptr_t>(X) |
+                                                 reinterpret_cast<uintptr_t>(S)) & 15) == 0;
+  if (pairs)
+    k_gemm_tall<true><<<cdiv(total, 8) * 8, 256, bytes, s>>>(n, p, q, alpha, X, ldx, S, lds, beta,
+                                                             Z, ldz);
+  else
+    k_gemm_tall<false><<<cdiv(total, 8) * 8, 256, bytes, s>>>(n, p, q, alpha, X, ldx, S, lds, beta,
+                                                              Z, ldz);
   return hipGetLastError();
 }
 

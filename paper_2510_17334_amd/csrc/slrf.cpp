@@ -1005,7 +1005,7 @@ size_t filter_slot_bytes(int n, int m, size_t sT, const std::vector<int>& amg_le
 size_t rr_bytes(int n, int nc, int nl) {
   const size_t pq = std::max(nc, nl);
   return (size_t)n * (6 * (size_t)nc + 2 * (size_t)nl) * sizeof(double) +
-         ((size_t)gram_chunks(n) * pq * pq + 16) * sizeof(double) +
+         (gram_part_doubles(n, (int)pq) + 16) * sizeof(double) +
          (3 * pq * pq + 4 * pq + 16) * sizeof(double) +
          (2 * (size_t)colstat_chunks(n) * nc + 2) * sizeof(double) + 16 * kAlign;
 }
@@ -1473,9 +1473,8 @@ slrf_status rr_rowmajor(slrf_ctx* h, int nc, double* Ur, int nl, const double* X
   HIPCHK(carve_t(h, (size_t)n * nc, &V));
   HIPCHK(carve_t(h, (size_t)n * nc, &AV));
   HIPCHK(carve_t(h, (size_t)n * nc, &BV));
-  const int gch = gram_chunks(n);
   const int pq = std::max(nc, nl);
-  HIPCHK(carve_t(h, (size_t)gch * pq * pq + 16, &gpart));
+  HIPCHK(carve_t(h, gram_part_doubles(n, pq) + 16, &gpart));
   HIPCHK(carve_t(h, (size_t)3 * pq * pq + 4 * pq + 16, &small));
   const int cch = colstat_chunks(n);
   HIPCHK(carve_t(h, (size_t)2 * cch * nc + 2, &cpart));
@@ -1490,14 +1489,14 @@ slrf_status rr_rowmajor(slrf_ctx* h, int nc, double* Ur, int nl, const double* X
     // U <- U - X (X^T B U), twice (Algorithm 2, B-orthogonalisation vs locked X)
     HIPCHK(launch_spmm_real(h->P, Ur, nc, nc, nullptr, BU, nullptr, nullptr, s));
     for (int pass = 0; pass < 2; ++pass) {
-      HIPCHK(launch_gram(n, nl, nc, Xl, nl, BU, nc, gpart, gch, Gd, nc, s));
+      HIPCHK(launch_gram(n, nl, nc, Xl, nl, BU, nc, gpart, Gd, nc, s));
       HIPCHK(launch_gemm_tall(n, nl, nc, -1.0, Xl, nl, Gd, nc, 1.0, Ur, nc, s));
       if (pass == 0) HIPCHK(launch_gemm_tall(n, nl, nc, -1.0, BXl, nl, Gd, nc, 1.0, BU, nc, s));
     }
   }
   HIPCHK(launch_spmm_real(h->P, Ur, nc, nc, AU, BU, nullptr, nullptr, s));
-  HIPCHK(launch_gram(n, nc, nc, Ur, nc, AU, nc, gpart, gch, Gd, nc, s));
-  HIPCHK(launch_gram(n, nc, nc, Ur, nc, BU, nc, gpart, gch, Gd2, nc, s));
+  HIPCHK(launch_gram(n, nc, nc, Ur, nc, AU, nc, gpart, Gd, nc, s));
+  HIPCHK(launch_gram(n, nc, nc, Ur, nc, BU, nc, gpart, Gd2, nc, s));
   std::vector<double> Ah((size_t)nc * nc), Bh((size_t)nc * nc), Sh((size_t)nc * nc);
   HIPCHK(hipMemcpyAsync(Ah.data(), Gd, sizeof(double) * nc * nc, hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(Bh.data(), Gd2, sizeof(double) * nc * nc, hipMemcpyDeviceToHost, s));

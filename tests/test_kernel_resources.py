@@ -51,3 +51,50 @@ def test_hot_kernels_use_no_scratch(descriptors):
     assert not spilled, spilled
     # and within the 512 registers a lane can address
     assert max(v[1] for v in hot.values()) <= 512
+
+
+def test_mfma_loops_keep_their_accumulators():
+    """The FP64 MFMA kernels of Rayleigh-Ritz (Gram and tall GEMM: 20-25
+    accumulator blocks per wave) compiled with the library's flags for their
+    file: no scratch, and the loop blocks that issue the MFMAs hold no
+    accumulator copies between register files (with 200 accumulator registers
+    the default allocation moved every accumulator twice per MFMA round)."""
+    if HIPCC is None:
+        pytest.skip("hipcc not available")
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "slrf_build", os.path.join(ROOT, "paper_2510_17334_amd", "build.py"))
+    build = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(build)
+    out = os.path.join(os.environ.get("TMPDIR", "/tmp"), "slrf_kernels_dense_%d.s" % os.getpid())
+    cmd = [HIPCC] + build.PER_FILE_FLAGS.get("kernels_dense.hip", []) + [
+        "--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature",
+        "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument",
+        "-I", os.path.join(ROOT, "include"), "-I", CSRC, "--cuda-device-only", "-S",
+        os.path.join(CSRC, "kernels_dense.hip"), "-o", out]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = open(out).read().splitlines()
+    os.remove(out)
+    starts = [(i, m.group(1)) for i, l in enumerate(lines)
+              for m in [re.match(r"^(_Z\S*(k_gram|k_gemm_tall)[IE]\S*):", l)] if m]
+    assert {re.search(r"(k_gram|k_gemm_tall)", f).group(1) for _, f in starts} == \
+        {"k_gram", "k_gemm_tall"}
+    text = "\n".join(lines)
+    for st, fn in starts:
+        en = next(i for i in range(st, len(lines)) if lines[i].strip().startswith(".Lfunc_end"))
+        body = lines[st:en]
+        cuts = [i for i, l in enumerate(body) if l.startswith(".LBB")] + [len(body)]
+        mfma_blocks = 0
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            ins = [x.strip() for x in body[a:b] if x.strip() and not x.strip().startswith((";", "."))]
+            n_mfma = sum("v_mfma_f64" in x for x in ins)
+            if n_mfma:
+                mfma_blocks += 1
+                copies = sum(x.startswith(("v_accvgpr_read", "v_accvgpr_write")) for x in ins)
+                assert copies <= n_mfma // 2, (fn, n_mfma, copies)
+        assert mfma_blocks > 0, fn
+        m = re.search(r"\.amdhsa_kernel " + re.escape(fn) + r"\n(.*?)\.end_amdhsa_kernel", text,
+                      re.S)
+        assert m and int(re.search(r"\.amdhsa_private_segment_fixed_size (\d+)",
+                                   m.group(1)).group(1)) == 0, fn

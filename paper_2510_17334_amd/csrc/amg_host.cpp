@@ -130,6 +130,14 @@ int aggregate(const HostLevel& L, double theta, std::vector<int>& agg) {
   return na;
 }
 
+std::vector<double> rho_start_vector(int n) {
+  std::vector<double> x(n);
+  std::mt19937_64 rng(12345);
+  std::normal_distribution<double> nd(0.0, 1.0);
+  for (auto& v : x) v = nd(rng);
+  return x;
+}
+
 // spectral radius of D^{-1} A by power iteration
 double rho_dinv_a(const HostLevel& L) {
   const int n = L.n;
@@ -137,9 +145,7 @@ double rho_dinv_a(const HostLevel& L) {
   for (int i = 0; i < n; ++i)
     for (int e = L.rp[i]; e < L.rp[i + 1]; ++e)
       if (L.ci[e] == i) d[i] = L.a[e];
-  std::mt19937_64 rng(12345);
-  std::normal_distribution<double> nd(0.0, 1.0);
-  for (auto& v : x) v = nd(rng);
+  x = rho_start_vector(n);
   double rho = 1.0;
   for (int it = 0; it < 20; ++it) {
     double nrm = 0.0;
@@ -313,12 +319,99 @@ void locality_order(const HostLevel& fine, std::vector<int>& order, int block) {
   });
 }
 
+// One level's products on the host: rho(D^-1 A) by power iteration,
+// A T, P = T - (omega_p / rho) D^-1 A T (T's entries added where A T has the
+// column), R = P^T, A P and B P on one pattern, and C = R (A P), R (B P)
+// (Gustavson order throughout, C not yet symmetrised).
+bool host_level_products(const HostLevel& L, int nc, const std::vector<int>& trp,
+                         const std::vector<int>& tci, const std::vector<double>& tv,
+                         double omega_p, double& rho, HostCsrP& P, HostCsrP& R,
+                         HostLevel& APBP, HostLevel& C) {
+  const int n = L.n;
+  rho = rho_dinv_a(L);
+  std::vector<int> arp, aci;
+  std::vector<double> at;
+  spgemm2(n, nc, L.rp, L.ci, L.a, nullptr, trp, tci, tv, arp, aci, at, nullptr);
+  std::vector<double> d(n, 1.0);
+  for (int i = 0; i < n; ++i)
+    for (int e = L.rp[i]; e < L.rp[i + 1]; ++e)
+      if (L.ci[e] == i) d[i] = L.a[e];
+  P = HostCsrP();
+  P.n = n;
+  P.m = nc;
+  P.rp = arp;
+  P.ci = aci;
+  P.v.resize(at.size());
+  const double w = omega_p / rho;
+  for (int i = 0; i < n; ++i) {
+    // (A T has every column of T's row i: A holds the diagonal)
+    int f = trp[i];
+    for (int e = arp[i]; e < arp[i + 1]; ++e) {
+      double v = -w * at[e] / d[i];
+      while (f < trp[i + 1] && tci[f] < aci[e]) ++f;
+      if (f < trp[i + 1] && tci[f] == aci[e]) v += tv[f];
+      P.v[e] = v;
+    }
+  }
+  R = HostCsrP();
+  R.n = nc;
+  R.m = n;
+  transpose(n, nc, P.rp, P.ci, P.v, R.rp, R.ci, R.v);
+  // Galerkin: AP, BP (shared pattern), then R (AP), R (BP)
+  std::vector<int> aprp, apci;
+  std::vector<double> apa, apb;
+  spgemm2(n, nc, L.rp, L.ci, L.a, &L.b, P.rp, P.ci, P.v, aprp, apci, apa, &apb);
+  C = HostLevel();
+  C.n = nc;
+  // R * (AP) and R * (BP) on one pattern: multiply R (single value array)
+  // into the two value arrays of AP/BP by swapping roles: C = R * AP and
+  // C' = R * BP share the pattern because AP and BP do.
+  {
+    SpRow wr(nc);
+    C.rp.assign(nc + 1, 0);
+    for (int i = 0; i < nc; ++i) {
+      wr.cols.clear();
+      for (int e = R.rp[i]; e < R.rp[i + 1]; ++e) {
+        const int k = R.ci[e];
+        const double rv = R.v[e];
+        for (int f = aprp[k]; f < aprp[k + 1]; ++f) {
+          const int j = apci[f];
+          if (wr.marker[j] != i) {
+            wr.marker[j] = i;
+            wr.cols.push_back(j);
+            wr.acc1[j] = 0.0;
+            wr.acc2[j] = 0.0;
+          }
+          wr.acc1[j] += rv * apa[f];
+          wr.acc2[j] += rv * apb[f];
+        }
+      }
+      std::sort(wr.cols.begin(), wr.cols.end());
+      for (int j : wr.cols) {
+        C.ci.push_back(j);
+        // symmetrise the tiny rounding asymmetry later by averaging with the transpose
+        C.a.push_back(wr.acc1[j]);
+        C.b.push_back(wr.acc2[j]);
+      }
+      C.rp[i + 1] = (int)C.ci.size();
+    }
+  }
+  APBP = HostLevel();
+  APBP.n = n;
+  APBP.rp = std::move(aprp);
+  APBP.ci = std::move(apci);
+  APBP.a = std::move(apa);
+  APBP.b = std::move(apb);
+  return true;
+}
+
 bool amg_build(const HostLevel& fine, const std::vector<std::complex<double>>& poles,
-               const AmgParams& prm, AmgHierarchy& H, std::string& err) {
+               const AmgParams& prm, AmgHierarchy& H, std::string& err, AmgNumeric* num) {
   H.levels.clear();
   H.P.clear();
   H.R.clear();
   H.rho.clear();
+  H.img.clear();
   H.levels.push_back(fine);
   // near-nullspace candidates of the current level (n x kns, row-major): the
   // constant (scalar), one translation per component, or the rigid-body modes
@@ -442,87 +535,27 @@ bool amg_build(const HostLevel& fine, const std::vector<std::complex<double>>& p
         trp[i + 1] = (int)tci.size();
       }
     }
-    // a row of T holds at most one entry per column: the diagonal-block term
-    // of P below adds T's value in that column
-    std::vector<int> agg_first(n);
-    for (int i = 0; i < n; ++i) agg_first[i] = dagg[i];
+    // (a row of T holds at most one entry per column: the diagonal-block
+    // term of P adds T's value in that column)
     std::vector<double> ns_next((size_t)nc * kns, 0.0);
     for (int a = 0; a < na; ++a)
       for (int j = 0; j < ka[a]; ++j)
         for (int c = 0; c < kns; ++c)
           ns_next[(size_t)(cbase[a] + j) * kns + c] = Ra[a][(size_t)j * kns + c];
-    // P = T - (omega / rho) D^{-1} A T
-    const double rho = rho_dinv_a(L);
-    H.rho.push_back(rho);
-    std::vector<int> arp, aci;
-    std::vector<double> at;
-    spgemm2(n, nc, L.rp, L.ci, L.a, nullptr, trp, tci, tv, arp, aci, at, nullptr);
-    std::vector<double> d(n, 1.0);
-    for (int i = 0; i < n; ++i)
-      for (int e = L.rp[i]; e < L.rp[i + 1]; ++e)
-        if (L.ci[e] == i) d[i] = L.a[e];
-    HostCsrP P;
-    P.n = n;
-    P.m = nc;
-    P.rp = arp;
-    P.ci = aci;
-    P.v.resize(at.size());
-    const double w = prm.omega_p / rho;
-    for (int i = 0; i < n; ++i) {
-      // (A T has every column of T's row i: A holds the diagonal)
-      int f = trp[i];
-      for (int e = arp[i]; e < arp[i + 1]; ++e) {
-        double v = -w * at[e] / d[i];
-        while (f < trp[i + 1] && tci[f] < aci[e]) ++f;
-        if (f < trp[i + 1] && tci[f] == aci[e]) v += tv[f];
-        P.v[e] = v;
-      }
-    }
-    (void)agg_first;
-    HostCsrP R;
-    R.n = nc;
-    R.m = n;
-    transpose(n, nc, P.rp, P.ci, P.v, R.rp, R.ci, R.v);
-    // Galerkin: AP, BP (shared pattern), then R (AP), R (BP)
-    std::vector<int> aprp, apci;
-    std::vector<double> apa, apb;
-    spgemm2(n, nc, L.rp, L.ci, L.a, &L.b, P.rp, P.ci, P.v, aprp, apci, apa, &apb);
-    HostLevel C;
-    C.n = nc;
-    std::vector<double> cb;
-    // R * (AP) and R * (BP) on one pattern: multiply R (single value array)
-    // into the two value arrays of AP/BP by swapping roles: C = R * AP and
-    // C' = R * BP share the pattern because AP and BP do.
+    // P = T - (omega / rho) D^{-1} A T, R = P^T, A P and B P, C = R (A P), R (B P)
+    double rho = 1.0;
+    HostCsrP P, R;
+    HostLevel APBP, C;
     {
-      SpRow wr(nc);
-      C.rp.assign(nc + 1, 0);
-      for (int i = 0; i < nc; ++i) {
-        wr.cols.clear();
-        for (int e = R.rp[i]; e < R.rp[i + 1]; ++e) {
-          const int k = R.ci[e];
-          const double rv = R.v[e];
-          for (int f = aprp[k]; f < aprp[k + 1]; ++f) {
-            const int j = apci[f];
-            if (wr.marker[j] != i) {
-              wr.marker[j] = i;
-              wr.cols.push_back(j);
-              wr.acc1[j] = 0.0;
-              wr.acc2[j] = 0.0;
-            }
-            wr.acc1[j] += rv * apa[f];
-            wr.acc2[j] += rv * apb[f];
-          }
-        }
-        std::sort(wr.cols.begin(), wr.cols.end());
-        for (int j : wr.cols) {
-          C.ci.push_back(j);
-          // symmetrise the tiny rounding asymmetry later by averaging with the transpose
-          C.a.push_back(wr.acc1[j]);
-          C.b.push_back(wr.acc2[j]);
-        }
-        C.rp[i + 1] = (int)C.ci.size();
+      std::string nerr;
+      const bool ok = num ? num->level(L, nc, trp, tci, tv, prm.omega_p, rho, P, R, APBP, C, nerr)
+                          : host_level_products(L, nc, trp, tci, tv, prm.omega_p, rho, P, R, APBP, C);
+      if (!ok) {
+        err = "AMG products: " + nerr;
+        return false;
       }
     }
+    H.rho.push_back(rho);
     // enforce exact symmetry of the coarse operators: (C + C^T)/2 on the shared pattern
     {
       std::vector<int> trp2, tci2;
@@ -536,6 +569,7 @@ bool amg_build(const HostLevel& fine, const std::vector<std::complex<double>>& p
         }
       }
     }
+    H.img.push_back(std::move(APBP));
     H.P.push_back(std::move(P));
     H.R.push_back(std::move(R));
     H.levels.push_back(std::move(C));
@@ -574,13 +608,12 @@ bool amg_coarse_inverses(AmgHierarchy& H, const std::vector<std::complex<double>
   return true;
 }
 
-bool fine_image(const HostLevel& L, const HostCsrP& P, std::vector<int>& rp,
-                std::vector<int>& ci, std::vector<double>& ap, std::vector<double>& bp,
-                std::vector<double>& pv) {
-  spgemm2(L.n, P.m, L.rp, L.ci, L.a, &L.b, P.rp, P.ci, P.v, rp, ci, ap, &bp);
+namespace {
+bool p_on_pattern(int n, const std::vector<int>& rp, const std::vector<int>& ci, const HostCsrP& P,
+                  std::vector<double>& pv) {
   pv.assign(ci.size(), 0.0);
   std::vector<int> at(P.m, -1);  // entry of column c in the current row
-  for (int i = 0; i < L.n; ++i) {
+  for (int i = 0; i < n; ++i) {
     for (int e = rp[i]; e < rp[i + 1]; ++e) at[ci[e]] = e;
     for (int f = P.rp[i]; f < P.rp[i + 1]; ++f) {
       const int e = at[P.ci[f]];
@@ -590,6 +623,18 @@ bool fine_image(const HostLevel& L, const HostCsrP& P, std::vector<int>& rp,
     for (int e = rp[i]; e < rp[i + 1]; ++e) at[ci[e]] = -1;
   }
   return true;
+}
+}  // namespace
+
+bool fine_image(const HostLevel& L, const HostCsrP& P, std::vector<int>& rp,
+                std::vector<int>& ci, std::vector<double>& ap, std::vector<double>& bp,
+                std::vector<double>& pv) {
+  spgemm2(L.n, P.m, L.rp, L.ci, L.a, &L.b, P.rp, P.ci, P.v, rp, ci, ap, &bp);
+  return p_on_pattern(L.n, rp, ci, P, pv);
+}
+
+bool image_p_values(const HostLevel& APBP, const HostCsrP& P, std::vector<double>& pv) {
+  return p_on_pattern(APBP.n, APBP.rp, APBP.ci, P, pv);
 }
 
 }  // namespace slrf

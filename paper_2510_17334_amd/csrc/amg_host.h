@@ -43,6 +43,9 @@ struct AmgHierarchy {
   std::vector<double> rho;        // rho[l] = spectral radius estimate of D_l^{-1} A_l
   int nc = 0;                     // coarsest size
   std::vector<std::complex<double>> coarse_inv;  // [pole][nc][nc] row-major
+  // img[l]: A_l P_l and B_l P_l (a and b on one row-sorted pattern), formed for
+  // the Galerkin product and kept for the fine-level images (may be cleared)
+  std::vector<HostLevel> img;
 };
 
 // Locality ordering of the rows (order[new] = old) from nested aggregation
@@ -53,10 +56,33 @@ void locality_order(const HostLevel& fine, std::vector<int>& order, int block = 
 // one column list made of whole node blocks, else 1.
 int detect_block(const HostLevel& L);
 
+// The numeric work of one level, given the level operator L and the tentative
+// prolongator T (n x nc): rho = rho(D^-1 A) by 20 power steps from a fixed
+// seeded start, P = T - (omega_p / rho) D^-1 A T, R = P^T, APBP = (A P, B P) on
+// one pattern and C = (R (A P), R (B P)), every product in Gustavson order with
+// row-sorted output (C not yet symmetrised).
+struct AmgNumeric {
+  virtual ~AmgNumeric() = default;
+  virtual bool level(const HostLevel& L, int nc, const std::vector<int>& trp,
+                     const std::vector<int>& tci, const std::vector<double>& tv, double omega_p,
+                     double& rho, HostCsrP& P, HostCsrP& R, HostLevel& APBP, HostLevel& C,
+                     std::string& err) = 0;
+};
+// The host implementation of AmgNumeric::level.
+bool host_level_products(const HostLevel& L, int nc, const std::vector<int>& trp,
+                         const std::vector<int>& tci, const std::vector<double>& tv,
+                         double omega_p, double& rho, HostCsrP& P, HostCsrP& R,
+                         HostLevel& APBP, HostLevel& C);
+// The power iteration's start vector for a level of n rows.
+std::vector<double> rho_start_vector(int n);
+
 // Builds the hierarchy and, for the given poles (none: skipped), the dense
-// inverses of the coarsest level operators A_c - sigma_j B_c.
+// inverses of the coarsest level operators A_c - sigma_j B_c.  The aggregation
+// and the tentative prolongators run on the host; each level's products run
+// through `num` (the host's own when null).
 bool amg_build(const HostLevel& fine, const std::vector<std::complex<double>>& poles,
-               const AmgParams& prm, AmgHierarchy& H, std::string& err);
+               const AmgParams& prm, AmgHierarchy& H, std::string& err,
+               AmgNumeric* num = nullptr);
 // (Re)computes H.coarse_inv for the given poles.
 bool amg_coarse_inverses(AmgHierarchy& H, const std::vector<std::complex<double>>& poles,
                          std::string& err);
@@ -68,5 +94,8 @@ bool amg_coarse_inverses(AmgHierarchy& H, const std::vector<std::complex<double>
 bool fine_image(const HostLevel& L, const HostCsrP& P, std::vector<int>& rp,
                 std::vector<int>& ci, std::vector<double>& ap, std::vector<double>& bp,
                 std::vector<double>& pv);
+// P's values on the pattern of its images (APBP: the A P / B P pattern of
+// AmgHierarchy::img); false if some entry of P falls outside it.
+bool image_p_values(const HostLevel& APBP, const HostCsrP& P, std::vector<double>& pv);
 
 }  // namespace slrf

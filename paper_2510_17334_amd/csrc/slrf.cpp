@@ -514,14 +514,17 @@ std::shared_ptr<const HostSetup> analyse(const slrf_csr* A, const slrf_csr* B,
     const int L = (int)hs->H.levels.size();
     hs->img.assign(std::max(L - 1, 0), HostImage());
     for (int l = 0; l + 1 < L; ++l) {
-      std::vector<int> irp, ici;
-      std::vector<double> iap, ibp, ipv;
+      std::vector<double> ipv;
       const HostLevel& lvl = hs->H.levels[l];
       HostImage& I = hs->img[l];
-      I.ok = fine_image(lvl, hs->H.P[l], irp, ici, iap, ibp, ipv) &&
-             build_halo(lvl.n, irp, ici, iap, ibp, kImgMaxH, kHaloTileRows, I.hx, &ipv);
+      // (A P and B P from the Galerkin product)
+      const HostLevel& ab = hs->H.img[l];
+      I.ok = image_p_values(ab, hs->H.P[l], ipv) &&
+             build_halo(lvl.n, ab.rp, ab.ci, ab.a, ab.b, kImgMaxH, kHaloTileRows, I.hx, &ipv);
       I.nc = hs->H.P[l].m;
     }
+    hs->H.img.clear();
+    hs->H.img.shrink_to_fit();
     hs->has_amg = true;
   }
   std::lock_guard<std::mutex> lk(g_an_mu);

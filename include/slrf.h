@@ -132,7 +132,26 @@ typedef struct {
                           (translations and rotations) instead of the
                           translations alone.  Read by slrf_workspace_size
                           and slrf_setup only.                               */
+  int32_t amg_setup;   /* where the AMG hierarchy is built (SLRF_PC_AMG only):
+                          SLRF_AMG_HOST (default): all of it on the host, by
+                          slrf_workspace_size's and slrf_setup's shared
+                          analysis; SLRF_AMG_DEVICE: the aggregation and the
+                          tentative prolongators on the host, each level's
+                          products (rho(D^-1 A) by power steps, A T, the
+                          smoothed prolongator P and R = P^T, A P, B P and the
+                          Galerkin products P^T A P, P^T B P: the construction
+                          phase of the smoothed aggregation the paper's
+                          GAMG reuse implies, Section 3.2) on the GPU inside
+                          slrf_setup, in the caller's workspace, with values
+                          equal to the host build's.  slrf_workspace_size then
+                          cannot see the hierarchy and returns a bound; setup
+                          fails with SLRF_E_NOMEM (message: the bytes needed)
+                          when the workspace is too small, and with SLRF_E_ARG
+                          when a product row has more than 1024 distinct
+                          columns.  Fixed at setup.                          */
 } slrf_options;
+
+enum { SLRF_AMG_HOST = 0, SLRF_AMG_DEVICE = 1 };
 
 /* Per-kernel-class counters (algorithmic bytes, launches, event time). */
 enum {

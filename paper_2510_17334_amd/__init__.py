@@ -13,6 +13,8 @@ from .slrf import (  # noqa: F401
     SLRF_PC_NONE,
     SLRF_PC_JACOBI,
     SLRF_PC_AMG,
+    SLRF_AMG_HOST,
+    SLRF_AMG_DEVICE,
     SlrfError,
     Handle,
     EigFn,

@@ -23,7 +23,10 @@ ARCH = "gfx950"
 # The MFMA kernels keep their FP64 accumulators (up to 200 registers) in the
 # VGPR form: otherwise the register allocator parks them in AGPRs and copies
 # them back and forth around every MFMA of the loop.
-PER_FILE_FLAGS = {"kernels_dense.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+# The device AMG products round every product before adding it (no fused
+# multiply-add), as the host build does, so the two hierarchies are equal.
+PER_FILE_FLAGS = {"kernels_dense.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+                  "amg_device.hip": ["-ffp-contract=off"]}
 
 
 def _hipcc() -> str:

@@ -16,6 +16,14 @@
 
 namespace slrf {
 
+std::vector<double> rho_start_vector(int n) {
+  std::vector<double> x(n);
+  std::mt19937_64 rng(12345);
+  std::normal_distribution<double> nd(0.0, 1.0);
+  for (auto& v : x) v = nd(rng);
+  return x;
+}
+
 namespace {
 
 // Gustavson product C = X * Y (pattern only + values for one or two value
@@ -128,14 +136,6 @@ int aggregate(const HostLevel& L, double theta, std::vector<int>& agg) {
     ++na;
   }
   return na;
-}
-
-std::vector<double> rho_start_vector(int n) {
-  std::vector<double> x(n);
-  std::mt19937_64 rng(12345);
-  std::normal_distribution<double> nd(0.0, 1.0);
-  for (auto& v : x) v = nd(rng);
-  return x;
 }
 
 // spectral radius of D^{-1} A by power iteration

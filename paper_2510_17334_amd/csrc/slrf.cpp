@@ -26,6 +26,7 @@
 #include <string>
 #include <vector>
 
+#include "amg_device.h"
 #include "amg_host.h"
 #include "halo_host.h"
 #include "ugroup_host.h"
@@ -275,6 +276,8 @@ slrf_status validate_options(slrf_ctx* h, const slrf_options& o) {
     return fail(h, SLRF_E_ARG, "n must be a multiple of amg_block");
   if (o.spmm_variant < 0 || o.spmm_variant >= kSpmmVariants)
     return fail(h, SLRF_E_ARG, "spmm_variant must be 0..7");
+  if (o.amg_setup != SLRF_AMG_HOST && o.amg_setup != SLRF_AMG_DEVICE)
+    return fail(h, SLRF_E_ARG, "amg_setup must be SLRF_AMG_HOST or SLRF_AMG_DEVICE");
   return SLRF_OK;
 }
 
@@ -334,6 +337,10 @@ struct HostSetup {
   bool has_amg = false;
   AmgHierarchy H;                    // without the per-pole coarse inverses
   std::vector<HostImage> img;        // img[l], l < levels - 1
+  // SLRF_AMG_DEVICE: the hierarchy is built by slrf_setup (parameters kept here)
+  bool amg_device = false;
+  AmgParams amg_prm;
+  std::vector<double> amg_xyz;       // node coordinates in the final order (or empty)
 };
 
 uint64_t fnv1a(uint64_t h, const void* p, size_t bytes) {
@@ -345,6 +352,25 @@ uint64_t fnv1a(uint64_t h, const void* p, size_t bytes) {
 std::mutex g_an_mu;
 uint64_t g_an_key = 0;
 std::shared_ptr<const HostSetup> g_an;
+
+// The level images (A_l P_l, B_l P_l with P_l's values) in halo tiles over the
+// next level's rows, from the Galerkin products the hierarchy kept (which are
+// then dropped).
+void amg_images(AmgHierarchy& H, std::vector<HostImage>& img) {
+  const int L = (int)H.levels.size();
+  img.assign(std::max(L - 1, 0), HostImage());
+  for (int l = 0; l + 1 < L; ++l) {
+    std::vector<double> ipv;
+    const HostLevel& lvl = H.levels[l];
+    HostImage& I = img[l];
+    const HostLevel& ab = H.img[l];
+    I.ok = image_p_values(ab, H.P[l], ipv) &&
+           build_halo(lvl.n, ab.rp, ab.ci, ab.a, ab.b, kImgMaxH, kHaloTileRows, I.hx, &ipv);
+    I.nc = H.P[l].m;
+  }
+  H.img.clear();
+  H.img.shrink_to_fit();
+}
 
 // Reads and validates A and B (device CSR, shared pattern, sorted, diagonal
 // present) and computes the host analysis; nullptr with `err` set on failure.
@@ -394,8 +420,8 @@ std::shared_ptr<const HostSetup> analyse(const slrf_csr* A, const slrf_csr* B,
   key = fnv1a(key, cl.data(), cl.size() * sizeof(int));
   key = fnv1a(key, av.data(), av.size() * sizeof(double));
   key = fnv1a(key, bv.data(), bv.size() * sizeof(double));
-  const int32_t kopt[5] = {opt.reorder, opt.amg_block, amg ? 1 : 0, n,
-                           opt.node_xyz != nullptr ? 1 : 0};
+  const int32_t kopt[6] = {opt.reorder, opt.amg_block, amg ? 1 : 0, n,
+                           opt.node_xyz != nullptr ? 1 : 0, opt.amg_setup};
   key = fnv1a(key, kopt, sizeof(kopt));
   if (opt.node_xyz) key = fnv1a(key, opt.node_xyz, sizeof(double) * n);
   {
@@ -506,26 +532,21 @@ std::shared_ptr<const HostSetup> analyse(const slrf_csr* A, const slrf_csr* B,
       }
       prm.xyz = &xyz;
     }
-    std::string aerr;
-    if (!amg_build(fine, {}, prm, hs->H, aerr)) {
-      err = "AMG setup: " + aerr;
-      return nullptr;
+    if (opt.amg_setup == SLRF_AMG_DEVICE) {
+      // built by slrf_setup, on the GPU, in the caller's workspace
+      hs->amg_device = true;
+      hs->amg_prm = prm;
+      hs->amg_prm.xyz = nullptr;
+      hs->amg_xyz = std::move(xyz);
+    } else {
+      std::string aerr;
+      if (!amg_build(fine, {}, prm, hs->H, aerr)) {
+        err = "AMG setup: " + aerr;
+        return nullptr;
+      }
+      amg_images(hs->H, hs->img);
+      hs->has_amg = true;
     }
-    const int L = (int)hs->H.levels.size();
-    hs->img.assign(std::max(L - 1, 0), HostImage());
-    for (int l = 0; l + 1 < L; ++l) {
-      std::vector<double> ipv;
-      const HostLevel& lvl = hs->H.levels[l];
-      HostImage& I = hs->img[l];
-      // (A P and B P from the Galerkin product)
-      const HostLevel& ab = hs->H.img[l];
-      I.ok = image_p_values(ab, hs->H.P[l], ipv) &&
-             build_halo(lvl.n, ab.rp, ab.ci, ab.a, ab.b, kImgMaxH, kHaloTileRows, I.hx, &ipv);
-      I.nc = hs->H.P[l].m;
-    }
-    hs->H.img.clear();
-    hs->H.img.shrink_to_fit();
-    hs->has_amg = true;
   }
   std::lock_guard<std::mutex> lk(g_an_mu);
   g_an_key = key;
@@ -659,10 +680,10 @@ hipError_t place_pencil(slrf_ctx* h, const HostSetup& hs, Placer& pl, const slrf
 
 // The AMG hierarchy (levels >= 1, transfers, images) and, for `npoles` poles,
 // room for the coarsest-level inverses (filled by setup).
-hipError_t place_amg(slrf_ctx* h, const HostSetup& hs, Placer& pl, int npoles) {
+hipError_t place_amg(slrf_ctx* h, const AmgHierarchy& H, const std::vector<HostImage>& img,
+                     Placer& pl, int npoles) {
   hipError_t e;
   DevAmg& A = h->amg;
-  const AmgHierarchy& H = hs.H;
   const int L = (int)H.levels.size();
   A = DevAmg();
   for (auto& lv : H.levels) A.n.push_back(lv.n);
@@ -720,7 +741,7 @@ hipError_t place_amg(slrf_ctx* h, const HostSetup& hs, Placer& pl, int npoles) {
   // tile's coarse halo would exceed kImgMaxH rows)
   A.img.assign(L, DevImage());
   for (int l = 0; l + 1 < L; ++l) {
-    const HostImage& hi = hs.img[l];
+    const HostImage& hi = img[l];
     if (!hi.ok) continue;
     const HostHalo& hx = hi.hx;
     DevImage& I = A.img[l];
@@ -757,8 +778,18 @@ size_t persistent_bytes(const HostSetup& hs, int npoles) {
   slrf_ctx tmp;
   Placer pl{&tmp, true};
   (void)place_pencil(&tmp, hs, pl, nullptr, nullptr);
-  if (hs.has_amg) (void)place_amg(&tmp, hs, pl, npoles);
+  if (hs.has_amg) (void)place_amg(&tmp, hs.H, hs.img, pl, npoles);
   return align_up(pl.bytes);
+}
+
+// SLRF_AMG_DEVICE: what slrf_workspace_size reserves for a hierarchy it has not
+// built (levels, P and R, the images and the coarse inverses): 200 bytes per
+// fine nonzero, 64 per fine row and the largest dense coarsest level for
+// every pole.  The 48^3 elasticity hierarchy (26.9 M nonzeros) takes about a
+// fifth of it.
+size_t amg_device_bound(const HostSetup& hs, int npoles) {
+  const size_t nc = (size_t)hs.amg_prm.dense_max;
+  return align_up((size_t)hs.nnz * 200 + (size_t)hs.n * 64 + (size_t)npoles * nc * nc * 24);
 }
 
 // Level vectors of the V-cycle for a pool of C slots.
@@ -1655,6 +1686,8 @@ void slrf_default_options(slrf_options* o) {
   o->inner_rtol = 1e-5;
   o->tol_eig = 1e-8;
   o->amg_block = 0;
+  o->node_xyz = nullptr;
+  o->amg_setup = SLRF_AMG_HOST;
 }
 
 int32_t slrf_get_n(slrf_handle h) { return h ? h->P.n : -1; }
@@ -1675,9 +1708,15 @@ slrf_status slrf_workspace_size(const slrf_csr* A, const slrf_csr* B, int32_t L,
   slrf_status st;
   auto hs = analyse(A, B, o, err, st);
   if (!hs) return st;
-  const size_t pers = persistent_bytes(*hs, npoles);
+  size_t pers = persistent_bytes(*hs, npoles);
   std::vector<int> lev;
   for (auto& lv : hs->H.levels) lev.push_back(lv.n);
+  if (hs->amg_device) {
+    // (the hierarchy is built by slrf_setup: a bound, and coarse levels taken
+    // to hold at most half the fine rows)
+    pers += amg_device_bound(*hs, npoles);
+    lev = {hs->n, std::max(1, hs->n / 2)};
+  }
   const int S = npoles * L;
   int full = (S + kPanel - 1) / kPanel * kPanel;
   if (o.max_slots > 0) full = std::min(full, o.max_slots);
@@ -1748,24 +1787,72 @@ slrf_status slrf_setup(slrf_handle* out, const slrf_csr* A, const slrf_csr* B, d
   h->block = hs->block;
   h->h_order = hs->order;
   hipStream_t s = h->stream;
+  // SLRF_AMG_DEVICE: the hierarchy built here (products on the GPU)
+  AmgHierarchy Hdev;
+  std::vector<HostImage> imgdev;
+  const AmgHierarchy* Hp = hs->has_amg ? &hs->H : nullptr;
+  const std::vector<HostImage>* imgp = hs->has_amg ? &hs->img : nullptr;
   {
     Placer pl{h, false};
     hipError_t e = place_pencil(h, *hs, pl, A, B);
-    if (e == hipSuccess && hs->has_amg) e = place_amg(h, *hs, pl, npoles);
+    if (e == hipSuccess && hs->amg_device) {
+      // the products run in the workspace above the pencil data and are
+      // released level by level, before the hierarchy itself is placed there
+      HostLevel fine;
+      fine.n = hs->n;
+      fine.rp = hs->rp;
+      fine.ci = hs->ci;
+      fine.a = hs->a;
+      fine.b = hs->b;
+      AmgParams prm = hs->amg_prm;
+      if (!hs->amg_xyz.empty()) prm.xyz = &hs->amg_xyz;
+      DeviceAmgNumeric num;
+      num.stream = s;
+      const size_t top0 = h->ar.top;
+      size_t short_by = 0;
+      num.take = [h, &short_by](size_t bytes) -> void* {
+        void* p = nullptr;
+        if (carve(h, bytes, &p) != hipSuccess) {
+          short_by = std::max(short_by, h->ar.short_by);
+          return nullptr;
+        }
+        return p;
+      };
+      num.release = [h, top0]() { h->ar.top = top0; };
+      std::string aerr;
+      const bool built = amg_build(fine, {}, prm, Hdev, aerr, &num);
+      h->ar.top = top0;
+      if (!built) {
+        if (short_by > 0) {
+          char buf[256];
+          std::snprintf(buf, sizeof(buf),
+                        "workspace too small for the device AMG setup (%zu more bytes needed)",
+                        short_by);
+          return bad(SLRF_E_NOMEM, buf);
+        }
+        return bad(SLRF_E_ARG, "AMG setup: " + aerr);
+      }
+      amg_images(Hdev, imgdev);
+      Hp = &Hdev;
+      imgp = &imgdev;
+    }
+    if (e == hipSuccess && Hp) e = place_amg(h, *Hp, *imgp, pl, npoles);
     if (e == hipErrorOutOfMemory) {
       char buf[256];
       std::snprintf(buf, sizeof(buf),
                     "workspace of %zu bytes too small for the pencil data (%zu bytes; see "
                     "slrf_workspace_size)",
-                    h->ar.cap, persistent_bytes(*hs, npoles));
+                    h->ar.cap,
+                    persistent_bytes(*hs, npoles) +
+                        (hs->amg_device ? amg_device_bound(*hs, npoles) : 0));
       return bad(SLRF_E_NOMEM, buf);
     }
     if (e != hipSuccess) return bad(SLRF_E_HIP, "upload of the pencil data failed");
   }
-  if (hs->has_amg) {
+  if (Hp) {
     // per-pole dense inverses of the coarsest level operators
     AmgHierarchy top;
-    top.levels.push_back(hs->H.levels.back());
+    top.levels.push_back(Hp->levels.back());
     std::vector<std::complex<double>> pz;
     for (auto& p : h->poles) pz.emplace_back(p.x, p.y);
     std::string aerr;
@@ -1824,8 +1911,9 @@ slrf_status slrf_set_options(slrf_handle h, const slrf_options* opt) {
   if (s != SLRF_OK) return s;
   if (opt->precond == SLRF_PC_AMG && !h->amg.ready)
     return fail(h, SLRF_E_ARG, "the AMG hierarchy is built at setup: set precond there");
-  if (opt->reorder != h->opt.reorder || opt->amg_block != h->opt.amg_block)
-    return fail(h, SLRF_E_ARG, "reorder and amg_block are fixed at setup");
+  if (opt->reorder != h->opt.reorder || opt->amg_block != h->opt.amg_block ||
+      opt->amg_setup != h->opt.amg_setup)
+    return fail(h, SLRF_E_ARG, "reorder, amg_block and amg_setup are fixed at setup");
   h->opt = *opt;
   if (opt->spmm_variant != kSpmmAuto) h->P.var32 = h->P.var64 = opt->spmm_variant;
   return SLRF_OK;

@@ -18,6 +18,8 @@ _LIB_PATH = os.path.join(HERE, "libslrf.so")
 
 SLRF_PREC_FP64 = 0
 SLRF_PREC_MIXED = 1
+SLRF_AMG_HOST = 0
+SLRF_AMG_DEVICE = 1
 SLRF_PC_NONE = 0
 SLRF_PC_JACOBI = 1
 SLRF_PC_AMG = 2
@@ -49,7 +51,7 @@ class Options(C.Structure):
                 ("tol_lin", C.c_double),
                 ("inner_rtol", C.c_double),
                 ("tol_eig", C.c_double), ("amg_block", C.c_int32),
-                ("node_xyz", C.c_void_p)]
+                ("node_xyz", C.c_void_p), ("amg_setup", C.c_int32)]
 
 
 class FilterStats(C.Structure):

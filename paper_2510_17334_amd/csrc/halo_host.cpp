@@ -102,4 +102,45 @@ bool build_halo(int n, const std::vector<int>& rp, const std::vector<int>& ci,
   return out.hmax <= hmax;
 }
 
+void build_halo_sub(int n, const HostHalo& hx, HostHaloSub& out) {
+  out = HostHaloSub();
+  const int S = kHaloSlice;
+  const int nslice = (n + S - 1) / S;
+  out.sptr.assign(nslice + 1, 0);
+  for (int s = 0; s < nslice; ++s) {
+    int wdt = 0;
+    for (int t = 0; t < S; ++t) {
+      const int r = s * S + t;
+      if (r >= n) break;
+      int cnt = 0;
+      for (int j = 0; j < hx.slen[r]; ++j) cnt += hx.c[halo_entry(hx.sptr[s], j, t)] != 0.0;
+      wdt = std::max(wdt, cnt);
+    }
+    out.sptr[s + 1] = out.sptr[s] + (wdt + kHaloPad - 1) / kHaloPad * kHaloPad;
+  }
+  const size_t nent = (size_t)out.sptr[nslice] * S;
+  out.lcol.assign(nent, 0);
+  out.v.assign(nent, 0.0);
+  for (int s = 0; s < nslice; ++s)
+    for (int t = 0; t < S; ++t) {
+      const int r = s * S + t;
+      if (r >= n) break;
+      int q = 0;
+      for (int j = 0; j < hx.slen[r]; ++j) {
+        const size_t k = halo_entry(hx.sptr[s], j, t);
+        if (hx.c[k] == 0.0) continue;
+        const size_t kk = halo_entry(out.sptr[s], q++, t);
+        out.lcol[kk] = hx.lcol[k];
+        out.v[kk] = hx.c[k];
+      }
+    }
+  for (int t = 0; t < hx.ntile; ++t) {
+    const int s0 = hx.trow[t] / S, s1 = (hx.trow[t + 1] + S - 1) / S;
+    for (int a = s0; a < s1; a += kHaloPassSlices) {
+      const int b = std::min(a + kHaloPassSlices, s1);
+      out.emax = std::max(out.emax, (out.sptr[b] - out.sptr[a]) * S);
+    }
+  }
+}
+
 }  // namespace slrf

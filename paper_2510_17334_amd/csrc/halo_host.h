@@ -44,6 +44,18 @@ inline size_t halo_entry(int sptr_s, int j, int t) {
          (size_t)t * kHaloPad + (size_t)(j % kHaloPad);
 }
 
+// The entries of a halo layout whose third value (c) is nonzero, on the same
+// tiles and halo positions, in a grouped slice layout of their own (same
+// entry placement rule; each row's entries keep their order): the prolongator
+// P inside the layout of its images A P, B P.
+struct HostHaloSub {
+  int emax = 0;                 // most entries of a pass (4 consecutive slices of a tile)
+  std::vector<int> sptr;        // [nslice + 1] slice offsets in steps of 8 entries
+  std::vector<uint16_t> lcol;   // local column (halo position) per entry
+  std::vector<double> v;        // value per entry
+};
+void build_halo_sub(int n, const HostHalo& hx, HostHaloSub& out);
+
 // Returns false (format not built) when a single slice references more than
 // hmax columns or hmax exceeds the 16-bit local index range.  The matrix may
 // be rectangular (columns are any non-negative indices); `c`, when given, is a

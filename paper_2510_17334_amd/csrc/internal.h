@@ -232,6 +232,10 @@ struct DevImage {
   const unsigned short* lcol = nullptr;
   const float2* ab32 = nullptr;
   const double2* ab64 = nullptr;
+  // P's own entries on the image tiles (its nonzeros only, same halo positions)
+  int pemax = 0;
+  const int* psptr = nullptr;
+  const unsigned short* plcol = nullptr;
   const float* p32 = nullptr;
   const double* p64 = nullptr;
 };

@@ -536,6 +536,15 @@ struct HaloView {
   const void* ab;
 };
 
+// A subset of a halo layout's entries (the prolongator's within an image's
+// pattern) in grouped slices of its own, on the same tiles and halo rows.
+struct PSubView {
+  int emax;
+  const int* sptr;
+  const unsigned short* lcol;
+  const void* v;
+};
+
 // Local columns staged in LDS as byte offsets of the halo row: every staged
 // halo row is 128 bytes (eight 16-byte lane vectors) and local indices stay
 // below 512 (the tile halo caps), so shifting a packed pair of 16-bit indices
@@ -821,7 +830,7 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
 // (HR1: r1 and x0 are complex bfloat16, complex-float sweeps only)
 template <typename T, bool HR1>
 __global__ __launch_bounds__(kThreads) void k_post_image(
-    int n, int nc, HaloView hv, const T* __restrict__ pv, PanelGrid g, int G,
+    int n, int nc, HaloView hv, PSubView pw, PanelGrid g, int G,
     const int* __restrict__ active, const double2* __restrict__ sigma,
     const typename CT<T>::t* __restrict__ E, const typename CT<T>::t* __restrict__ X0,
     const typename CT<T>::t* __restrict__ R1, typename CT<T>::t* __restrict__ Out,
@@ -836,10 +845,12 @@ __global__ __launch_bounds__(kThreads) void k_post_image(
   extern __shared__ __attribute__((aligned(16))) double smem_d[];  // 16-byte vectors live here
   V* sZ = reinterpret_cast<V*>(smem_d);                            // [hmax][8]
   AB* s_ab = reinterpret_cast<AB*>(sZ + (size_t)g.rpb * 8);        // [emax]
-  T* s_p = reinterpret_cast<T*>(s_ab + hv.emax);                   // [emax]
-  unsigned* s_lc = reinterpret_cast<unsigned*>(s_p + hv.emax);  // [emax]
-  int* sH = reinterpret_cast<int*>(s_lc + hv.emax);                         // [hmax]
+  T* s_p = reinterpret_cast<T*>(s_ab + hv.emax);                   // [pemax] P's values
+  unsigned* s_lc = reinterpret_cast<unsigned*>(s_p + pw.emax);     // [emax]
+  unsigned* s_plc = s_lc + hv.emax;                                // [pemax] P's offsets
+  int* sH = reinterpret_cast<int*>(s_plc + pw.emax);              // [hmax]
   __shared__ int s_sp[kHaloTileRows / 8 + 1];
+  __shared__ int s_psp[kHaloTileRows / 8 + 1];
   __shared__ int s_uact[kHaloMaxG];
   const int nunit = g.npan * UPP;
   const int nug = (nunit + G - 1) / G;
@@ -850,7 +861,10 @@ __global__ __launch_bounds__(kThreads) void k_post_image(
   const int h0 = hv.hptr[tile], H = hv.hptr[tile + 1] - h0;
   const int nsl = (r1 - r0 + 7) >> 3, sl0 = r0 >> 3;  // (nsl <= 4: format invariant)
   for (int t = tid; t < H; t += kThreads) sH[t] = hv.halo[h0 + t];
-  if (tid <= nsl) s_sp[tid] = hv.sptr[sl0 + tid];
+  if (tid <= nsl) {
+    s_sp[tid] = hv.sptr[sl0 + tid];
+    s_psp[tid] = pw.sptr[sl0 + tid];
+  }
   if (tid < G) {
     const int u = ug * G + tid;
     int any = 0;
@@ -886,21 +900,30 @@ __global__ __launch_bounds__(kThreads) void k_post_image(
   } while (0)
   SLRF_IMG_ISSUE(gu);
   {
+    // the images' coefficients (A P, B P) and, apart, P's own entries
     const int e0 = s_sp[0] * 8, ne = (s_sp[nsl] - s_sp[0]) * 8;
-    const int nlc = ne / 8, nab = ne * (int)sizeof(AB) / 16, np = ne * (int)sizeof(T) / 16;
+    const int nlc = ne / 8, nab = ne * (int)sizeof(AB) / 16;
     const uint4* __restrict__ glc = reinterpret_cast<const uint4*>(hv.lcol) + e0 / 8;
     const uint4* __restrict__ gab =
         static_cast<const uint4*>(hv.ab) + (size_t)e0 * sizeof(AB) / 16;
-    const uint4* __restrict__ gp = reinterpret_cast<const uint4*>(pv) + (size_t)e0 * sizeof(T) / 16;
     for (int t = tid; t < nlc; t += kThreads)
       halo_stage_cols(glc[t], reinterpret_cast<uint4*>(s_lc) + 2 * t);
     for (int t = tid; t < nab; t += kThreads) reinterpret_cast<uint4*>(s_ab)[t] = gab[t];
-    for (int t = tid; t < np; t += kThreads) reinterpret_cast<uint4*>(s_p)[t] = gp[t];
+    const int pe0 = s_psp[0] * 8, pne = (s_psp[nsl] - s_psp[0]) * 8;
+    const int npl = pne / 8, npv = pne * (int)sizeof(T) / 16;
+    const uint4* __restrict__ gplc = reinterpret_cast<const uint4*>(pw.lcol) + pe0 / 8;
+    const uint4* __restrict__ gpv =
+        static_cast<const uint4*>(pw.v) + (size_t)pe0 * sizeof(T) / 16;
+    for (int t = tid; t < npl; t += kThreads)
+      halo_stage_cols(gplc[t], reinterpret_cast<uint4*>(s_plc) + 2 * t);
+    for (int t = tid; t < npv; t += kThreads) reinterpret_cast<uint4*>(s_p)[t] = gpv[t];
   }
   const int row = r0 + w * 8 + rr;
   // (a wave's slice width is uniform across the wave: scalar loop control)
   const int wdt = __builtin_amdgcn_readfirstlane(w < nsl ? s_sp[w + 1] - s_sp[w] : 0);
   const int soff = w < nsl ? (s_sp[w] - s_sp[0]) * 8 + rr * 4 : 0;  // (groups of 4)
+  const int pwdt = __builtin_amdgcn_readfirstlane(w < nsl ? s_psp[w + 1] - s_psp[w] : 0);
+  const int psoff = w < nsl ? (s_psp[w] - s_psp[0]) * 8 + rr * 4 : 0;
   while (gu < G) {
     const int u = ug * G + gu;
     const int pan = u / UPP, half = u % UPP;
@@ -924,7 +947,6 @@ __global__ __launch_bounds__(kThreads) void k_post_image(
     if (gn < G) SLRF_IMG_ISSUE(gn);
     if (w < nsl) {
       const AB* __restrict__ pab = s_ab + soff;
-      const T* __restrict__ pp = s_p + soff;
       const unsigned* __restrict__ plc = s_lc + soff;
       const V* __restrict__ pz = sZ + lr;
       T acc[4 * SPL], accp[2 * SPL];
@@ -935,8 +957,20 @@ __global__ __launch_bounds__(kThreads) void k_post_image(
       halo_slice_groups(plc, wdt, [&](int j, const uint4& co) {
         V z[UNR];
         AB ab[UNR];
-        T pw[UNR];
         halo_ab4(pab + j * 8, ab);
+        z[0] = halo_at(pz, co.x);
+        z[1] = halo_at(pz, co.y);
+        z[2] = halo_at(pz, co.z);
+        z[3] = halo_at(pz, co.w);
+#pragma unroll
+        for (int uu = 0; uu < UNR; ++uu) lane_fma<T, SPL>(acc, ab[uu].x, ab[uu].y, z[uu]);
+      });
+      // P's entries are a subset of the image's pattern, kept in slices of
+      // their own so that the rows' zeros of P cost nothing
+      const T* __restrict__ pp = s_p + psoff;
+      halo_slice_groups(s_plc + psoff, pwdt, [&](int j, const uint4& co) {
+        V z[UNR];
+        T pw[UNR];
         halo_val4(pp + j * 8, pw);
         z[0] = halo_at(pz, co.x);
         z[1] = halo_at(pz, co.y);
@@ -944,7 +978,6 @@ __global__ __launch_bounds__(kThreads) void k_post_image(
         z[3] = halo_at(pz, co.w);
 #pragma unroll
         for (int uu = 0; uu < UNR; ++uu) {
-          lane_fma<T, SPL>(acc, ab[uu].x, ab[uu].y, z[uu]);
           accp[0] = mad(pw[uu], (T)z[uu].x, accp[0]);
           accp[1] = mad(pw[uu], (T)z[uu].y, accp[1]);
           if constexpr (SPL == 2) {
@@ -2471,7 +2504,8 @@ bool launch_post_image(const DevImage& I, const DevPencil& P, const PanelGrid& g
   const long total = (long)I.ntile * nug;
   const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
   const size_t bytes = (size_t)I.hmax * (8 * sizeof(typename LaneVec<T>::V) + sizeof(int)) +
-                       (size_t)I.emax * (3 * sizeof(T) + sizeof(unsigned));
+                       (size_t)I.emax * (2 * sizeof(T) + sizeof(unsigned)) +
+                       (size_t)I.pemax * (sizeof(T) + sizeof(unsigned));
   HaloView hv;
   hv.ntile = I.ntile;
   hv.emax = I.emax;
@@ -2483,11 +2517,15 @@ bool launch_post_image(const DevImage& I, const DevPencil& P, const PanelGrid& g
   hv.lcol = I.lcol;
   hv.ab = std::is_same<T, float>::value ? static_cast<const void*>(I.ab32)
                                         : static_cast<const void*>(I.ab64);
-  const T* pv = std::is_same<T, float>::value ? reinterpret_cast<const T*>(I.p32)
-                                              : reinterpret_cast<const T*>(I.p64);
+  PSubView pw;
+  pw.emax = I.pemax;
+  pw.sptr = I.psptr;
+  pw.lcol = I.plcol;
+  pw.v = std::is_same<T, float>::value ? static_cast<const void*>(I.p32)
+                                       : static_cast<const void*>(I.p64);
 #define SLRF_POST(H)                                                                             \
   k_post_image<T, H><<<blocks, kThreads, bytes, s>>>(                                            \
-      P.n, I.nc, hv, pv, gg, G, st.active, st.sigma, static_cast<const C*>(E),                   \
+      P.n, I.nc, hv, pw, gg, G, st.active, st.sigma, static_cast<const C*>(E),                   \
       static_cast<const C*>(X0), static_cast<const C*>(R1), static_cast<C*>(Out), P.da, P.db, \
       omega)
   if (r1_bf16 && std::is_same<T, float>::value)

@@ -318,6 +318,7 @@ struct HostImage {
   bool ok = false;
   int nc = 0;
   HostHalo hx;
+  HostHaloSub p;   // P's nonzeros on the image tiles
 };
 
 struct HostSetup {
@@ -366,6 +367,7 @@ void amg_images(AmgHierarchy& H, std::vector<HostImage>& img) {
     const HostLevel& ab = H.img[l];
     I.ok = image_p_values(ab, H.P[l], ipv) &&
            build_halo(lvl.n, ab.rp, ab.ci, ab.a, ab.b, kImgMaxH, kHaloTileRows, I.hx, &ipv);
+    if (I.ok) build_halo_sub(lvl.n, I.hx, I.p);
     I.nc = H.P[l].m;
   }
   H.img.clear();
@@ -758,8 +760,11 @@ hipError_t place_amg(slrf_ctx* h, const AmgHierarchy& H, const std::vector<HostI
     if ((e = pl.put(hx.lcol, &I.lcol)) != hipSuccess) return e;
     if ((e = pl.put(ab32, &I.ab32)) != hipSuccess) return e;
     if ((e = pl.put(ab64, &I.ab64)) != hipSuccess) return e;
-    if ((e = pl.put(to_f32(hx.c), &I.p32)) != hipSuccess) return e;
-    if ((e = pl.put(hx.c, &I.p64)) != hipSuccess) return e;
+    if ((e = pl.put(hi.p.sptr, &I.psptr)) != hipSuccess) return e;
+    if ((e = pl.put(hi.p.lcol, &I.plcol)) != hipSuccess) return e;
+    if ((e = pl.put(to_f32(hi.p.v), &I.p32)) != hipSuccess) return e;
+    if ((e = pl.put(hi.p.v, &I.p64)) != hipSuccess) return e;
+    I.pemax = hi.p.emax;
     I.nc = hi.nc;
     I.hmax = hx.hmax;
     I.emax = hx.emax;

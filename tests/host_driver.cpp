@@ -142,6 +142,12 @@ int main(int argc, char** argv) {
     put(X.lcol);
     put(X.ab);
     put(X.c);
+    HostHaloSub S;
+    if (hok) build_halo_sub(n, X, S);
+    put_i(S.emax);
+    put(S.sptr);
+    put(S.lcol);
+    put(S.v);
   } else if (mode == "ugroup") {
     HostUGroup G;
     const bool ok = build_ugroup(n, L.rp, L.ci, L.a, L.b, std::atoi(argv[4]), std::atoi(argv[5]), G);

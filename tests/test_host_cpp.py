@@ -272,6 +272,31 @@ def test_fine_image_of_prolongator(driver, which):
     for vals, ref in ((va, AP), (vb, BP), (vc, PP)):
         M = sp.csr_matrix((vals, (rows, cols)), shape=(n, nc))
         assert abs(M - ref).max() == 0.0
+    # P's nonzeros again in slices of their own (same tiles, same halo rows):
+    # every nonzero exactly once, padding zero, widths padded to 4, and emax
+    # the most entries of one tile's pass
+    pemax = r.i()
+    psptr, plcol, pval = r.arr(np.int32), r.arr(np.uint16), r.arr(np.float64)
+    assert len(psptr) == len(sptr) and np.all(np.diff(psptr) % 4 == 0)
+    assert np.all(np.diff(psptr) <= np.diff(sptr))
+    rows, cols, vals, seen = [], [], [], np.zeros(len(pval), bool)
+    emax = 0
+    for t in range(len(trow) - 1):
+        h = halo[hptr[t]:hptr[t + 1]]
+        s0, s1 = trow[t] // 8, (trow[t + 1] + 7) // 8
+        emax = max(emax, (psptr[s1] - psptr[s0]) * 8)
+        for rrow in range(trow[t], trow[t + 1]):
+            s_, ln = rrow // 8, rrow % 8
+            W = psptr[s_ + 1] - psptr[s_]
+            k = _halo_entry(psptr[s_], np.arange(W), ln)
+            seen[k] = True
+            nz = pval[k] != 0.0
+            rows += [rrow] * int(nz.sum())
+            cols += list(h[plcol[k[nz]]])
+            vals += list(pval[k[nz]])
+    assert pemax == emax and np.all(pval[~seen] == 0.0)
+    M = sp.csr_matrix((vals, (rows, cols)), shape=(n, nc))
+    assert M.nnz == PP.count_nonzero() and abs(M - PP).max() == 0.0
 
 
 @pytest.mark.parametrize("which,R,U", [("q1_3d", 4, 4), ("elasticity", 4, 4), ("q1_2d_ragged", 3, 2)])

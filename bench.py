@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--m", type=int, default=64, help="Q1 nodes per direction (64 = metric)")
     ap.add_argument("--precond", choices=["amg", "jacobi"], default="amg")
     ap.add_argument("--restart", type=int, default=5, help="GCR restart length m")
+    ap.add_argument("--coarse-min", type=int, default=512,
+                    help="AMG smallest coarse level (options.amg_coarse_min) of the Q1 workload")
     ap.add_argument("--ncols", type=int, default=160)
     ap.add_argument("--workload", choices=["q1_3d", "batch64", "itmax", "elasticity48", "fd32"],
                     default="q1_3d",
@@ -162,7 +164,7 @@ def cpu_baseline(m, L, tol):
                                  "threads": 1}}
 
 
-def eigen_runs(P, torch, p, gamma, poles, weights, nev, V1d, restart, lam_exact):
+def eigen_runs(P, torch, p, gamma, poles, weights, nev, V1d, restart, lam_exact, cmin):
     """Time to all NEV eigenpairs in (0, gamma] (Algorithm 2: locking and warm
     start, the benchmark's filter options) per precision, with the largest
     relative eigenvalue error against the closed form and Ritz residuals of
@@ -175,7 +177,7 @@ def eigen_runs(P, torch, p, gamma, poles, weights, nev, V1d, restart, lam_exact)
     A, B = p.A(), p.B()
     for name, prec in (("mixed", P.SLRF_PREC_MIXED), ("fp64", P.SLRF_PREC_FP64)):
         opt = P.default_options(precision=prec, precond=P.SLRF_PC_AMG, restart=restart,
-                                tol_lin=1e-8, lock=1, warm_start=1)
+                                tol_lin=1e-8, lock=1, warm_start=1, amg_coarse_min=cmin)
         h = P.Handle.from_pencil(p, gamma, poles, weights, opt, max_cols=V1d.shape[1],
                                  budget=0.6)
         torch.cuda.synchronize()
@@ -255,8 +257,10 @@ def profiled_traffic():
         return None
 
 
-def run_precision(P, torch, p, gamma, poles, weights, Xd, prec, steps, warmup, tol, pc, restart):
-    opt = P.default_options(precision=prec, tol_lin=tol, timing=1, precond=pc, restart=restart)
+def run_precision(P, torch, p, gamma, poles, weights, Xd, prec, steps, warmup, tol, pc, restart,
+                  cmin):
+    opt = P.default_options(precision=prec, tol_lin=tol, timing=1, precond=pc, restart=restart,
+                            amg_coarse_min=cmin)
     # workspace for every system resident (up to 60 % of the free device memory)
     h = P.Handle.from_pencil(p, gamma, poles, weights, opt, max_cols=Xd.shape[1], budget=0.6)
     ncols = Xd.shape[1]
@@ -717,7 +721,7 @@ def main():
         pc = P.SLRF_PC_AMG if args.precond == "amg" else P.SLRF_PC_JACOBI
         results[name], Us[name] = run_precision(P, torch, p, c["gamma"], poles, weights, Xd,
                                                 prec, args.steps, args.warmup, tol, pc,
-                                                args.restart)
+                                                args.restart, args.coarse_min)
         print(f"{name}: {results[name]['ms_per_step']:.1f} ms/step, "
               f"{results[name]['solves_per_s']:.1f} solves/s", file=sys.stderr, flush=True)
     spmm = spmm_rate(P, torch, p, c["gamma"], poles, weights, args.ncols * c["npoles"])
@@ -757,6 +761,7 @@ def main():
         "config": {"workload": f"q1_3d_m{args.m}", "n": p.n, "nnz": p.nnz, "ncols": args.ncols,
                    "npoles": c["npoles"], "systems": args.ncols * c["npoles"], "tol_lin": tol,
                    "solver": f"GCR({args.restart})+{'AMG V-cycle' if args.precond == 'amg' else 'Jacobi'}",
+                   "amg_coarse_min": args.coarse_min,
                    "step": "Algorithm 1 outer iteration",
                    "precision": main_name},
         "roofline": roofline_entry(dom, r, achieved, nl, traffic,
@@ -775,7 +780,7 @@ def main():
         lam_ex = np.sort((lam1[:, None, None] + lam1[None, :, None] +
                           lam1[None, None, :]).ravel())
         line["eigen"] = eigen_runs(P, torch, p, c["gamma"], poles, weights, c["nev"], Xd,
-                                  args.restart, lam_ex)
+                                  args.restart, lam_ex, args.coarse_min)
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line, default=float))

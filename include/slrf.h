@@ -149,6 +149,20 @@ typedef struct {
                           when the workspace is too small, and with SLRF_E_ARG
                           when a product row has more than 1024 distinct
                           columns.  Fixed at setup.                          */
+  int32_t amg_coarse_min; /* smallest coarse level of the AMG hierarchy, 0..2048;
+                          0 (default): off.  Where an aggregation would leave
+                          fewer coarse dofs, the strength threshold is raised
+                          (0.01, 0.02, ... 0.64) to the first value that leaves
+                          at least this many while still halving the level;
+                          failing that, a level small enough for the dense
+                          solve becomes the coarsest.  The shifted systems are
+                          indefinite on the modes below Re sigma_j, which the
+                          smoothing cannot damp and only the coarse correction
+                          reaches: a coarsest level of a few times the number
+                          of eigenvalues in (0, gamma] keeps the inner
+                          iteration counts low (3D Q1, n = 262,144, 102
+                          eigenvalues: 512 instead of 125 coarse dofs).
+                          Fixed at setup.                                    */
 } slrf_options;
 
 enum { SLRF_AMG_HOST = 0, SLRF_AMG_DEVICE = 1 };

@@ -459,13 +459,35 @@ bool amg_build(const HostLevel& fine, const std::vector<std::complex<double>>& p
     const int bs = lev_block > 1 && n % lev_block == 0 ? lev_block : 1;
     // aggregates of dofs (whole nodes when bs > 1)
     std::vector<int> dagg(n);
-    int na;
-    if (bs > 1) {
-      std::vector<int> nagg;
-      na = aggregate(node_graph(L, bs), prm.theta, nagg);
-      for (int i = 0; i < n; ++i) dagg[i] = nagg[i / bs];
-    } else {
-      na = aggregate(L, prm.theta, dagg);
+    auto aggregate_at = [&](double theta, std::vector<int>& out) {
+      if (bs > 1) {
+        std::vector<int> nagg;
+        const int k = aggregate(node_graph(L, bs), theta, nagg);
+        for (int i = 0; i < n; ++i) out[i] = nagg[i / bs];
+        return k;
+      }
+      return aggregate(L, theta, out);
+    };
+    // coarse dofs: kns columns per aggregate (fewer where dependent ones drop)
+    const int ncols = rigid_modes ? kns : bs;
+    int na = aggregate_at(prm.theta, dagg);
+    if (prm.coarse_min > 0 && (long)na * ncols < prm.coarse_min) {
+      // too small a coarse space: smaller aggregates (a higher strength
+      // threshold) that still at least halve the aggregated units; failing
+      // that, this level is the coarsest if the dense solve takes it
+      bool found = false;
+      std::vector<int> trial(n);
+      const int units = n / bs;
+      for (double th = 0.01; th <= 0.64 && !found; th *= 2.0) {
+        if (th <= prm.theta) continue;
+        const int k = aggregate_at(th, trial);
+        if ((long)k * ncols >= prm.coarse_min && 2 * k <= units) {
+          na = k;
+          dagg.swap(trial);
+          found = true;
+        }
+      }
+      if (!found && n <= prm.dense_max) break;
     }
     if (na == 0) break;
     // tentative prolongator T: per aggregate, an orthonormal basis of the

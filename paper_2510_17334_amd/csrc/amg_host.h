@@ -25,6 +25,12 @@ struct AmgParams {
   double theta = 0.0;     // strength threshold |a_ij| > theta sqrt(a_ii a_jj)
   double omega_p = 4.0 / 3.0;  // prolongator smoothing weight (times 1/rho(D^-1 A))
   int coarse_max = 400;   // stop coarsening at or below this size
+  // smallest coarse level worth forming: where the aggregation would leave
+  // fewer coarse dofs, the strength threshold is raised (0.01, 0.02, ... 0.64)
+  // to the first value that leaves at least this many while still halving the
+  // level; if none does, a level that fits the dense solve becomes the
+  // coarsest (0: off)
+  int coarse_min = 0;
   int dense_max = 2048;   // largest coarsest level inverted densely
   int max_levels = 10;
   int block = 1;          // dofs per node (node-major numbering): nodes are aggregated,

@@ -278,6 +278,8 @@ slrf_status validate_options(slrf_ctx* h, const slrf_options& o) {
     return fail(h, SLRF_E_ARG, "spmm_variant must be 0..7");
   if (o.amg_setup != SLRF_AMG_HOST && o.amg_setup != SLRF_AMG_DEVICE)
     return fail(h, SLRF_E_ARG, "amg_setup must be SLRF_AMG_HOST or SLRF_AMG_DEVICE");
+  if (o.amg_coarse_min < 0 || o.amg_coarse_min > AmgParams().dense_max)
+    return fail(h, SLRF_E_ARG, "amg_coarse_min must be 0..2048");
   return SLRF_OK;
 }
 
@@ -422,8 +424,9 @@ std::shared_ptr<const HostSetup> analyse(const slrf_csr* A, const slrf_csr* B,
   key = fnv1a(key, cl.data(), cl.size() * sizeof(int));
   key = fnv1a(key, av.data(), av.size() * sizeof(double));
   key = fnv1a(key, bv.data(), bv.size() * sizeof(double));
-  const int32_t kopt[6] = {opt.reorder, opt.amg_block, amg ? 1 : 0, n,
-                           opt.node_xyz != nullptr ? 1 : 0, opt.amg_setup};
+  const int32_t kopt[7] = {opt.reorder, opt.amg_block, amg ? 1 : 0, n,
+                           opt.node_xyz != nullptr ? 1 : 0, opt.amg_setup,
+                           opt.amg_coarse_min};
   key = fnv1a(key, kopt, sizeof(kopt));
   if (opt.node_xyz) key = fnv1a(key, opt.node_xyz, sizeof(double) * n);
   {
@@ -523,6 +526,7 @@ std::shared_ptr<const HostSetup> analyse(const slrf_csr* A, const slrf_csr* B,
     fine.b = hs->b;
     AmgParams prm;
     prm.block = hs->block;
+    prm.coarse_min = opt.amg_coarse_min;
     std::vector<double> xyz;
     if (opt.node_xyz && (hs->block == 2 || hs->block == 3)) {
       // coordinates in the final node order (a node's dofs stay together)
@@ -1693,6 +1697,7 @@ void slrf_default_options(slrf_options* o) {
   o->amg_block = 0;
   o->node_xyz = nullptr;
   o->amg_setup = SLRF_AMG_HOST;
+  o->amg_coarse_min = 0;
 }
 
 int32_t slrf_get_n(slrf_handle h) { return h ? h->P.n : -1; }
@@ -1917,8 +1922,9 @@ slrf_status slrf_set_options(slrf_handle h, const slrf_options* opt) {
   if (opt->precond == SLRF_PC_AMG && !h->amg.ready)
     return fail(h, SLRF_E_ARG, "the AMG hierarchy is built at setup: set precond there");
   if (opt->reorder != h->opt.reorder || opt->amg_block != h->opt.amg_block ||
-      opt->amg_setup != h->opt.amg_setup)
-    return fail(h, SLRF_E_ARG, "reorder, amg_block and amg_setup are fixed at setup");
+      opt->amg_setup != h->opt.amg_setup || opt->amg_coarse_min != h->opt.amg_coarse_min)
+    return fail(h, SLRF_E_ARG,
+                "reorder, amg_block, amg_setup and amg_coarse_min are fixed at setup");
   h->opt = *opt;
   if (opt->spmm_variant != kSpmmAuto) h->P.var32 = h->P.var64 = opt->spmm_variant;
   return SLRF_OK;

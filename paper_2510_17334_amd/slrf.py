@@ -51,7 +51,8 @@ class Options(C.Structure):
                 ("tol_lin", C.c_double),
                 ("inner_rtol", C.c_double),
                 ("tol_eig", C.c_double), ("amg_block", C.c_int32),
-                ("node_xyz", C.c_void_p), ("amg_setup", C.c_int32)]
+                ("node_xyz", C.c_void_p), ("amg_setup", C.c_int32),
+                ("amg_coarse_min", C.c_int32)]
 
 
 class FilterStats(C.Structure):

@@ -74,6 +74,11 @@ int main(int argc, char** argv) {
     AmgParams prm;
     prm.block = std::atoi(argv[4]);
     std::vector<double> xyz;
+    // optional trailing argument cmin=<k>: AmgParams::coarse_min
+    if (argc > 7 && std::strncmp(argv[argc - 1], "cmin=", 5) == 0) {
+      prm.coarse_min = std::atoi(argv[argc - 1] + 5);
+      --argc;
+    }
     if (argc > 7) {  // node coordinates: float64 [n] (nodes x block)
       FILE* fx = std::fopen(argv[7], "rb");
       if (!fx) return 3;

@@ -30,17 +30,18 @@ def _pencil(which):
     return si.hex_elasticity_pencil(ne, np.exp(rng.normal(0, .3, ne ** 3))), 5.0
 
 
-@pytest.mark.parametrize("which,prec", [("q1_3d", P.SLRF_PREC_MIXED),
-                                        ("q1_3d", P.SLRF_PREC_FP64),
-                                        ("elasticity", P.SLRF_PREC_FP64)])
-def test_device_amg_setup_equals_host_build(which, prec):
+@pytest.mark.parametrize("which,prec,cmin", [("q1_3d", P.SLRF_PREC_MIXED, 0),
+                                             ("q1_3d", P.SLRF_PREC_FP64, 0),
+                                             ("q1_3d", P.SLRF_PREC_MIXED, 512),
+                                             ("elasticity", P.SLRF_PREC_FP64, 0)])
+def test_device_amg_setup_equals_host_build(which, prec, cmin):
     p, gamma = _pencil(which)
     poles, weights = si.slrf_poles(gamma)
     X = _dev(np.random.default_rng(5).standard_normal((p.n, 16)))
     out = {}
     for where in (P.SLRF_AMG_HOST, P.SLRF_AMG_DEVICE):
         opt = P.default_options(precision=prec, precond=P.SLRF_PC_AMG, restart=5, tol_lin=1e-9,
-                                amg_setup=where)
+                                amg_setup=where, amg_coarse_min=cmin)
         h = P.Handle.from_pencil(p, gamma, poles, weights, opt, max_cols=16)
         U, st = h.slrf_filter(X)
         out[where] = (U, st, h.workspace_sizes(16))

@@ -305,12 +305,14 @@ def _sine_block_3d(m, ks):
 
 @pytest.mark.parametrize("prec", [P.SLRF_PREC_MIXED, P.SLRF_PREC_FP64])
 def test_filter_sine_full_size_benchmark_options(prec):
-    """The benchmark's filter exactly as it runs (n = 262,144, 8 poles, AMG V-cycle,
-    GCR(5), tol_lin 1e-8, cold start, autotuned sweep): in the mixed form this is
-    the path whose cycles keep the Gram-Schmidt basis in complex bfloat16.  Per
-    column U = Phi(lambda) u (closed form, Eq. (3)) within the bound the
-    residual tolerance implies; modes inside (0, gamma], at the cluster by gamma,
-    just above it and at the top of the spectrum."""
+    """The benchmark's filter exactly as it runs (n = 262,144, 8 poles, AMG V-cycle
+    with a coarsest level of at least 512, GCR(5), tol_lin 1e-8, cold start,
+    autotuned sweep): in the mixed form this is the path whose cycles keep the
+    Gram-Schmidt basis in complex bfloat16.  Per column U = Phi(lambda) u
+    (closed form, Eq. (3)) within the bound the residual tolerance implies;
+    modes inside (0, gamma], at the cluster by gamma, just above it and at the
+    top of the spectrum.  The same with the default hierarchy (125 coarse
+    dofs), which needs over a quarter more inner iterations."""
     m = 64
     c = si.config_q1_3d()
     p = c["pencil"]
@@ -320,15 +322,19 @@ def test_filter_sine_full_size_benchmark_options(prec):
     X, lam = _sine_block_3d(m, ks)
     phi = np.sum(2 * np.real(weights[None, :] / (lam[:, None] - poles[None, :])), axis=1)
     tol = 1e-8
-    h = _handle(p, c["gamma"], poles, weights, precision=prec, tol_lin=tol,
-                precond=P.SLRF_PC_AMG, restart=5)
-    U, st = h.slrf_filter(_dev(X))
-    h.close()
-    assert st["basis_bf16"] == (1 if prec == P.SLRF_PREC_MIXED else 0)
-    assert st["converged"] == 8 * len(ks) and st["max_rel_resid"] <= tol
-    err = np.linalg.norm(_host(U) - X * phi[None, :], axis=0)
     bound = _filter_bound(p.B() @ X, poles, weights, tol, _q1_lambda_min_B(m, 3))
-    assert np.all(err <= bound), (prec, (err / bound).max())
+    iters = {}
+    for cmin in (512, 0):
+        h = _handle(p, c["gamma"], poles, weights, precision=prec, tol_lin=tol,
+                    precond=P.SLRF_PC_AMG, restart=5, amg_coarse_min=cmin)
+        U, st = h.slrf_filter(_dev(X))
+        h.close()
+        assert st["basis_bf16"] == (1 if prec == P.SLRF_PREC_MIXED else 0)
+        assert st["converged"] == 8 * len(ks) and st["max_rel_resid"] <= tol
+        err = np.linalg.norm(_host(U) - X * phi[None, :], axis=0)
+        assert np.all(err <= bound), (prec, cmin, (err / bound).max())
+        iters[cmin] = st["total_iters"]
+    assert iters[0] > 1.25 * iters[512], iters
 
 
 @pytest.mark.parametrize("prec", [P.SLRF_PREC_MIXED, P.SLRF_PREC_FP64])
@@ -338,7 +344,8 @@ def test_filter_lu_oracle_benchmark_options(cfg1, prec):
     system's FP64 residual recomputed on the host from the single-pole solves."""
     p = cfg1["pencil"]
     tol = 1e-8
-    opt = dict(precision=prec, tol_lin=tol, precond=P.SLRF_PC_AMG, restart=5, spmm_variant=6)
+    opt = dict(precision=prec, tol_lin=tol, precond=P.SLRF_PC_AMG, restart=5, spmm_variant=6,
+               amg_coarse_min=512)
     h = _handle(p, cfg1["gamma"], cfg1["poles"], cfg1["weights"], **opt)
     X = cfg1["V1"]
     U, st = h.slrf_filter(_dev(X))

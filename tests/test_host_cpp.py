@@ -402,3 +402,27 @@ def test_amg_rigid_body_modes_in_the_coarse_space(driver, coords):
         assert res.max() <= 1e-10
     else:
         assert res[:3].max() <= 1e-10 and res[3:].min() > 1e-3
+
+
+@pytest.mark.parametrize("m,cmin,sizes", [
+    (32, 0, [32768, 1331, 27]),    # off: plain aggregation down to <= 400
+    (32, 64, [32768, 1331, 64]),   # 27 < 64: a raised threshold leaves 64
+    (32, 128, [32768, 1331]),      # no halving aggregation leaves >= 128: 1331 is dense-solvable
+    (16, 512, [4096, 216]),        # nothing reaches 512 and 4096 is too large: kept
+    (16, 256, [4096, 310]),        # 216 < 256 on the fine level: a raised threshold leaves 310
+])
+def test_amg_coarse_min(driver, m, cmin, sizes):
+    """options.amg_coarse_min: where the aggregation would leave fewer coarse dofs
+    than the minimum, the strength threshold rises to the first value that leaves
+    at least that many while halving the level; failing that a dense-solvable
+    level becomes the coarsest.  Every level stays a Galerkin product and every
+    coarsening at least halves."""
+    p = si.q1_kron_pencil(m, 3)
+    levels, Ps = _read_amg(_run(driver, p, "amg", 1, 10.0, 10.0, f"cmin={cmin}"))
+    assert [L[0].shape[0] for L in levels] == sizes
+    for l, P in enumerate(Ps):
+        n0, n1 = P.shape
+        assert 2 * n1 <= n0
+        for M0, M1 in zip(levels[l], levels[l + 1]):
+            G = (P.T @ M0 @ P).toarray()
+            assert np.abs(M1.toarray() - G).max() <= 1e-12 * np.abs(G).max()

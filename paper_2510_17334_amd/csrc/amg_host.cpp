@@ -473,15 +473,14 @@ bool amg_build(const HostLevel& fine, const std::vector<std::complex<double>>& p
     int na = aggregate_at(prm.theta, dagg);
     if (prm.coarse_min > 0 && (long)na * ncols < prm.coarse_min) {
       // too small a coarse space: smaller aggregates (a higher strength
-      // threshold) that still at least halve the aggregated units; failing
+      // threshold) whose coarse dofs still at most halve the level; failing
       // that, this level is the coarsest if the dense solve takes it
       bool found = false;
       std::vector<int> trial(n);
-      const int units = n / bs;
       for (double th = 0.01; th <= 0.64 && !found; th *= 2.0) {
         if (th <= prm.theta) continue;
         const int k = aggregate_at(th, trial);
-        if ((long)k * ncols >= prm.coarse_min && 2 * k <= units) {
+        if ((long)k * ncols >= prm.coarse_min && 2L * k * ncols <= n) {
           na = k;
           dagg.swap(trial);
           found = true;

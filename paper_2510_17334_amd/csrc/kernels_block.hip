@@ -1942,7 +1942,10 @@ __global__ __launch_bounds__(kThreads) void k_lvl_jacobi0(
 }
 
 // coarsest level: x = (A_c - sigma_j B_c)^{-1} b with the dense inverse of the
-// slot's pole j = sys % npoles
+// slot's pole j = sys % npoles.  One row per thread (16 rows by 16 slots per
+// workgroup); the launch deals each XCD a contiguous range of row blocks over
+// all panels, so the inverse rows an XCD reads stay in its L2.  Four partial
+// sums per row (columns j mod 4) keep four loads in flight.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_coarse_solve(
     int nc, PanelGrid g, const int* __restrict__ active, const int* __restrict__ sys, int npoles,
@@ -1953,22 +1956,31 @@ __global__ __launch_bounds__(kThreads) void k_coarse_solve(
   if (!map_block(g, rb, pan)) return;
   const int lane = threadIdx.x & 15, rs = threadIdx.x >> 4;
   const int slot = pan * kPanel + lane;
-  if (active != nullptr && active[slot] == 0) return;
+  const int row = rb * g.rpb + rs;
+  if (row >= nc || (active != nullptr && active[slot] == 0)) return;
   const int sy = sys[slot];
   if (sy < 0) return;
-  const C* __restrict__ Mp = Minv + (size_t)(sy % npoles) * nc * nc;
-  const C* __restrict__ Bp = Bin + (size_t)pan * nc * kPanel;
-  const int r0 = rb * g.rpb, r1 = min(r0 + g.rpb, nc);
-  for (int row = r0 + rs; row < r1; row += 16) {
-    double sx = 0.0, syy = 0.0;
-    for (int j = 0; j < nc; ++j) {
-      const C m = Mp[(size_t)row * nc + j];
-      const C b = Bp[j * kPanel + lane];
-      sx += (double)m.x * b.x - (double)m.y * b.y;
-      syy += (double)m.x * b.y + (double)m.y * b.x;
+  const C* __restrict__ Mr = Minv + ((size_t)(sy % npoles) * nc + row) * nc;
+  const C* __restrict__ Bp = Bin + (size_t)pan * nc * kPanel + lane;
+  double ax[4] = {0.0, 0.0, 0.0, 0.0}, ay[4] = {0.0, 0.0, 0.0, 0.0};
+  const int n4 = nc & ~3;
+  for (int j = 0; j < n4; j += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const C m = Mr[j + u];
+      const C b = Bp[(size_t)(j + u) * kPanel];
+      ax[u] += (double)m.x * b.x - (double)m.y * b.y;
+      ay[u] += (double)m.x * b.y + (double)m.y * b.x;
     }
-    Out[(size_t)pan * nc * kPanel + row * kPanel + lane] = mk<C>(sx, syy);
   }
+  for (int j = n4; j < nc; ++j) {
+    const C m = Mr[j];
+    const C b = Bp[(size_t)j * kPanel];
+    ax[j - n4] += (double)m.x * b.x - (double)m.y * b.y;
+    ay[j - n4] += (double)m.x * b.y + (double)m.y * b.x;
+  }
+  Out[(size_t)pan * nc * kPanel + row * kPanel + lane] =
+      mk<C>((ax[0] + ax[1]) + (ax[2] + ax[3]), (ay[0] + ay[1]) + (ay[2] + ay[3]));
 }
 
 inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
@@ -3306,7 +3318,11 @@ template <typename T>
 hipError_t launch_coarse_solve(int nc, const PanelGrid& g, const SlotTables& st, int npoles,
                                const void* Minv, const void* In, void* Out, hipStream_t s) {
   using C = typename CT<T>::t;
-  k_coarse_solve<T><<<g.blocks(), kThreads, 0, s>>>(nc, g, st.active, st.sys, npoles,
+  PanelGrid gc = g;
+  gc.rpb = kThreads / kPanel;  // one row per thread
+  gc.nrb = (nc + gc.rpb - 1) / gc.rpb;
+  gc.group = gc.npan;  // row block-major: an XCD's rows over all panels
+  k_coarse_solve<T><<<gc.blocks(), kThreads, 0, s>>>(nc, gc, st.active, st.sys, npoles,
                                                     static_cast<const C*>(Minv),
                                                     static_cast<const C*>(In),
                                                     static_cast<C*>(Out));

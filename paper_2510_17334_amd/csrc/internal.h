@@ -239,7 +239,8 @@ struct DevImage {
   const float* p32 = nullptr;
   const double* p64 = nullptr;
 };
-constexpr int kImgMaxH = 64;  // largest coarse halo of an image tile
+constexpr int kImgMaxH = 64;    // coarse-halo cap of an image tile's first layout attempt
+constexpr int kImgMaxH2 = 128;  // the cap of the second attempt (fewer, wider tiles fail less)
 
 // Level-0 up-step in one pass: with x = x0 + P e (e the coarse correction),
 // Out = x + omega D^-1 (r1 - (A P - sigma B P) e), where r1 = b - M x0 is the

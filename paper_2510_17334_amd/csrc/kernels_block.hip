@@ -827,8 +827,9 @@ __global__ __launch_bounds__(kThreads) void k_apply_halo(
 // units, the tile's coefficients staged once, each unit's coarse halo rows of
 // e copied into LDS (loaded into registers while the previous unit is formed).
 // ---------------------------------------------------------------------------
-// (HR1: r1 and x0 are complex bfloat16, complex-float sweeps only)
-template <typename T, bool HR1>
+// (HR1: r1 and x0 are complex bfloat16, complex-float sweeps only; HM: the
+// largest coarse halo of a tile the staging registers cover)
+template <typename T, bool HR1, int HM>
 __global__ __launch_bounds__(kThreads) void k_post_image(
     int n, int nc, HaloView hv, PSubView pw, PanelGrid g, int G,
     const int* __restrict__ active, const double2* __restrict__ sigma,
@@ -878,7 +879,7 @@ __global__ __launch_bounds__(kThreads) void k_post_image(
   int gu = 0;
   while (gu < G && !s_uact[gu]) ++gu;
   if (gu >= G) return;
-  constexpr int HP = (kImgMaxH * 8 + kThreads - 1) / kThreads;
+  constexpr int HP = (HM * 8 + kThreads - 1) / kThreads;
   V hreg[HP];
   // this thread's coarse-halo element offsets, the same for every unit (row 0
   // past the halo: the loads stay unconditional and are not stored)
@@ -2503,7 +2504,8 @@ bool launch_post_image(const DevImage& I, const DevPencil& P, const PanelGrid& g
                        const void* R1, void* Out, hipStream_t s, hipError_t& err,
                        bool r1_bf16) {
   using C = typename CT<T>::t;
-  if (I.ntile == 0 || I.hmax > kImgMaxH) return false;
+  if (I.ntile == 0 || I.hmax > kImgMaxH2) return false;
+  err = hipSuccess;
   constexpr int UPP = std::is_same<T, float>::value ? 1 : 2;
   const int G = kHaloMaxG;
   const int nug = (g.npan * UPP + G - 1) / G;
@@ -2535,17 +2537,25 @@ bool launch_post_image(const DevImage& I, const DevPencil& P, const PanelGrid& g
   pw.lcol = I.plcol;
   pw.v = std::is_same<T, float>::value ? static_cast<const void*>(I.p32)
                                        : static_cast<const void*>(I.p64);
-#define SLRF_POST(H)                                                                             \
-  k_post_image<T, H><<<blocks, kThreads, bytes, s>>>(                                            \
+  // (beyond 64 KiB of dynamic LDS the kernel must be allowed the size first)
+#define SLRF_POST(H, HM)                                                                         \
+  if (bytes > 65536 &&                                                                           \
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_post_image<T, H, HM>),                \
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) \
+    err = hipErrorInvalidValue;                                                                  \
+  else                                                                                           \
+    k_post_image<T, H, HM><<<blocks, kThreads, bytes, s>>>(                                      \
       P.n, I.nc, hv, pw, gg, G, st.active, st.sigma, static_cast<const C*>(E),                   \
       static_cast<const C*>(X0), static_cast<const C*>(R1), static_cast<C*>(Out), P.da, P.db, \
       omega)
-  if (r1_bf16 && std::is_same<T, float>::value)
-    SLRF_POST(true);
-  else
-    SLRF_POST(false);
+  const bool wide = I.hmax > kImgMaxH;
+  if (r1_bf16 && std::is_same<T, float>::value) {
+    if (wide) SLRF_POST(true, kImgMaxH2); else SLRF_POST(true, kImgMaxH);
+  } else {
+    if (wide) SLRF_POST(false, kImgMaxH2); else SLRF_POST(false, kImgMaxH);
+  }
 #undef SLRF_POST
-  err = hipGetLastError();
+  if (err == hipSuccess) err = hipGetLastError();
   return true;
 }
 

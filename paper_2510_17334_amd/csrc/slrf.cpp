@@ -367,8 +367,11 @@ void amg_images(AmgHierarchy& H, std::vector<HostImage>& img) {
     const HostLevel& lvl = H.levels[l];
     HostImage& I = img[l];
     const HostLevel& ab = H.img[l];
+    // tiles under a 64-row coarse halo where the image allows, else under 128
+    // (the up-step's halo staging is compiled for either)
     I.ok = image_p_values(ab, H.P[l], ipv) &&
-           build_halo(lvl.n, ab.rp, ab.ci, ab.a, ab.b, kImgMaxH, kHaloTileRows, I.hx, &ipv);
+           (build_halo(lvl.n, ab.rp, ab.ci, ab.a, ab.b, kImgMaxH, kHaloTileRows, I.hx, &ipv) ||
+            build_halo(lvl.n, ab.rp, ab.ci, ab.a, ab.b, kImgMaxH2, kHaloTileRows, I.hx, &ipv));
     if (I.ok) build_halo_sub(lvl.n, I.hx, I.p);
     I.nc = H.P[l].m;
   }
@@ -744,7 +747,7 @@ hipError_t place_amg(slrf_ctx* h, const AmgHierarchy& H, const std::vector<HostI
   }
   // images (A_l P_l, B_l P_l) with P_l's values, in 32-row halo tiles over
   // the next level's rows: the fused up-step of level l (absent when a
-  // tile's coarse halo would exceed kImgMaxH rows)
+  // tile's coarse halo would exceed kImgMaxH2 rows)
   A.img.assign(L, DevImage());
   for (int l = 0; l + 1 < L; ++l) {
     const HostImage& hi = img[l];
@@ -852,7 +855,7 @@ template <typename T>
 bool amg_level0_bf16(const slrf_ctx* h) {
   const DevAmg& A = h->amg;
   return std::is_same<T, float>::value && sweep_is_halo<T>(h->P) && !A.img.empty() &&
-         A.img[0].ntile > 0 && A.img[0].hmax <= kImgMaxH;
+         A.img[0].ntile > 0 && A.img[0].hmax <= kImgMaxH2;
 }
 
 // z = V(r): one V-cycle (damped-Jacobi pre/post smoothing from a zero guess,

@@ -20,6 +20,7 @@ namespace slrf {
 
 constexpr int kPanel = 16;      // systems per panel
 constexpr int kMaxRestart = 32; // GCR(m) with m <= 32
+constexpr int kMaxPoles = 64;   // poles per handle
 constexpr int kThreads = 256;   // workgroup size of the block-vector kernels
 
 // Device view of the pencil (shared CSR pattern).
@@ -129,6 +130,10 @@ struct SlotTables {
   const double* theta = nullptr;   // warm-start Ritz value of the column
   const int* src = nullptr;        // compaction source slot (-1 = newly admitted)
   int* active = nullptr;           // 1 while the slot iterates in the current cycle
+  // scratch of the coarsest-level solve: the active slots grouped by pole
+  // (plist, C entries) and each group's start (poff, kMaxPoles + 1 entries)
+  int* plist = nullptr;
+  int* poff = nullptr;
 };
 
 // ----- shifted block kernels (inner precision T = float or double) -----

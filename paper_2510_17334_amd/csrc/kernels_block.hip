@@ -1984,6 +1984,117 @@ __global__ __launch_bounds__(kThreads) void k_coarse_solve(
       mk<C>((ax[0] + ax[1]) + (ax[2] + ax[3]), (ay[0] + ay[1]) + (ay[2] + ay[3]));
 }
 
+// The active slots grouped by pole (a group's order is arbitrary: every slot's
+// coarse solution is formed on its own): poff[j] .. poff[j + 1] in plist.
+__global__ __launch_bounds__(kThreads) void k_pole_lists(int nslot, int npoles,
+                                                         const int* __restrict__ active,
+                                                         const int* __restrict__ sys,
+                                                         int* __restrict__ plist,
+                                                         int* __restrict__ poff) {
+  __shared__ int cnt[kMaxPoles], cur[kMaxPoles];
+  const int tid = threadIdx.x;
+  for (int j = tid; j < npoles; j += kThreads) cnt[j] = 0;
+  __syncthreads();
+  for (int s = tid; s < nslot; s += kThreads) {
+    const int sy = sys[s];
+    if (sy >= 0 && (active == nullptr || active[s] != 0)) atomicAdd(&cnt[sy % npoles], 1);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int j = 0; j < npoles; ++j) {
+      cur[j] = acc;
+      poff[j] = acc;
+      acc += cnt[j];
+    }
+    poff[npoles] = acc;
+  }
+  __syncthreads();
+  for (int s = tid; s < nslot; s += kThreads) {
+    const int sy = sys[s];
+    if (sy >= 0 && (active == nullptr || active[s] != 0))
+      plist[atomicAdd(&cur[sy % npoles], 1)] = s;
+  }
+}
+
+// Coarsest level as one product per pole: X_j = (A_c - sigma_j B_c)^{-1} B_j
+// over the slots of pole j.  A workgroup forms 64 rows by 32 slots of one
+// pole (4 rows x 2 slots per thread), the inverse's rows and the gathered
+// right-hand sides staged through LDS in chunks of 32 columns, FP64
+// accumulation in column order.  Workgroup b takes pole b mod npoles: with 8
+// poles each XCD reads one pole's inverse.
+constexpr int kCgRows = 64, kCgSlots = 32, kCgK = 32;
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_coarse_gemm(
+    int nc, int npoles, int nrt, const int* __restrict__ plist, const int* __restrict__ poff,
+    const typename CT<T>::t* __restrict__ Minv, const typename CT<T>::t* __restrict__ Bin,
+    typename CT<T>::t* __restrict__ Out) {
+  using C = typename CT<T>::t;
+  const int p = (int)(blockIdx.x % (unsigned)npoles);
+  const int rest = (int)(blockIdx.x / (unsigned)npoles);
+  const int rt = rest % nrt, stile = rest / nrt;
+  const int s0 = poff[p] + stile * kCgSlots, s1 = poff[p + 1];
+  if (s0 >= s1) return;
+  __shared__ double2 Ms[kCgRows][kCgK + 1];
+  __shared__ double2 Bs[kCgK][kCgSlots];
+  __shared__ int sl[kCgSlots];
+  const int tid = threadIdx.x;
+  if (tid < kCgSlots) sl[tid] = s0 + tid < s1 ? plist[s0 + tid] : -1;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int r0 = rt * kCgRows;
+  const C* __restrict__ Mp = Minv + (size_t)p * nc * nc;
+  double2 acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) acc[i][0] = acc[i][1] = make_double2(0.0, 0.0);
+  __syncthreads();
+  for (int k0 = 0; k0 < nc; k0 += kCgK) {
+    for (int e = tid; e < kCgRows * kCgK; e += kThreads) {
+      const int r = e / kCgK, k = e % kCgK, gr = r0 + r, gk = k0 + k;
+      double2 v = make_double2(0.0, 0.0);
+      if (gr < nc && gk < nc) {
+        const C m = Mp[(size_t)gr * nc + gk];
+        v = make_double2(m.x, m.y);
+      }
+      Ms[r][k] = v;
+    }
+    for (int e = tid; e < kCgK * kCgSlots; e += kThreads) {
+      const int k = e / kCgSlots, j = e % kCgSlots, sj = sl[j], gk = k0 + k;
+      double2 v = make_double2(0.0, 0.0);
+      if (sj >= 0 && gk < nc) {
+        const C b = Bin[((size_t)(sj / kPanel) * nc + gk) * kPanel + sj % kPanel];
+        v = make_double2(b.x, b.y);
+      }
+      Bs[k][j] = v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < kCgK; ++k) {
+      const double2 b0 = Bs[k][2 * tx], b1 = Bs[k][2 * tx + 1];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double2 m = Ms[4 * ty + i][k];
+        acc[i][0].x += m.x * b0.x - m.y * b0.y;
+        acc[i][0].y += m.x * b0.y + m.y * b0.x;
+        acc[i][1].x += m.x * b1.x - m.y * b1.y;
+        acc[i][1].y += m.x * b1.y + m.y * b1.x;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = r0 + 4 * ty + i;
+    if (row >= nc) continue;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int sj = sl[2 * tx + j];
+      if (sj >= 0)
+        Out[((size_t)(sj / kPanel) * nc + row) * kPanel + sj % kPanel] =
+            mk<C>(acc[i][j].x, acc[i][j].y);
+    }
+  }
+}
+
 inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
 
 }  // namespace
@@ -3328,6 +3439,17 @@ template <typename T>
 hipError_t launch_coarse_solve(int nc, const PanelGrid& g, const SlotTables& st, int npoles,
                                const void* Minv, const void* In, void* Out, hipStream_t s) {
   using C = typename CT<T>::t;
+  if (st.plist != nullptr && st.poff != nullptr && npoles <= kMaxPoles) {
+    const int nslot = g.npan * kPanel;
+    if (nslot == 0) return hipSuccess;
+    k_pole_lists<<<1, kThreads, 0, s>>>(nslot, npoles, st.active, st.sys, st.plist, st.poff);
+    const int nrt = (nc + kCgRows - 1) / kCgRows;
+    const long nblk = (long)npoles * nrt * ((nslot + kCgSlots - 1) / kCgSlots);
+    k_coarse_gemm<T><<<(unsigned)nblk, kThreads, 0, s>>>(
+        nc, npoles, nrt, st.plist, st.poff, static_cast<const C*>(Minv),
+        static_cast<const C*>(In), static_cast<C*>(Out));
+    return hipGetLastError();
+  }
   PanelGrid gc = g;
   gc.rpb = kThreads / kPanel;  // one row per thread
   gc.nrb = (nc + gc.rpb - 1) / gc.rpb;

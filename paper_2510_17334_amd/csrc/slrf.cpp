@@ -1033,14 +1033,14 @@ size_t filter_fixed_bytes(int n, int nc, int N) {
   const size_t S = (size_t)N * nc;
   const size_t Spad = (S + kPanel - 1) / kPanel * kPanel;
   return 4 * (size_t)n * nc * sizeof(double) + (nc + 1) * sizeof(double) +
-         Spad * n * 16 + (3 * S + 8) * sizeof(int) +
+         Spad * n * 16 + (3 * S + 8 + kMaxPoles + 1) * sizeof(int) +
          (2 * (size_t)colstat_chunks(n) * nc + 2) * sizeof(double) + 16 * kAlign;
 }
 
 size_t filter_slot_bytes(int n, int m, size_t sT, const std::vector<int>& amg_levels) {
   const int ND = std::max(m, 2);
   size_t b = (size_t)n * (2 * 16 + 4 * sT + 2 * (size_t)m * sT) +
-             (size_t)nrb_for(n) * ND * 16 + (size_t)ND * 16 + 6 * sizeof(int) +
+             (size_t)nrb_for(n) * ND * 16 + (size_t)ND * 16 + 7 * sizeof(int) +
              3 * sizeof(double) +
              ((size_t)5 * kMaxRestart + 1 + 2 * (size_t)kMaxRestart * kMaxRestart) * sizeof(double);
   return b + amg_vec_bytes(amg_levels, 1, sT);
@@ -1142,11 +1142,12 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
   HIPCHK(carve(h, (size_t)m * C * n * sT, &Pb));
   HIPCHK(carve_t(h, (size_t)nrb * ND * C, &part));
   HIPCHK(carve_t(h, (size_t)ND * C, &red));
-  // slot tables: int: sys, col, src, active, status, retire (6C); double2 sigma (C);
-  // double theta (C)
+  // slot tables: int: sys, col, src, active, status, retire (6C), the slots
+  // grouped by pole (C) and the groups' offsets (kMaxPoles + 1); double2
+  // sigma (C); double theta (C)
   int* itab;
   double* dtab;
-  HIPCHK(carve_t(h, (size_t)6 * C, &itab));
+  HIPCHK(carve_t(h, (size_t)7 * C + kMaxPoles + 1, &itab));
   HIPCHK(carve_t(h, (size_t)3 * C, &dtab));
   int *d_sys = itab, *d_col = itab + C, *d_src = itab + 2 * C, *d_act = itab + 3 * C,
       *d_status = itab + 4 * C, *d_retire = itab + 5 * C;
@@ -1231,6 +1232,8 @@ slrf_status run_filter(slrf_ctx* h, int nc, const double* X, const double* theta
   tabs.col = d_col;
   tabs.theta = d_theta_slot;
   tabs.active = d_act;
+  tabs.plist = itab + 6 * (size_t)C;
+  tabs.poff = itab + 7 * (size_t)C;
 
   while (true) {
     // ----- cycle boundary: fold directions into y, FP64 true residual, status

@@ -52,8 +52,9 @@ def parse():
     ap.add_argument("--m", type=int, default=64, help="Q1 nodes per direction (64 = metric)")
     ap.add_argument("--precond", choices=["amg", "jacobi"], default="amg")
     ap.add_argument("--restart", type=int, default=5, help="GCR restart length m")
-    ap.add_argument("--coarse-min", type=int, default=512,
-                    help="AMG smallest coarse level (options.amg_coarse_min) of the Q1 workload")
+    ap.add_argument("--coarse-min", type=int, default=None,
+                    help="AMG smallest coarse level (options.amg_coarse_min); default 512 for the "
+                         "Q1 workload, 0 (off) for the others")
     ap.add_argument("--ncols", type=int, default=160)
     ap.add_argument("--workload", choices=["q1_3d", "batch64", "itmax", "elasticity48", "fd32"],
                     default="q1_3d",
@@ -396,11 +397,14 @@ def run_batch64(args):
         p = d["pencil"]
         poles, weights = si.slrf_poles(g["gamma"])
         opt = P.default_options(precision=P.SLRF_PREC_MIXED, precond=P.SLRF_PC_AMG,
-                                restart=args.restart, tol_lin=1e-8, timing=0)
+                                restart=args.restart, tol_lin=1e-8, timing=0,
+                                amg_coarse_min=args.coarse_min)
         hs.append(P.Handle.from_pencil(p, g["gamma"], poles, weights, opt,
                                        stream=torch.cuda.Stream(), max_cols=d["L"],
                                        budget=max(left / (len(draws) - i), 2.0)))
         left -= hs[-1].workspace.numel()
+        if (i + 1) % 8 == 0:
+            print(f"batch64: {i + 1} handles set up", file=sys.stderr, flush=True)
         V = si.start_block(p.n, d["L"], d["seed"])
         Xs.append(torch.as_tensor(np.ascontiguousarray(V.T), device="cuda").t())
         nsys += d["L"] * len(poles)
@@ -440,6 +444,7 @@ def run_batch64(args):
                    "n_range": [min(g["n"] for g in gold), max(g["n"] for g in gold)],
                    "systems": nsys, "tol_lin": 1e-8,
                    "solver": f"GCR({args.restart})+AMG V-cycle, mixed",
+                   "amg_coarse_min": args.coarse_min,
                    "step": "Algorithm 1 outer iteration on every pencil"},
         "modes": res,
         "batching_speedup": res["one_at_a_time"]["ms_per_step"] / r["ms_per_step"],
@@ -539,7 +544,7 @@ def run_elasticity48(args):
         poles, weights = si.slrf_poles(gamma)
         opt = P.default_options(precision=prec, precond=P.SLRF_PC_AMG, restart=5,
                                 tol_lin=1e-14, it_max_lin=40, lock=1, warm_start=1,
-                                max_outer=max_outer)
+                                max_outer=max_outer, amg_coarse_min=args.coarse_min)
         t = time.perf_counter()
         h = P.Handle.from_pencil(p, gamma, poles, weights, opt, max_cols=L, budget=0.6)
         ts = time.perf_counter() - t
@@ -584,7 +589,8 @@ def run_elasticity48(args):
             "higher_is_better": False, "dtype": "c64+f64", "data": "synthetic",
             "config": {"workload": "elasticity_48", "n": p.n, "nnz": p.nnz, "nev": nev, "L": L,
                        "npoles": 8, "solver": "GCR(5)+AMG (rigid-body modes), It_max 40, "
-                                              "lock + warm start"},
+                                              "lock + warm start",
+                       "amg_coarse_min": args.coarse_min},
             "gamma": gamma, "gamma_source": "pre-pass (see docstring)",
             "gap_after_200": float((th0[nev] - th0[nev - 1]) / th0[nev - 1]),
             "next_value_above_gamma": float(th0[nev]), "prepass": pre, "runs": runs,
@@ -676,6 +682,8 @@ def main():
               f"independent, a multi-GPU run would shard them by column (see the design "
               f"notes); --gpus {args.gpus} is not supported.", file=sys.stderr)
         sys.exit(2)
+    if args.coarse_min is None:
+        args.coarse_min = 512 if args.workload == "q1_3d" else 0
     if args.workload == "batch64":
         run_batch64(args)
         return

@@ -9,10 +9,12 @@
 #include "amg_host.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <complex>
 #include <numeric>
 #include <random>
+#include <thread>
 
 namespace slrf {
 
@@ -163,39 +165,70 @@ double rho_dinv_a(const HostLevel& L) {
 }
 
 // Dense inverse of a complex matrix by Gauss-Jordan with partial pivoting.
+// In-place Gauss-Jordan inversion with partial pivoting (row exchanges
+// recorded, undone on the columns at the end): n^3 complex multiply-adds, the
+// real and imaginary parts kept apart so the row updates vectorise.
 bool invert_dense(int n, std::vector<std::complex<double>>& M) {
-  std::vector<std::complex<double>> I((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) I[(size_t)i * n + i] = 1.0;
+  std::vector<double> re((size_t)n * n), im((size_t)n * n);
+  for (size_t i = 0; i < re.size(); ++i) {
+    re[i] = M[i].real();
+    im[i] = M[i].imag();
+  }
+  std::vector<int> perm(n);
   for (int c = 0; c < n; ++c) {
     int piv = c;
-    double best = std::abs(M[(size_t)c * n + c]);
-    for (int r = c + 1; r < n; ++r)
-      if (std::abs(M[(size_t)r * n + c]) > best) {
-        best = std::abs(M[(size_t)r * n + c]);
+    double best = std::hypot(re[(size_t)c * n + c], im[(size_t)c * n + c]);
+    for (int r = c + 1; r < n; ++r) {
+      const double v = std::hypot(re[(size_t)r * n + c], im[(size_t)r * n + c]);
+      if (v > best) {
+        best = v;
         piv = r;
       }
+    }
     if (!(best > 0.0)) return false;
-    if (piv != c)
-      for (int k = 0; k < n; ++k) {
-        std::swap(M[(size_t)c * n + k], M[(size_t)piv * n + k]);
-        std::swap(I[(size_t)c * n + k], I[(size_t)piv * n + k]);
-      }
-    const std::complex<double> inv = 1.0 / M[(size_t)c * n + c];
+    perm[c] = piv;
+    if (piv != c) {
+      std::swap_ranges(re.begin() + (size_t)c * n, re.begin() + (size_t)(c + 1) * n,
+                       re.begin() + (size_t)piv * n);
+      std::swap_ranges(im.begin() + (size_t)c * n, im.begin() + (size_t)(c + 1) * n,
+                       im.begin() + (size_t)piv * n);
+    }
+    double* cr = re.data() + (size_t)c * n;
+    double* ci = im.data() + (size_t)c * n;
+    // 1 / pivot
+    const double d = cr[c] * cr[c] + ci[c] * ci[c];
+    const double pr = cr[c] / d, pi = -ci[c] / d;
+    cr[c] = 1.0;
+    ci[c] = 0.0;
     for (int k = 0; k < n; ++k) {
-      M[(size_t)c * n + k] *= inv;
-      I[(size_t)c * n + k] *= inv;
+      const double xr = cr[k], xi = ci[k];
+      cr[k] = xr * pr - xi * pi;
+      ci[k] = xr * pi + xi * pr;
     }
     for (int r = 0; r < n; ++r) {
       if (r == c) continue;
-      const std::complex<double> f = M[(size_t)r * n + c];
-      if (f == 0.0) continue;
+      double* rr = re.data() + (size_t)r * n;
+      double* ri = im.data() + (size_t)r * n;
+      const double fr = rr[c], fi = ri[c];
+      if (fr == 0.0 && fi == 0.0) continue;
+      rr[c] = 0.0;
+      ri[c] = 0.0;
       for (int k = 0; k < n; ++k) {
-        M[(size_t)r * n + k] -= f * M[(size_t)c * n + k];
-        I[(size_t)r * n + k] -= f * I[(size_t)c * n + k];
+        rr[k] -= fr * cr[k] - fi * ci[k];
+        ri[k] -= fr * ci[k] + fi * cr[k];
       }
     }
   }
-  M.swap(I);
+  // the row exchanges of A become column exchanges of A^-1, in reverse order
+  for (int c = n - 1; c >= 0; --c) {
+    const int q = perm[c];
+    if (q == c) continue;
+    for (int r = 0; r < n; ++r) {
+      std::swap(re[(size_t)r * n + c], re[(size_t)r * n + q]);
+      std::swap(im[(size_t)r * n + c], im[(size_t)r * n + q]);
+    }
+  }
+  for (size_t i = 0; i < re.size(); ++i) M[i] = std::complex<double>(re[i], im[i]);
   return true;
 }
 
@@ -615,17 +648,34 @@ bool amg_coarse_inverses(AmgHierarchy& H, const std::vector<std::complex<double>
   const int nc = Lc.n;
   H.nc = nc;
   H.coarse_inv.assign(poles.size() * (size_t)nc * nc, 0.0);
-  for (size_t j = 0; j < poles.size(); ++j) {
+  // one host thread per pole (each inversion is independent and n^3)
+  const int np = (int)poles.size();
+  std::vector<char> ok(np, 1);
+  auto one = [&](int j) {
     std::vector<std::complex<double>> M((size_t)nc * nc, 0.0);
     for (int i = 0; i < nc; ++i)
       for (int e = Lc.rp[i]; e < Lc.rp[i + 1]; ++e)
         M[(size_t)i * nc + Lc.ci[e]] = Lc.a[e] - poles[j] * Lc.b[e];
-    if (!invert_dense(nc, M)) {
+    ok[j] = invert_dense(nc, M) ? 1 : 0;
+    if (ok[j]) std::copy(M.begin(), M.end(), H.coarse_inv.begin() + j * (size_t)nc * nc);
+  };
+  const int nt = std::max(1, std::min(np, (int)std::thread::hardware_concurrency()));
+  if (nt <= 1 || (double)nc * nc * nc < 1e7) {
+    for (int j = 0; j < np; ++j) one(j);
+  } else {
+    std::atomic<int> next(0);
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nt; ++t)
+      pool.emplace_back([&] {
+        for (int j = next++; j < np; j = next++) one(j);
+      });
+    for (auto& t : pool) t.join();
+  }
+  for (int j = 0; j < np; ++j)
+    if (!ok[j]) {
       err = "singular coarsest AMG operator";
       return false;
     }
-    std::copy(M.begin(), M.end(), H.coarse_inv.begin() + j * (size_t)nc * nc);
-  }
   return true;
 }
 

@@ -45,7 +45,7 @@ def driver(tmp_path_factory):
         pytest.skip("g++ not available")
     d = tmp_path_factory.mktemp("host")
     exe = str(d / "host_driver")
-    cmd = [gxx, "-O1", "-std=c++17", "-I", CSRC, os.path.join(HERE, "host_driver.cpp"),
+    cmd = [gxx, "-O1", "-std=c++17", "-pthread", "-I", CSRC, os.path.join(HERE, "host_driver.cpp"),
            os.path.join(CSRC, "amg_host.cpp"), os.path.join(CSRC, "halo_host.cpp"),
            os.path.join(CSRC, "ugroup_host.cpp"), "-o", exe]
     subprocess.run(cmd, check=True, capture_output=True)

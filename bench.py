@@ -479,12 +479,14 @@ def run_itmax(args):
         lam = np.sort((l1[:, None, None] + l1[None, :, None] + l1[None, None, :]).ravel())[:nev]
         tol, workload = 1e-8, f"q1_3d_m{args.m}"
     poles, weights = si.slrf_poles(gamma)
+    # the Q1 pencil runs with the benchmark's coarse level unless one is given
+    cmin = args.coarse_min if args.coarse_min_given or args.itmax_pencil != "q1_3d" else 512
     V1 = torch.as_tensor(np.ascontiguousarray(si.start_block(p.n, L, seed).T), device="cuda").t()
     rows = []
     for itmax in [int(x) for x in args.itmax.split(",")]:
         opt = P.default_options(precision=P.SLRF_PREC_MIXED, precond=P.SLRF_PC_AMG,
                                 restart=args.restart, tol_lin=tol, lock=1, warm_start=1,
-                                max_outer=100, it_max_lin=itmax)
+                                max_outer=100, it_max_lin=itmax, amg_coarse_min=cmin)
         h = P.Handle.from_pencil(p, gamma, poles, weights, opt, max_cols=L, budget=0.6)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -508,7 +510,8 @@ def run_itmax(args):
             "higher_is_better": False, "dtype": "c64+f64", "data": "synthetic",
             "config": {"workload": workload, "n": p.n, "nnz": p.nnz, "nev": nev, "L": L,
                        "tol_lin": tol,
-                       "solver": f"GCR({args.restart})+AMG, mixed, lock + warm start"},
+                       "solver": f"GCR({args.restart})+AMG, mixed, lock + warm start",
+                       "amg_coarse_min": cmin},
             "chosen_it_max_linear": best["it_max_linear"] if best else None, "sweep": rows}
     print(json.dumps(line, default=float))
 
@@ -682,6 +685,7 @@ def main():
               f"independent, a multi-GPU run would shard them by column (see the design "
               f"notes); --gpus {args.gpus} is not supported.", file=sys.stderr)
         sys.exit(2)
+    args.coarse_min_given = args.coarse_min is not None
     if args.coarse_min is None:
         # measured per workload: 512 on the Q1 pencil (102 eigenvalues), 128 on
         # the 64-pencil batch (10-60 eigenvalues each: 35.2k solves/s against

@@ -1942,48 +1942,6 @@ __global__ __launch_bounds__(kThreads) void k_lvl_jacobi0(
   }
 }
 
-// coarsest level: x = (A_c - sigma_j B_c)^{-1} b with the dense inverse of the
-// slot's pole j = sys % npoles.  One row per thread (16 rows by 16 slots per
-// workgroup); the launch deals each XCD a contiguous range of row blocks over
-// all panels, so the inverse rows an XCD reads stay in its L2.  Four partial
-// sums per row (columns j mod 4) keep four loads in flight.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_coarse_solve(
-    int nc, PanelGrid g, const int* __restrict__ active, const int* __restrict__ sys, int npoles,
-    const typename CT<T>::t* __restrict__ Minv, const typename CT<T>::t* __restrict__ Bin,
-    typename CT<T>::t* __restrict__ Out) {
-  using C = typename CT<T>::t;
-  int rb, pan;
-  if (!map_block(g, rb, pan)) return;
-  const int lane = threadIdx.x & 15, rs = threadIdx.x >> 4;
-  const int slot = pan * kPanel + lane;
-  const int row = rb * g.rpb + rs;
-  if (row >= nc || (active != nullptr && active[slot] == 0)) return;
-  const int sy = sys[slot];
-  if (sy < 0) return;
-  const C* __restrict__ Mr = Minv + ((size_t)(sy % npoles) * nc + row) * nc;
-  const C* __restrict__ Bp = Bin + (size_t)pan * nc * kPanel + lane;
-  double ax[4] = {0.0, 0.0, 0.0, 0.0}, ay[4] = {0.0, 0.0, 0.0, 0.0};
-  const int n4 = nc & ~3;
-  for (int j = 0; j < n4; j += 4) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const C m = Mr[j + u];
-      const C b = Bp[(size_t)(j + u) * kPanel];
-      ax[u] += (double)m.x * b.x - (double)m.y * b.y;
-      ay[u] += (double)m.x * b.y + (double)m.y * b.x;
-    }
-  }
-  for (int j = n4; j < nc; ++j) {
-    const C m = Mr[j];
-    const C b = Bp[(size_t)j * kPanel];
-    ax[j - n4] += (double)m.x * b.x - (double)m.y * b.y;
-    ay[j - n4] += (double)m.x * b.y + (double)m.y * b.x;
-  }
-  Out[(size_t)pan * nc * kPanel + row * kPanel + lane] =
-      mk<C>((ax[0] + ax[1]) + (ax[2] + ax[3]), (ay[0] + ay[1]) + (ay[2] + ay[3]));
-}
-
 // The active slots grouped by pole (a group's order is arbitrary: every slot's
 // coarse solution is formed on its own): poff[j] .. poff[j + 1] in plist.
 __global__ __launch_bounds__(kThreads) void k_pole_lists(int nslot, int npoles,
@@ -3439,25 +3397,16 @@ template <typename T>
 hipError_t launch_coarse_solve(int nc, const PanelGrid& g, const SlotTables& st, int npoles,
                                const void* Minv, const void* In, void* Out, hipStream_t s) {
   using C = typename CT<T>::t;
-  if (st.plist != nullptr && st.poff != nullptr && npoles <= kMaxPoles) {
-    const int nslot = g.npan * kPanel;
-    if (nslot == 0) return hipSuccess;
-    k_pole_lists<<<1, kThreads, 0, s>>>(nslot, npoles, st.active, st.sys, st.plist, st.poff);
-    const int nrt = (nc + kCgRows - 1) / kCgRows;
-    const long nblk = (long)npoles * nrt * ((nslot + kCgSlots - 1) / kCgSlots);
-    k_coarse_gemm<T><<<(unsigned)nblk, kThreads, 0, s>>>(
-        nc, npoles, nrt, st.plist, st.poff, static_cast<const C*>(Minv),
-        static_cast<const C*>(In), static_cast<C*>(Out));
-    return hipGetLastError();
-  }
-  PanelGrid gc = g;
-  gc.rpb = kThreads / kPanel;  // one row per thread
-  gc.nrb = (nc + gc.rpb - 1) / gc.rpb;
-  gc.group = gc.npan;  // row block-major: an XCD's rows over all panels
-  k_coarse_solve<T><<<gc.blocks(), kThreads, 0, s>>>(nc, gc, st.active, st.sys, npoles,
-                                                    static_cast<const C*>(Minv),
-                                                    static_cast<const C*>(In),
-                                                    static_cast<C*>(Out));
+  // the slot tables carry the pole-list scratch (npoles <= kMaxPoles at setup)
+  if (st.plist == nullptr || st.poff == nullptr || npoles > kMaxPoles) return hipErrorInvalidValue;
+  const int nslot = g.npan * kPanel;
+  if (nslot == 0) return hipSuccess;
+  k_pole_lists<<<1, kThreads, 0, s>>>(nslot, npoles, st.active, st.sys, st.plist, st.poff);
+  const int nrt = (nc + kCgRows - 1) / kCgRows;
+  const long nblk = (long)npoles * nrt * ((nslot + kCgSlots - 1) / kCgSlots);
+  k_coarse_gemm<T><<<(unsigned)nblk, kThreads, 0, s>>>(
+      nc, npoles, nrt, st.plist, st.poff, static_cast<const C*>(Minv),
+      static_cast<const C*>(In), static_cast<C*>(Out));
   return hipGetLastError();
 }
 

@@ -100,3 +100,29 @@ def test_host_check_of_gradient_element_data():
     assert chk(hb=1, sb=0, lb=10) == 1
     assert chk(k=6) == 1               # unsupported element size
     assert chk(ne=0, d=np.zeros(0, np.int32), la=0) == 0
+
+
+
+def test_coarse_level_floor_is_validated_before_any_device_work():
+    """slrf_setup checks its options before it touches the pencil or a device: an
+    AMG coarse-level floor outside [0, 2048] is SLRF_E_ARG with its own message
+    (host-only structures suffice; a valid floor gets past the check and fails
+    later, on this machine for want of a device or a readable pencil)."""
+    import ctypes as C
+    L = P.lib()
+    csr = P.slrf.Csr()
+    zd = (P.slrf.Zd * 8)()
+    ws = (C.c_char * 4096)()
+    msgs = {}
+    for cmin in (-1, 2049, 0, 2048):
+        o = P.default_options(precond=P.SLRF_PC_AMG, amg_coarse_min=cmin)
+        h = C.c_void_p()
+        st = L.slrf_setup(C.byref(h), C.byref(csr), C.byref(csr), 1.0, 8, zd, zd, C.byref(o),
+                          ws, 4096, None)
+        assert st != 0
+        msgs[cmin] = (st, L.slrf_last_error(h).decode())
+        L.slrf_destroy(h)
+    for bad in (-1, 2049):
+        assert msgs[bad][0] == 1 and "amg_coarse_min" in msgs[bad][1], msgs[bad]
+    for good in (0, 2048):
+        assert "amg_coarse_min" not in msgs[good][1], msgs[good]

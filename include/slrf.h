@@ -155,7 +155,8 @@ typedef struct {
                           (0.01, 0.02, ... 0.64) to the first value that leaves
                           at least this many while still halving the level;
                           failing that, a level small enough for the dense
-                          solve becomes the coarsest.  The shifted systems are
+                          solve becomes the coarsest, and a larger one takes
+                          the largest halving coarse space the thresholds gave.  The shifted systems are
                           indefinite on the modes below Re sigma_j, which the
                           smoothing cannot damp and only the coarse correction
                           reaches: a coarsest level of a few times the number

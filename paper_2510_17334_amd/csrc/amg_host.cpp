@@ -509,17 +509,29 @@ bool amg_build(const HostLevel& fine, const std::vector<std::complex<double>>& p
       // threshold) whose coarse dofs still at most halve the level; failing
       // that, this level is the coarsest if the dense solve takes it
       bool found = false;
-      std::vector<int> trial(n);
+      int best = na;
+      std::vector<int> trial(n), best_agg;
       for (double th = 0.01; th <= 0.64 && !found; th *= 2.0) {
         if (th <= prm.theta) continue;
         const int k = aggregate_at(th, trial);
-        if ((long)k * ncols >= prm.coarse_min && 2L * k * ncols <= n) {
+        if (2L * k * ncols > n) continue;
+        if ((long)k * ncols >= prm.coarse_min) {
           na = k;
           dagg.swap(trial);
           found = true;
+        } else if (k > best) {
+          best = k;
+          best_agg = trial;
         }
       }
-      if (!found && n <= prm.dense_max) break;
+      if (!found) {
+        if (n <= prm.dense_max) break;
+        // too large for the dense solve: the largest coarse space that halves
+        if (best > na) {
+          na = best;
+          dagg.swap(best_agg);
+        }
+      }
     }
     if (na == 0) break;
     // tentative prolongator T: per aggregate, an orthonormal basis of the

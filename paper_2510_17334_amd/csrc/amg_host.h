@@ -29,7 +29,8 @@ struct AmgParams {
   // fewer coarse dofs, the strength threshold is raised (0.01, 0.02, ... 0.64)
   // to the first value that leaves at least this many while still halving the
   // level; if none does, a level that fits the dense solve becomes the
-  // coarsest (0: off)
+  // coarsest, and a larger one takes the largest halving coarse space the
+  // thresholds gave (0: off)
   int coarse_min = 0;
   int dense_max = 2048;   // largest coarsest level inverted densely
   int max_levels = 10;

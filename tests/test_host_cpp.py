@@ -408,15 +408,16 @@ def test_amg_rigid_body_modes_in_the_coarse_space(driver, coords):
     (32, 0, [32768, 1331, 27]),    # off: plain aggregation down to <= 400
     (32, 64, [32768, 1331, 64]),   # 27 < 64: a raised threshold leaves 64
     (32, 128, [32768, 1331]),      # no halving aggregation leaves >= 128: 1331 is dense-solvable
-    (16, 512, [4096, 216]),        # nothing reaches 512 and 4096 is too large: kept
+    (16, 512, [4096, 310]),        # nothing reaches 512, 4096 is too large: the largest halving
     (16, 256, [4096, 310]),        # 216 < 256 on the fine level: a raised threshold leaves 310
 ])
 def test_amg_coarse_min(driver, m, cmin, sizes):
     """options.amg_coarse_min: where the aggregation would leave fewer coarse dofs
     than the minimum, the strength threshold rises to the first value that leaves
     at least that many while halving the level; failing that a dense-solvable
-    level becomes the coarsest.  Every level stays a Galerkin product and every
-    coarsening at least halves."""
+    level becomes the coarsest, and a larger one takes the largest halving
+    coarse space the thresholds gave.  Every level stays a Galerkin product and
+    every coarsening at least halves."""
     p = si.q1_kron_pencil(m, 3)
     levels, Ps = _read_amg(_run(driver, p, "amg", 1, 10.0, 10.0, f"cmin={cmin}"))
     assert [L[0].shape[0] for L in levels] == sizes

@@ -675,13 +675,22 @@ bool amg_coarse_inverses(AmgHierarchy& H, const std::vector<std::complex<double>
   if (nt <= 1 || (double)nc * nc * nc < 1e7) {
     for (int j = 0; j < np; ++j) one(j);
   } else {
+    // (a thread that cannot be started leaves its share to the others, and
+    // to this thread when none started)
     std::atomic<int> next(0);
     std::vector<std::thread> pool;
-    for (int t = 0; t < nt; ++t)
-      pool.emplace_back([&] {
-        for (int j = next++; j < np; j = next++) one(j);
-      });
+    auto work = [&] {
+      for (int j = next++; j < np; j = next++) one(j);
+    };
+    for (int t = 0; t < nt; ++t) {
+      try {
+        pool.emplace_back(work);
+      } catch (...) {
+        break;
+      }
+    }
     for (auto& t : pool) t.join();
+    work();
   }
   for (int j = 0; j < np; ++j)
     if (!ok[j]) {

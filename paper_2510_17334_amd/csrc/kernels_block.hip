@@ -1976,12 +1976,12 @@ __global__ __launch_bounds__(kThreads) void k_pole_lists(int nslot, int npoles,
 }
 
 // Coarsest level as one product per pole: X_j = (A_c - sigma_j B_c)^{-1} B_j
-// over the slots of pole j.  A workgroup forms 64 rows by 32 slots of one
-// pole (4 rows x 2 slots per thread), the inverse's rows and the gathered
+// over the slots of pole j.  A workgroup forms 32 rows by 32 slots of one
+// pole (2 rows x 2 slots per thread), the inverse's rows and the gathered
 // right-hand sides staged through LDS in chunks of 32 columns, FP64
 // accumulation in column order.  Workgroup b takes pole b mod npoles: with 8
 // poles each XCD reads one pole's inverse.
-constexpr int kCgRows = 64, kCgSlots = 32, kCgK = 32;
+constexpr int kCgRows = 32, kCgSlots = 32, kCgK = 32, kCgRT = kCgRows / 16;
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_coarse_gemm(
     int nc, int npoles, int nrt, const int* __restrict__ plist, const int* __restrict__ poff,
@@ -2001,9 +2001,9 @@ __global__ __launch_bounds__(kThreads) void k_coarse_gemm(
   const int tx = tid & 15, ty = tid >> 4;
   const int r0 = rt * kCgRows;
   const C* __restrict__ Mp = Minv + (size_t)p * nc * nc;
-  double2 acc[4][2];
+  double2 acc[kCgRT][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) acc[i][0] = acc[i][1] = make_double2(0.0, 0.0);
+  for (int i = 0; i < kCgRT; ++i) acc[i][0] = acc[i][1] = make_double2(0.0, 0.0);
   __syncthreads();
   for (int k0 = 0; k0 < nc; k0 += kCgK) {
     for (int e = tid; e < kCgRows * kCgK; e += kThreads) {
@@ -2029,8 +2029,8 @@ __global__ __launch_bounds__(kThreads) void k_coarse_gemm(
     for (int k = 0; k < kCgK; ++k) {
       const double2 b0 = Bs[k][2 * tx], b1 = Bs[k][2 * tx + 1];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const double2 m = Ms[4 * ty + i][k];
+      for (int i = 0; i < kCgRT; ++i) {
+        const double2 m = Ms[kCgRT * ty + i][k];
         acc[i][0].x += m.x * b0.x - m.y * b0.y;
         acc[i][0].y += m.x * b0.y + m.y * b0.x;
         acc[i][1].x += m.x * b1.x - m.y * b1.y;
@@ -2040,8 +2040,8 @@ __global__ __launch_bounds__(kThreads) void k_coarse_gemm(
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int row = r0 + 4 * ty + i;
+  for (int i = 0; i < kCgRT; ++i) {
+    const int row = r0 + kCgRT * ty + i;
     if (row >= nc) continue;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {

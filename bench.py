@@ -33,6 +33,8 @@ HBM_PEAK_GBPS = 8000.0
 # FP32 / FP64 FMA rate of the vector ALUs without packed-FP32 instructions (the
 # build disables them): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz.
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# the published FP32 vector rate (two FP32 FMAs per packed instruction)
+PACKED_FP32_PEAK_TFLOPS = 157.3
 # the shifted sweep q = (A - sigma B) z does 2 complex-by-real products per
 # stored entry and system: 8 real flop (accumulated A z and B z)
 SWEEP_FLOP_PER_ENTRY = 8.0
@@ -356,7 +358,11 @@ def roofline_entry(dom, r, achieved_gbps, nl, traffic, tflops, intensity):
     if tflops is not None and intensity is not None and intensity > ridge:
         out = {"bound": "alu", "achieved": tflops, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                "frac": tflops / VALU_PEAK_TFLOPS, "flop_per_byte": intensity,
-               "ridge_flop_per_byte": ridge}
+               "ridge_flop_per_byte": ridge,
+               # against the published FP32 vector rate, which needs the packed
+               # FP32 instructions this build does not use
+               "peak_packed_fp32": PACKED_FP32_PEAK_TFLOPS,
+               "frac_of_packed_fp32_peak": tflops / PACKED_FP32_PEAK_TFLOPS}
     else:
         out = {"bound": "hbm", "achieved": achieved_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                "frac": achieved_gbps / HBM_PEAK_GBPS}

@@ -178,9 +178,13 @@ def eigen_runs(P, torch, p, gamma, poles, weights, nev, V1d, restart, lam_exact,
 
     out = {}
     A, B = p.A(), p.B()
-    for name, prec in (("mixed", P.SLRF_PREC_MIXED), ("fp64", P.SLRF_PREC_FP64)):
+    # the two precisions uncapped, then the mixed form with the automatic
+    # It_max-linear (the enhanced form of Section 4)
+    for name, prec, itmax in (("mixed", P.SLRF_PREC_MIXED, 0), ("fp64", P.SLRF_PREC_FP64, 0),
+                              ("mixed_it_max_auto", P.SLRF_PREC_MIXED, -1)):
         opt = P.default_options(precision=prec, precond=P.SLRF_PC_AMG, restart=restart,
-                                tol_lin=1e-8, lock=1, warm_start=1, amg_coarse_min=cmin)
+                                tol_lin=1e-8, lock=1, warm_start=1, amg_coarse_min=cmin,
+                                it_max_lin=itmax)
         h = P.Handle.from_pencil(p, gamma, poles, weights, opt, max_cols=V1d.shape[1],
                                  budget=0.6)
         torch.cuda.synchronize()
@@ -198,6 +202,8 @@ def eigen_runs(P, torch, p, gamma, poles, weights, nev, V1d, restart, lam_exact,
         out[name] = {"seconds": dt, "nconv": nconv, "outer_iters": st["outer_iters"],
                      "inner_iters": st["inner_iters"], "max_rel_eig_err": err,
                      "sampled_max_ritz_resid": None if res is None else float(res)}
+        if itmax:
+            out[name]["it_max_linear"] = st["auto_it_max"]
         print(f"eigen {name}: {dt:.2f} s to {nconv} pairs, err {err}", file=sys.stderr,
               flush=True)
     out["algorithm"] = "Algorithm 2 (locking, warm start), tol_lin 1e-8, tol_eig 1e-8"

@@ -100,3 +100,40 @@ def test_solve_batch_64_uneven_pencils_match_oracle():
     print("worst relative eigenvalue error", worst)
     for h in hs:
         h.close()
+
+
+def test_filter_batch_benchmark_options_coarse_floor():
+    """Four pencils of the 64-pencil batch with the batch benchmark's options
+    (mixed, AMG with a coarse-level floor of 128, GCR(5), tol_lin 1e-8): three
+    of the hierarchies end in dense levels of 1728, 625 and 729 unknowns
+    instead of 27 to 81 (the fourth already ends in 343), every system
+    converges to its FP64 residual, the batched call equals the single calls
+    bit for bit, and the floor cuts the inner iterations against the default
+    hierarchy."""
+    gold = json.load(open(GOLDEN))["pencils"]
+    idx = [5, 40, 3, 19]
+    draws = si.batched_pencils(64, seed=1004, only=idx)
+    iters = {}
+    for cmin in (128, 0):
+        hs, Xs = [], []
+        for d in draws:
+            g = gold[d["index"]]
+            poles, weights = si.slrf_poles(g["gamma"])
+            opt = P.default_options(precision=P.SLRF_PREC_MIXED, precond=P.SLRF_PC_AMG,
+                                    restart=5, tol_lin=1e-8, amg_coarse_min=cmin)
+            hs.append(P.Handle.from_pencil(d["pencil"], g["gamma"], poles, weights, opt,
+                                           stream=torch.cuda.Stream(), max_cols=d["L"]))
+            Xs.append(_dev(si.start_block(d["pencil"].n, d["L"], d["seed"])))
+        torch.cuda.synchronize()
+        out = P.slrf_filter_batch(hs, Xs, nthreads=4)
+        total = 0
+        for h, X, (U, st) in zip(hs, Xs, out):
+            assert st["converged"] == st["nsystems"] and st["max_rel_resid"] <= 1e-8
+            total += st["total_iters"]
+            if cmin:
+                U1, st1 = h.slrf_filter(X)
+                assert torch.equal(U, U1) and st["total_iters"] == st1["total_iters"]
+        iters[cmin] = total
+        for h in hs:
+            h.close()
+    assert iters[0] > 1.15 * iters[128], iters

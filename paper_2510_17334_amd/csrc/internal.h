@@ -301,6 +301,11 @@ hipError_t launch_fin_true(const double2* red, int nslots, const SlotTables& st,
                            int itcap, hipStream_t s);
 
 // ----- real dense / sparse kernels for Rayleigh-Ritz (row-major blocks) -----
+// launch_spmm_real on the pencil's complex-double halo tiles; false (nothing
+// launched) where the tiles are absent or nc, ld or the alignment of X do not fit.
+bool launch_spmm_real_halo(const DevPencil& P, const double* X, int ld, int nc, double* AX,
+                           double* BX, const double* theta, double* E, hipStream_t s,
+                           hipError_t& err);
 hipError_t launch_spmm_real(const DevPencil& P, const double* X, int ld, int nc, double* AX,
                             double* BX, const double* theta, double* E, hipStream_t s);
 // out[c * ldout + omap(r)] = in[r * ldin + imap(c)]; maps optional (NULL = identity)

@@ -1171,6 +1171,118 @@ __global__ __launch_bounds__(kThreads) void k_true_halo(
 }
 #undef SLRF_TRUE_ISSUE
 
+// Y_A = A X and Y_B = B X (optionally E = Y_A - theta_c Y_B) for a row-major
+// real FP64 block X (row stride ld, even; nc even) on the halo tiles of the
+// complex-double sweep.  A pair of columns fills one 16-byte lane element the
+// way one complex system does there, so a unit is 16 columns (8 lanes x 2):
+// each workgroup takes one tile, stages its coefficients once and its halo
+// rows of X per unit (loaded into registers while the previous unit is
+// formed).  A row's entries are summed in CSR order, the padding adding
+// zeros, so the results equal the CSR kernel's.
+__global__ __launch_bounds__(kThreads) void k_spmm_real_halo(
+    int n, HaloView hv, int hmax, int nunit, int G, const double* __restrict__ X, int ld,
+    int nc, double* __restrict__ AX, double* __restrict__ BX,
+    const double* __restrict__ theta, double* __restrict__ E) {
+  using V = double2;
+  constexpr int UNR = 4;  // = kHaloPad
+  extern __shared__ __attribute__((aligned(16))) double smem_d[];
+  V* sZ = reinterpret_cast<V*>(smem_d);                                  // [hmax][8]
+  double2* s_ab = reinterpret_cast<double2*>(sZ + (size_t)hmax * 8);    // [emax]
+  unsigned* s_lc = reinterpret_cast<unsigned*>(s_ab + hv.emax);         // [emax]
+  int* sH = reinterpret_cast<int*>(s_lc + hv.emax);                     // [hmax]
+  __shared__ int s_sp[kHaloTileRows / 8 + 1];
+  const int nug = (nunit + G - 1) / G;
+  int tile, ug;
+  if (!map_tile(hv.ntile, nug, 1, tile, ug)) return;
+  const int tid = threadIdx.x, w = tid >> 6, rr = (tid >> 3) & 7, lr = tid & 7;
+  const int r0 = hv.trow[tile], r1 = hv.trow[tile + 1];
+  const int h0 = hv.hptr[tile], H = hv.hptr[tile + 1] - h0;
+  const int nsl = (r1 - r0 + 7) >> 3, sl0 = r0 >> 3;
+  for (int t = tid; t < H; t += kThreads) sH[t] = hv.halo[h0 + t];
+  if (tid <= nsl) s_sp[tid] = hv.sptr[sl0 + tid];
+  __syncthreads();
+  const int gend = min(G, nunit - ug * G);  // units of this group
+  constexpr int HP = (kHaloMaxH * 8 + kThreads - 1) / kThreads;
+  V hreg[HP];
+  // this thread's halo elements: halo row t / 8, column pair t % 8 = lr of
+  // the unit (past the halo: row 0, loaded and not stored)
+  unsigned hoff[HP];
+#pragma unroll
+  for (int i = 0; i < HP; ++i) {
+    const int t = i * kThreads + tid;
+    hoff[i] = (unsigned)((t < H * 8 ? sH[t >> 3] * (ld >> 1) : 0) + (t & 7));
+  }
+  const V* __restrict__ Xv = reinterpret_cast<const V*>(X);
+#define SLRF_RX_ISSUE(GX)                                                           \
+  do {                                                                              \
+    const int c0_ = (ug * G + (GX)) * 16;                                           \
+    const V* __restrict__ xu_ = Xv + (c0_ >> 1);                                     \
+    _Pragma("unroll") for (int i_ = 0; i_ < HP; ++i_) {                             \
+      /* (every element of this thread is column pair lr; past nc: zero) */         \
+      const V v_ = c0_ + 2 * lr < nc ? xu_[hoff[i_]] : make_double2(0.0, 0.0);       \
+      hreg[i_] = v_;                                                                \
+    }                                                                               \
+  } while (0)
+  SLRF_RX_ISSUE(0);
+  {
+    const int e0 = s_sp[0] * 8, ne = (s_sp[nsl] - s_sp[0]) * 8;
+    const int nlc = ne / 8, nab = ne * (int)sizeof(double2) / 16;
+    const uint4* __restrict__ glc = reinterpret_cast<const uint4*>(hv.lcol) + e0 / 8;
+    const uint4* __restrict__ gab =
+        static_cast<const uint4*>(hv.ab) + (size_t)e0 * sizeof(double2) / 16;
+    for (int t = tid; t < nlc; t += kThreads)
+      halo_stage_cols(glc[t], reinterpret_cast<uint4*>(s_lc) + 2 * t);
+    for (int t = tid; t < nab; t += kThreads) reinterpret_cast<uint4*>(s_ab)[t] = gab[t];
+  }
+  const int row = r0 + w * 8 + rr;
+  const int wdt = __builtin_amdgcn_readfirstlane(w < nsl ? s_sp[w + 1] - s_sp[w] : 0);
+  const int soff = w < nsl ? (s_sp[w] - s_sp[0]) * 8 + rr * 4 : 0;
+  for (int gu = 0; gu < gend; ++gu) {
+#pragma unroll
+    for (int i = 0; i < HP; ++i) {
+      const int t = i * kThreads + tid;
+      if (t < H * 8) sZ[t] = hreg[i];
+    }
+    __syncthreads();
+    if (gu + 1 < gend) SLRF_RX_ISSUE(gu + 1);
+    if (w < nsl) {
+      const double2* __restrict__ pab = s_ab + soff;
+      const unsigned* __restrict__ plc = s_lc + soff;
+      const V* __restrict__ pz = sZ + lr;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      halo_slice_groups(plc, wdt, [&](int j, const uint4& co) {
+        V z[UNR];
+        double2 ab[UNR];
+        halo_ab4(pab + j * 8, ab);
+        z[0] = halo_at(pz, co.x);
+        z[1] = halo_at(pz, co.y);
+        z[2] = halo_at(pz, co.z);
+        z[3] = halo_at(pz, co.w);
+#pragma unroll
+        for (int uu = 0; uu < UNR; ++uu) lane_fma<double, 1>(acc, ab[uu].x, ab[uu].y, z[uu]);
+      });
+      const int c = (ug * G + gu) * 16 + 2 * lr;
+      if (row < r1 && c < nc) {
+        const size_t o = (size_t)row * ld + c;
+        if (AX) {
+          AX[o] = acc[0];
+          AX[o + 1] = acc[1];
+        }
+        if (BX) {
+          BX[o] = acc[2];
+          BX[o + 1] = acc[3];
+        }
+        if (E) {
+          E[o] = acc[0] - theta[c] * acc[2];
+          E[o + 1] = acc[1] - theta[c + 1] * acc[3];
+        }
+      }
+    }
+    __syncthreads();  // the unit's halo consumed
+  }
+}
+#undef SLRF_RX_ISSUE
+
 // ||r||^2 per slot from the stored residual R, as partial sums per row block
 // (rows r0 + 16 i of the block summed per thread, then the 16 row groups).
 template <typename TI>
@@ -2784,6 +2896,23 @@ hipError_t launch_yupdate(int n, const PanelGrid& g, const SlotTables& st, doubl
                                                static_cast<const C*>(Zbase), vstride, kk,
                                                alpha, bhist);
   return hipGetLastError();
+}
+
+bool launch_spmm_real_halo(const DevPencil& P, const double* X, int ld, int nc, double* AX,
+                           double* BX, const double* theta, double* E, hipStream_t s,
+                           hipError_t& err) {
+  if (P.hx_ntile == 0 || P.hx_ab64 == nullptr || nc <= 0 || (nc & 1) || (ld & 1) ||
+      (reinterpret_cast<uintptr_t>(X) & 15))
+    return false;
+  const int G = kHaloMaxG;
+  const int nunit = (nc + 15) / 16;
+  const int nug = (nunit + G - 1) / G;
+  const long total = (long)P.hx_ntile * nug;
+  const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
+  k_spmm_real_halo<<<blocks, kThreads, halo_lds_bytes<double>(P), s>>>(
+      P.n, halo_view<double>(P), P.hx_hmax, nunit, G, X, ld, nc, AX, BX, theta, E);
+  err = hipGetLastError();
+  return true;
 }
 
 template <typename T>

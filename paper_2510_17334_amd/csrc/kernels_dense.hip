@@ -446,6 +446,8 @@ int colstat_chunks(int n) { return n <= 0 ? 1 : (n + kColRows - 1) / kColRows; }
 hipError_t launch_spmm_real(const DevPencil& P, const double* X, int ld, int nc, double* AX,
                             double* BX, const double* theta, double* E, hipStream_t s) {
   if (P.n == 0 || nc == 0) return hipSuccess;
+  hipError_t err = hipSuccess;
+  if (launch_spmm_real_halo(P, X, ld, nc, AX, BX, theta, E, s, err)) return err;
   k_spmm_real<<<cdiv(cdiv(P.n, 4), 8) * 8, 256, 0, s>>>(P.n, P.rowptr, P.col, P.a, P.b, X, ld,
                                                          nc, AX, BX, theta, E);
   return hipGetLastError();

@@ -18,7 +18,7 @@ HIPCC = "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else shut
 
 # kernels of the filter's inner loop (mangled-name fragments)
 HOT = ["k_apply_halo", "k_true_halo", "k_post_image", "k_restrict", "k_orth_lv", "k_dots_lv",
-       "k_step_lv", "k_yupdate", "k_lvl_jacobi0", "k_prolong_lds",
+       "k_step_lv", "k_yupdate", "k_lvl_jacobi0", "k_prolong_lds", "k_spmm_real_halo",
        "k_coarse_gemm", "k_pole_lists"]
 
 

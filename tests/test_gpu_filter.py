@@ -590,3 +590,27 @@ def test_workspace_minimum_streams_and_undersized_is_refused(cfg1):
         h.slrf_filter(X)
     assert e.value.status == 2 and "workspace" in str(e.value)
     h.close()
+
+
+@pytest.mark.parametrize("prec", [P.SLRF_PREC_FP64, P.SLRF_PREC_MIXED])
+def test_real_spmm_halo_and_csr_forms_agree_bitwise(prec):
+    """The right-hand sides F = B X come from the halo-tile real SpMM for an even
+    column count and from the CSR kernel for an odd one; both sum each row in
+    CSR order.  A system's arithmetic does not depend on its slot, so the first
+    seven columns of a filtered 8-column block equal the 7-column filter bit
+    for bit; warm-started filters (E = A X - theta B X on the same paths) too."""
+    p = si.q1_diffusion_pencil(24, 3, np.exp(np.random.default_rng(21).normal(0, .5, 25 ** 3)))
+    gamma = 60.0
+    poles, weights = si.slrf_poles(gamma)
+    X = si.start_block(p.n, 8, 2101)
+    h = _handle(p, gamma, poles, weights, precision=prec, precond=P.SLRF_PC_AMG, restart=5,
+                tol_lin=1e-9)
+    U8, st8 = h.slrf_filter(_dev(X))
+    U7, st7 = h.slrf_filter(_dev(X[:, :7]))
+    assert st8["converged"] == 64 and st7["converged"] == 56
+    assert torch.equal(U8[:, :7], U7)
+    theta = np.linspace(5.0, 40.0, 8)
+    W8, _ = h.slrf_filter(_dev(X), theta_warm=theta)
+    W7, _ = h.slrf_filter(_dev(X[:, :7]), theta_warm=theta[:7])
+    assert torch.equal(W8[:, :7], W7)
+    h.close()

@@ -360,25 +360,41 @@ __global__ __launch_bounds__(256, 1) void k_gemm_tall(int n, int p, int q, doubl
       }
 }
 
+// Per column c: sum over a chunk of rows of (X - theta_c Y)^2 and of W Y.  A
+// workgroup takes one chunk and 64 columns; its four waves take a quarter of
+// the chunk's rows each and their partial sums are added in wave order.
 __global__ __launch_bounds__(256) void k_colstats(int n, int nc, const double* __restrict__ X,
                                                   const double* __restrict__ Y, int ld,
                                                   const double* __restrict__ theta,
                                                   const double* __restrict__ W,
                                                   double* __restrict__ part, int rows_per_chunk) {
+  __shared__ double red[2][4][64];
   const int chunk = blockIdx.x;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = blockIdx.y * 64 + lane;
   const int r0 = chunk * rows_per_chunk, r1 = min(r0 + rows_per_chunk, n);
-  for (int c = threadIdx.x; c < nc; c += 256) {
-    double s1 = 0.0, s2 = 0.0;
+  const int q = (rows_per_chunk + 3) / 4;
+  const int a0 = min(r0 + w * q, r1), a1 = min(a0 + q, r1);
+  double s1 = 0.0, s2 = 0.0;
+  if (c < nc) {
     const double th = theta ? theta[c] : 0.0;
-    for (int r = r0; r < r1; ++r) {
+#pragma unroll 4
+    for (int r = a0; r < a1; ++r) {
       const size_t o = (size_t)r * ld + c;
       double x = X[o];
       if (theta) x -= th * Y[o];
       s1 = fma(x, x, s1);
       if (W) s2 = fma(W[o], Y[o], s2);
     }
-    part[((size_t)chunk * 2 + 0) * nc + c] = s1;
-    part[((size_t)chunk * 2 + 1) * nc + c] = s2;
+  }
+  red[0][w][lane] = s1;
+  red[1][w][lane] = s2;
+  __syncthreads();
+  if (w == 0 && c < nc) {
+    part[((size_t)chunk * 2 + 0) * nc + c] =
+        ((red[0][0][lane] + red[0][1][lane]) + red[0][2][lane]) + red[0][3][lane];
+    part[((size_t)chunk * 2 + 1) * nc + c] =
+        ((red[1][0][lane] + red[1][1][lane]) + red[1][2][lane]) + red[1][3][lane];
   }
 }
 
@@ -524,7 +540,7 @@ hipError_t launch_colstats(int n, int nc, const double* X, const double* Y, int 
                            double* out, double* out2, hipStream_t s) {
   if (nc == 0) return hipSuccess;
   const int rpc = (n + nchunk - 1) / nchunk;
-  k_colstats<<<nchunk, 256, 0, s>>>(n, nc, X, Y, ld, theta, W, part, rpc);
+  k_colstats<<<dim3(nchunk, cdiv(nc, 64)), 256, 0, s>>>(n, nc, X, Y, ld, theta, W, part, rpc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_colreduce<<<cdiv(nc, 256), 256, 0, s>>>(part, nchunk, nc, out, out2);

@@ -302,6 +302,8 @@ def run_precision(P, torch, p, gamma, poles, weights, Xd, prec, steps, warmup, t
         "filter_s": st["seconds"],
         "iters_min_max": [st["min_iters"], st["max_iters"]],
         "total_inner_iters": st["total_iters"],
+        # fine-row iterations per second (comparable with the uneven batch)
+        "row_iterations_per_s": float(p.n) * st["total_iters"] / dt,
         "pole_ratio": st["max_pole_iters_ratio_x1000"] / 1000.0,
         "max_rel_resid": st["max_rel_resid"],
         "converged": st["converged"],
@@ -439,9 +441,14 @@ def run_batch64(args):
             out = step(nt)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / max(args.steps, 1)
+        # work done, in fine-row iterations (each inner iteration of a system
+        # sweeps its pencil's n rows once per operator application): the rate
+        # compares pencils of any size, and the batch with the large pencil
+        row_its = sum(float(h.n) * st["total_iters"] for h, (_, st) in zip(hs, out))
         res[label] = {"ms_per_step": dt * 1e3, "solves_per_s": nsys / dt, "threads": nt,
                       "converged": int(sum(st["converged"] for _, st in out)),
-                      "inner_iters": int(sum(st["total_iters"] for _, st in out))}
+                      "inner_iters": int(sum(st["total_iters"] for _, st in out)),
+                      "row_iterations_per_s": row_its / dt}
         print(f"{label}: {dt * 1e3:.1f} ms/step, {nsys / dt:.1f} solves/s", file=sys.stderr,
               flush=True)
     for h in hs:

@@ -2748,13 +2748,28 @@ hipError_t launch_dots(const DevPencil& P, const PanelGrid& g, const SlotTables&
   auto Qc = static_cast<const C*>(Qk);
   auto Qb = static_cast<const C*>(Qbase);
   if (k <= 0) return hipSuccess;
+  // (the accumulators of MAXK directions stay live whatever k is: the
+  // smallest instantiation that holds k keeps the register count down)
   if (hq) {
     if (!std::is_same<T, float>::value || k > 8) return hipErrorInvalidValue;
-    k_dots_lv<T, 8, true><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, Qc, Qb, vstride,
-                                                           k, part);
+    if (k <= 2)
+      k_dots_lv<T, 2, true><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, Qc, Qb, vstride,
+                                                             k, part);
+    else if (k <= 4)
+      k_dots_lv<T, 4, true><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, Qc, Qb, vstride,
+                                                             k, part);
+    else
+      k_dots_lv<T, 8, true><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, Qc, Qb, vstride,
+                                                             k, part);
     return hipGetLastError();
   }
-  if (k <= 8)
+  if (k <= 2)
+    k_dots_lv<T, 2><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, Qc, Qb, vstride, k,
+                                                     part);
+  else if (k <= 4)
+    k_dots_lv<T, 4><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, Qc, Qb, vstride, k,
+                                                     part);
+  else if (k <= 8)
     k_dots_lv<T, 8><<<g.blocks(), kThreads, 0, s>>>(P.n, g, st.active, Qc, Qb, vstride, k,
                                                      part);
   else if (k <= 16)

@@ -53,7 +53,7 @@ def parse():
                     help="also run a plain 2 GiB device copy (counter scale reference)")
     ap.add_argument("--m", type=int, default=64, help="Q1 nodes per direction (64 = metric)")
     ap.add_argument("--precond", choices=["amg", "jacobi"], default="amg")
-    ap.add_argument("--restart", type=int, default=5, help="GCR restart length m")
+    ap.add_argument("--restart", type=int, default=4, help="GCR restart length m")
     ap.add_argument("--coarse-min", type=int, default=None,
                     help="AMG smallest coarse level (options.amg_coarse_min); default 512 for the "
                          "Q1 workload, 0 (off) for the others")

@@ -104,7 +104,7 @@ def test_solve_batch_64_uneven_pencils_match_oracle():
 
 def test_filter_batch_benchmark_options_coarse_floor():
     """Four pencils of the 64-pencil batch with the batch benchmark's options
-    (mixed, AMG with a coarse-level floor of 128, GCR(5), tol_lin 1e-8): three
+    (mixed, AMG with a coarse-level floor of 128, GCR(4), tol_lin 1e-8): three
     of the hierarchies end in dense levels of 1728, 625 and 729 unknowns
     instead of 27 to 81 (the fourth already ends in 343), every system
     converges to its FP64 residual, the batched call equals the single calls
@@ -120,7 +120,7 @@ def test_filter_batch_benchmark_options_coarse_floor():
             g = gold[d["index"]]
             poles, weights = si.slrf_poles(g["gamma"])
             opt = P.default_options(precision=P.SLRF_PREC_MIXED, precond=P.SLRF_PC_AMG,
-                                    restart=5, tol_lin=1e-8, amg_coarse_min=cmin)
+                                    restart=4, tol_lin=1e-8, amg_coarse_min=cmin)
             hs.append(P.Handle.from_pencil(d["pencil"], g["gamma"], poles, weights, opt,
                                            stream=torch.cuda.Stream(), max_cols=d["L"]))
             Xs.append(_dev(si.start_block(d["pencil"].n, d["L"], d["seed"])))

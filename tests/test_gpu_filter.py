@@ -306,7 +306,7 @@ def _sine_block_3d(m, ks):
 @pytest.mark.parametrize("prec", [P.SLRF_PREC_MIXED, P.SLRF_PREC_FP64])
 def test_filter_sine_full_size_benchmark_options(prec):
     """The benchmark's filter exactly as it runs (n = 262,144, 8 poles, AMG V-cycle
-    with a coarsest level of at least 512, GCR(5), tol_lin 1e-8, cold start,
+    with a coarsest level of at least 512, GCR(4), tol_lin 1e-8, cold start,
     autotuned sweep): in the mixed form this is the path whose cycles keep the
     Gram-Schmidt basis in complex bfloat16.  Per column U = Phi(lambda) u
     (closed form, Eq. (3)) within the bound the residual tolerance implies;
@@ -326,7 +326,7 @@ def test_filter_sine_full_size_benchmark_options(prec):
     iters = {}
     for cmin in (512, 0):
         h = _handle(p, c["gamma"], poles, weights, precision=prec, tol_lin=tol,
-                    precond=P.SLRF_PC_AMG, restart=5, amg_coarse_min=cmin)
+                    precond=P.SLRF_PC_AMG, restart=4, amg_coarse_min=cmin)
         U, st = h.slrf_filter(_dev(X))
         h.close()
         assert st["basis_bf16"] == (1 if prec == P.SLRF_PREC_MIXED else 0)
@@ -339,12 +339,12 @@ def test_filter_sine_full_size_benchmark_options(prec):
 
 @pytest.mark.parametrize("prec", [P.SLRF_PREC_MIXED, P.SLRF_PREC_FP64])
 def test_filter_lu_oracle_benchmark_options(cfg1, prec):
-    """The benchmark's filter options (AMG, GCR(5), tol_lin 1e-8, halo sweep) on the
+    """The benchmark's filter options (AMG, GCR(4), tol_lin 1e-8, halo sweep) on the
     2D configuration against the exact-LU oracle, column by column, with every
     system's FP64 residual recomputed on the host from the single-pole solves."""
     p = cfg1["pencil"]
     tol = 1e-8
-    opt = dict(precision=prec, tol_lin=tol, precond=P.SLRF_PC_AMG, restart=5, spmm_variant=6,
+    opt = dict(precision=prec, tol_lin=tol, precond=P.SLRF_PC_AMG, restart=4, spmm_variant=6,
                amg_coarse_min=512)
     h = _handle(p, cfg1["gamma"], cfg1["poles"], cfg1["weights"], **opt)
     X = cfg1["V1"]

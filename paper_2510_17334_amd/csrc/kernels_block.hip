@@ -2916,8 +2916,11 @@ hipError_t launch_yupdate(int n, const PanelGrid& g, const SlotTables& st, doubl
 bool launch_spmm_real_halo(const DevPencil& P, const double* X, int ld, int nc, double* AX,
                            double* BX, const double* theta, double* E, hipStream_t s,
                            hipError_t& err) {
+  // (on rows of many entries the tiles' halos are wide and the CSR kernel is
+  // faster: 48^3 elasticity, 78 entries per row, 300 columns: 6.1 against
+  // 3.9 ms; the 27-point Q1 pencil at 160 columns: 0.37 against 0.74 ms)
   if (P.hx_ntile == 0 || P.hx_ab64 == nullptr || nc <= 0 || (nc & 1) || (ld & 1) ||
-      (reinterpret_cast<uintptr_t>(X) & 15))
+      (reinterpret_cast<uintptr_t>(X) & 15) || P.nnz > 40L * P.n)
     return false;
   const int G = kHaloMaxG;
   const int nunit = (nc + 15) / 16;

@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--m", type=int, default=64, help="Q1 nodes per direction (64 = metric)")
     ap.add_argument("--precond", choices=["amg", "jacobi"], default="amg")
     ap.add_argument("--restart", type=int, default=4, help="GCR restart length m")
+    ap.add_argument("--spmm-variant", type=int, default=0,
+                    help="options.spmm_variant of the elasticity workload (0: autotuned)")
     ap.add_argument("--coarse-min", type=int, default=None,
                     help="AMG smallest coarse level (options.amg_coarse_min); default 512 for the "
                          "Q1 workload, 0 (off) for the others")
@@ -566,7 +568,8 @@ def run_elasticity48(args):
         poles, weights = si.slrf_poles(gamma)
         opt = P.default_options(precision=prec, precond=P.SLRF_PC_AMG, restart=5,
                                 tol_lin=1e-14, it_max_lin=40, lock=1, warm_start=1,
-                                max_outer=max_outer, amg_coarse_min=args.coarse_min)
+                                max_outer=max_outer, amg_coarse_min=args.coarse_min,
+                                spmm_variant=args.spmm_variant)
         t = time.perf_counter()
         h = P.Handle.from_pencil(p, gamma, poles, weights, opt, max_cols=L, budget=0.6)
         ts = time.perf_counter() - t
